@@ -1,0 +1,97 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the smoke check.
+
+This module holds workload descriptions and random draws only -- none of the
+method's arithmetic.  Both the GPU library's tests and the CPU oracle's tests
+take their inputs from here, so a parity comparison always starts from the
+same bytes.
+
+Workloads (sizes follow the paper's problem class; the numbers are the
+repository's workload definitions):
+
+* ``plain_small``  -- 1x1 cm, 64x64 Q1, D = 1e-3 cm^2/ms, Aliev-Panfilov,
+  global forward Euler dt = 0.01 ms for 10 ms, 0.1x0.1 cm corner stimulus
+  for 1 ms, FP64, zero initial state.
+* ``amr_2d``       -- 2x2 cm, 256x256 Q1 roots, up to 3 refinement levels,
+  4 LTS levels, random stimulus site, 50 ms.
+* ``amr_3d``       -- 2.0x0.7x0.3 cm slab, 128x48x24 Q2 roots, anisotropic
+  D = diag(1.3e-3, 0.33e-3, 0.33e-3), up to 3 refinement levels, 4 LTS
+  levels, corner-cube stimulus, 40 ms.
+"""
+import numpy as np
+
+# Aliev-Panfilov constants: k, a, eps0 from the workload definitions; mu1, mu2
+# are the model's standard values (the workloads do not state them).
+AP_PARAMS = (8.0, 0.15, 0.002, 0.2, 0.3)
+
+WORKLOADS = {
+    "plain_small": dict(dim=2, p=1, n=(64, 64, 1), length=(1.0, 1.0, 1.0), max_depth=0,
+                        n_levels=1, D=(1e-3, 1e-3, 1e-3), gamma=2.0, dt=0.01, t_end=10.0,
+                        stim=[((0.0, 0.0, 0.0), (0.1, 0.1, 1.0), 0.0, 1.0, 1.0)], fp="f64"),
+    "amr_2d": dict(dim=2, p=1, n=(256, 256, 1), length=(2.0, 2.0, 1.0), max_depth=3, n_levels=4,
+                   D=(1e-3, 1e-3, 1e-3), gamma=2.0, t_end=50.0, stim_size=0.1, stim_dur=1.0,
+                   tau_refine=None, tau_coarsen=None, fp="f32"),
+    "amr_3d": dict(dim=3, p=2, n=(128, 48, 24), length=(2.0, 0.7, 0.3), max_depth=3, n_levels=4,
+                   D=(1.3e-3, 0.33e-3, 0.33e-3), gamma=4.0, t_end=40.0,
+                   stim=[((0.0, 0.0, 0.0), (0.1, 0.1, 0.1), 0.0, 1.0, 1.0)], fp="f32"),
+}
+
+
+def rng(seed):
+    return np.random.default_rng(seed)
+
+
+def stimulus_site(seed, length=(2.0, 2.0), size=0.1, margin=0.1, t_on=0.0, t_off=1.0, amp=1.0):
+    """A square (cube) stimulus of edge `size` centred at a uniform site in
+    [margin, L - margin]; returns one box as (lo, hi, t_on, t_off, amp)."""
+    r = rng(seed)
+    dim = len(length)
+    c = [r.uniform(margin, length[k] - margin) for k in range(dim)]
+    lo = [c[k] - 0.5 * size for k in range(dim)] + [0.0] * (3 - dim)
+    hi = [c[k] + 0.5 * size for k in range(dim)] + [1.0] * (3 - dim)
+    return (tuple(lo), tuple(hi), t_on, t_off, amp)
+
+
+def box_array(boxes):
+    """[(lo3, hi3, t_on, t_off, amp), ...] -> float64 array [n, 9]."""
+    out = np.zeros((len(boxes), 9))
+    for i, (lo, hi, t0, t1, amp) in enumerate(boxes):
+        lo = list(lo) + [0.0] * (3 - len(lo))
+        hi = list(hi) + [1.0] * (3 - len(hi))
+        out[i, 0:3] = lo[:3]
+        out[i, 3:6] = hi[:3]
+        out[i, 6:9] = (t0, t1, amp)
+    return out
+
+
+def random_state(seed, n_dof, u_range=(-0.05, 1.0), v_range=(0.0, 1.5)):
+    """Uniform random u and v fields (canonical node order)."""
+    r = rng(seed)
+    u = r.uniform(u_range[0], u_range[1], n_dof)
+    v = r.uniform(v_range[0], v_range[1], n_dof)
+    return u, v
+
+
+def random_eta(seed, n_leaves, scale=1.0, frac_hot=0.15):
+    """Indicator-like values: mostly small, a random fraction large."""
+    r = rng(seed)
+    eta = r.uniform(0.0, 0.2 * scale, n_leaves)
+    hot = r.random(n_leaves) < frac_hot
+    eta[hot] = r.uniform(0.8 * scale, 2.0 * scale, int(hot.sum()))
+    return eta
+
+
+def random_levels(seed, n_leaves, n_levels):
+    return rng(seed).integers(0, n_levels, n_leaves).astype(np.int8)
+
+
+def uniform_tree_bits(n_roots, depth, dim):
+    """Refine-bit stream of a forest uniformly refined to `depth`."""
+    def one(dd):
+        if dd == depth:
+            return [0]
+        out = [1]
+        for _ in range(1 << dim):
+            out += one(dd + 1)
+        return out
+    per_root = one(0)
+    return np.array(per_root * n_roots, dtype=np.uint8)

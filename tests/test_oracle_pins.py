@@ -1,0 +1,503 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test below checks the oracle against something other than itself:
+closed forms, invariants, textbook special cases, brute force on tiny inputs,
+and the worked example of Sec. 2.3 (tests/golden/).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.integrate import solve_ivp
+
+from oracle.oracle import Oracle, EUNSTABLE
+from paper_2310_07607_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+NO_REACTION = (0.0, 0.15, 0.0, 0.0, 0.3)  # k = eps0 = mu1 = 0: pure diffusion
+
+
+def make(dim, p, n, length, depth=0, D=None, gamma=2.0, ap=inputs.AP_PARAMS):
+    o = Oracle(dim, p, n, length, depth)
+    if D is None:
+        D = np.eye(3) * 1e-3
+    o.set_params(D, gamma, ap)
+    return o
+
+
+def refine_some(o, seeds=(0, 1), frac=0.3, rounds=2):
+    """Random non-conforming refinement through the oracle's own AMR."""
+    for s in seeds[:rounds]:
+        eta = inputs.random_eta(s, o.n_leaves, frac_hot=frac)
+        o.adapt(eta, 0.5, -1.0)
+    return o
+
+
+# --------------------------------------------------------------------------
+# basis, quadrature and mass (Sec. 2.1: GL nodes, GL quadrature, diagonal M)
+# --------------------------------------------------------------------------
+GL = {
+    1: ([-1 / math.sqrt(3), 1 / math.sqrt(3)], [1.0, 1.0]),
+    2: ([-math.sqrt(0.6), 0.0, math.sqrt(0.6)], [5 / 9, 8 / 9, 5 / 9]),
+    3: ([-math.sqrt(3 / 7 + 2 / 7 * math.sqrt(6 / 5)), -math.sqrt(3 / 7 - 2 / 7 * math.sqrt(6 / 5)),
+         math.sqrt(3 / 7 - 2 / 7 * math.sqrt(6 / 5)), math.sqrt(3 / 7 + 2 / 7 * math.sqrt(6 / 5))],
+        [(18 - math.sqrt(30)) / 36, (18 + math.sqrt(30)) / 36, (18 + math.sqrt(30)) / 36,
+         (18 - math.sqrt(30)) / 36]),
+}
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_nodes_are_gauss_legendre_closed_forms(p):
+    o = make(2, p, [1, 1], [2.0, 2.0])  # one element = the reference square
+    X = o.leaf_nodes()
+    xi, _ = GL[p]
+    m = p + 1
+    for j in range(m * m):
+        assert X[j, 0] - 1.0 == pytest.approx(xi[j % m], abs=1e-15)
+        assert X[j, 1] - 1.0 == pytest.approx(xi[j // m], abs=1e-15)
+
+
+@pytest.mark.parametrize("dim,p", [(2, 1), (2, 2), (3, 1), (3, 2), (2, 3)])
+def test_mass_is_diagonal_with_gl_weights(dim, p):
+    n = [2, 1, 1][:dim]
+    L = [0.5, 0.3, 0.2][:dim]
+    o = make(dim, p, n, L)
+    _, M = o.dense_operators()
+    off = M - np.diag(np.diag(M))
+    assert np.abs(off).max() <= 1e-15 * np.abs(M).max()
+    _, w = GL[p]
+    m = p + 1
+    h = [L[k] / n[k] for k in range(dim)]
+    jac = np.prod([hk / 2 for hk in h])
+    for j in range((p + 1) ** dim):
+        idx = [(j // m ** k) % m for k in range(dim)]
+        expect = jac * np.prod([w[i] for i in idx])
+        assert M[j, j] == pytest.approx(expect, rel=1e-14)
+
+
+# --------------------------------------------------------------------------
+# SIPG operator (Sec. 2.1)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dim,p,gamma", [(2, 1, 2.0), (2, 2, 4.0), (3, 1, 2.0), (3, 2, 4.0)])
+def test_operator_symmetric_zero_on_constants_negative_semidefinite(dim, p, gamma):
+    n = [3, 2, 2][:dim]
+    o = make(dim, p, n, [0.3, 0.2, 0.2][:dim], depth=2, gamma=gamma)
+    refine_some(o, rounds=1 if dim == 3 else 2)
+    K, _ = o.dense_operators()
+    scale = np.abs(K).max()
+    assert np.abs(K - K.T).max() <= 1e-13 * scale          # symmetric interior penalty
+    assert np.abs(K @ np.ones(K.shape[0])).max() <= 1e-13 * scale  # Neumann: K 1 = 0
+    ev = np.linalg.eigvalsh(-0.5 * (K + K.T))
+    assert ev.min() >= -1e-12 * scale                      # coercive for this gamma
+
+
+def test_q2_penalty_two_is_not_coercive_three_is():
+    # Appendix-A style check of the penalty threshold for degree 2
+    for gamma, coercive in ((2.0, False), (3.0, True)):
+        o = make(2, 2, [4, 4], [1.0, 1.0], gamma=gamma)
+        K, _ = o.dense_operators()
+        ev = np.linalg.eigvalsh(-K)
+        if coercive:
+            assert ev.min() > -1e-12 * np.abs(K).max()
+        else:
+            assert ev.min() < -1e-4 * np.abs(K).max()
+
+
+def _q1_blocks(gamma):
+    with open(os.path.join(GOLDEN, "sipg_q1_1d_blocks.json")) as f:
+        g = json.load(f)
+    env = {"gamma": gamma, "sqrt": math.sqrt}
+    return np.array(eval(g["interior_block"], {}, env)), np.array(eval(g["right_coupling_block"], {}, env))
+
+
+@pytest.mark.parametrize("gamma", [1.0, 2.0, 4.0])
+def test_q1_one_dimensional_blocks_closed_form(gamma):
+    # a 2-D row of elements with D_yy = 0 is the 1-D operator (x) the y-mass
+    h, Dxx, hy = 0.25, 1.3e-3, 0.1
+    o = make(2, 1, [5, 1], [5 * h, hy], D=np.diag([Dxx, 0.0, 0.0]), gamma=gamma)
+    K, M = o.dense_operators()
+    A0, Ap = _q1_blocks(gamma)
+    My = np.diag([hy / 2, hy / 2])
+    e = 2  # interior element
+    sl = lambda i: slice(4 * i, 4 * i + 4)
+    # node order x fastest: (x0,y0),(x1,y0),(x0,y1),(x1,y1) -> kron(My, A)
+    np.testing.assert_allclose(K[sl(e), sl(e)], -(Dxx / h) * np.kron(My, A0), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(K[sl(e), sl(e + 1)], -(Dxx / h) * np.kron(My, Ap), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(K[sl(e + 1), sl(e)], -(Dxx / h) * np.kron(My, Ap.T), rtol=0, atol=1e-15)
+    assert np.abs(K[sl(e), sl(e + 2)]).max() == 0.0
+
+
+def test_kronecker_sum_structure_uniform_2d():
+    # uniform mesh, diagonal D: K2 = Kx (x) My + Mx (x) Ky, with the 1-D
+    # factors taken from one-row meshes (the y-row with D_xx = 0)
+    nx, ny, Lx, Ly, Dx, Dy, g = 4, 3, 0.8, 0.45, 1.1e-3, 0.4e-3, 2.0
+    o2 = make(2, 1, [nx, ny], [Lx, Ly], D=np.diag([Dx, Dy, 0]), gamma=g)
+    K2, M2 = o2.dense_operators()
+    ox = make(2, 1, [nx, 1], [Lx, 2.0], D=np.diag([Dx, 0, 0]), gamma=g)
+    Kx, Mx = ox.dense_operators()
+    oy = make(2, 1, [1, ny], [2.0, Ly], D=np.diag([0, Dy, 0]), gamma=g)
+    Ky, My = oy.dense_operators()
+    # strip the unit-width second dimension: Kx = kx (x) diag(1,1) (ref width 2 -> jac 1)
+    kx = Kx.reshape(nx, 2, 2, nx, 2, 2)[:, 0, :, :, 0, :].reshape(2 * nx, 2 * nx)
+    mx = np.diag(np.diag(Mx).reshape(nx, 2, 2)[:, 0, :].reshape(-1))
+    ky = Ky.reshape(ny, 2, 2, ny, 2, 2)[:, :, :, :, :, 0][:, :, 0, :, :].reshape(2 * ny, 2 * ny)
+    my = np.diag(np.diag(My).reshape(ny, 2, 2)[:, :, 0].reshape(-1))
+
+    def to_elem(A1x, A1y):
+        # (ex,ix),(ey,iy) -> element (ex + nx*ey), node ix + 2*iy
+        A = np.kron(A1y, A1x)  # index (ey,iy,ex,ix)
+        A = A.reshape(ny, 2, nx, 2, ny, 2, nx, 2).transpose(0, 2, 1, 3, 4, 6, 5, 7)
+        return A.reshape(4 * nx * ny, 4 * nx * ny)
+    Kk = to_elem(kx, my) + to_elem(mx, ky)
+    np.testing.assert_allclose(K2, Kk, rtol=0, atol=1e-14 * np.abs(K2).max())
+
+
+@pytest.mark.parametrize("dim,p", [(2, 1), (2, 2), (3, 1), (3, 2)])
+def test_linear_fields_are_stationary_away_from_the_boundary(dim, p):
+    # SIPG consistency: a linear u has zero flux jumps, so (K u)_i = 0 on every
+    # element without a boundary face -- also across non-conforming faces and
+    # with a full diffusion tensor; and the face-jump indicator vanishes.
+    D = np.array([[1.2e-3, 0.3e-3, 0.1e-3], [0.3e-3, 0.8e-3, 0.2e-3], [0.1e-3, 0.2e-3, 0.5e-3]])
+    n = [4, 4, 3][:dim]
+    o = make(dim, p, n, [0.4, 0.4, 0.3][:dim], depth=2, D=D)
+    refine_some(o, rounds=1)
+    X = o.leaf_nodes()
+    u = 0.3 + 0.7 * X[:, 0] - 0.2 * X[:, 1] + (0.5 * X[:, 2] if dim == 3 else 0.0)
+    Ku = o.apply_K(u).reshape(o.n_leaves, -1)
+    depth, coords = o.leaf_info()
+    for e in range(o.n_leaves):
+        interior = all(0 < coords[e, k] < n[k] * 2 ** depth[e] - 1 for k in range(dim))
+        if interior:
+            assert np.abs(Ku[e]).max() < 1e-15
+    o.set_state(u, np.zeros_like(u))
+    assert np.abs(o.indicator()).max() < 1e-12
+
+
+@pytest.mark.parametrize("p,ratio_min,sizes", [(1, 3.7, (8, 16)), (2, 15.0, (4, 8))])
+def test_smallest_eigenvalue_converges_to_laplacian_mode(p, ratio_min, sizes):
+    # -M^-1 K has smallest non-zero eigenvalue -> pi^2 D / Lx^2 (Neumann box)
+    D, Lx, Ly = 1e-3, 1.0, 0.5
+    errs = []
+    for n in sizes:
+        o = make(2, p, [n, n // 2], [Lx, Ly], D=np.eye(3) * D, gamma=2.0 if p == 1 else 4.0)
+        K, M = o.dense_operators()
+        d = 1.0 / np.sqrt(np.diag(M))
+        ev = np.sort(np.linalg.eigvalsh(-(d[:, None] * K * d[None, :])))
+        lam = ev[1]
+        errs.append(abs(lam - math.pi ** 2 * D / Lx ** 2) / (math.pi ** 2 * D / Lx ** 2))
+    assert errs[1] < 2e-2
+    assert errs[0] / errs[1] > ratio_min   # O(h^{2p}) eigenvalue convergence
+
+
+def test_manufactured_diffusion_solution_converges_second_order_q1():
+    D, Lx, Ly = 1e-3, 1.0, 1.0
+    lam = math.pi ** 2 * D * (1 / Lx ** 2 + 1 / Ly ** 2)
+    T = 20.0
+    errs = []
+    for n in (8, 16):
+        o = make(2, 1, [n, n], [Lx, Ly], D=np.eye(3) * D, gamma=2.0, ap=NO_REACTION)
+        X = o.leaf_nodes()
+        u0 = np.cos(math.pi * X[:, 0] / Lx) * np.cos(math.pi * X[:, 1] / Ly)
+        o.set_state(u0, np.zeros_like(u0))
+        dt = 0.25 * o.cfl().min()
+        steps = int(round(T / dt))
+        dt = T / steps
+        o.step_global(dt, 0.0, steps)
+        u, _ = o.get_state()
+        errs.append(np.abs(u - u0 * math.exp(-lam * T)).max())
+    assert errs[1] < 5e-3
+    assert errs[0] / errs[1] > 3.3
+
+
+def test_pure_diffusion_conserves_mass():
+    o = make(2, 2, [3, 3], [0.3, 0.3], depth=2, gamma=4.0, ap=NO_REACTION)
+    refine_some(o)
+    u, _ = inputs.random_state(3, o.n_leaves * o.np_)
+    o.set_state(u, np.zeros_like(u))
+    _, M = o.dense_operators()
+    m0 = np.diag(M) @ u
+    o.step_global(0.5 * o.cfl().min(), 0.0, 20)
+    u1, _ = o.get_state()
+    assert abs(np.diag(M) @ u1 - m0) <= 1e-13 * np.abs(np.diag(M) @ np.abs(u)).max()
+
+
+# --------------------------------------------------------------------------
+# ionic model and its time integrator (Sec. 2.3)
+# --------------------------------------------------------------------------
+def _ap_rhs(t, y, k=8.0, a=0.15, e0=0.002, m1=0.2, m2=0.3):
+    # Aliev-Panfilov two-variable model (the published model equations)
+    u, v = y
+    return [-k * u * (u - a) * (u - 1) - u * v, (e0 + m1 * v / (u + m2)) * (-v - k * u * (u - a - 1))]
+
+
+def _single_cell(dt, T, u0):
+    # a constant field has K u = 0, so every node is one isolated cell
+    o = make(2, 1, [1, 1], [0.1, 0.1])
+    o.set_state(np.full(4, u0), np.zeros(4))
+    o.step_global(dt, 0.0, int(round(T / dt)))
+    u, v = o.get_state()
+    return u[0], v[0]
+
+
+def test_single_cell_first_order_convergence_to_ode_solution():
+    T, u0 = 20.0, 0.3
+    ref = solve_ivp(_ap_rhs, (0, T), [u0, 0.0], method="DOP853", rtol=1e-12, atol=1e-13).y[:, -1]
+    e1 = np.hypot(*(np.array(_single_cell(0.01, T, u0)) - ref))
+    e2 = np.hypot(*(np.array(_single_cell(0.005, T, u0)) - ref))
+    assert e1 < 5e-3
+    assert 1.7 < e1 / e2 < 2.3   # first order in dt
+
+
+def test_cell_threshold_behaviour():
+    # f(u, 0) = -k u (u-a)(u-1): below the threshold a the cell returns to
+    # rest, above it the cell depolarises towards u = 1
+    assert _single_cell(0.01, 10.0, 0.12)[0] < 0.05
+    assert _single_cell(0.01, 10.0, 0.18)[0] > 0.9
+    assert _single_cell(0.01, 10.0, 0.0) == (0.0, 0.0)
+
+
+def test_stimulus_acts_only_inside_box_and_window():
+    o = make(2, 1, [4, 4], [0.4, 0.4], ap=NO_REACTION)
+    o.set_stimulus(inputs.box_array([((0.0, 0.0), (0.1, 0.1), 0.5, 1.0, 2.0)]))
+    X = o.leaf_nodes()
+    inside = (X[:, 0] <= 0.1) & (X[:, 1] <= 0.1)
+    o.step_global(0.01, 0.0, 50)           # t in [0, 0.5): off
+    u, _ = o.get_state()
+    assert np.abs(u).max() == 0.0
+    o.step_global(0.01, 0.5, 1)            # t = 0.5: on
+    u, _ = o.get_state()
+    assert np.all(u[inside] == pytest.approx(0.02, abs=1e-18))
+    assert np.all(u[~inside] == 0.0)
+
+
+# --------------------------------------------------------------------------
+# CFL, levels and the LTS schedule (Sec. 2.3, Algorithm 1)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("p,gamma,rowsum", [(1, 2.0, 12.0), (1, 4.0, 24.0), (2, 4.0, 41.3333), (2, 8.0, 97.3333)])
+def test_interior_gershgorin_bound_matches_1d_row_sums(p, gamma, rowsum):
+    # interior element of a uniform mesh, isotropic D: CFL = h^2 / (d * r D)
+    # with r the 1-D row sum (Q1: 6 gamma; Q2 values as tabulated)
+    h, D = 0.1, 1e-3
+    o = make(2, p, [5, 5], [0.5, 0.5], D=np.eye(3) * D, gamma=gamma)
+    cfl = o.cfl().reshape(5, 5)
+    assert cfl[2, 2] == pytest.approx(h * h / (2 * rowsum * D), rel=1e-5)
+    assert cfl.min() <= cfl[2, 2]
+
+
+def test_levels_powers_of_two_and_unstable_flag():
+    o = make(2, 1, [6, 6], [0.6, 0.6], depth=2)
+    refine_some(o)
+    cfl = o.cfl()
+    dt = 4 * cfl.min()
+    lv, rc = o.levels(dt, 3)
+    assert rc == 0
+    for e in range(o.n_leaves):
+        b = lv[e]
+        assert dt * 2.0 ** -b <= cfl[e]
+        assert b == 0 or dt * 2.0 ** -(b - 1) > cfl[e]
+    _, rc = o.levels(8 * cfl.min(), 3)
+    assert rc == EUNSTABLE
+
+
+def test_bucket_is_stable_sort_finest_first():
+    lv = inputs.random_levels(5, 1000, 4)
+    perm, cnt = Oracle.bucket(lv, 4)
+    ref = np.argsort(-lv.astype(int), kind="stable")
+    assert np.array_equal(perm, ref)
+    for l in range(4):
+        assert cnt[l] == int((lv >= l).sum())
+
+
+def test_worked_example_of_fig2():
+    with open(os.path.join(GOLDEN, "fig2_worked_example.json")) as f:
+        g = json.load(f)
+    o = make(2, 1, g["roots"], [0.3, 0.1], depth=1)
+    bits = np.array([0, 1, 0, 0, 0, 0, 0], dtype=np.uint8)
+    o.set_tree(bits)
+    assert o.n_leaves == 6
+    lv = np.array(g["levels"], dtype=np.int8)
+    u, v = inputs.random_state(1, o.n_leaves * 4)
+    o.set_state(u, v)
+    n_upd, tr = o.lts_barrier(0.01, 0.0, lv, mode=0, trace_cap=1000)
+    assert n_upd == g["updates_per_barrier"]
+    sweeps = [sorted(set(int(e) for i, e, _, _ in tr if int(i) == s)) for s in range(g["n_sweeps"])]
+    assert sweeps == g["sweep_members"]
+    outer = {0, 5}
+    for s in range(g["n_sweeps"]):
+        th = {row[3] for row in tr if int(row[0]) == s and int(row[1]) in (1, 2, 3, 4) and int(row[2]) in outer}
+        assert th == {g["theta_of_outer_neighbour_seen_by_children"][s]}
+
+
+def _random_refined(dim, p, seed, depth=2):
+    n = [5, 4, 3][:dim]
+    o = make(dim, p, n, [0.5, 0.4, 0.3][:dim], depth=depth, gamma=2.0 if p == 1 else 4.0)
+    refine_some(o, seeds=(seed, seed + 1))
+    u, v = inputs.random_state(seed, o.n_leaves * o.np_)
+    o.set_state(u, v)
+    return o, u, v
+
+
+@pytest.mark.parametrize("dim,p", [(2, 1), (2, 2), (3, 1)])
+def test_queue_form_equals_two_slot_level_form_bitwise(dim, p):
+    o, u, v = _random_refined(dim, p, 11)
+    cfl = o.cfl()
+    dt = 4 * cfl.min() * (1 - 2 ** -20)
+    lv, rc = o.levels(dt, 3)
+    assert rc == 0 and lv.max() == 2 and lv.min() == 0
+    o.set_state(u, v)
+    n0, _ = o.lts_barrier(dt, 0.3, lv, mode=0)
+    a = o.get_state()
+    o.set_state(u, v)
+    n1, _ = o.lts_barrier(dt, 0.3, lv, mode=1)
+    b = o.get_state()
+    assert n0 == n1 == int((2 ** lv.astype(int)).sum())
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("level", [0, 1, 2])
+def test_single_level_lts_equals_global_stepping_bitwise(level):
+    o, u, v = _random_refined(2, 1, 5)
+    o.set_stimulus(inputs.box_array([((0.0, 0.0), (0.2, 0.2), 0.0, 0.31, 1.0)]))
+    dt = 0.2 * o.cfl().min() * 2 ** level
+    lv = np.full(o.n_leaves, level, dtype=np.int8)
+    o.set_state(u, v)
+    o.lts_barrier(dt, 0.3, lv, mode=0)
+    a = o.get_state()
+    o.set_state(u, v)
+    o.step_global(dt / 2 ** level, 0.3, 2 ** level)
+    b = o.get_state()
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_lts_converges_to_fine_global_stepping_first_order():
+    # LTS differs from global stepping at the finest dt by the first-order
+    # time error of the coarse elements: halving the barrier step (same
+    # level pattern) halves the difference.
+    o, _, _ = _random_refined(2, 1, 7)
+    o.set_params(np.eye(3) * 1e-3, 2.0, NO_REACTION)
+    X = o.leaf_nodes()
+    u = np.cos(math.pi * X[:, 0] / 0.5) * np.cos(math.pi * X[:, 1] / 0.4)
+    v = np.zeros_like(u)
+    dt0 = 4 * o.cfl().min() * (1 - 2 ** -20)
+    lv, _ = o.levels(dt0, 3)
+    T = 16 * dt0
+    diffs = []
+    for scale in (1, 2):
+        dt = dt0 / scale
+        o.set_state(u, v)
+        for n in range(16 * scale):
+            o.lts_barrier(dt, n * dt, lv)
+        a, _ = o.get_state()
+        o.set_state(u, v)
+        o.step_global(dt / 4, 0.0, 64 * scale)
+        b, _ = o.get_state()
+        diffs.append(np.abs(a - b).max() / np.abs(b - u).max())
+    assert diffs[0] < 0.05
+    assert 1.7 < diffs[0] / diffs[1] < 2.3
+
+
+# --------------------------------------------------------------------------
+# indicator and adaptivity (Sec. 2.2, Algorithm 1)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("p", [1, 2])
+def test_indicator_closed_form_for_a_kink(p):
+    # u = |x - x0| with x0 on an element face: the normal flux jumps by 2D on
+    # that face only, so eta_e^2 = h/(2p) * h^2 * (h * (2D)^2) for the two
+    # adjacent elements of a uniform 2-D mesh (|F| = h), zero elsewhere.
+    h, D = 0.1, 1e-3
+    o = make(2, p, [4, 3], [0.4, 0.3], D=np.eye(3) * D)
+    X = o.leaf_nodes()
+    u = np.abs(X[:, 0] - 0.2)
+    o.set_state(u, np.zeros_like(u))
+    eta = o.indicator().reshape(3, 4)
+    expect = math.sqrt(h / (2 * p) * h ** 2 * h * (2 * D) ** 2)
+    np.testing.assert_allclose(eta[:, 1:3], expect, rtol=1e-12)
+    assert np.abs(eta[:, [0, 3]]).max() < 1e-15
+
+
+def test_tree_bits_roundtrip_and_validation():
+    o = make(2, 1, [3, 2], [0.3, 0.2], depth=2)
+    refine_some(o)
+    bits = o.tree_bits()
+    o2 = make(2, 1, [3, 2], [0.3, 0.2], depth=2)
+    o2.set_tree(bits)
+    assert np.array_equal(o2.tree_bits(), bits)
+    assert np.array_equal(o2.leaf_info()[1], o.leaf_info()[1])
+    # over-depth and unbalanced streams are rejected
+    o3 = make(2, 1, [2, 1], [0.2, 0.1], depth=1)
+    with pytest.raises(Exception):
+        o3.set_tree(np.array([1, 1, 0, 0, 0, 0, 0, 0, 0, 0], dtype=np.uint8))
+    o4 = make(2, 1, [2, 1], [0.2, 0.1], depth=2)
+    # root 0 refined twice in its upper-right child, root 1 a leaf -> 2:1 violated
+    with pytest.raises(Exception):
+        o4.set_tree(np.array([1, 0, 1, 0, 0, 0, 0, 0, 0, 0], dtype=np.uint8))
+    o4.set_tree(np.array([1, 0, 1, 0, 0, 0, 0, 0, 0, 1, 0, 0, 0, 0], dtype=np.uint8))
+
+
+def test_refinement_closure_keeps_two_to_one():
+    o = make(2, 1, [3, 3], [0.3, 0.3], depth=3)
+    eta = np.zeros(9)
+    eta[4] = 1.0
+    o.adapt(eta, 0.5, -1.0)                 # centre root -> depth 1
+    depth, coords = o.leaf_info()
+    # refine the depth-1 child touching root 1 (below): its coarser neighbour
+    # root must be refined too
+    e = [i for i in range(o.n_leaves) if depth[i] == 1 and coords[i, 0] == 2 and coords[i, 1] == 2][0]
+    eta = np.zeros(o.n_leaves)
+    eta[e] = 1.0
+    nr, nc = o.adapt(eta, 0.5, -1.0)
+    assert nr == 3  # the marked child plus its two coarser face neighbours (roots 1 and 3)
+    depth, coords = o.leaf_info()
+    assert depth.max() == 2
+    assert o.n_leaves == 9 - 1 + 4 - 1 + 4 - 2 + 8
+
+
+def test_coarsening_rules():
+    o = make(2, 1, [2, 1], [0.2, 0.1], depth=2)
+    o.adapt(np.array([1.0, 1.0]), 0.5, -1.0)        # both roots -> 8 leaves
+    eta = np.array([0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.2])
+    nr, nc = o.adapt(eta, 0.5, 0.1)                  # root 0 coarsens, root 1 not
+    assert (nr, nc) == (0, 1) and o.n_leaves == 5
+    o.adapt(np.ones(5), 0.5, -1.0)                   # everything one deeper (closure ok)
+    assert o.n_leaves == 4 + 16
+
+
+@pytest.mark.parametrize("dim,p", [(2, 1), (2, 2), (3, 1)])
+def test_transfer_prolong_then_restrict_is_identity_and_conservative(dim, p):
+    n = [2, 2, 2][:dim]
+    o = make(dim, p, n, [0.2, 0.2, 0.2][:dim], depth=1, ap=NO_REACTION)
+    u, v = inputs.random_state(2, o.n_leaves * o.np_)
+    o.set_state(u, v)
+    _, M = o.dense_operators()
+    mass0 = np.diag(M) @ u
+    o.adapt(np.ones(o.n_leaves), 0.5, -1.0)
+    _, M1 = o.dense_operators()
+    u1, _ = o.get_state()
+    assert np.diag(M1) @ u1 == pytest.approx(mass0, rel=1e-13)
+    o.adapt(np.zeros(o.n_leaves), 0.5, 0.1)
+    u2, v2 = o.get_state()
+    np.testing.assert_allclose(u2, u, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(v2, v, rtol=0, atol=1e-13)
+    # restriction of a random fine field preserves the integral
+    o.adapt(np.ones(o.n_leaves), 0.5, -1.0)
+    uf, vf = inputs.random_state(4, o.n_leaves * o.np_)
+    o.set_state(uf, vf)
+    _, Mf = o.dense_operators()
+    mf = np.diag(Mf) @ uf
+    o.adapt(np.zeros(o.n_leaves), 0.5, 0.1)
+    _, Mc = o.dense_operators()
+    uc, _ = o.get_state()
+    assert np.diag(Mc) @ uc == pytest.approx(mf, rel=1e-13)
+
+
+def test_point_evaluation_reproduces_nodal_values_and_linears():
+    o = make(2, 2, [3, 2], [0.3, 0.2], depth=2, gamma=4.0)
+    refine_some(o)
+    X = o.leaf_nodes()
+    u = 1.0 + 2.0 * X[:, 0] - 3.0 * X[:, 1]
+    o.set_state(u, np.zeros_like(u))
+    np.testing.assert_allclose(o.eval_points(X[:, :2]), u, atol=1e-14)
+    pts = inputs.rng(9).uniform([0, 0], [0.3, 0.2], (50, 2))
+    np.testing.assert_allclose(o.eval_points(pts), 1.0 + 2.0 * pts[:, 0] - 3.0 * pts[:, 1], atol=1e-13)
