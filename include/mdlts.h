@@ -1,0 +1,192 @@
+/*
+ * mdlts.h -- C ABI of the MI355X (gfx950) library for the explicit SIPG-DG
+ * monodomain step under synchronous local time stepping.
+ *
+ * Method: Ogiermann, Balzani, Perotti, "An Explicit Local Space-Time Adaptive
+ * Framework for Monodomain Models in Cardiac Electrophysiology",
+ * arXiv:2310.07607.  Problem statement: Sec. 2 (monodomain model with
+ * homogeneous Neumann boundary, D = kappa/(chi C_m), I = I'/C_m); spatial
+ * discretisation: Sec. 2.1; adaptivity: Sec. 2.2; synchronous LTS: Sec. 2.3
+ * and Algorithm 1.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every function returns an mdlts_status; MDLTS_OK (0) on success.  No
+ *    function aborts, prints, or retains a host pointer after it returns.
+ *  - Host arrays are owned by the caller and copied during the call.
+ *  - Device memory comes from the allocator given to mdlts_ctx_create (or
+ *    hipMalloc when none is given) and is used on the context's stream.
+ *  - Mesh: an axis-aligned box [0,len0]x[0,len1](x[0,len2]) split into a root
+ *    grid n0 x n1 (x n2) of boxes ("root elements", Sec. 2.2); each root is
+ *    the root of a 2^d-tree.  Root id = rx + n0*(ry + n1*rz).  Child index =
+ *    bx | by<<1 | bz<<2 (bit k set: upper half in dimension k).
+ *  - Canonical leaf order: roots in id order, pre-order inside each tree.
+ *  - Element nodes: tensor Gauss-Legendre nodes of degree `order`, node index
+ *    ix + m*iy + m*m*iz with m = order+1 (x fastest).  State vectors are
+ *    [leaf][node] in canonical leaf order, FP64 at this ABI.
+ *  - Refine-bit stream: pre-order over every node of every tree, roots in id
+ *    order, one byte per node: 1 = refined (its 2^d children follow in child
+ *    index order), 0 = leaf.  Trees must be 2:1 balanced across faces.
+ *  - Units: cm, ms; u (transmembrane potential) and v (gate) dimensionless.
+ *  - Thread safety: one context per host thread; calls on one context are
+ *    serialised by the caller.
+ */
+#ifndef MDLTS_H
+#define MDLTS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MDLTS_OK = 0,
+    MDLTS_EINVAL = 1,     /* bad argument, size, or mesh */
+    MDLTS_ENOMEM = 2,     /* device allocation failed */
+    MDLTS_EDEVICE = 3,    /* a HIP call or kernel failed */
+    MDLTS_EUNSTABLE = 4,  /* a leaf needs more LTS levels than configured, or non-finite state */
+    MDLTS_ESTATE = 5,     /* call out of order (e.g. step before assign_levels) */
+    MDLTS_EBUSY = 6       /* simulation belongs to a running batch */
+} mdlts_status;
+
+enum { MDLTS_FP64 = 0, MDLTS_FP32 = 1 };
+
+typedef struct mdlts_ctx mdlts_ctx;
+typedef struct mdlts_sim mdlts_sim;
+
+/* Optional device allocator (e.g. a framework's caching allocator).  alloc
+ * returns NULL on failure; both are called with the context's stream. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *stream, void *user);
+    void (*free)(void *ptr, void *stream, void *user);
+    void *user;
+} mdlts_allocator;
+
+typedef struct {
+    int dim;          /* 2 or 3 */
+    int order;        /* polynomial degree p: 1 or 2 */
+    int n[3];         /* root grid (n[2] ignored for dim 2) */
+    double len[3];    /* box edge lengths [cm] */
+    int max_depth;    /* refinement depth cap, 0..8 */
+    int n_levels;     /* LTS levels L, 1..8; level l takes 2^l substeps */
+    int precision;    /* MDLTS_FP64 or MDLTS_FP32 (bulk arithmetic and storage) */
+} mdlts_mesh_desc;
+
+/* Aliev-Panfilov two-variable model: du/dt += -k u (u-a)(u-1) - u v;
+ * dv/dt = (eps0 + mu1 v/(u+mu2)) (-v - k u (u-a-1)). */
+typedef struct { double k, a, eps0, mu1, mu2; } mdlts_ap_params;
+
+/* Stimulus: adds amp [1/ms] to du/dt at nodes with lo <= x <= hi for
+ * t_on <= t < t_off (the -I_stim/C_m term of the model, Sec. 2). */
+typedef struct { double lo[3], hi[3], t_on, t_off, amp; } mdlts_stim_box;
+
+const char *mdlts_strerror(mdlts_status s);
+
+/* ---- context ------------------------------------------------------------ */
+/* device: HIP device ordinal; hip_stream: a hipStream_t (NULL = default
+ * stream); alloc may be NULL.  Errors: EINVAL, EDEVICE. */
+mdlts_status mdlts_ctx_create(int device, void *hip_stream, const mdlts_allocator *alloc, mdlts_ctx **out);
+/* EBUSY while simulations created on the context are still alive. */
+mdlts_status mdlts_ctx_destroy(mdlts_ctx *ctx);
+/* Waits for the stream and reports asynchronous kernel failures (EDEVICE). */
+mdlts_status mdlts_sync(mdlts_ctx *ctx);
+
+/* ---- simulation: mesh and parameters (Sec. 2, Sec. 2.2) ------------------ */
+/* Creates a simulation on the root mesh (all roots leaves, u = v = 0, t = 0,
+ * D = 1e-3 I, gamma = 2, standard Aliev-Panfilov constants, no stimulus). */
+mdlts_status mdlts_sim_create(mdlts_ctx *ctx, const mdlts_mesh_desc *desc, mdlts_sim **out);
+mdlts_status mdlts_sim_destroy(mdlts_sim *sim);
+/* Replaces the forest (refine-bit stream, see above).  The state is reset to
+ * zero.  EINVAL: malformed stream, depth above max_depth, or not 2:1 balanced. */
+mdlts_status mdlts_set_tree(mdlts_sim *sim, const uint8_t *refine_bits, size_t n_bits);
+/* Serialises the current forest; *n_bits receives the length (also when
+ * bits is NULL or cap is too small, in which case nothing is written). */
+mdlts_status mdlts_get_tree(mdlts_sim *sim, uint8_t *bits, size_t cap, size_t *n_bits);
+mdlts_status mdlts_n_leaves(mdlts_sim *sim, size_t *n_leaves);
+/* Diffusion tensor D (Sec. 2: D = kappa/(chi C_m)) as Dxx,Dyy,Dzz,Dxy,Dxz,Dyz
+ * [cm^2/ms] and the SIPG penalty gamma (Sec. 2.1).  This library supports a
+ * diagonal D (axis-aligned fibres); EINVAL for off-diagonal entries, a
+ * non-positive diagonal, or a gamma for which the element blocks lose their
+ * negative diagonal. */
+mdlts_status mdlts_set_conductivity(mdlts_sim *sim, const double D_sym[6], double gamma);
+mdlts_status mdlts_set_ionic(mdlts_sim *sim, const mdlts_ap_params *p);
+/* At most 8 boxes. */
+mdlts_status mdlts_set_stimulus(mdlts_sim *sim, const mdlts_stim_box *boxes, int n_boxes);
+/* u, v: [n_leaves * (order+1)^dim] FP64 in canonical order; n_dof must match.
+ * Either pointer may be NULL (that field is left unchanged / not read). */
+mdlts_status mdlts_set_state(mdlts_sim *sim, const double *u, const double *v, size_t n_dof);
+mdlts_status mdlts_get_state(mdlts_sim *sim, double *u, double *v, size_t n_dof);
+/* Simulated time of the next barrier; also resets the barrier counter. */
+mdlts_status mdlts_set_time(mdlts_sim *sim, double t);
+
+/* ---- LTS levels (Sec. 2.3: Gershgorin CFL, b^CFL, S_e = 2^b) ------------- */
+/* Per leaf: CFL_e = 1 / max_i sum_j |(M_e^-1 K_ee)_ij| (own block, neighbours
+ * frozen), level b_e = smallest b >= 0 with dt_barrier*2^-b <= CFL_e.  Leaves
+ * are then grouped by level, finest first, stable in canonical order.  Runs on
+ * the device.  level_hist (optional, [n_levels]) receives the counts per
+ * level.  EUNSTABLE if some leaf needs b_e > n_levels-1 (levels are then
+ * left unassigned). */
+mdlts_status mdlts_assign_levels(mdlts_sim *sim, double dt_barrier, int32_t *level_hist);
+/* Copies the last assignment: level [n_leaves] (canonical order), perm
+ * [n_leaves] (grouped position -> canonical leaf), cnt_ge [n_levels]
+ * (number of leaves with level >= l).  Any pointer may be NULL. */
+mdlts_status mdlts_get_levels(mdlts_sim *sim, int8_t *level, int32_t *perm, int32_t *cnt_ge, size_t n_leaves);
+/* FP64 CFL_e per leaf in canonical order, as used by mdlts_assign_levels. */
+mdlts_status mdlts_get_cfl(mdlts_sim *sim, double *cfl, size_t n_leaves);
+
+/* ---- stepping (Sec. 2.3, Algorithm 1) ------------------------------------ */
+/* Advances n_barriers barrier intervals.  In each, substep i = 0..2^lmax-1
+ * updates every leaf of level >= lmax - v2(i) (all at i = 0) by one
+ * forward-Euler step of the SIPG operator (element volume + interior-penalty
+ * faces + inverse diagonal mass) with the Aliev-Panfilov reaction and the
+ * stimulus, and one exponential step of the gate, with dt_e = dt_barrier /
+ * 2^level; neighbours not updated at substep i are linearly interpolated in
+ * time.  Asynchronous on the context stream.  ESTATE if levels are not
+ * assigned for the current forest. */
+mdlts_status mdlts_step(mdlts_sim *sim, int n_barriers);
+
+/* ---- error indicator and adaptivity (Sec. 2.2, Algorithm 1) -------------- */
+/* Kelly-type indicator eta_e^2 = sum over interior face pieces F of e of
+ * h_F/(2p) * W_F^2 * ||[[D grad u . n]]||^2_{L2(F)} at the barrier (FP64
+ * accumulation on the device).  eta: [n_leaves] canonical order (may be
+ * NULL); eta_max: max over leaves (may be NULL).  Synchronises the stream.
+ * EUNSTABLE if the state holds a non-finite value. */
+mdlts_status mdlts_indicator(mdlts_sim *sim, double *eta, size_t n_leaves, double *eta_max);
+/* Refines leaves with eta >= tau_refine (below max_depth), closes the 2:1
+ * balance by refining coarser face neighbours, coarsens parents whose
+ * children all have eta <= tau_coarsen (when that keeps 2:1 balance), and
+ * transfers u and v (prolongation by evaluation, restriction by L2
+ * projection).  eta: [n_leaves] canonical order, or NULL to use the last
+ * mdlts_indicator result.  Levels must be assigned again afterwards. */
+mdlts_status mdlts_adapt(mdlts_sim *sim, const double *eta, size_t n_leaves, double tau_refine,
+                         double tau_coarsen, int64_t *n_refined, int64_t *n_coarsened);
+
+/* DoF-updates performed so far (sum over substeps of active leaves times
+ * nodes per leaf) and the simulated time of the next barrier. */
+mdlts_status mdlts_counters(mdlts_sim *sim, uint64_t *dof_updates, double *t_sim);
+
+/* ---- host-only planning utilities (no device work) ---------------------- */
+/* Lower bound on CFL_e over the leaves of the given depth (worst face kinds
+ * per direction that a 2:1-balanced forest allows; attained on uniform
+ * meshes).  A barrier step of 2^(L-1) * bound(max_depth) keeps every leaf
+ * within L levels. */
+mdlts_status mdlts_cfl_bound(const mdlts_mesh_desc *desc, const double D_sym[6], double gamma, int depth,
+                             double *cfl_min);
+/* The adaptation decisions of mdlts_adapt on a given forest and indicator,
+ * computed on the host: writes the new refine-bit stream (*n_out receives
+ * its length; nothing is written if cap is too small). */
+mdlts_status mdlts_plan_adapt(const mdlts_mesh_desc *desc, const uint8_t *bits, size_t n_bits, const double *eta,
+                              size_t n_leaves, double tau_refine, double tau_coarsen, uint8_t *out_bits,
+                              size_t cap, size_t *n_out);
+/* Levels, grouping and CFL of mdlts_assign_levels computed on the host for a
+ * given forest (any output pointer may be NULL). */
+mdlts_status mdlts_plan_levels(const mdlts_mesh_desc *desc, const uint8_t *bits, size_t n_bits, const double D_sym[6],
+                               double gamma, double dt_barrier, int8_t *level, int32_t *perm, int32_t *cnt_ge,
+                               double *cfl, size_t n_leaves);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

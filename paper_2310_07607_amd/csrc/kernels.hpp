@@ -1,0 +1,373 @@
+// kernels.hpp -- device kernels of the SIPG-DG / synchronous-LTS hot path
+// for gfx950 (64-wide wavefronts).  Included only by mdlts.hip.
+//
+// Layout in HBM (one simulation):
+//   u      [2 slots][np][cap]  bulk precision T; element j of the level-grouped
+//                              order, node n at u[slot*np*cap + n*cap + j]
+//   v      [np][cap]           gate state (element-local, updated in place)
+//   key    [cap]               packed depth + cell coordinates (2-D: 32 bit)
+//   nbr    [2d][cap]           packed face entries: kind(2) | level(3) | id(27)
+//   fine   [groups][2^(d-1)]   entries of the fine neighbours of a face
+// Element threads read their own nodes with unit stride across the wave
+// (coalesced), and gather neighbour nodes through the face entries.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "host.hpp"
+
+namespace mdlts {
+
+constexpr uint32_t kIdMask27 = 0x07ffffffu;
+constexpr uint32_t kIdMask30 = 0x3fffffffu;
+constexpr int kMaxStim = 8;
+constexpr int kMaxLevels = 8;
+
+template <typename T>
+struct DevRef {
+    T A[kMaxM][kMaxM];
+    T B[2][kMaxM], G[2][kMaxM];
+    T Isub[2][kMaxM][kMaxM], Lsub[2][kMaxM][kMaxM];
+    T w[kMaxM], winv[kMaxM];
+    double xi[kMaxM];
+};
+
+template <typename T>
+struct StepArgs {
+    T *u;
+    T *v;
+    const void *key;
+    const uint32_t *nbr;
+    const uint32_t *fine;
+    long long slot_stride;
+    int cap;
+    int n_act;
+    int lmax;
+    int i;
+    int parity;
+    int cnt_ge[kMaxLevels];
+    double dt_bar;
+    double t_i;
+    double h0[3];
+    T Dk[3];
+    T gamma;
+    T apk, apa, eps0, mu1, mu2;
+    int n_stim;
+    double stim[kMaxStim][9];
+    DevRef<T> ref;
+};
+
+template <int DIM>
+struct KeyOf;
+template <>
+struct KeyOf<2> {
+    using type = uint32_t;
+    static constexpr int bits = 14;
+};
+template <>
+struct KeyOf<3> {
+    using type = uint64_t;
+    static constexpr int bits = 20;
+};
+
+template <int DIM>
+__host__ __device__ inline typename KeyOf<DIM>::type pack_key(int depth, const uint32_t *c)
+{
+    using K = typename KeyOf<DIM>::type;
+    constexpr int b = KeyOf<DIM>::bits;
+    K k = (K)depth;
+    for (int q = 0; q < DIM; q++) k |= (K)c[q] << (4 + b * q);
+    return k;
+}
+
+template <int DIM>
+__device__ __forceinline__ void unpack_key(typename KeyOf<DIM>::type k, int &depth, uint32_t *c)
+{
+    constexpr int b = KeyOf<DIM>::bits;
+    depth = (int)(k & 15);
+#pragma unroll
+    for (int q = 0; q < DIM; q++) c[q] = (uint32_t)((k >> (4 + b * q)) & ((1u << b) - 1));
+}
+
+template <int DIM, int P>
+struct Shape {
+    static constexpr int M = P + 1;
+    static constexpr int NP = DIM == 2 ? M * M : M * M * M;
+    static constexpr int NF = DIM == 2 ? M : M * M;
+    static constexpr int NS = DIM == 2 ? 2 : 4;
+};
+
+// node index of tangential point g and normal index b for faces normal to k
+template <int DIM, int M>
+__device__ __forceinline__ constexpr int fnode(int k, int g, int b)
+{
+    if (DIM == 2) return k == 0 ? b + M * g : g + M * b;
+    const int g0 = g % M, g1 = g / M;
+    if (k == 0) return b + M * (g0 + M * g1);
+    if (k == 1) return g0 + M * (b + M * g1);
+    return g0 + M * (g1 + M * b);
+}
+
+// blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+// range of elements so that neighbour gathers hit that XCD's L2
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    const int x = b & 7, q = nb >> 3, r = nb & 7;
+    const int i = b >> 3;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// out = (I[pos0] (x) I[pos1]) in over the tangential points of a face
+template <typename T, int DIM, int M>
+__device__ __forceinline__ void tang_apply(const T (&I)[2][kMaxM][kMaxM], int pos0, int pos1, const T *in, T *out)
+{
+    if constexpr (DIM == 2) {
+#pragma unroll
+        for (int g = 0; g < M; g++) {
+            T s = 0;
+#pragma unroll
+            for (int q = 0; q < M; q++) s += (pos0 ? I[1][g][q] : I[0][g][q]) * in[q];
+            out[g] = s;
+        }
+    } else {
+        T tmp[M * M];
+#pragma unroll
+        for (int g1 = 0; g1 < M; g1++)
+#pragma unroll
+            for (int g0 = 0; g0 < M; g0++) {
+                T s = 0;
+#pragma unroll
+                for (int q = 0; q < M; q++) s += (pos0 ? I[1][g0][q] : I[0][g0][q]) * in[q + M * g1];
+                tmp[g0 + M * g1] = s;
+            }
+#pragma unroll
+        for (int g1 = 0; g1 < M; g1++)
+#pragma unroll
+            for (int g0 = 0; g0 < M; g0++) {
+                T s = 0;
+#pragma unroll
+                for (int q = 0; q < M; q++) s += (pos1 ? I[1][g1][q] : I[0][g1][q]) * tmp[g0 + M * q];
+                out[g0 + M * g1] = s;
+            }
+    }
+}
+
+// Trace (value and reference normal derivative) of a neighbour on its face
+// `side` normal to k, at the neighbour's interpolated time for substep i:
+// a neighbour updated at this substep is read from its current slot; one
+// that is not (it is coarser) is linear in time between its two slots.
+template <typename T, int DIM, int P>
+__device__ __forceinline__ void neighbour_trace(const StepArgs<T> &a, uint32_t ent, int k, int side, T *tu, T *tq)
+{
+    using S = Shape<DIM, P>;
+    constexpr int M = S::M;
+    const uint32_t id = ent & kIdMask27;
+    const int ln = (int)((ent >> 27) & 7);
+    const int sh = a.lmax - ln;
+    const int base = ln == 0 ? a.parity : 0;
+    const int cur = base ^ ((a.i >> sh) & 1);
+    const int rem = a.i & ((1 << sh) - 1);
+    const T *p0 = a.u + (long long)cur * a.slot_stride + id;
+#pragma unroll
+    for (int g = 0; g < S::NF; g++) { tu[g] = 0; tq[g] = 0; }
+    if (rem == 0) {
+#pragma unroll
+        for (int g = 0; g < S::NF; g++)
+#pragma unroll
+            for (int b = 0; b < M; b++) {
+                const T val = p0[(long long)fnode<DIM, M>(k, g, b) * a.cap];
+                tu[g] += a.ref.B[side][b] * val;
+                tq[g] += a.ref.G[side][b] * val;
+            }
+    } else {
+        const T th = (T)rem * (T)ldexp(1.0, -sh);
+        const T *p1 = a.u + (long long)(cur ^ 1) * a.slot_stride + id;
+#pragma unroll
+        for (int g = 0; g < S::NF; g++)
+#pragma unroll
+            for (int b = 0; b < M; b++) {
+                const long long o = (long long)fnode<DIM, M>(k, g, b) * a.cap;
+                const T val = ((T)1 - th) * p0[o] + th * p1[o];
+                tu[g] += a.ref.B[side][b] * val;
+                tq[g] += a.ref.G[side][b] * val;
+            }
+    }
+}
+
+// One substep (Sec. 2.3, Algorithm 1) for the active prefix of the
+// level-grouped elements: element-volume diffusion, SIPG face fluxes
+// (Sec. 2.1), inverse diagonal mass, Aliev-Panfilov reaction + stimulus,
+// forward Euler for u and an exponential step for v.  Reads the current
+// slot, writes the other one; v is updated in place.
+template <int DIM, int P, typename T>
+__global__ __launch_bounds__(256) void k_substep(const StepArgs<T> a)
+{
+    using S = Shape<DIM, P>;
+    constexpr int M = S::M, NP = S::NP, NF = S::NF, NS = S::NS;
+    const int j = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (j >= a.n_act) return;
+
+    int lv = 0;
+#pragma unroll
+    for (int l = 1; l < kMaxLevels; l++) lv += (j < a.cnt_ge[l]) ? 1 : 0;
+    const int sh = a.lmax - lv;
+    const int cur = (lv == 0 ? a.parity : 0) ^ ((a.i >> sh) & 1);
+    const T dt = (T)ldexp(a.dt_bar, -lv);
+
+    int depth;
+    uint32_t c[3] = {0, 0, 0};
+    unpack_key<DIM>(static_cast<const typename KeyOf<DIM>::type *>(a.key)[j], depth, c);
+    T h[DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; k++) h[k] = (T)ldexp(a.h0[k], -depth);
+
+    const T *uc = a.u + (long long)cur * a.slot_stride + j;
+    T u[NP], r[NP];
+#pragma unroll
+    for (int n = 0; n < NP; n++) {
+        u[n] = uc[(long long)n * a.cap];
+        r[n] = 0;
+    }
+
+    // element volume: -(4 D_kk / h_k^2) A along each direction
+#pragma unroll
+    for (int k = 0; k < DIM; k++) {
+        const T ck = (T)4 * a.Dk[k] / (h[k] * h[k]);
+#pragma unroll
+        for (int g = 0; g < NF; g++)
+#pragma unroll
+            for (int aa = 0; aa < M; aa++) {
+                T s = 0;
+#pragma unroll
+                for (int b = 0; b < M; b++) s += a.ref.A[aa][b] * u[fnode<DIM, M>(k, g, b)];
+                r[fnode<DIM, M>(k, g, aa)] -= ck * s;
+            }
+    }
+
+    // interior faces
+#pragma unroll
+    for (int k = 0; k < DIM; k++) {
+        const T hk = h[k];
+        const T c2 = (T)2 / hk;
+        const T Dkk = a.Dk[k];
+        int pos0 = 0, pos1 = 0;  // own position inside a coarser neighbour's face
+        {
+            int t = 0;
+#pragma unroll
+            for (int q = 0; q < DIM; q++) {
+                if (q == k) continue;
+                if (t == 0) pos0 = c[q] & 1; else pos1 = c[q] & 1;
+                t++;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 2; s++) {
+            const uint32_t ent = a.nbr[(long long)(2 * k + s) * a.cap + j];
+            const uint32_t kind = ent >> 30;
+            if (kind == kBoundary) continue;
+            const T ns = s ? (T)1 : (T)-1;
+            const T qs = ns * Dkk * c2;
+            T tu[NF], tq[NF];
+#pragma unroll
+            for (int g = 0; g < NF; g++) {
+                T su = 0, sq = 0;
+#pragma unroll
+                for (int b = 0; b < M; b++) {
+                    su += a.ref.B[s][b] * u[fnode<DIM, M>(k, g, b)];
+                    sq += a.ref.G[s][b] * u[fnode<DIM, M>(k, g, b)];
+                }
+                tu[g] = su;
+                tq[g] = sq;
+            }
+            T Fl[NF], Hl[NF];
+            if (kind != kFiner) {
+                T nu[NF], nq[NF];
+                neighbour_trace<T, DIM, P>(a, ent, k, 1 - s, nu, nq);
+                const T hn = kind == kSame ? hk : (T)2 * hk;
+                if (kind == kCoarser) {
+                    T iu[NF], iq[NF];
+                    tang_apply<T, DIM, M>(a.ref.Isub, pos0, pos1, nu, iu);
+                    tang_apply<T, DIM, M>(a.ref.Isub, pos0, pos1, nq, iq);
+#pragma unroll
+                    for (int g = 0; g < NF; g++) { nu[g] = iu[g]; nq[g] = iq[g]; }
+                }
+                const T sigma = a.gamma * (T)0.5 * (Dkk / hk + Dkk / hn);
+                const T qn = ns * Dkk * ((T)2 / hn);
+#pragma unroll
+                for (int g = 0; g < NF; g++) {
+                    const T jmp = tu[g] - nu[g];
+                    Fl[g] = (T)0.5 * (qs * tq[g] + qn * nq[g]) - sigma * jmp;
+                    Hl[g] = (T)0.5 * jmp;
+                }
+            } else {
+                const uint32_t grp = ent & kIdMask27;
+                const T hn = (T)0.5 * hk;
+                const T sigma = a.gamma * (T)0.5 * (Dkk / hk + Dkk / hn);
+                const T qn = ns * Dkk * ((T)2 / hn);
+#pragma unroll
+                for (int g = 0; g < NF; g++) { Fl[g] = 0; Hl[g] = 0; }
+#pragma unroll
+                for (int sub = 0; sub < NS; sub++) {
+                    const int p0 = sub & 1, p1 = sub >> 1;
+                    T ou[NF], oq[NF], nu[NF], nq[NF], F[NF], H[NF], lf[NF], lh[NF];
+                    tang_apply<T, DIM, M>(a.ref.Isub, p0, p1, tu, ou);
+                    tang_apply<T, DIM, M>(a.ref.Isub, p0, p1, tq, oq);
+                    neighbour_trace<T, DIM, P>(a, a.fine[(long long)grp * NS + sub], k, 1 - s, nu, nq);
+#pragma unroll
+                    for (int g = 0; g < NF; g++) {
+                        const T jmp = ou[g] - nu[g];
+                        F[g] = (T)0.5 * (qs * oq[g] + qn * nq[g]) - sigma * jmp;
+                        H[g] = (T)0.5 * jmp;
+                    }
+                    tang_apply<T, DIM, M>(a.ref.Lsub, p0, p1, F, lf);
+                    tang_apply<T, DIM, M>(a.ref.Lsub, p0, p1, H, lh);
+#pragma unroll
+                    for (int g = 0; g < NF; g++) { Fl[g] += lf[g]; Hl[g] += lh[g]; }
+                }
+            }
+            // lift to the own nodes, already multiplied by the inverse mass
+#pragma unroll
+            for (int g = 0; g < NF; g++)
+#pragma unroll
+                for (int b = 0; b < M; b++)
+                    r[fnode<DIM, M>(k, g, b)] += c2 * a.ref.winv[b] * (Fl[g] * a.ref.B[s][b] + Hl[g] * qs * a.ref.G[s][b]);
+        }
+    }
+
+    // pointwise reaction, stimulus and update
+    T *uo = a.u + (long long)(cur ^ 1) * a.slot_stride + j;
+    T *vp = a.v + j;
+#pragma unroll
+    for (int n = 0; n < NP; n++) {
+        const T un = u[n];
+        const T vn = vp[(long long)n * a.cap];
+        T stim = 0;
+        if (a.n_stim > 0) {
+            double X[3];
+            int nn = n;
+#pragma unroll
+            for (int k = 0; k < DIM; k++) {
+                const double hk = ldexp(a.h0[k], -depth);
+                const double lo = (double)c[k] * hk;
+                X[k] = lo + 0.5 * (a.ref.xi[nn % M] + 1.0) * hk;
+                nn /= M;
+            }
+            for (int b = 0; b < a.n_stim; b++) {
+                bool in = true;
+#pragma unroll
+                for (int k = 0; k < DIM; k++) in = in && X[k] >= a.stim[b][k] && X[k] <= a.stim[b][3 + k];
+                if (in) stim += (T)a.stim[b][8];
+            }
+        }
+        const T f = -a.apk * un * (un - a.apa) * (un - (T)1) - un * vn;
+        T den = un + a.mu2;
+        den = den < (T)1e-6 ? (T)1e-6 : den;
+        const T eps = a.eps0 + a.mu1 * vn / den;
+        const T vinf = a.apk * un * ((T)1 + a.apa - un);
+        uo[(long long)n * a.cap] = un + dt * (r[n] + f + stim);
+        vp[(long long)n * a.cap] = vinf + (vn - vinf) * exp(-eps * dt);
+    }
+}
+
+}  // namespace mdlts

@@ -1,0 +1,1284 @@
+// mdlts.hip -- the C ABI (include/mdlts.h) and the non-substep kernels:
+// CFL + level assignment, stable grouping by level, table remapping, state
+// permutation, FP64 error indicator, refinement transfer.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "host.hpp"
+#include "kernels.hpp"
+#include "mdlts.h"
+
+using namespace mdlts;
+
+#define HIP_TRY(x)                                  \
+    do {                                            \
+        if ((x) != hipSuccess) return MDLTS_EDEVICE; \
+    } while (0)
+#define MD_TRY(x)                           \
+    do {                                    \
+        mdlts_status _s = (x);              \
+        if (_s != MDLTS_OK) return _s;      \
+    } while (0)
+
+namespace {
+
+constexpr int kBlock = 256;
+
+// ---------------------------------------------------------------------------
+// level assignment (Sec. 2.3: Gershgorin CFL per element, b^CFL) and the
+// stable grouping of elements by level, finest first
+// ---------------------------------------------------------------------------
+struct LevelArgs {
+    const void *key;
+    const uint32_t *face;  // canonical [2d][E]
+    int E;
+    int dim;
+    int n_levels;
+    double dt_bar;
+    double h0[3];
+    double Dk[3];
+    double G[4][4];
+    uint8_t *level;
+    double *cfl;
+    int *hist;      // [blocks][8]
+    int *bad;       // set if some leaf needs more levels than configured
+};
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_levels(const LevelArgs a)
+{
+#pragma clang fp contract(off)
+    __shared__ int sh[kMaxLevels];
+    if (threadIdx.x < kMaxLevels) sh[threadIdx.x] = 0;
+    __syncthreads();
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    if (e < a.E) {
+        int depth;
+        uint32_t c[3];
+        unpack_key<DIM>(static_cast<const typename KeyOf<DIM>::type *>(a.key)[e], depth, c);
+        double s = 0.0;
+        for (int k = 0; k < DIM; k++) {
+            const double h = ldexp(a.h0[k], -depth);
+            const uint32_t lo = a.face[(long long)(2 * k) * a.E + e] >> 30;
+            const uint32_t hi = a.face[(long long)(2 * k + 1) * a.E + e] >> 30;
+            s += a.Dk[k] / (h * h) * a.G[lo][hi];
+        }
+        const double cfl = 1.0 / s;
+        int b = 0;
+        while (b < 64 && ldexp(a.dt_bar, -b) > cfl) b++;
+        if (b > a.n_levels - 1) {
+            atomicOr(a.bad, 1);
+            b = a.n_levels - 1;
+        }
+        a.level[e] = (uint8_t)b;
+        a.cfl[e] = cfl;
+        atomicAdd(&sh[b], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxLevels) a.hist[blockIdx.x * kMaxLevels + threadIdx.x] = sh[threadIdx.x];
+}
+
+// exclusive offsets of every (block, level) in the finest-first order
+__global__ __launch_bounds__(kBlock) void k_level_scan(int *hist, int nb, int n_levels, int *cnt_ge)
+{
+    __shared__ int part[kBlock][kMaxLevels];
+    __shared__ int base[kMaxLevels];
+    const int t = threadIdx.x;
+    const int chunk = (nb + kBlock - 1) / kBlock;
+    const int b0 = t * chunk, b1 = min(nb, b0 + chunk);
+    for (int l = 0; l < kMaxLevels; l++) {
+        int s = 0;
+        for (int b = b0; b < b1; b++) s += hist[b * kMaxLevels + l];
+        part[t][l] = s;
+    }
+    __syncthreads();
+    if (t < kMaxLevels) {
+        int run = 0;
+        for (int q = 0; q < kBlock; q++) {
+            const int v = part[q][t];
+            part[q][t] = run;
+            run += v;
+        }
+        base[t] = run;  // total per level for now
+    }
+    __syncthreads();
+    if (t == 0) {
+        int run = 0;
+        for (int l = kMaxLevels - 1; l >= 0; l--) {
+            const int tot = base[l];
+            base[l] = run;  // leaves of finer levels come first
+            run += tot;
+            if (l < n_levels) cnt_ge[l] = run;
+        }
+    }
+    __syncthreads();
+    for (int l = 0; l < kMaxLevels; l++) {
+        int run = base[l] + part[t][l];
+        for (int b = b0; b < b1; b++) {
+            const int v = hist[b * kMaxLevels + l];
+            hist[b * kMaxLevels + l] = run;
+            run += v;
+        }
+    }
+}
+
+// position of every element: block offset + rank among equal levels inside
+// the block (wavefront ballots keep the canonical order: stable)
+__global__ __launch_bounds__(kBlock) void k_level_scatter(const uint8_t *level, int E, const int *off, int *perm,
+                                                          int *inv)
+{
+    __shared__ int wcount[kBlock / 64][kMaxLevels];
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int l = e < E ? level[e] : -1;
+    int rank = 0;
+    for (int q = 0; q < kMaxLevels; q++) {
+        const unsigned long long m = __ballot(l == q);
+        if (lane == 0) wcount[wave][q] = __popcll(m);
+        if (l == q) rank = __popcll(m & ((1ull << lane) - 1ull));
+    }
+    __syncthreads();
+    if (e < E) {
+        int pos = off[blockIdx.x * kMaxLevels + l] + rank;
+        for (int w = 0; w < wave; w++) pos += wcount[w][l];
+        perm[pos] = e;
+        inv[e] = pos;
+    }
+}
+
+template <typename KT>
+__global__ __launch_bounds__(kBlock) void k_remap(int E, int nfaces, const int *perm, const int *inv,
+                                                  const uint8_t *level, const KT *key_c, const uint32_t *face_c,
+                                                  KT *key_s, uint32_t *nbr_s, int cap)
+{
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= E) return;
+    const int e = perm[j];
+    key_s[j] = key_c[e];
+    for (int f = 0; f < nfaces; f++) {
+        const uint32_t ent = face_c[(long long)f * E + e];
+        const uint32_t kind = ent >> 30;
+        uint32_t out = ent & 0xc0000000u;
+        if (kind == kSame || kind == kCoarser) {
+            const uint32_t n = ent & kIdMask30;
+            out |= ((uint32_t)level[n] << 27) | (uint32_t)inv[n];
+        } else if (kind == kFiner) {
+            out |= ent & kIdMask30;
+        }
+        nbr_s[(long long)f * cap + j] = out;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_remap_fine(int n, const uint32_t *fine_c, const int *inv,
+                                                       const uint8_t *level, uint32_t *fine_s)
+{
+    const int q = blockIdx.x * kBlock + threadIdx.x;
+    if (q >= n) return;
+    const uint32_t e = fine_c[q];
+    fine_s[q] = ((uint32_t)level[e] << 27) | (uint32_t)inv[e];
+}
+
+// canonical [np][E] -> grouped slot 0 [np][cap]
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_permute(int E, int np, int cap, const int *perm, const T *uc, const T *vc,
+                                                    T *us, T *vs)
+{
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= E) return;
+    const int e = perm[j];
+    for (int n = 0; n < np; n++) {
+        us[(long long)n * cap + j] = uc[(long long)n * E + e];
+        vs[(long long)n * cap + j] = vc[(long long)n * E + e];
+    }
+}
+
+// grouped current slot -> canonical [np][E] (at a barrier)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gather(int E, int np, int cap, long long slot_stride, const int *perm,
+                                                   const int *cnt_ge, int parity, const T *us, const T *vs, T *uc,
+                                                   T *vc)
+{
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= E) return;
+    // level-0 elements sit at the end of the grouped order
+    const bool lvl0 = j >= cnt_ge[1];
+    const int cur = lvl0 ? parity : 0;
+    const int e = perm[j];
+    for (int n = 0; n < np; n++) {
+        uc[(long long)n * E + e] = us[(long long)cur * slot_stride + (long long)n * cap + j];
+        vc[(long long)n * E + e] = vs[(long long)n * cap + j];
+    }
+}
+
+// host FP64 [E][np] <-> device T [np][E]
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_from_host(int E, int np, const double *h, T *d)
+{
+    const long long q = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= (long long)E * np) return;
+    const long long e = q / np, n = q % np;
+    d[n * E + e] = (T)h[q];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_to_host(int E, int np, const T *d, double *h)
+{
+    const long long q = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= (long long)E * np) return;
+    const long long e = q / np, n = q % np;
+    h[q] = (double)d[n * E + e];
+}
+
+// ---------------------------------------------------------------------------
+// Kelly-type indicator (Sec. 2.2), FP64 accumulation, canonical layout
+// ---------------------------------------------------------------------------
+struct IndArgs {
+    const void *u;  // canonical [np][E], bulk precision
+    const void *key;
+    const uint32_t *face;
+    const uint32_t *fine;
+    int E;
+    int p;
+    double h0[3];
+    double Dk[3];
+    DevRef<double> ref;
+    double *eta;
+    unsigned long long *eta_max_bits;
+    int *nonfinite;
+};
+
+template <int DIM, int P, typename T>
+__device__ __forceinline__ void canon_trace(const IndArgs &a, uint32_t id, int k, int side, double *tu, double *tq)
+{
+    using S = Shape<DIM, P>;
+    const T *u = static_cast<const T *>(a.u);
+#pragma unroll
+    for (int g = 0; g < S::NF; g++) {
+        double su = 0.0, sq = 0.0;
+#pragma unroll
+        for (int b = 0; b < S::M; b++) {
+            const double val = (double)u[(long long)fnode<DIM, S::M>(k, g, b) * a.E + id];
+            su += a.ref.B[side][b] * val;
+            sq += a.ref.G[side][b] * val;
+        }
+        tu[g] = su;
+        tq[g] = sq;
+    }
+}
+
+template <int DIM, int P, typename T>
+__global__ __launch_bounds__(kBlock) void k_indicator(const IndArgs a)
+{
+    using S = Shape<DIM, P>;
+    constexpr int M = S::M, NF = S::NF, NS = S::NS;
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    double eta = 0.0;
+    if (e < a.E) {
+        int depth;
+        uint32_t c[3] = {0, 0, 0};
+        unpack_key<DIM>(static_cast<const typename KeyOf<DIM>::type *>(a.key)[e], depth, c);
+        double h[3] = {1, 1, 1};
+        for (int k = 0; k < DIM; k++) h[k] = ldexp(a.h0[k], -depth);
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < DIM; k++) {
+            int pos0 = 0, pos1 = 0, t = 0;
+            double area = 1.0;
+            for (int q = 0; q < DIM; q++) {
+                if (q == k) continue;
+                if (t == 0) pos0 = c[q] & 1; else pos1 = c[q] & 1;
+                area *= h[q];
+                t++;
+            }
+            // reference weights of the tangential GL rule on [0,1]^(d-1)
+            double om[NF];
+#pragma unroll
+            for (int g = 0; g < NF; g++)
+                om[g] = DIM == 2 ? 0.5 * a.ref.w[g] : 0.25 * a.ref.w[g % M] * a.ref.w[g / M];
+#pragma unroll
+            for (int s = 0; s < 2; s++) {
+                const uint32_t ent = a.face[(long long)(2 * k + s) * a.E + e];
+                const uint32_t kind = ent >> 30;
+                if (kind == kBoundary) continue;
+                const double ns = s ? 1.0 : -1.0;
+                const double qs = ns * a.Dk[k] * 2.0 / h[k];
+                double tu[NF], tq[NF];
+                canon_trace<DIM, P, T>(a, (uint32_t)e, k, s, tu, tq);
+                if (kind != kFiner) {
+                    double nu[NF], nq[NF];
+                    canon_trace<DIM, P, T>(a, ent & kIdMask30, k, 1 - s, nu, nq);
+                    const double hn = kind == kSame ? h[k] : 2.0 * h[k];
+                    if (kind == kCoarser) {
+                        double iq[NF];
+                        tang_apply<double, DIM, M>(a.ref.Isub, pos0, pos1, nq, iq);
+                        for (int g = 0; g < NF; g++) nq[g] = iq[g];
+                    }
+                    const double qn = ns * a.Dk[k] * 2.0 / hn;
+                    double integral = 0.0;
+                    for (int g = 0; g < NF; g++) {
+                        const double jmp = qs * tq[g] - qn * nq[g];
+                        integral += om[g] * area * jmp * jmp;
+                    }
+                    const double hF = DIM == 2 ? area : sqrt(area);
+                    acc += hF / (2.0 * a.p) * area * area * integral;
+                } else {
+                    const uint32_t grp = ent & kIdMask30;
+                    const double sarea = DIM == 2 ? 0.5 * area : 0.25 * area;
+                    const double hF = DIM == 2 ? sarea : sqrt(sarea);
+                    const double qn = ns * a.Dk[k] * 2.0 / (0.5 * h[k]);
+                    for (int sub = 0; sub < NS; sub++) {
+                        double oq[NF], nu[NF], nq[NF];
+                        tang_apply<double, DIM, M>(a.ref.Isub, sub & 1, sub >> 1, tq, oq);
+                        canon_trace<DIM, P, T>(a, a.fine[(long long)grp * NS + sub], k, 1 - s, nu, nq);
+                        double integral = 0.0;
+                        for (int g = 0; g < NF; g++) {
+                            const double jmp = qs * oq[g] - qn * nq[g];
+                            integral += om[g] * sarea * jmp * jmp;
+                        }
+                        acc += hF / (2.0 * a.p) * sarea * sarea * integral;
+                    }
+                }
+            }
+        }
+        eta = sqrt(acc);
+        a.eta[e] = eta;
+        if (!isfinite(eta)) atomicOr(a.nonfinite, 1);
+    }
+    // block maximum through wavefront shuffles, one atomic per wave
+    double m = isfinite(eta) ? eta : 0.0;
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(a.eta_max_bits, (unsigned long long)__double_as_longlong(m));
+}
+
+// ---------------------------------------------------------------------------
+// refinement transfer: copy, prolongation by evaluation, L2 restriction
+// ---------------------------------------------------------------------------
+struct XferArgs {
+    const void *u_old, *v_old;
+    void *u_new, *v_new;
+    int E_old, E_new;
+    const uint8_t *kind;
+    const int32_t *src;
+    const uint8_t *child;
+    DevRef<double> ref;
+};
+
+template <int DIM, int P, typename T>
+__global__ __launch_bounds__(kBlock) void k_transfer(const XferArgs a)
+{
+    using S = Shape<DIM, P>;
+    constexpr int M = S::M, NP = S::NP;
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    if (e >= a.E_new) return;
+    const int kind = a.kind[e], src = a.src[e], ci = a.child[e];
+    for (int f = 0; f < 2; f++) {
+        const T *in = static_cast<const T *>(f ? a.v_old : a.u_old);
+        T *out = static_cast<T *>(f ? a.v_new : a.u_new);
+        if (kind == 0) {
+            for (int n = 0; n < NP; n++) out[(long long)n * a.E_new + e] = in[(long long)n * a.E_old + src];
+            continue;
+        }
+        for (int n = 0; n < NP; n++) {
+            int nk[3] = {n % M, (n / M) % M, n / (M * M)};
+            double s = 0.0;
+            const int nkids = kind == 1 ? 1 : (1 << DIM);
+            for (int cc = 0; cc < nkids; cc++) {
+                const int bits = kind == 1 ? ci : cc;
+                for (int q = 0; q < NP; q++) {
+                    int qk[3] = {q % M, (q / M) % M, q / (M * M)};
+                    double wgt = 1.0;
+                    for (int k = 0; k < DIM; k++) {
+                        const int bit = (bits >> k) & 1;
+                        wgt *= kind == 1 ? a.ref.Isub[bit][nk[k]][qk[k]] : a.ref.Lsub[bit][nk[k]][qk[k]];
+                    }
+                    s += wgt * (double)in[(long long)q * a.E_old + src + (kind == 1 ? 0 : cc)];
+                }
+            }
+            out[(long long)n * a.E_new + e] = (T)s;
+        }
+    }
+}
+
+inline int nblocks(long long n) { return (int)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// context and simulation objects
+// ---------------------------------------------------------------------------
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct mdlts_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    mdlts_allocator alloc{};
+    bool has_alloc = false;
+    int n_sims = 0;  // live simulations; the context outlives them
+};
+
+struct mdlts_sim {
+    mdlts_ctx *ctx = nullptr;
+    mdlts_mesh_desc desc{};
+    int np = 0;
+    size_t tsize = 8;  // bytes of the bulk precision
+    Forest forest;
+    RefTables ref{};
+    double h0[3] = {1, 1, 1};
+    double Dk[3] = {1e-3, 1e-3, 1e-3};
+    double gamma = 2.0;
+    double G[4][4] = {};
+    mdlts_ap_params ap{8.0, 0.15, 0.002, 0.2, 0.3};
+    std::vector<mdlts_stim_box> stim;
+    // canonical device data
+    DevBuf key_c, face_c, fine_c, u_c, v_c, level_c, cfl_c, eta_c, tmp_u, tmp_v;
+    // grouped device data
+    DevBuf u_s, v_s, key_s, nbr_s, fine_s, perm, inv, hist, cnt_ge_d, flags, xk, xs, xc, stage;
+    int cap = 0;
+    bool state_grouped = false;  // else canonical
+    bool levels_valid = false;
+    std::vector<int32_t> cnt_ge;  // [n_levels]
+    int lmax = 0;
+    double dt_bar = 0.0;
+    double t_start = 0.0;
+    long long n_bar = 0;  // barriers since t_start (time bookkeeping)
+    long long n_since_assign = 0;
+    uint64_t dof_updates = 0;
+    std::vector<double> eta_host;
+};
+
+namespace {
+
+mdlts_status dev_free(mdlts_ctx *c, DevBuf &b)
+{
+    if (b.p) {
+        if (c->has_alloc) c->alloc.free(b.p, c->stream, c->alloc.user);
+        else if (hipFree(b.p) != hipSuccess) return MDLTS_EDEVICE;
+    }
+    b.p = nullptr;
+    b.bytes = 0;
+    return MDLTS_OK;
+}
+
+mdlts_status dev_alloc(mdlts_ctx *c, DevBuf &b, size_t bytes)
+{
+    if (b.p && b.bytes >= bytes) return MDLTS_OK;
+    MD_TRY(dev_free(c, b));
+    if (bytes == 0) bytes = 256;
+    void *p = nullptr;
+    if (c->has_alloc) {
+        p = c->alloc.alloc(bytes, c->stream, c->alloc.user);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+    }
+    if (!p) return MDLTS_ENOMEM;
+    b.p = p;
+    b.bytes = bytes;
+    return MDLTS_OK;
+}
+
+template <typename T>
+T *P(DevBuf &b)
+{
+    return static_cast<T *>(b.p);
+}
+
+template <typename T>
+void fill_ref(const RefTables &R, DevRef<T> &D)
+{
+    std::memset(&D, 0, sizeof(D));
+    for (int a = 0; a < kMaxM; a++) {
+        D.w[a] = (T)R.w[a];
+        D.winv[a] = a < R.m ? (T)(1.0 / R.w[a]) : (T)0;
+        D.xi[a] = R.xi[a];
+        for (int b = 0; b < kMaxM; b++) D.A[a][b] = (T)R.A[a][b];
+    }
+    for (int s = 0; s < 2; s++)
+        for (int b = 0; b < kMaxM; b++) {
+            D.B[s][b] = (T)R.B[s][b];
+            D.G[s][b] = (T)R.G[s][b];
+            for (int q = 0; q < kMaxM; q++) {
+                D.Isub[s][b][q] = (T)R.Isub[s][b][q];
+                D.Lsub[s][b][q] = (T)R.Lsub[s][b][q];
+            }
+        }
+}
+
+bool valid_desc(const mdlts_mesh_desc *d)
+{
+    if (!d) return false;
+    if (d->dim != 2 && d->dim != 3) return false;
+    if (d->order != 1 && d->order != 2) return false;
+    if (d->max_depth < 0 || d->max_depth > 8) return false;
+    if (d->n_levels < 1 || d->n_levels > kMaxLevels) return false;
+    if (d->precision != MDLTS_FP64 && d->precision != MDLTS_FP32) return false;
+    const int bits = d->dim == 2 ? 14 : 20;
+    long long roots = 1;
+    for (int k = 0; k < d->dim; k++) {
+        if (d->n[k] < 1 || !(d->len[k] > 0.0) || !std::isfinite(d->len[k])) return false;
+        if (((long long)d->n[k] << d->max_depth) > (1ll << bits)) return false;
+        roots *= d->n[k];
+    }
+    return roots < (1ll << 26);
+}
+
+void forest_from_desc(const mdlts_mesh_desc *d, Forest &F)
+{
+    F.dim = d->dim;
+    F.max_depth = d->max_depth;
+    for (int k = 0; k < 3; k++) F.n[k] = k < d->dim ? d->n[k] : 1;
+}
+
+bool diag_of(const double D_sym[6], int dim, double Dk[3])
+{
+    if (!D_sym) return false;
+    for (int q = 3; q < 6; q++)
+        if (D_sym[q] != 0.0) return false;
+    for (int k = 0; k < 3; k++) Dk[k] = D_sym[k];
+    for (int k = 0; k < dim; k++)
+        if (!(Dk[k] > 0.0) || !std::isfinite(Dk[k])) return false;
+    return true;
+}
+
+mdlts_status sync(mdlts_ctx *c)
+{
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return MDLTS_EDEVICE;
+    if (hipGetLastError() != hipSuccess) return MDLTS_EDEVICE;
+    return MDLTS_OK;
+}
+
+template <typename T>
+mdlts_status copy_h2d(mdlts_ctx *c, DevBuf &b, const T *src, size_t n)
+{
+    MD_TRY(dev_alloc(c, b, n * sizeof(T)));
+    if (n) HIP_TRY(hipMemcpyAsync(b.p, src, n * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    return MDLTS_OK;
+}
+
+// upload the canonical geometry and face tables of the forest
+mdlts_status upload_forest(mdlts_sim *s)
+{
+    mdlts_ctx *c = s->ctx;
+    const Forest &F = s->forest;
+    const size_t E = F.size();
+    if (s->desc.dim == 2) {
+        std::vector<uint32_t> key(E);
+        for (size_t e = 0; e < E; e++) key[e] = pack_key<2>(F.leaves[e].depth, F.leaves[e].c);
+        MD_TRY(copy_h2d(c, s->key_c, key.data(), E));
+    } else {
+        std::vector<uint64_t> key(E);
+        for (size_t e = 0; e < E; e++) key[e] = pack_key<3>(F.leaves[e].depth, F.leaves[e].c);
+        MD_TRY(copy_h2d(c, s->key_c, key.data(), E));
+    }
+    MD_TRY(copy_h2d(c, s->face_c, F.face.data(), F.face.size()));
+    MD_TRY(copy_h2d(c, s->fine_c, F.fine.data(), F.fine.size()));
+    // host vectors die at return: wait for the copies
+    return sync(c);
+}
+
+mdlts_status alloc_canonical_state(mdlts_sim *s)
+{
+    const size_t n = (size_t)s->forest.size() * s->np * s->tsize;
+    MD_TRY(dev_alloc(s->ctx, s->u_c, n));
+    MD_TRY(dev_alloc(s->ctx, s->v_c, n));
+    return MDLTS_OK;
+}
+
+mdlts_status zero_canonical_state(mdlts_sim *s)
+{
+    MD_TRY(alloc_canonical_state(s));
+    const size_t n = (size_t)s->forest.size() * s->np * s->tsize;
+    HIP_TRY(hipMemsetAsync(s->u_c.p, 0, n, s->ctx->stream));
+    HIP_TRY(hipMemsetAsync(s->v_c.p, 0, n, s->ctx->stream));
+    s->state_grouped = false;
+    return MDLTS_OK;
+}
+
+// grouped -> canonical at a barrier
+mdlts_status to_canonical(mdlts_sim *s)
+{
+    if (!s->state_grouped) return MDLTS_OK;
+    const int E = (int)s->forest.size();
+    MD_TRY(alloc_canonical_state(s));
+    const long long stride = (long long)s->np * s->cap;
+    const int parity = (int)(s->n_since_assign & 1);
+    if (s->desc.precision == MDLTS_FP64)
+        k_gather<double><<<nblocks(E), kBlock, 0, s->ctx->stream>>>(E, s->np, s->cap, stride, P<int>(s->perm),
+                                                                     P<int>(s->cnt_ge_d), parity, P<double>(s->u_s),
+                                                                     P<double>(s->v_s), P<double>(s->u_c),
+                                                                     P<double>(s->v_c));
+    else
+        k_gather<float><<<nblocks(E), kBlock, 0, s->ctx->stream>>>(E, s->np, s->cap, stride, P<int>(s->perm),
+                                                                    P<int>(s->cnt_ge_d), parity, P<float>(s->u_s),
+                                                                    P<float>(s->v_s), P<float>(s->u_c),
+                                                                    P<float>(s->v_c));
+    HIP_TRY(hipGetLastError());
+    s->state_grouped = false;
+    return MDLTS_OK;
+}
+
+// canonical -> grouped slot 0 (after a level assignment)
+mdlts_status to_grouped(mdlts_sim *s)
+{
+    const int E = (int)s->forest.size();
+    if (s->desc.precision == MDLTS_FP64)
+        k_permute<double><<<nblocks(E), kBlock, 0, s->ctx->stream>>>(E, s->np, s->cap, P<int>(s->perm),
+                                                                      P<double>(s->u_c), P<double>(s->v_c),
+                                                                      P<double>(s->u_s), P<double>(s->v_s));
+    else
+        k_permute<float><<<nblocks(E), kBlock, 0, s->ctx->stream>>>(E, s->np, s->cap, P<int>(s->perm),
+                                                                     P<float>(s->u_c), P<float>(s->v_c),
+                                                                     P<float>(s->u_s), P<float>(s->v_s));
+    HIP_TRY(hipGetLastError());
+    s->state_grouped = true;
+    s->n_since_assign = 0;
+    return MDLTS_OK;
+}
+
+mdlts_status set_forest(mdlts_sim *s, Forest &&F)
+{
+    s->forest = std::move(F);
+    s->levels_valid = false;
+    return upload_forest(s);
+}
+
+// ---- substep launch -------------------------------------------------------
+template <int DIM, int P_, typename T>
+void launch_substep(const StepArgs<T> &a, hipStream_t st)
+{
+    k_substep<DIM, P_, T><<<nblocks(a.n_act), kBlock, 0, st>>>(a);
+}
+
+template <typename T>
+mdlts_status run_barriers(mdlts_sim *s, int n_barriers)
+{
+    StepArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    a.u = P<T>(s->u_s);
+    a.v = P<T>(s->v_s);
+    a.key = s->key_s.p;
+    a.nbr = P<uint32_t>(s->nbr_s);
+    a.fine = P<uint32_t>(s->fine_s);
+    a.slot_stride = (long long)s->np * s->cap;
+    a.cap = s->cap;
+    a.lmax = s->lmax;
+    for (int l = 0; l < kMaxLevels; l++) a.cnt_ge[l] = l < (int)s->cnt_ge.size() && l <= s->lmax ? s->cnt_ge[l] : 0;
+    a.dt_bar = s->dt_bar;
+    for (int k = 0; k < 3; k++) {
+        a.h0[k] = s->h0[k];
+        a.Dk[k] = (T)s->Dk[k];
+    }
+    a.gamma = (T)s->gamma;
+    a.apk = (T)s->ap.k;
+    a.apa = (T)s->ap.a;
+    a.eps0 = (T)s->ap.eps0;
+    a.mu1 = (T)s->ap.mu1;
+    a.mu2 = (T)s->ap.mu2;
+    fill_ref(s->ref, a.ref);
+    const long long maxS = 1ll << s->lmax;
+    const double h_tick = s->dt_bar / (double)maxS;
+    hipStream_t st = s->ctx->stream;
+    for (int nb = 0; nb < n_barriers; nb++) {
+        const double t_n = s->t_start + (double)s->n_bar * s->dt_bar;
+        a.parity = (int)(s->n_since_assign & 1);
+        for (long long i = 0; i < maxS; i++) {
+            int v2 = 0;
+            while (i > 0 && ((i >> v2) & 1) == 0) v2++;
+            const int lmin = i == 0 ? 0 : s->lmax - v2;
+            a.i = (int)i;
+            a.n_act = s->cnt_ge[lmin];
+            a.t_i = t_n + (double)i * h_tick;
+            a.n_stim = 0;
+            for (const auto &b : s->stim)
+                if (a.t_i >= b.t_on && a.t_i < b.t_off && a.n_stim < kMaxStim) {
+                    double *q = a.stim[a.n_stim++];
+                    for (int k = 0; k < 3; k++) { q[k] = b.lo[k]; q[3 + k] = b.hi[k]; }
+                    q[6] = b.t_on; q[7] = b.t_off; q[8] = b.amp;
+                }
+            if (a.n_act == 0) continue;
+            const int key = s->desc.dim * 10 + s->desc.order;
+            switch (key) {
+            case 21: launch_substep<2, 1, T>(a, st); break;
+            case 22: launch_substep<2, 2, T>(a, st); break;
+            case 31: launch_substep<3, 1, T>(a, st); break;
+            case 32: launch_substep<3, 2, T>(a, st); break;
+            default: return MDLTS_EINVAL;
+            }
+            s->dof_updates += (uint64_t)a.n_act * (uint64_t)s->np;
+        }
+        HIP_TRY(hipGetLastError());
+        s->n_bar++;
+        s->n_since_assign++;
+    }
+    return MDLTS_OK;
+}
+
+template <typename T>
+mdlts_status run_indicator(mdlts_sim *s, unsigned long long *max_bits, int *nonfinite)
+{
+    IndArgs a;
+    std::memset(&a, 0, sizeof(a));
+    const int E = (int)s->forest.size();
+    a.u = s->u_c.p;
+    a.key = s->key_c.p;
+    a.face = P<uint32_t>(s->face_c);
+    a.fine = P<uint32_t>(s->fine_c);
+    a.E = E;
+    a.p = s->desc.order;
+    for (int k = 0; k < 3; k++) { a.h0[k] = s->h0[k]; a.Dk[k] = s->Dk[k]; }
+    fill_ref(s->ref, a.ref);
+    a.eta = P<double>(s->eta_c);
+    a.eta_max_bits = max_bits;
+    a.nonfinite = nonfinite;
+    hipStream_t st = s->ctx->stream;
+    switch (s->desc.dim * 10 + s->desc.order) {
+    case 21: k_indicator<2, 1, T><<<nblocks(E), kBlock, 0, st>>>(a); break;
+    case 22: k_indicator<2, 2, T><<<nblocks(E), kBlock, 0, st>>>(a); break;
+    case 31: k_indicator<3, 1, T><<<nblocks(E), kBlock, 0, st>>>(a); break;
+    case 32: k_indicator<3, 2, T><<<nblocks(E), kBlock, 0, st>>>(a); break;
+    default: return MDLTS_EINVAL;
+    }
+    HIP_TRY(hipGetLastError());
+    return MDLTS_OK;
+}
+
+template <typename T>
+mdlts_status run_transfer(mdlts_sim *s, const AdaptPlan &plan, int E_old)
+{
+    mdlts_ctx *c = s->ctx;
+    const int E_new = (int)plan.next.size();
+    MD_TRY(copy_h2d(c, s->xk, plan.kind.data(), plan.kind.size()));
+    MD_TRY(copy_h2d(c, s->xs, plan.src.data(), plan.src.size()));
+    MD_TRY(copy_h2d(c, s->xc, plan.child.data(), plan.child.size()));
+    const size_t bytes = (size_t)E_new * s->np * sizeof(T);
+    MD_TRY(dev_alloc(c, s->tmp_u, bytes));
+    MD_TRY(dev_alloc(c, s->tmp_v, bytes));
+    XferArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.u_old = s->u_c.p;
+    a.v_old = s->v_c.p;
+    a.u_new = s->tmp_u.p;
+    a.v_new = s->tmp_v.p;
+    a.E_old = E_old;
+    a.E_new = E_new;
+    a.kind = P<uint8_t>(s->xk);
+    a.src = P<int32_t>(s->xs);
+    a.child = P<uint8_t>(s->xc);
+    fill_ref(s->ref, a.ref);
+    hipStream_t st = c->stream;
+    switch (s->desc.dim * 10 + s->desc.order) {
+    case 21: k_transfer<2, 1, T><<<nblocks(E_new), kBlock, 0, st>>>(a); break;
+    case 22: k_transfer<2, 2, T><<<nblocks(E_new), kBlock, 0, st>>>(a); break;
+    case 31: k_transfer<3, 1, T><<<nblocks(E_new), kBlock, 0, st>>>(a); break;
+    case 32: k_transfer<3, 2, T><<<nblocks(E_new), kBlock, 0, st>>>(a); break;
+    default: return MDLTS_EINVAL;
+    }
+    HIP_TRY(hipGetLastError());
+    std::swap(s->u_c, s->tmp_u);
+    std::swap(s->v_c, s->tmp_v);
+    return sync(c);  // the host plan vectors are freed by the caller
+}
+
+mdlts_status compute_G(mdlts_sim *s)
+{
+    if (!gershgorin_table(s->ref, s->gamma, s->G)) return MDLTS_EINVAL;
+    return MDLTS_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *mdlts_strerror(mdlts_status s)
+{
+    switch (s) {
+    case MDLTS_OK: return "ok";
+    case MDLTS_EINVAL: return "invalid argument";
+    case MDLTS_ENOMEM: return "device allocation failed";
+    case MDLTS_EDEVICE: return "device error";
+    case MDLTS_EUNSTABLE: return "more LTS levels needed than configured, or non-finite state";
+    case MDLTS_ESTATE: return "call out of order";
+    case MDLTS_EBUSY: return "simulation is busy";
+    }
+    return "unknown status";
+}
+
+mdlts_status mdlts_ctx_create(int device, void *hip_stream, const mdlts_allocator *alloc, mdlts_ctx **out)
+{
+    if (!out) return MDLTS_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return MDLTS_EINVAL;
+    if (alloc && (!alloc->alloc || !alloc->free)) return MDLTS_EINVAL;
+    HIP_TRY(hipSetDevice(device));
+    mdlts_ctx *c = new (std::nothrow) mdlts_ctx;
+    if (!c) return MDLTS_ENOMEM;
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    if (alloc) {
+        c->alloc = *alloc;
+        c->has_alloc = true;
+    }
+    *out = c;
+    return MDLTS_OK;
+}
+
+mdlts_status mdlts_ctx_destroy(mdlts_ctx *ctx)
+{
+    if (!ctx) return MDLTS_EINVAL;
+    if (ctx->n_sims > 0) return MDLTS_EBUSY;
+    delete ctx;
+    return MDLTS_OK;
+}
+
+mdlts_status mdlts_sync(mdlts_ctx *ctx)
+{
+    if (!ctx) return MDLTS_EINVAL;
+    return sync(ctx);
+}
+
+mdlts_status mdlts_sim_create(mdlts_ctx *ctx, const mdlts_mesh_desc *desc, mdlts_sim **out)
+{
+    if (!ctx || !out || !valid_desc(desc)) return MDLTS_EINVAL;
+    *out = nullptr;
+    mdlts_sim *s = new (std::nothrow) mdlts_sim;
+    if (!s) return MDLTS_ENOMEM;
+    s->ctx = ctx;
+    ctx->n_sims++;
+    s->desc = *desc;
+    if (desc->dim == 2) { s->desc.n[2] = 1; s->desc.len[2] = 1.0; }
+    s->np = 1;
+    for (int k = 0; k < desc->dim; k++) s->np *= desc->order + 1;
+    s->tsize = desc->precision == MDLTS_FP64 ? 8 : 4;
+    for (int k = 0; k < 3; k++) s->h0[k] = s->desc.len[k] / (double)s->desc.n[k];
+    make_ref_tables(desc->order, s->ref);
+    mdlts_status st = compute_G(s);
+    Forest F;
+    forest_from_desc(&s->desc, F);
+    F.init_roots();
+    if (st == MDLTS_OK && !F.build_faces()) st = MDLTS_EINVAL;
+    if (st == MDLTS_OK) st = set_forest(s, std::move(F));
+    if (st == MDLTS_OK) st = zero_canonical_state(s);
+    if (st == MDLTS_OK) st = sync(ctx);
+    if (st != MDLTS_OK) {
+        mdlts_sim_destroy(s);
+        return st;
+    }
+    *out = s;
+    return MDLTS_OK;
+}
+
+mdlts_status mdlts_sim_destroy(mdlts_sim *s)
+{
+    if (!s) return MDLTS_EINVAL;
+    mdlts_ctx *c = s->ctx;
+    (void)hipStreamSynchronize(c->stream);
+    DevBuf *bufs[] = {&s->key_c, &s->face_c, &s->fine_c, &s->u_c, &s->v_c, &s->level_c, &s->cfl_c, &s->eta_c,
+                      &s->tmp_u, &s->tmp_v, &s->u_s, &s->v_s, &s->key_s, &s->nbr_s, &s->fine_s, &s->perm,
+                      &s->inv, &s->hist, &s->cnt_ge_d, &s->flags, &s->xk, &s->xs, &s->xc, &s->stage};
+    mdlts_status st = MDLTS_OK;
+    for (DevBuf *b : bufs)
+        if (dev_free(c, *b) != MDLTS_OK) st = MDLTS_EDEVICE;
+    c->n_sims--;
+    delete s;
+    return st;
+}
+
+mdlts_status mdlts_set_tree(mdlts_sim *s, const uint8_t *bits, size_t n_bits)
+{
+    if (!s || (!bits && n_bits)) return MDLTS_EINVAL;
+    Forest F;
+    forest_from_desc(&s->desc, F);
+    if (!F.parse_bits(bits, n_bits)) return MDLTS_EINVAL;
+    if (F.size() >= (1u << 27)) return MDLTS_EINVAL;
+    MD_TRY(set_forest(s, std::move(F)));
+    return zero_canonical_state(s);
+}
+
+mdlts_status mdlts_get_tree(mdlts_sim *s, uint8_t *bits, size_t cap, size_t *n_bits)
+{
+    if (!s || !n_bits) return MDLTS_EINVAL;
+    std::vector<uint8_t> out;
+    s->forest.write_bits(out);
+    *n_bits = out.size();
+    if (bits && cap >= out.size()) std::memcpy(bits, out.data(), out.size());
+    return MDLTS_OK;
+}
+
+mdlts_status mdlts_n_leaves(mdlts_sim *s, size_t *n)
+{
+    if (!s || !n) return MDLTS_EINVAL;
+    *n = s->forest.size();
+    return MDLTS_OK;
+}
+
+mdlts_status mdlts_set_conductivity(mdlts_sim *s, const double D_sym[6], double gamma)
+{
+    if (!s || !(gamma > 0.0) || !std::isfinite(gamma)) return MDLTS_EINVAL;
+    double Dk[3];
+    if (!diag_of(D_sym, s->desc.dim, Dk)) return MDLTS_EINVAL;
+    double G[4][4];
+    if (!gershgorin_table(s->ref, gamma, G)) return MDLTS_EINVAL;
+    for (int k = 0; k < 3; k++) s->Dk[k] = k < s->desc.dim ? Dk[k] : 0.0;
+    s->gamma = gamma;
+    std::memcpy(s->G, G, sizeof(G));
+    s->levels_valid = s->levels_valid && false;
+    return MDLTS_OK;
+}
+
+mdlts_status mdlts_set_ionic(mdlts_sim *s, const mdlts_ap_params *p)
+{
+    if (!s || !p) return MDLTS_EINVAL;
+    s->ap = *p;
+    return MDLTS_OK;
+}
+
+mdlts_status mdlts_set_stimulus(mdlts_sim *s, const mdlts_stim_box *boxes, int n_boxes)
+{
+    if (!s || n_boxes < 0 || n_boxes > kMaxStim || (n_boxes && !boxes)) return MDLTS_EINVAL;
+    s->stim.assign(boxes, boxes + n_boxes);
+    return MDLTS_OK;
+}
+
+mdlts_status mdlts_set_state(mdlts_sim *s, const double *u, const double *v, size_t n_dof)
+{
+    if (!s) return MDLTS_EINVAL;
+    const size_t E = s->forest.size();
+    if (n_dof != E * (size_t)s->np) return MDLTS_EINVAL;
+    mdlts_ctx *c = s->ctx;
+    MD_TRY(to_canonical(s));
+    MD_TRY(dev_alloc(c, s->stage, n_dof * sizeof(double)));
+    const double *src[2] = {u, v};
+    DevBuf *dst[2] = {&s->u_c, &s->v_c};
+    for (int f = 0; f < 2; f++) {
+        if (!src[f]) continue;
+        HIP_TRY(hipMemcpyAsync(s->stage.p, src[f], n_dof * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        if (s->desc.precision == MDLTS_FP64)
+            k_from_host<double><<<nblocks((long long)n_dof), kBlock, 0, c->stream>>>((int)E, s->np, P<double>(s->stage),
+                                                                                    P<double>(*dst[f]));
+        else
+            k_from_host<float><<<nblocks((long long)n_dof), kBlock, 0, c->stream>>>((int)E, s->np, P<double>(s->stage),
+                                                                                   P<float>(*dst[f]));
+        HIP_TRY(hipGetLastError());
+        MD_TRY(sync(c));  // the staging buffer is reused
+    }
+    if (s->levels_valid) MD_TRY(to_grouped(s));
+    return sync(c);
+}
+
+mdlts_status mdlts_get_state(mdlts_sim *s, double *u, double *v, size_t n_dof)
+{
+    if (!s) return MDLTS_EINVAL;
+    const size_t E = s->forest.size();
+    if (n_dof != E * (size_t)s->np) return MDLTS_EINVAL;
+    mdlts_ctx *c = s->ctx;
+    const bool was_grouped = s->state_grouped;
+    MD_TRY(to_canonical(s));
+    MD_TRY(dev_alloc(c, s->stage, n_dof * sizeof(double)));
+    double *dst[2] = {u, v};
+    DevBuf *src[2] = {&s->u_c, &s->v_c};
+    for (int f = 0; f < 2; f++) {
+        if (!dst[f]) continue;
+        if (s->desc.precision == MDLTS_FP64)
+            k_to_host<double><<<nblocks((long long)n_dof), kBlock, 0, c->stream>>>((int)E, s->np, P<double>(*src[f]),
+                                                                                  P<double>(s->stage));
+        else
+            k_to_host<float><<<nblocks((long long)n_dof), kBlock, 0, c->stream>>>((int)E, s->np, P<float>(*src[f]),
+                                                                                 P<double>(s->stage));
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(dst[f], s->stage.p, n_dof * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        MD_TRY(sync(c));
+    }
+    // the grouped copy is still current: keep stepping from it
+    if (was_grouped) s->state_grouped = true;
+    return MDLTS_OK;
+}
+
+mdlts_status mdlts_set_time(mdlts_sim *s, double t)
+{
+    if (!s || !std::isfinite(t)) return MDLTS_EINVAL;
+    s->t_start = t;
+    s->n_bar = 0;
+    return MDLTS_OK;
+}
+
+mdlts_status mdlts_assign_levels(mdlts_sim *s, double dt_barrier, int32_t *level_hist)
+{
+    if (!s || !(dt_barrier > 0.0) || !std::isfinite(dt_barrier)) return MDLTS_EINVAL;
+    mdlts_ctx *c = s->ctx;
+    const int E = (int)s->forest.size();
+    const int L = s->desc.n_levels;
+    const int nb = nblocks(E);
+    MD_TRY(to_canonical(s));
+    MD_TRY(dev_alloc(c, s->level_c, (size_t)E));
+    MD_TRY(dev_alloc(c, s->cfl_c, (size_t)E * sizeof(double)));
+    MD_TRY(dev_alloc(c, s->hist, (size_t)nb * kMaxLevels * sizeof(int)));
+    MD_TRY(dev_alloc(c, s->cnt_ge_d, kMaxLevels * sizeof(int)));
+    MD_TRY(dev_alloc(c, s->flags, 64));
+    MD_TRY(dev_alloc(c, s->perm, (size_t)E * sizeof(int)));
+    MD_TRY(dev_alloc(c, s->inv, (size_t)E * sizeof(int)));
+    HIP_TRY(hipMemsetAsync(s->flags.p, 0, 64, c->stream));
+    HIP_TRY(hipMemsetAsync(s->cnt_ge_d.p, 0, kMaxLevels * sizeof(int), c->stream));
+    LevelArgs la;
+    std::memset(&la, 0, sizeof(la));
+    la.key = s->key_c.p;
+    la.face = P<uint32_t>(s->face_c);
+    la.E = E;
+    la.dim = s->desc.dim;
+    la.n_levels = L;
+    la.dt_bar = dt_barrier;
+    for (int k = 0; k < 3; k++) { la.h0[k] = s->h0[k]; la.Dk[k] = s->Dk[k]; }
+    std::memcpy(la.G, s->G, sizeof(la.G));
+    la.level = P<uint8_t>(s->level_c);
+    la.cfl = P<double>(s->cfl_c);
+    la.hist = P<int>(s->hist);
+    la.bad = P<int>(s->flags);
+    if (s->desc.dim == 2) k_levels<2><<<nb, kBlock, 0, c->stream>>>(la);
+    else k_levels<3><<<nb, kBlock, 0, c->stream>>>(la);
+    HIP_TRY(hipGetLastError());
+    int bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, s->flags.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    MD_TRY(sync(c));
+    if (bad) {
+        s->levels_valid = false;
+        return MDLTS_EUNSTABLE;
+    }
+    k_level_scan<<<1, kBlock, 0, c->stream>>>(P<int>(s->hist), nb, L, P<int>(s->cnt_ge_d));
+    k_level_scatter<<<nb, kBlock, 0, c->stream>>>(P<uint8_t>(s->level_c), E, P<int>(s->hist), P<int>(s->perm),
+                                                   P<int>(s->inv));
+    // grouped tables
+    s->cap = E;
+    const size_t ksz = s->desc.dim == 2 ? 4 : 8;
+    MD_TRY(dev_alloc(c, s->key_s, (size_t)s->cap * ksz));
+    MD_TRY(dev_alloc(c, s->nbr_s, (size_t)s->cap * 2 * s->desc.dim * sizeof(uint32_t)));
+    MD_TRY(dev_alloc(c, s->fine_s, std::max<size_t>(1, s->forest.fine.size()) * sizeof(uint32_t)));
+    if (s->desc.dim == 2)
+        k_remap<uint32_t><<<nb, kBlock, 0, c->stream>>>(E, 4, P<int>(s->perm), P<int>(s->inv), P<uint8_t>(s->level_c),
+                                                         P<uint32_t>(s->key_c), P<uint32_t>(s->face_c),
+                                                         P<uint32_t>(s->key_s), P<uint32_t>(s->nbr_s), s->cap);
+    else
+        k_remap<uint64_t><<<nb, kBlock, 0, c->stream>>>(E, 6, P<int>(s->perm), P<int>(s->inv), P<uint8_t>(s->level_c),
+                                                         P<uint64_t>(s->key_c), P<uint32_t>(s->face_c),
+                                                         P<uint64_t>(s->key_s), P<uint32_t>(s->nbr_s), s->cap);
+    const int nfine = (int)s->forest.fine.size();
+    if (nfine)
+        k_remap_fine<<<nblocks(nfine), kBlock, 0, c->stream>>>(nfine, P<uint32_t>(s->fine_c), P<int>(s->inv),
+                                                                P<uint8_t>(s->level_c), P<uint32_t>(s->fine_s));
+    const size_t sbytes = (size_t)s->cap * s->np * s->tsize;
+    MD_TRY(dev_alloc(c, s->u_s, 2 * sbytes));
+    MD_TRY(dev_alloc(c, s->v_s, sbytes));
+    HIP_TRY(hipGetLastError());
+    std::vector<int32_t> cnt(kMaxLevels, 0);
+    HIP_TRY(hipMemcpyAsync(cnt.data(), s->cnt_ge_d.p, kMaxLevels * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    MD_TRY(sync(c));
+    s->cnt_ge.assign(cnt.begin(), cnt.begin() + L);
+    s->lmax = 0;
+    for (int l = 0; l < L; l++)
+        if (s->cnt_ge[l] > 0) s->lmax = l;
+    if (level_hist)
+        for (int l = 0; l < L; l++) level_hist[l] = s->cnt_ge[l] - (l + 1 < L ? s->cnt_ge[l + 1] : 0);
+    if (dt_barrier != s->dt_bar) {
+        s->t_start = s->t_start + (double)s->n_bar * s->dt_bar;
+        s->n_bar = 0;
+        s->dt_bar = dt_barrier;
+    }
+    s->levels_valid = true;
+    MD_TRY(to_grouped(s));
+    return sync(c);
+}
+
+mdlts_status mdlts_get_levels(mdlts_sim *s, int8_t *level, int32_t *perm, int32_t *cnt_ge, size_t n_leaves)
+{
+    if (!s) return MDLTS_EINVAL;
+    if (!s->levels_valid) return MDLTS_ESTATE;
+    if (n_leaves != s->forest.size()) return MDLTS_EINVAL;
+    mdlts_ctx *c = s->ctx;
+    if (level) HIP_TRY(hipMemcpyAsync(level, s->level_c.p, n_leaves, hipMemcpyDeviceToHost, c->stream));
+    if (perm) HIP_TRY(hipMemcpyAsync(perm, s->perm.p, n_leaves * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    if (cnt_ge)
+        for (size_t l = 0; l < s->cnt_ge.size(); l++) cnt_ge[l] = s->cnt_ge[l];
+    return sync(c);
+}
+
+mdlts_status mdlts_get_cfl(mdlts_sim *s, double *cfl, size_t n_leaves)
+{
+    if (!s || !cfl) return MDLTS_EINVAL;
+    if (!s->levels_valid) return MDLTS_ESTATE;
+    if (n_leaves != s->forest.size()) return MDLTS_EINVAL;
+    HIP_TRY(hipMemcpyAsync(cfl, s->cfl_c.p, n_leaves * sizeof(double), hipMemcpyDeviceToHost, s->ctx->stream));
+    return sync(s->ctx);
+}
+
+mdlts_status mdlts_step(mdlts_sim *s, int n_barriers)
+{
+    if (!s || n_barriers < 0) return MDLTS_EINVAL;
+    if (!s->levels_valid || !s->state_grouped) return MDLTS_ESTATE;
+    if (s->desc.precision == MDLTS_FP64) return run_barriers<double>(s, n_barriers);
+    return run_barriers<float>(s, n_barriers);
+}
+
+mdlts_status mdlts_indicator(mdlts_sim *s, double *eta, size_t n_leaves, double *eta_max)
+{
+    if (!s) return MDLTS_EINVAL;
+    const size_t E = s->forest.size();
+    if (eta && n_leaves != E) return MDLTS_EINVAL;
+    mdlts_ctx *c = s->ctx;
+    const bool was_grouped = s->state_grouped;
+    MD_TRY(to_canonical(s));
+    MD_TRY(dev_alloc(c, s->eta_c, E * sizeof(double)));
+    MD_TRY(dev_alloc(c, s->flags, 64));
+    HIP_TRY(hipMemsetAsync(s->flags.p, 0, 64, c->stream));
+    unsigned long long *maxb = reinterpret_cast<unsigned long long *>(static_cast<char *>(s->flags.p) + 8);
+    int *nonf = reinterpret_cast<int *>(static_cast<char *>(s->flags.p) + 16);
+    if (s->desc.precision == MDLTS_FP64) MD_TRY(run_indicator<double>(s, maxb, nonf));
+    else MD_TRY(run_indicator<float>(s, maxb, nonf));
+    s->eta_host.resize(E);
+    HIP_TRY(hipMemcpyAsync(s->eta_host.data(), s->eta_c.p, E * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    struct { unsigned long long m; int nf; } fl{};
+    HIP_TRY(hipMemcpyAsync(&fl.m, maxb, 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(&fl.nf, nonf, 4, hipMemcpyDeviceToHost, c->stream));
+    MD_TRY(sync(c));
+    if (was_grouped) s->state_grouped = true;
+    if (eta) std::memcpy(eta, s->eta_host.data(), E * sizeof(double));
+    if (eta_max) {
+        double m;
+        std::memcpy(&m, &fl.m, 8);
+        *eta_max = m;
+    }
+    return fl.nf ? MDLTS_EUNSTABLE : MDLTS_OK;
+}
+
+mdlts_status mdlts_adapt(mdlts_sim *s, const double *eta, size_t n_leaves, double tau_refine, double tau_coarsen,
+                         int64_t *n_refined, int64_t *n_coarsened)
+{
+    if (!s) return MDLTS_EINVAL;
+    const size_t E = s->forest.size();
+    if (eta && n_leaves != E) return MDLTS_EINVAL;
+    if (!eta && s->eta_host.size() != E) return MDLTS_ESTATE;
+    const double *ee = eta ? eta : s->eta_host.data();
+    AdaptPlan plan;
+    if (!plan_adapt(s->forest, ee, tau_refine, tau_coarsen, plan)) return MDLTS_EINVAL;
+    if (plan.next.size() >= (1u << 27)) return MDLTS_EINVAL;
+    MD_TRY(to_canonical(s));
+    if (s->desc.precision == MDLTS_FP64) MD_TRY(run_transfer<double>(s, plan, (int)E));
+    else MD_TRY(run_transfer<float>(s, plan, (int)E));
+    if (n_refined) *n_refined = plan.n_refined;
+    if (n_coarsened) *n_coarsened = plan.n_coarsened;
+    s->eta_host.clear();
+    return set_forest(s, std::move(plan.next));
+}
+
+mdlts_status mdlts_counters(mdlts_sim *s, uint64_t *dof_updates, double *t_sim)
+{
+    if (!s) return MDLTS_EINVAL;
+    if (dof_updates) *dof_updates = s->dof_updates;
+    if (t_sim) *t_sim = s->t_start + (double)s->n_bar * s->dt_bar;
+    return MDLTS_OK;
+}
+
+mdlts_status mdlts_cfl_bound(const mdlts_mesh_desc *desc, const double D_sym[6], double gamma, int depth,
+                             double *cfl_min)
+{
+    if (!valid_desc(desc) || !cfl_min || depth < 0 || depth > desc->max_depth || !(gamma > 0.0)) return MDLTS_EINVAL;
+    double Dk[3];
+    if (!diag_of(D_sym, desc->dim, Dk)) return MDLTS_EINVAL;
+    RefTables R;
+    make_ref_tables(desc->order, R);
+    double G[4][4];
+    if (!gershgorin_table(R, gamma, G)) return MDLTS_EINVAL;
+    // Face kinds a leaf of this depth can have in direction k: no finer
+    // neighbour at the depth cap, no coarser one at depth 0, both faces on
+    // the boundary only for a single root across the box, and below the
+    // roots one face always sees the sibling cell (same size or finer).
+    double s = 0.0;
+    for (int k = 0; k < desc->dim; k++) {
+        double worst = 0.0;
+        for (int lo = 0; lo < 4; lo++)
+            for (int hi = 0; hi < 4; hi++) {
+                bool ok = true;
+                if ((lo == kFiner || hi == kFiner) && depth == desc->max_depth) ok = false;
+                if ((lo == kCoarser || hi == kCoarser) && depth == 0) ok = false;
+                if (lo == kBoundary && hi == kBoundary && !(depth == 0 && desc->n[k] == 1)) ok = false;
+                const bool sib_lo = lo == kSame || lo == kFiner, sib_hi = hi == kSame || hi == kFiner;
+                if (depth > 0 && !sib_lo && !sib_hi) ok = false;
+                if (ok) worst = std::max(worst, G[lo][hi]);
+            }
+        const double h = std::ldexp(desc->len[k] / (double)desc->n[k], -depth);
+        s += Dk[k] / (h * h) * worst;
+    }
+    *cfl_min = 1.0 / s;
+    return MDLTS_OK;
+}
+
+mdlts_status mdlts_plan_adapt(const mdlts_mesh_desc *desc, const uint8_t *bits, size_t n_bits, const double *eta,
+                              size_t n_leaves, double tau_refine, double tau_coarsen, uint8_t *out_bits, size_t cap,
+                              size_t *n_out)
+{
+    if (!valid_desc(desc) || !eta || !n_out) return MDLTS_EINVAL;
+    Forest F;
+    forest_from_desc(desc, F);
+    if (!F.parse_bits(bits, n_bits)) return MDLTS_EINVAL;
+    if (F.size() != n_leaves) return MDLTS_EINVAL;
+    AdaptPlan plan;
+    if (!plan_adapt(F, eta, tau_refine, tau_coarsen, plan)) return MDLTS_EINVAL;
+    std::vector<uint8_t> out;
+    plan.next.write_bits(out);
+    *n_out = out.size();
+    if (out_bits && cap >= out.size()) std::memcpy(out_bits, out.data(), out.size());
+    return MDLTS_OK;
+}
+
+mdlts_status mdlts_plan_levels(const mdlts_mesh_desc *desc, const uint8_t *bits, size_t n_bits, const double D_sym[6],
+                               double gamma, double dt_barrier, int8_t *level, int32_t *perm, int32_t *cnt_ge,
+                               double *cfl, size_t n_leaves)
+{
+    if (!valid_desc(desc) || !(dt_barrier > 0.0) || !(gamma > 0.0)) return MDLTS_EINVAL;
+    double Dk[3];
+    if (!diag_of(D_sym, desc->dim, Dk)) return MDLTS_EINVAL;
+    Forest F;
+    forest_from_desc(desc, F);
+    if (!F.parse_bits(bits, n_bits)) return MDLTS_EINVAL;
+    if (F.size() != n_leaves) return MDLTS_EINVAL;
+    RefTables R;
+    make_ref_tables(desc->order, R);
+    double G[4][4];
+    if (!gershgorin_table(R, gamma, G)) return MDLTS_EINVAL;
+    double h0[3];
+    for (int k = 0; k < 3; k++) h0[k] = k < desc->dim ? desc->len[k] / (double)desc->n[k] : 1.0;
+    std::vector<double> c(n_leaves);
+    host_cfl(F, h0, Dk, G, c.data());
+    std::vector<int> lv(n_leaves);
+    mdlts_status st = MDLTS_OK;
+    for (size_t e = 0; e < n_leaves; e++) {
+        lv[e] = level_of(dt_barrier, c[e]);
+        if (lv[e] > desc->n_levels - 1) st = MDLTS_EUNSTABLE;
+    }
+    if (cfl) std::memcpy(cfl, c.data(), n_leaves * sizeof(double));
+    if (level)
+        for (size_t e = 0; e < n_leaves; e++) level[e] = (int8_t)std::min(lv[e], 127);
+    if (perm || cnt_ge) {
+        size_t pos = 0;
+        for (int l = desc->n_levels - 1; l >= 0; l--) {
+            for (size_t e = 0; e < n_leaves; e++)
+                if (lv[e] == l) {
+                    if (perm) perm[pos] = (int32_t)e;
+                    pos++;
+                }
+            if (cnt_ge) cnt_ge[l] = (int32_t)pos;
+        }
+    }
+    return st;
+}
+
+}  // extern "C"
