@@ -1,0 +1,213 @@
+"""Benchmark: DoF-updates/s of the SIPG + Aliev-Panfilov step under synchronous
+LTS with adaptivity, FP32 bulk, against the plain FP64 global step, on one
+MI355X.
+
+Workload (default ``amr_2d``): 2x2 cm, 256x256 Q1 roots, quadtree refinement
+up to depth 3 driven by the Kelly-type indicator, 4 LTS levels, random
+stimulus site (seed 0), Aliev-Panfilov; synthetic (no dataset).
+
+One step = one adaptation interval: indicator + readback, adaptation (host
+plan + device transfer), level assignment and grouping on the device, then
+`amr_every` barrier intervals of substeps.  Warm-up steps start at t = 0
+from the resting state; the front is established before timing starts.
+
+Prints one JSON line (rank 0, N = 1).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DoF-updates/s (SIPG apply+ionic, LTS) FP32 vs FP64 plain; p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per DoF-update of the Q1-2D FP32 substep: read u, v and
+# write u, v (16 B) plus per element a 4 B key and four 4 B face entries over
+# 4 nodes (5 B)
+BYTES_PER_DOF_Q1_2D_F32 = 21.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=300)
+    ap.add_argument("--workload", default="amr_2d")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plain-barriers", type=int, default=200)
+    return ap.parse_args()
+
+
+def setup(ctx, W, seed, precision, n_levels=None):
+    from paper_2310_07607_amd import inputs, mdlts
+    L = W["n_levels"] if n_levels is None else n_levels
+    sim = mdlts.Simulation(ctx, W["dim"], W["p"], W["n"], W["length"], W["max_depth"], L, precision)
+    sim.set_conductivity(W["D"][: W["dim"]], W["gamma"])
+    sim.set_ionic(*inputs.AP_PARAMS)
+    box = inputs.stimulus_site(seed, W["length"][: W["dim"]], W["stim_size"], 0.1, 0.0, W["stim_dur"], 1.0)
+    sim.set_stimulus(inputs.box_array([box]))
+    return sim
+
+
+def barrier_step(W):
+    from paper_2310_07607_amd import mdlts
+    desc = mdlts.make_desc(W["dim"], W["p"], W["n"], W["length"], W["max_depth"], W["n_levels"])
+    b = mdlts.cfl_bound(desc, W["D"][: W["dim"]], W["gamma"], W["max_depth"])
+    return 2 ** (W["n_levels"] - 1) * b * (1 - 2 ** -20)
+
+
+def interval(sim, W, dt):
+    sim.indicator()
+    sim.adapt(W["tau_refine"], W["tau_coarsen"])
+    sim.assign_levels(dt)
+    sim.step(W["amr_every"])
+
+
+def cpu_baseline(W, dt, seconds, seed):
+    """The FP64 oracle (one thread) on the same workload from t = 0."""
+    import numpy as np
+    from oracle.oracle import Oracle
+    from paper_2310_07607_amd import inputs
+    o = Oracle(W["dim"], W["p"], W["n"][: W["dim"]], W["length"][: W["dim"]], W["max_depth"])
+    o.set_params(np.diag(list(W["D"][: W["dim"]]) + [0.0] * (3 - W["dim"])), W["gamma"], inputs.AP_PARAMS)
+    box = inputs.stimulus_site(seed, W["length"][: W["dim"]], W["stim_size"], 0.1, 0.0, W["stim_dur"], 1.0)
+    o.set_stimulus(inputs.box_array([box]))
+    n_dof_upd = 0
+    n_bar = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        if n_bar % W["amr_every"] == 0:
+            eta = o.indicator()
+            o.adapt(eta, W["tau_refine"], W["tau_coarsen"])
+            lv, rc = o.levels(dt, W["n_levels"])
+        nu, _ = o.lts_barrier(dt, n_bar * dt, lv)
+        n_dof_upd += nu * o.np_
+        n_bar += 1
+    el = time.perf_counter() - t0
+    return {"value": n_dof_upd / el, "unit": "DoF-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 oracle, same workload from t=0 (root mesh, stimulus on), {n_bar} barriers "
+                      f"with adaptation every {W['amr_every']}, {n_dof_upd} DoF-updates in {el:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in DESIGN.md "
+                                   "but not built", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2310_07607_amd import inputs, mdlts
+
+    W = dict(inputs.WORKLOADS[args.workload])
+    dt = barrier_step(W)
+    ctx = mdlts.Context(0)
+    sim = setup(ctx, W, args.seed, "f32")
+    sim.set_time(0.0)
+    for _ in range(args.warmup):
+        interval(sim, W, dt)
+    torch.cuda.synchronize()
+    n0, t_sim0 = sim.counters()
+    sim.profile(True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for _ in range(args.steps):
+        interval(sim, W, dt)
+    ctx.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    k_ms, k_launch, k_dof = sim.profile_read()
+    sim.profile(False)
+    n1, t_sim1 = sim.counters()
+    dof = n1 - n0
+    leaves = sim.n_leaves
+    hist = sim.assign_levels(dt)
+    value = dof / wall
+
+    # plain FP64 global step on the same mesh and state (frozen mesh)
+    u, v = sim.get_state()
+    bits = sim.get_tree()
+    plain = setup(ctx, W, args.seed, "f64", n_levels=1)
+    plain.set_tree(bits)
+    plain.set_state(u, v)
+    dt_plain = dt / 2 ** (W["n_levels"] - 1)
+    plain.assign_levels(dt_plain)
+    plain.set_time(t_sim1)
+    plain.step(5)
+    ctx.sync()
+    p0, _ = plain.counters()
+    plain.profile(True)
+    wp = time.perf_counter()
+    plain.step(args.plain_barriers)
+    ctx.sync()
+    wplain = time.perf_counter() - wp
+    p_ms, p_launch, p_dof = plain.profile_read()
+    p1, _ = plain.counters()
+    plain_rate = (p1 - p0) / wplain
+
+    # FP32 LTS vs FP64 plain over the same simulated window (frozen mesh)
+    lts = setup(ctx, W, args.seed, "f32")
+    lts.set_tree(bits)
+    lts.set_state(u, v)
+    lts.assign_levels(dt)
+    lts.set_time(t_sim1)
+    ref = setup(ctx, W, args.seed, "f64", n_levels=1)
+    ref.set_tree(bits)
+    ref.set_state(u, v)
+    ref.assign_levels(dt_plain)
+    ref.set_time(t_sim1)
+    nb = 16
+    lts.step(nb)
+    ref.step(nb * 2 ** (W["n_levels"] - 1))
+    ul, _ = lts.get_state()
+    ur, _ = ref.get_state()
+    err = float(np.linalg.norm(ul - ur) / np.linalg.norm(ur))
+
+    achieved = BYTES_PER_DOF_Q1_2D_F32 * k_dof / (k_ms * 1e-3) / 1e9 if k_ms > 0 else 0.0
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DoF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "amr_2d: 2x2 cm, 256x256 Q1 roots, refinement depth <= 3, 4 LTS levels, "
+                               "Aliev-Panfilov, seeded stimulus site, FP32 bulk + FP64 bookkeeping",
+                   "step": f"one adaptation interval = indicator + adapt + levels + {W['amr_every']} barriers",
+                   "dt_barrier_ms": dt, "leaves_at_end": leaves, "level_hist_at_end": hist.tolist(),
+                   "t_sim_ms": [t_sim0, t_sim1]},
+        "kernel_only": {"value": k_dof / (k_ms * 1e-3) if k_ms > 0 else None, "unit": "DoF-updates/s",
+                        "substep_ms": k_ms, "launches": k_launch,
+                        "share_of_wall": k_ms * 1e-3 / wall},
+        "fp64_plain": {"value": plain_rate, "unit": "DoF-updates/s", "dt_ms": dt_plain,
+                       "kernel_ms_per_launch": p_ms / max(p_launch, 1),
+                       "sim_ms_per_s": args.plain_barriers * dt_plain / wplain,
+                       "lts_fp32_sim_ms_per_s": (t_sim1 - t_sim0) / wall,
+                       "rel_l2_fp32_lts_vs_fp64_plain": err, "window_ms": nb * dt},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_substep<2,1,float>", "bytes_per_dof_update": BYTES_PER_DOF_Q1_2D_F32,
+                     "avg_launch_us": k_ms * 1e3 / max(k_launch, 1)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(W, dt, args.cpu_seconds, args.seed)
+    print(json.dumps(out), flush=True)
+    for s in (sim, plain, lts, ref):
+        s.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

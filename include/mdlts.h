@@ -167,6 +167,15 @@ mdlts_status mdlts_adapt(mdlts_sim *sim, const double *eta, size_t n_leaves, dou
  * nodes per leaf) and the simulated time of the next barrier. */
 mdlts_status mdlts_counters(mdlts_sim *sim, uint64_t *dof_updates, double *t_sim);
 
+/* ---- measurement ---------------------------------------------------------- */
+/* enable != 0: bracket every substep kernel launch with a pair of HIP events
+ * on the context stream (resets the accumulators). */
+mdlts_status mdlts_profile(mdlts_sim *sim, int enable);
+/* Waits for the recorded events and returns, since the last read or enable,
+ * the summed substep kernel time [ms], the number of launches and the
+ * DoF-updates they performed; then resets the accumulators. */
+mdlts_status mdlts_profile_read(mdlts_sim *sim, double *substep_ms, uint64_t *n_launches, uint64_t *dof_updates);
+
 /* ---- host-only planning utilities (no device work) ---------------------- */
 /* Lower bound on CFL_e over the leaves of the given depth (worst face kinds
  * per direction that a 2:1-balanced forest allows; attained on uniform

@@ -1,0 +1,82 @@
+"""Calibrate the refine/coarsen thresholds of the 2-D Aliev-Panfilov workload
+on the CPU oracle (test infrastructure; its output is frozen into
+paper_2310_07607_amd/inputs.py).
+
+The paper tunes tau_refine for its own ionic model and units (Sec. 3) and
+uses tau_coarsen = tau_refine / 3.  For the Aliev-Panfilov workload the
+rule used here is: a plane front resolved on a uniform mesh of depth
+max_depth-1 must be refined (its largest indicator exceeds tau_refine by a
+factor 2).  The indicator of a front falls by about 8x per refinement
+depth, so children of a just-refined leaf sit near tau_refine/8; with
+tau_coarsen = tau_refine/3 they would be coarsened again at once.  Hence
+tau_coarsen = tau_refine/16 here.  The script also measures the front speed
+from two snapshots, which sets how many barriers may pass between two
+adaptations (the front may cross at most one finest element per interval).
+
+Usage: python oracle/calibrate_thresholds.py
+"""
+import math
+import os
+import sys
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path = [q for q in sys.path if os.path.abspath(q or ".") != _HERE]
+sys.path.insert(0, os.path.dirname(_HERE))
+from oracle.oracle import Oracle  # noqa: E402
+
+AP = (8.0, 0.15, 0.002, 0.2, 0.3)
+
+
+def strip(depth, n_roots=64, h0=2.0 / 256, D=1e-3, gamma=2.0):
+    L = n_roots * h0
+    o = Oracle(2, 1, [n_roots, 1], [L, h0], depth)
+    o.set_params(np.diag([D, D, 0.0]), gamma, AP)
+    for _ in range(depth):
+        o.adapt(np.ones(o.n_leaves), 0.5, -1.0)
+    o.set_stimulus(np.array([[0, 0, 0, 0.1, h0, 1, 0.0, 1.0, 1.0]]))
+    return o
+
+
+def front_position(o):
+    X = o.leaf_nodes()
+    u, _ = o.get_state()
+    ahead = X[u > 0.5, 0]
+    return ahead.max() if ahead.size else 0.0
+
+
+def run(depth, t_end=5.0):
+    o = strip(depth)
+    dt = 0.9 * o.cfl().min()
+    n = int(math.ceil(t_end / dt))
+    dt = t_end / n
+    snaps = {}
+    t_marks = {3.0: None, t_end: None}
+    t = 0.0
+    step = 0
+    for tm in sorted(t_marks):
+        k = int(round(tm / dt)) - step
+        o.step_global(dt, t, k)
+        step += k
+        t = step * dt
+        snaps[tm] = front_position(o)
+    return o, snaps
+
+
+def main():
+    out = {}
+    for depth in (0, 1, 2):
+        o, snaps = run(depth)
+        eta = o.indicator()
+        c = (snaps[5.0] - snaps[3.0]) / 2.0
+        out[depth] = (eta.max(), c)
+        print(f"depth {depth}: max eta {eta.max():.4e}, front speed {c:.4f} cm/ms", flush=True)
+    tau_r = 0.5 * out[2][0]
+    ratio = out[1][0] / out[2][0]
+    print(f"indicator ratio per depth {ratio:.2f}")
+    print(f"tau_refine = {tau_r:.3e}, tau_coarsen = {tau_r / 16:.3e}")
+
+
+if __name__ == "__main__":
+    main()

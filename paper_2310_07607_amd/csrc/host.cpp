@@ -133,14 +133,10 @@ bool gershgorin_table(const RefTables &T, double gamma, double out[4][4])
 // ---------------------------------------------------------------------------
 // linear forest
 // ---------------------------------------------------------------------------
-uint64_t cell_key(int depth, const int64_t *c)
-{
-    return ((uint64_t)depth << 60) | ((uint64_t)c[0] << 40) | ((uint64_t)c[1] << 20) | (uint64_t)c[2];
-}
-
 void Forest::init_roots()
 {
     leaves.clear();
+    leaves.reserve((size_t)n[0] * n[1] * n[2]);
     for (int z = 0; z < n[2]; z++)
         for (int y = 0; y < n[1]; y++)
             for (int x = 0; x < n[0]; x++) {
@@ -175,6 +171,7 @@ static bool parse_rec(Forest &F, int depth, const int64_t *c, const uint8_t *bit
 bool Forest::parse_bits(const uint8_t *bits, size_t n_bits)
 {
     leaves.clear();
+    leaves.reserve(n_bits);
     size_t pos = 0;
     for (int z = 0; z < n[2]; z++)
         for (int y = 0; y < n[1]; y++)
@@ -207,6 +204,7 @@ static void write_rec(const Forest &F, int depth, const int64_t *c, size_t &pos,
 void Forest::write_bits(std::vector<uint8_t> &out) const
 {
     out.clear();
+    out.reserve(leaves.size() * 2);
     size_t pos = 0;
     for (int z = 0; z < n[2]; z++)
         for (int y = 0; y < n[1]; y++)
@@ -216,20 +214,81 @@ void Forest::write_bits(std::vector<uint8_t> &out) const
             }
 }
 
-int64_t Forest::find(int depth, const int64_t *c) const
+static inline uint32_t spread2(uint32_t x)  // 8 bits -> even bits of 16
 {
-    auto it = index.find(cell_key(depth, c));
-    return it == index.end() ? -1 : it->second;
+    x = (x | (x << 4)) & 0x0F0Fu;
+    x = (x | (x << 2)) & 0x3333u;
+    x = (x | (x << 1)) & 0x5555u;
+    return x;
+}
+
+static inline uint32_t spread3(uint32_t x)  // 8 bits -> every third bit of 24
+{
+    x = (x | (x << 16)) & 0x030000FFu;
+    x = (x | (x << 8)) & 0x0300F00Fu;
+    x = (x | (x << 4)) & 0x030C30C3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+
+uint32_t Forest::morton(int depth, const int64_t *local) const
+{
+    // interleave the bits of the cell's corner at the depth cap, x lowest
+    const int sh = max_depth - depth;
+    if (dim == 2) return spread2((uint32_t)(local[0] << sh)) | (spread2((uint32_t)(local[1] << sh)) << 1);
+    return spread3((uint32_t)(local[0] << sh)) | (spread3((uint32_t)(local[1] << sh)) << 1) |
+           (spread3((uint32_t)(local[2] << sh)) << 2);
+}
+
+int64_t Forest::containing(int depth, const int64_t *c) const
+{
+    int64_t rc[3] = {0, 0, 0}, loc[3] = {0, 0, 0};
+    for (int k = 0; k < dim; k++) {
+        rc[k] = c[k] >> depth;
+        loc[k] = c[k] - (rc[k] << depth);
+    }
+    const int64_t rid = rc[0] + (int64_t)n[0] * (rc[1] + (int64_t)n[1] * rc[2]);
+    const uint32_t m = morton(depth, loc);
+    // last leaf of the root whose key is <= m (the first key of a root is 0)
+    const int64_t lo = root_start[rid];
+    int64_t len = root_start[rid + 1] - lo;
+    if (len <= 0) return -1;
+    const uint32_t *base = &mkey[lo];
+    while (len > 1) {
+        const int64_t half = len >> 1;
+        base = base[half] <= m ? base + half : base;
+        len -= half;
+    }
+    return base - mkey.data();
 }
 
 bool Forest::build_faces()
 {
     const size_t E = leaves.size();
-    index.clear();
-    index.reserve(E * 2);
-    for (size_t e = 0; e < E; e++) {
-        int64_t c[3] = {leaves[e].c[0], leaves[e].c[1], leaves[e].c[2]};
-        index[cell_key(leaves[e].depth, c)] = (int32_t)e;
+    const size_t n_roots = (size_t)n[0] * n[1] * n[2];
+    root_start.assign(n_roots + 1, 0);
+    mkey.resize(E);
+    {
+        size_t e = 0;
+        for (size_t r = 0; r < n_roots; r++) {
+            root_start[r] = (int32_t)e;
+            const int64_t rc[3] = {(int64_t)(r % n[0]), (int64_t)((r / n[0]) % n[1]),
+                                   (int64_t)(r / ((size_t)n[0] * n[1]))};
+            while (e < E) {
+                const Leaf &L = leaves[e];
+                bool in = true;
+                int64_t loc[3] = {0, 0, 0};
+                for (int k = 0; k < dim; k++) {
+                    if (((int64_t)L.c[k] >> L.depth) != rc[k]) in = false;
+                    loc[k] = (int64_t)L.c[k] - (rc[k] << L.depth);
+                }
+                if (!in) break;
+                mkey[e] = morton(L.depth, loc);
+                e++;
+            }
+        }
+        root_start[n_roots] = (int32_t)e;
+        if (e != E) return false;  // leaves not grouped by root in root order
     }
     face.assign((size_t)n_faces() * E, 0);
     fine.clear();
@@ -241,27 +300,29 @@ bool Forest::build_faces()
                 t[k] += s ? 1 : -1;
                 uint32_t entry = kBoundary << 30;
                 if (t[k] >= 0 && t[k] < ((int64_t)n[k] << L.depth)) {
-                    int64_t id = find(L.depth, t);
-                    if (id >= 0) {
+                    const int64_t id = containing(L.depth, t);
+                    if (id < 0) return false;
+                    const Leaf &N = leaves[id];
+                    if (N.depth == L.depth) {
                         entry = (kSame << 30) | (uint32_t)id;
-                    } else {
-                        int64_t up[3] = {t[0] >> 1, t[1] >> 1, t[2] >> 1};
-                        int64_t pid = L.depth > 0 ? find(L.depth - 1, up) : -1;
-                        if (pid >= 0) {
-                            entry = (kCoarser << 30) | (uint32_t)pid;
-                        } else {
-                            const uint32_t g = (uint32_t)(fine.size() / n_sub());
-                            const int want = s ? 0 : 1;
-                            for (int ci = 0; ci < (1 << dim); ci++) {
-                                if (((ci >> k) & 1) != want) continue;
-                                int64_t cc[3] = {0, 0, 0};
-                                for (int q = 0; q < dim; q++) cc[q] = 2 * t[q] + ((ci >> q) & 1);
-                                int64_t fid = find(L.depth + 1, cc);
-                                if (fid < 0) return false;  // not 2:1 balanced
-                                fine.push_back((uint32_t)fid);
-                            }
-                            entry = (kFiner << 30) | g;
+                    } else if (N.depth + 1 == L.depth) {
+                        entry = (kCoarser << 30) | (uint32_t)id;
+                    } else if (N.depth > L.depth) {
+                        // the neighbour cell is refined: its children on
+                        // this face must be leaves (2:1 balance)
+                        const uint32_t g = (uint32_t)(fine.size() / n_sub());
+                        const int want = s ? 0 : 1;
+                        for (int ci = 0; ci < (1 << dim); ci++) {
+                            if (((ci >> k) & 1) != want) continue;
+                            int64_t cc[3] = {0, 0, 0};
+                            for (int q = 0; q < dim; q++) cc[q] = 2 * t[q] + ((ci >> q) & 1);
+                            const int64_t fid = containing(L.depth + 1, cc);
+                            if (fid < 0 || leaves[fid].depth != L.depth + 1) return false;
+                            fine.push_back((uint32_t)fid);
                         }
+                        entry = (kFiner << 30) | g;
+                    } else {
+                        return false;  // coarser by more than one depth
                     }
                 }
                 face[(size_t)(2 * k + s) * E + e] = entry;
@@ -334,6 +395,7 @@ bool plan_adapt(const Forest &cur, const double *eta, double tau_refine, double 
     plan.next.max_depth = cur.max_depth;
     for (int k = 0; k < 3; k++) plan.next.n[k] = cur.n[k];
     plan.next.leaves.clear();
+    plan.next.leaves.reserve(E + E / 2);
     plan.kind.clear();
     plan.src.clear();
     plan.child.clear();

@@ -4,7 +4,6 @@
 #pragma once
 #include <cstddef>
 #include <cstdint>
-#include <unordered_map>
 #include <vector>
 
 namespace mdlts {
@@ -47,7 +46,11 @@ struct Forest {
     std::vector<Leaf> leaves;             // canonical order
     std::vector<uint32_t> face;           // [2*dim][E]: kind<<30 | canonical id (or fine group)
     std::vector<uint32_t> fine;           // [groups][2^(dim-1)] canonical ids
-    std::unordered_map<uint64_t, int32_t> index;
+    // lookup: the leaves of root r are [root_start[r], root_start[r+1]) and,
+    // inside a root, sorted by the Morton key of their lower corner at the
+    // depth cap (pre-order of a 2^d-tree with child bit k = dimension k)
+    std::vector<int32_t> root_start;
+    std::vector<uint32_t> mkey;
 
     int n_faces() const { return 2 * dim; }
     int n_sub() const { return 1 << (dim - 1); }
@@ -57,12 +60,12 @@ struct Forest {
     // returns false for malformed, too deep, or unbalanced streams
     bool parse_bits(const uint8_t *bits, size_t n_bits);
     void write_bits(std::vector<uint8_t> &out) const;
-    // hashed lookup and face table; false if 2:1 balance is violated
+    // lookup tables and face table; false if 2:1 balance is violated
     bool build_faces();
-    int64_t find(int depth, const int64_t *c) const;
+    // the leaf containing the lower corner of cell c at `depth`, or -1
+    int64_t containing(int depth, const int64_t *c) const;
+    uint32_t morton(int depth, const int64_t *local) const;
 };
-
-uint64_t cell_key(int depth, const int64_t *c);
 
 // Adaptation plan (Algorithm 1 thresholds; 2:1 closure; balanced coarsening).
 // For each new leaf: kind (0 copy, 1 prolong from parent, 2 restrict from

@@ -195,16 +195,49 @@ __device__ __forceinline__ void neighbour_trace(const StepArgs<T> &a, uint32_t e
     }
 }
 
+// Value of a neighbour's nodes at substep i (packed entry: level | id): a
+// neighbour updated at this substep is read from its current slot; one that
+// is not (it is coarser) is linear in time between its two slots.  Both
+// slots are always loaded (the second from the first's address when not
+// needed) so that the loads of all faces issue together without branches.
+template <typename T, int NP>
+__device__ __forceinline__ void neighbour_values(const StepArgs<T> &a, uint32_t ent, T *val)
+{
+    const uint32_t id = ent & kIdMask27;
+    const int ln = (int)((ent >> 27) & 7);
+    const int sh = a.lmax - ln;
+    const int base = ln == 0 ? a.parity : 0;
+    const int cur = base ^ ((a.i >> sh) & 1);
+    const int rem = a.i & ((1 << sh) - 1);
+    const T th = (T)rem * (T)ldexp(1.0, -sh);
+    const T *p0 = a.u + (long long)cur * a.slot_stride + id;
+    const T *p1 = rem ? a.u + (long long)(cur ^ 1) * a.slot_stride + id : p0;
+#pragma unroll
+    for (int n = 0; n < NP; n++) {
+        const T x0 = p0[(long long)n * a.cap];
+        const T x1 = p1[(long long)n * a.cap];
+        val[n] = x0 + th * (x1 - x0);
+    }
+}
+
 // One substep (Sec. 2.3, Algorithm 1) for the active prefix of the
 // level-grouped elements: element-volume diffusion, SIPG face fluxes
 // (Sec. 2.1), inverse diagonal mass, Aliev-Panfilov reaction + stimulus,
 // forward Euler for u and an exponential step for v.  Reads the current
 // slot, writes the other one; v is updated in place.
+//
+// Memory schedule: the element's own nodes, its face entries and (for
+// same-size or coarser faces) one neighbour per face are loaded before any
+// arithmetic, so a wave waits for memory twice; faces with finer neighbours
+// (rare, at refinement interfaces) load their 2^(d-1) neighbours on demand.
 template <int DIM, int P, typename T>
 __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> a)
 {
     using S = Shape<DIM, P>;
     constexpr int M = S::M, NP = S::NP, NF = S::NF, NS = S::NS;
+    constexpr int NFACE = 2 * DIM;
+    // prefetch every face's neighbour unless it costs too many registers
+    constexpr bool kPrefetch = NFACE * NP <= 64;
     const int j = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (j >= a.n_act) return;
 
@@ -214,21 +247,42 @@ __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> a)
     const int sh = a.lmax - lv;
     const int cur = (lv == 0 ? a.parity : 0) ^ ((a.i >> sh) & 1);
     const T dt = (T)ldexp(a.dt_bar, -lv);
+    const uint32_t self_ent = ((uint32_t)lv << 27) | (uint32_t)j;
+
+    // ---- loads that depend on nothing but j
+    uint32_t ent[NFACE];
+#pragma unroll
+    for (int f = 0; f < NFACE; f++) ent[f] = a.nbr[(long long)f * a.cap + j];
+    const typename KeyOf<DIM>::type kraw = static_cast<const typename KeyOf<DIM>::type *>(a.key)[j];
+    const T *uc = a.u + (long long)cur * a.slot_stride + j;
+    T *vp = a.v + j;
+    T u[NP], vv[NP];
+#pragma unroll
+    for (int n = 0; n < NP; n++) {
+        u[n] = uc[(long long)n * a.cap];
+        vv[n] = vp[(long long)n * a.cap];
+    }
+    // ---- one neighbour per face (same-size or coarser), at the substep time
+    T nb[kPrefetch ? NFACE : 1][NP];
+    if constexpr (kPrefetch) {
+#pragma unroll
+        for (int f = 0; f < NFACE; f++) {
+            const uint32_t kind = ent[f] >> 30;
+            const bool one = kind == kSame || kind == kCoarser;
+            neighbour_values<T, NP>(a, one ? ent[f] : self_ent, nb[f]);
+        }
+    }
 
     int depth;
     uint32_t c[3] = {0, 0, 0};
-    unpack_key<DIM>(static_cast<const typename KeyOf<DIM>::type *>(a.key)[j], depth, c);
+    unpack_key<DIM>(kraw, depth, c);
     T h[DIM];
 #pragma unroll
     for (int k = 0; k < DIM; k++) h[k] = (T)ldexp(a.h0[k], -depth);
 
-    const T *uc = a.u + (long long)cur * a.slot_stride + j;
-    T u[NP], r[NP];
+    T r[NP];
 #pragma unroll
-    for (int n = 0; n < NP; n++) {
-        u[n] = uc[(long long)n * a.cap];
-        r[n] = 0;
-    }
+    for (int n = 0; n < NP; n++) r[n] = 0;
 
     // element volume: -(4 D_kk / h_k^2) A along each direction
 #pragma unroll
@@ -263,8 +317,8 @@ __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> a)
         }
 #pragma unroll
         for (int s = 0; s < 2; s++) {
-            const uint32_t ent = a.nbr[(long long)(2 * k + s) * a.cap + j];
-            const uint32_t kind = ent >> 30;
+            const int f = 2 * k + s;
+            const uint32_t kind = ent[f] >> 30;
             if (kind == kBoundary) continue;
             const T ns = s ? (T)1 : (T)-1;
             const T qs = ns * Dkk * c2;
@@ -283,7 +337,21 @@ __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> a)
             T Fl[NF], Hl[NF];
             if (kind != kFiner) {
                 T nu[NF], nq[NF];
-                neighbour_trace<T, DIM, P>(a, ent, k, 1 - s, nu, nq);
+                if constexpr (kPrefetch) {
+#pragma unroll
+                    for (int g = 0; g < NF; g++) {
+                        T su = 0, sq = 0;
+#pragma unroll
+                        for (int b = 0; b < M; b++) {
+                            su += a.ref.B[1 - s][b] * nb[f][fnode<DIM, M>(k, g, b)];
+                            sq += a.ref.G[1 - s][b] * nb[f][fnode<DIM, M>(k, g, b)];
+                        }
+                        nu[g] = su;
+                        nq[g] = sq;
+                    }
+                } else {
+                    neighbour_trace<T, DIM, P>(a, ent[f], k, 1 - s, nu, nq);
+                }
                 const T hn = kind == kSame ? hk : (T)2 * hk;
                 if (kind == kCoarser) {
                     T iu[NF], iq[NF];
@@ -301,19 +369,22 @@ __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> a)
                     Hl[g] = (T)0.5 * jmp;
                 }
             } else {
-                const uint32_t grp = ent & kIdMask27;
+                const uint32_t grp = ent[f] & kIdMask27;
                 const T hn = (T)0.5 * hk;
                 const T sigma = a.gamma * (T)0.5 * (Dkk / hk + Dkk / hn);
                 const T qn = ns * Dkk * ((T)2 / hn);
 #pragma unroll
                 for (int g = 0; g < NF; g++) { Fl[g] = 0; Hl[g] = 0; }
+                uint32_t fe[NS];
+#pragma unroll
+                for (int sub = 0; sub < NS; sub++) fe[sub] = a.fine[(long long)grp * NS + sub];
 #pragma unroll
                 for (int sub = 0; sub < NS; sub++) {
                     const int p0 = sub & 1, p1 = sub >> 1;
                     T ou[NF], oq[NF], nu[NF], nq[NF], F[NF], H[NF], lf[NF], lh[NF];
                     tang_apply<T, DIM, M>(a.ref.Isub, p0, p1, tu, ou);
                     tang_apply<T, DIM, M>(a.ref.Isub, p0, p1, tq, oq);
-                    neighbour_trace<T, DIM, P>(a, a.fine[(long long)grp * NS + sub], k, 1 - s, nu, nq);
+                    neighbour_trace<T, DIM, P>(a, fe[sub], k, 1 - s, nu, nq);
 #pragma unroll
                     for (int g = 0; g < NF; g++) {
                         const T jmp = ou[g] - nu[g];
@@ -337,11 +408,10 @@ __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> a)
 
     // pointwise reaction, stimulus and update
     T *uo = a.u + (long long)(cur ^ 1) * a.slot_stride + j;
-    T *vp = a.v + j;
 #pragma unroll
     for (int n = 0; n < NP; n++) {
         const T un = u[n];
-        const T vn = vp[(long long)n * a.cap];
+        const T vn = vv[n];
         T stim = 0;
         if (a.n_stim > 0) {
             double X[3];

@@ -452,6 +452,12 @@ struct mdlts_sim {
     long long n_since_assign = 0;
     uint64_t dof_updates = 0;
     std::vector<double> eta_host;
+    // optional event timing of every substep launch
+    bool prof = false;
+    std::vector<hipEvent_t> ev;  // pairs: start, stop
+    size_t ev_used = 0;          // pairs recorded and not yet read
+    double prof_ms = 0.0;
+    uint64_t prof_launches = 0, prof_dof = 0;
 };
 
 namespace {
@@ -657,6 +663,21 @@ void launch_substep(const StepArgs<T> &a, hipStream_t st)
     k_substep<DIM, P_, T><<<nblocks(a.n_act), kBlock, 0, st>>>(a);
 }
 
+mdlts_status drain_events(mdlts_sim *s)
+{
+    if (s->ev_used == 0) return MDLTS_OK;
+    HIP_TRY(hipEventSynchronize(s->ev[2 * s->ev_used - 1]));
+    for (size_t q = 0; q < s->ev_used; q++) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, s->ev[2 * q], s->ev[2 * q + 1]));
+        s->prof_ms += ms;
+    }
+    s->ev_used = 0;
+    return MDLTS_OK;
+}
+
+constexpr size_t kMaxEventPairs = 4096;
+
 template <typename T>
 mdlts_status run_barriers(mdlts_sim *s, int n_barriers)
 {
@@ -704,6 +725,15 @@ mdlts_status run_barriers(mdlts_sim *s, int n_barriers)
                     q[6] = b.t_on; q[7] = b.t_off; q[8] = b.amp;
                 }
             if (a.n_act == 0) continue;
+            if (s->prof) {
+                if (s->ev_used == kMaxEventPairs) MD_TRY(drain_events(s));
+                while (s->ev.size() < 2 * (s->ev_used + 1)) {
+                    hipEvent_t e;
+                    HIP_TRY(hipEventCreate(&e));
+                    s->ev.push_back(e);
+                }
+                HIP_TRY(hipEventRecord(s->ev[2 * s->ev_used], st));
+            }
             const int key = s->desc.dim * 10 + s->desc.order;
             switch (key) {
             case 21: launch_substep<2, 1, T>(a, st); break;
@@ -713,6 +743,12 @@ mdlts_status run_barriers(mdlts_sim *s, int n_barriers)
             default: return MDLTS_EINVAL;
             }
             s->dof_updates += (uint64_t)a.n_act * (uint64_t)s->np;
+            if (s->prof) {
+                HIP_TRY(hipEventRecord(s->ev[2 * s->ev_used + 1], st));
+                s->ev_used++;
+                s->prof_launches++;
+                s->prof_dof += (uint64_t)a.n_act * (uint64_t)s->np;
+            }
         }
         HIP_TRY(hipGetLastError());
         s->n_bar++;
@@ -890,6 +926,7 @@ mdlts_status mdlts_sim_destroy(mdlts_sim *s)
     mdlts_status st = MDLTS_OK;
     for (DevBuf *b : bufs)
         if (dev_free(c, *b) != MDLTS_OK) st = MDLTS_EDEVICE;
+    for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
     c->n_sims--;
     delete s;
     return st;
@@ -1184,6 +1221,28 @@ mdlts_status mdlts_counters(mdlts_sim *s, uint64_t *dof_updates, double *t_sim)
     if (!s) return MDLTS_EINVAL;
     if (dof_updates) *dof_updates = s->dof_updates;
     if (t_sim) *t_sim = s->t_start + (double)s->n_bar * s->dt_bar;
+    return MDLTS_OK;
+}
+
+mdlts_status mdlts_profile(mdlts_sim *s, int enable)
+{
+    if (!s) return MDLTS_EINVAL;
+    MD_TRY(drain_events(s));
+    s->prof = enable != 0;
+    s->prof_ms = 0.0;
+    s->prof_launches = s->prof_dof = 0;
+    return MDLTS_OK;
+}
+
+mdlts_status mdlts_profile_read(mdlts_sim *s, double *substep_ms, uint64_t *n_launches, uint64_t *dof_updates)
+{
+    if (!s) return MDLTS_EINVAL;
+    MD_TRY(drain_events(s));
+    if (substep_ms) *substep_ms = s->prof_ms;
+    if (n_launches) *n_launches = s->prof_launches;
+    if (dof_updates) *dof_updates = s->prof_dof;
+    s->prof_ms = 0.0;
+    s->prof_launches = s->prof_dof = 0;
     return MDLTS_OK;
 }
 

@@ -27,9 +27,12 @@ WORKLOADS = {
     "plain_small": dict(dim=2, p=1, n=(64, 64, 1), length=(1.0, 1.0, 1.0), max_depth=0,
                         n_levels=1, D=(1e-3, 1e-3, 1e-3), gamma=2.0, dt=0.01, t_end=10.0,
                         stim=[((0.0, 0.0, 0.0), (0.1, 0.1, 1.0), 0.0, 1.0, 1.0)], fp="f64"),
+    # thresholds from oracle/calibrate_thresholds.py (plane front, tau_coarsen =
+    # tau_refine/16); 32 barriers per adaptation let the front (0.044 cm/ms)
+    # cross under half a finest element between adaptations
     "amr_2d": dict(dim=2, p=1, n=(256, 256, 1), length=(2.0, 2.0, 1.0), max_depth=3, n_levels=4,
                    D=(1e-3, 1e-3, 1e-3), gamma=2.0, t_end=50.0, stim_size=0.1, stim_dur=1.0,
-                   tau_refine=None, tau_coarsen=None, fp="f32"),
+                   tau_refine=1.42e-9, tau_coarsen=1.42e-9 / 16, amr_every=32, fp="f32"),
     "amr_3d": dict(dim=3, p=2, n=(128, 48, 24), length=(2.0, 0.7, 0.3), max_depth=3, n_levels=4,
                    D=(1.3e-3, 0.33e-3, 0.33e-3), gamma=4.0, t_end=40.0,
                    stim=[((0.0, 0.0, 0.0), (0.1, 0.1, 0.1), 0.0, 1.0, 1.0)], fp="f32"),

@@ -87,6 +87,8 @@ def lib():
         "mdlts_indicator": (I, [P, P, S, P]),
         "mdlts_adapt": (I, [P, P, S, D, D, P, P]),
         "mdlts_counters": (I, [P, P, P]),
+        "mdlts_profile": (I, [P, I]),
+        "mdlts_profile_read": (I, [P, P, P, P]),
         "mdlts_cfl_bound": (I, [P, P, D, I, P]),
         "mdlts_plan_adapt": (I, [P, P, S, P, S, D, D, P, S, P]),
         "mdlts_plan_levels": (I, [P, P, S, P, D, D, P, P, P, P, S]),
@@ -329,6 +331,17 @@ class Simulation:
                                    ctypes.byref(nc))
         _chk(st, "mdlts_adapt")
         return nr.value, nc.value
+
+    def profile(self, enable=True):
+        _chk(lib().mdlts_profile(self.h, 1 if enable else 0), "mdlts_profile")
+
+    def profile_read(self):
+        """(substep kernel ms, launches, DoF-updates) since the last read."""
+        ms = ctypes.c_double()
+        nl, nd = ctypes.c_uint64(), ctypes.c_uint64()
+        _chk(lib().mdlts_profile_read(self.h, ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(nd)),
+             "mdlts_profile_read")
+        return ms.value, nl.value, nd.value
 
     def counters(self):
         n = ctypes.c_uint64()
