@@ -159,7 +159,9 @@ mdlts_status mdlts_indicator(mdlts_sim *sim, double *eta, size_t n_leaves, doubl
  * children all have eta <= tau_coarsen (when that keeps 2:1 balance), and
  * transfers u and v (prolongation by evaluation, restriction by L2
  * projection).  eta: [n_leaves] canonical order, or NULL to use the last
- * mdlts_indicator result.  Levels must be assigned again afterwards. */
+ * mdlts_indicator result (ESTATE if the state or forest changed since).
+ * Runs on the device; the host reads back only the new leaf count.  Levels
+ * must be assigned again afterwards. */
 mdlts_status mdlts_adapt(mdlts_sim *sim, const double *eta, size_t n_leaves, double tau_refine,
                          double tau_coarsen, int64_t *n_refined, int64_t *n_coarsened);
 

@@ -7,7 +7,9 @@
 //   v      [np][cap]           gate state (element-local, updated in place)
 //   key    [cap]               packed depth + cell coordinates (2-D: 32 bit)
 //   nbr    [2d][cap]           packed face entries: kind(2) | level(3) | id(27)
-//   fine   [groups][2^(d-1)]   entries of the fine neighbours of a face
+//                              (same-size or coarser neighbour)
+//   fine   [2d][cap][2^(d-1)]  entries (level | id) of the finer neighbours
+//                              of a face whose entry has kind "finer"
 // Element threads read their own nodes with unit stride across the wave
 // (coalesced), and gather neighbour nodes through the face entries.
 #pragma once
@@ -369,7 +371,6 @@ __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> a)
                     Hl[g] = (T)0.5 * jmp;
                 }
             } else {
-                const uint32_t grp = ent[f] & kIdMask27;
                 const T hn = (T)0.5 * hk;
                 const T sigma = a.gamma * (T)0.5 * (Dkk / hk + Dkk / hn);
                 const T qn = ns * Dkk * ((T)2 / hn);
@@ -377,7 +378,7 @@ __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> a)
                 for (int g = 0; g < NF; g++) { Fl[g] = 0; Hl[g] = 0; }
                 uint32_t fe[NS];
 #pragma unroll
-                for (int sub = 0; sub < NS; sub++) fe[sub] = a.fine[(long long)grp * NS + sub];
+                for (int sub = 0; sub < NS; sub++) fe[sub] = a.fine[((long long)f * a.cap + j) * NS + sub];
 #pragma unroll
                 for (int sub = 0; sub < NS; sub++) {
                     const int p0 = sub & 1, p1 = sub >> 1;

@@ -9,6 +9,7 @@
 #include <new>
 #include <vector>
 
+#include "amr.hpp"
 #include "host.hpp"
 #include "kernels.hpp"
 #include "mdlts.h"
@@ -151,10 +152,11 @@ __global__ __launch_bounds__(kBlock) void k_level_scatter(const uint8_t *level, 
     }
 }
 
-template <typename KT>
+template <typename KT, int NS>
 __global__ __launch_bounds__(kBlock) void k_remap(int E, int nfaces, const int *perm, const int *inv,
                                                   const uint8_t *level, const KT *key_c, const uint32_t *face_c,
-                                                  KT *key_s, uint32_t *nbr_s, int cap)
+                                                  const uint32_t *fine_c, KT *key_s, uint32_t *nbr_s,
+                                                  uint32_t *fine_s, int cap)
 {
     const int j = blockIdx.x * kBlock + threadIdx.x;
     if (j >= E) return;
@@ -168,19 +170,13 @@ __global__ __launch_bounds__(kBlock) void k_remap(int E, int nfaces, const int *
             const uint32_t n = ent & kIdMask30;
             out |= ((uint32_t)level[n] << 27) | (uint32_t)inv[n];
         } else if (kind == kFiner) {
-            out |= ent & kIdMask30;
+            for (int q = 0; q < NS; q++) {
+                const uint32_t n = fine_c[((long long)f * E + e) * NS + q];
+                fine_s[((long long)f * cap + j) * NS + q] = ((uint32_t)level[n] << 27) | (uint32_t)inv[n];
+            }
         }
         nbr_s[(long long)f * cap + j] = out;
     }
-}
-
-__global__ __launch_bounds__(kBlock) void k_remap_fine(int n, const uint32_t *fine_c, const int *inv,
-                                                       const uint8_t *level, uint32_t *fine_s)
-{
-    const int q = blockIdx.x * kBlock + threadIdx.x;
-    if (q >= n) return;
-    const uint32_t e = fine_c[q];
-    fine_s[q] = ((uint32_t)level[e] << 27) | (uint32_t)inv[e];
 }
 
 // canonical [np][E] -> grouped slot 0 [np][cap]
@@ -327,14 +323,13 @@ __global__ __launch_bounds__(kBlock) void k_indicator(const IndArgs a)
                     const double hF = DIM == 2 ? area : sqrt(area);
                     acc += hF / (2.0 * a.p) * area * area * integral;
                 } else {
-                    const uint32_t grp = ent & kIdMask30;
                     const double sarea = DIM == 2 ? 0.5 * area : 0.25 * area;
                     const double hF = DIM == 2 ? sarea : sqrt(sarea);
                     const double qn = ns * a.Dk[k] * 2.0 / (0.5 * h[k]);
                     for (int sub = 0; sub < NS; sub++) {
                         double oq[NF], nu[NF], nq[NF];
                         tang_apply<double, DIM, M>(a.ref.Isub, sub & 1, sub >> 1, tq, oq);
-                        canon_trace<DIM, P, T>(a, a.fine[(long long)grp * NS + sub], k, 1 - s, nu, nq);
+                        canon_trace<DIM, P, T>(a, a.fine[((long long)(2 * k + s) * a.E + e) * NS + sub], k, 1 - s, nu, nq);
                         double integral = 0.0;
                         for (int g = 0; g < NF; g++) {
                             const double jmp = qs * oq[g] - qn * nq[g];
@@ -429,7 +424,9 @@ struct mdlts_sim {
     mdlts_mesh_desc desc{};
     int np = 0;
     size_t tsize = 8;  // bytes of the bulk precision
-    Forest forest;
+    Forest forest;                 // host mirror of the leaves (lazily refreshed)
+    bool host_forest_valid = true;
+    size_t E = 0;                  // number of leaves
     RefTables ref{};
     double h0[3] = {1, 1, 1};
     double Dk[3] = {1e-3, 1e-3, 1e-3};
@@ -441,6 +438,8 @@ struct mdlts_sim {
     DevBuf key_c, face_c, fine_c, u_c, v_c, level_c, cfl_c, eta_c, tmp_u, tmp_v;
     // grouped device data
     DevBuf u_s, v_s, key_s, nbr_s, fine_s, perm, inv, hist, cnt_ge_d, flags, xk, xs, xc, stage;
+    // device mesh management
+    DevBuf root_start, mkey, refine, cflag, cnt, off, bsums, key_n;
     int cap = 0;
     bool state_grouped = false;  // else canonical
     bool levels_valid = false;
@@ -451,7 +450,7 @@ struct mdlts_sim {
     long long n_bar = 0;  // barriers since t_start (time bookkeeping)
     long long n_since_assign = 0;
     uint64_t dof_updates = 0;
-    std::vector<double> eta_host;
+    bool eta_valid = false;  // eta_c holds the indicator of the current forest
     // optional event timing of every substep launch
     bool prof = false;
     std::vector<hipEvent_t> ev;  // pairs: start, stop
@@ -569,30 +568,109 @@ mdlts_status copy_h2d(mdlts_ctx *c, DevBuf &b, const T *src, size_t n)
     return MDLTS_OK;
 }
 
-// upload the canonical geometry and face tables of the forest
+MeshGeo geo_of(const mdlts_sim *s)
+{
+    MeshGeo g;
+    for (int k = 0; k < 3; k++) g.n[k] = s->desc.n[k];
+    g.max_depth = s->desc.max_depth;
+    return g;
+}
+
+int n_sub(const mdlts_sim *s) { return s->desc.dim == 2 ? 2 : 4; }
+
+// face tables of the canonical leaves in key_c, built on the device
+mdlts_status device_faces(mdlts_sim *s)
+{
+    mdlts_ctx *c = s->ctx;
+    const int E = (int)s->E;
+    const int dim = s->desc.dim;
+    const int n_roots = s->desc.n[0] * s->desc.n[1] * (dim == 3 ? s->desc.n[2] : 1);
+    MD_TRY(dev_alloc(c, s->root_start, (size_t)(n_roots + 1) * sizeof(int)));
+    MD_TRY(dev_alloc(c, s->mkey, (size_t)E * sizeof(uint32_t)));
+    MD_TRY(dev_alloc(c, s->face_c, (size_t)2 * dim * E * sizeof(uint32_t)));
+    MD_TRY(dev_alloc(c, s->fine_c, (size_t)2 * dim * E * n_sub(s) * sizeof(uint32_t)));
+    MD_TRY(dev_alloc(c, s->flags, 64));
+    HIP_TRY(hipMemsetAsync(s->flags.p, 0, 64, c->stream));
+    const MeshGeo g = geo_of(s);
+    if (dim == 2) {
+        k_mesh_index<2><<<nblocks(E), kBlock, 0, c->stream>>>(E, n_roots, g, P<uint32_t>(s->key_c),
+                                                               P<int>(s->root_start), P<uint32_t>(s->mkey));
+        k_mesh_faces<2><<<nblocks(E), kBlock, 0, c->stream>>>(E, g, P<uint32_t>(s->key_c), P<int>(s->root_start),
+                                                               P<uint32_t>(s->mkey), P<uint32_t>(s->face_c),
+                                                               P<uint32_t>(s->fine_c), P<int>(s->flags));
+    } else {
+        k_mesh_index<3><<<nblocks(E), kBlock, 0, c->stream>>>(E, n_roots, g, P<uint64_t>(s->key_c),
+                                                               P<int>(s->root_start), P<uint32_t>(s->mkey));
+        k_mesh_faces<3><<<nblocks(E), kBlock, 0, c->stream>>>(E, g, P<uint64_t>(s->key_c), P<int>(s->root_start),
+                                                               P<uint32_t>(s->mkey), P<uint32_t>(s->face_c),
+                                                               P<uint32_t>(s->fine_c), P<int>(s->flags));
+    }
+    HIP_TRY(hipGetLastError());
+    int bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, s->flags.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    MD_TRY(sync(c));
+    return bad ? MDLTS_EINVAL : MDLTS_OK;
+}
+
+// upload the leaf keys of the host forest and build the face tables
 mdlts_status upload_forest(mdlts_sim *s)
 {
     mdlts_ctx *c = s->ctx;
     const Forest &F = s->forest;
     const size_t E = F.size();
+    s->E = E;
+    s->host_forest_valid = true;
     if (s->desc.dim == 2) {
         std::vector<uint32_t> key(E);
         for (size_t e = 0; e < E; e++) key[e] = pack_key<2>(F.leaves[e].depth, F.leaves[e].c);
         MD_TRY(copy_h2d(c, s->key_c, key.data(), E));
+        MD_TRY(sync(c));
     } else {
         std::vector<uint64_t> key(E);
         for (size_t e = 0; e < E; e++) key[e] = pack_key<3>(F.leaves[e].depth, F.leaves[e].c);
         MD_TRY(copy_h2d(c, s->key_c, key.data(), E));
+        MD_TRY(sync(c));
     }
-    MD_TRY(copy_h2d(c, s->face_c, F.face.data(), F.face.size()));
-    MD_TRY(copy_h2d(c, s->fine_c, F.fine.data(), F.fine.size()));
-    // host vectors die at return: wait for the copies
-    return sync(c);
+    return device_faces(s);
+}
+
+// refresh the host mirror of the leaves from the device keys
+mdlts_status refresh_host_forest(mdlts_sim *s)
+{
+    if (s->host_forest_valid) return MDLTS_OK;
+    mdlts_ctx *c = s->ctx;
+    const size_t E = s->E;
+    Forest &F = s->forest;
+    forest_from_desc(&s->desc, F);
+    F.leaves.resize(E);
+    if (s->desc.dim == 2) {
+        std::vector<uint32_t> key(E);
+        HIP_TRY(hipMemcpyAsync(key.data(), s->key_c.p, E * 4, hipMemcpyDeviceToHost, c->stream));
+        MD_TRY(sync(c));
+        for (size_t e = 0; e < E; e++) {
+            F.leaves[e].depth = (uint8_t)(key[e] & 15);
+            F.leaves[e].c[0] = (key[e] >> 4) & 0x3fff;
+            F.leaves[e].c[1] = (key[e] >> 18) & 0x3fff;
+            F.leaves[e].c[2] = 0;
+        }
+    } else {
+        std::vector<uint64_t> key(E);
+        HIP_TRY(hipMemcpyAsync(key.data(), s->key_c.p, E * 8, hipMemcpyDeviceToHost, c->stream));
+        MD_TRY(sync(c));
+        for (size_t e = 0; e < E; e++) {
+            F.leaves[e].depth = (uint8_t)(key[e] & 15);
+            for (int k = 0; k < 3; k++) F.leaves[e].c[k] = (uint32_t)((key[e] >> (4 + 20 * k)) & 0xfffff);
+        }
+    }
+    F.face.clear();
+    F.fine.clear();
+    s->host_forest_valid = true;
+    return MDLTS_OK;
 }
 
 mdlts_status alloc_canonical_state(mdlts_sim *s)
 {
-    const size_t n = (size_t)s->forest.size() * s->np * s->tsize;
+    const size_t n = (size_t)s->E * s->np * s->tsize;
     MD_TRY(dev_alloc(s->ctx, s->u_c, n));
     MD_TRY(dev_alloc(s->ctx, s->v_c, n));
     return MDLTS_OK;
@@ -601,7 +679,7 @@ mdlts_status alloc_canonical_state(mdlts_sim *s)
 mdlts_status zero_canonical_state(mdlts_sim *s)
 {
     MD_TRY(alloc_canonical_state(s));
-    const size_t n = (size_t)s->forest.size() * s->np * s->tsize;
+    const size_t n = (size_t)s->E * s->np * s->tsize;
     HIP_TRY(hipMemsetAsync(s->u_c.p, 0, n, s->ctx->stream));
     HIP_TRY(hipMemsetAsync(s->v_c.p, 0, n, s->ctx->stream));
     s->state_grouped = false;
@@ -612,7 +690,7 @@ mdlts_status zero_canonical_state(mdlts_sim *s)
 mdlts_status to_canonical(mdlts_sim *s)
 {
     if (!s->state_grouped) return MDLTS_OK;
-    const int E = (int)s->forest.size();
+    const int E = (int)s->E;
     MD_TRY(alloc_canonical_state(s));
     const long long stride = (long long)s->np * s->cap;
     const int parity = (int)(s->n_since_assign & 1);
@@ -634,7 +712,7 @@ mdlts_status to_canonical(mdlts_sim *s)
 // canonical -> grouped slot 0 (after a level assignment)
 mdlts_status to_grouped(mdlts_sim *s)
 {
-    const int E = (int)s->forest.size();
+    const int E = (int)s->E;
     if (s->desc.precision == MDLTS_FP64)
         k_permute<double><<<nblocks(E), kBlock, 0, s->ctx->stream>>>(E, s->np, s->cap, P<int>(s->perm),
                                                                       P<double>(s->u_c), P<double>(s->v_c),
@@ -653,6 +731,7 @@ mdlts_status set_forest(mdlts_sim *s, Forest &&F)
 {
     s->forest = std::move(F);
     s->levels_valid = false;
+    s->eta_valid = false;
     return upload_forest(s);
 }
 
@@ -762,7 +841,7 @@ mdlts_status run_indicator(mdlts_sim *s, unsigned long long *max_bits, int *nonf
 {
     IndArgs a;
     std::memset(&a, 0, sizeof(a));
-    const int E = (int)s->forest.size();
+    const int E = (int)s->E;
     a.u = s->u_c.p;
     a.key = s->key_c.p;
     a.face = P<uint32_t>(s->face_c);
@@ -786,14 +865,12 @@ mdlts_status run_indicator(mdlts_sim *s, unsigned long long *max_bits, int *nonf
     return MDLTS_OK;
 }
 
+// new canonical state from the old one through the device transfer map
+// (xk: 0 copy, 1 prolong from the parent, 2 restrict from 2^d children)
 template <typename T>
-mdlts_status run_transfer(mdlts_sim *s, const AdaptPlan &plan, int E_old)
+mdlts_status run_transfer(mdlts_sim *s, int E_old, int E_new)
 {
     mdlts_ctx *c = s->ctx;
-    const int E_new = (int)plan.next.size();
-    MD_TRY(copy_h2d(c, s->xk, plan.kind.data(), plan.kind.size()));
-    MD_TRY(copy_h2d(c, s->xs, plan.src.data(), plan.src.size()));
-    MD_TRY(copy_h2d(c, s->xc, plan.child.data(), plan.child.size()));
     const size_t bytes = (size_t)E_new * s->np * sizeof(T);
     MD_TRY(dev_alloc(c, s->tmp_u, bytes));
     MD_TRY(dev_alloc(c, s->tmp_v, bytes));
@@ -820,7 +897,67 @@ mdlts_status run_transfer(mdlts_sim *s, const AdaptPlan &plan, int E_old)
     HIP_TRY(hipGetLastError());
     std::swap(s->u_c, s->tmp_u);
     std::swap(s->v_c, s->tmp_v);
-    return sync(c);  // the host plan vectors are freed by the caller
+    return MDLTS_OK;
+}
+
+// Algorithm 1's adaptation on the device: mark (eta >= tau_refine), close
+// the 2:1 balance, flag coarsenable sibling groups, count and scan the new
+// leaves, emit keys and the transfer map, transfer u and v, rebuild faces.
+template <int DIM>
+mdlts_status device_adapt(mdlts_sim *s, double tau_refine, double tau_coarsen, int64_t *n_refined,
+                          int64_t *n_coarsened)
+{
+    using KT = typename KeyOf<DIM>::type;
+    mdlts_ctx *c = s->ctx;
+    hipStream_t st = c->stream;
+    const int E = (int)s->E;
+    const int nb = nblocks(E);
+    const int nb4 = (E + 1023) / 1024;
+    MD_TRY(dev_alloc(c, s->refine, (size_t)E));
+    MD_TRY(dev_alloc(c, s->cflag, (size_t)E));
+    MD_TRY(dev_alloc(c, s->cnt, (size_t)E * sizeof(int)));
+    MD_TRY(dev_alloc(c, s->off, (size_t)E * sizeof(int)));
+    MD_TRY(dev_alloc(c, s->bsums, (size_t)(nb4 + 1) * sizeof(int)));
+    MD_TRY(dev_alloc(c, s->flags, 64));
+    HIP_TRY(hipMemsetAsync(s->flags.p, 0, 64, st));
+    unsigned long long *tallies = reinterpret_cast<unsigned long long *>(static_cast<char *>(s->flags.p) + 8);
+    int *total = reinterpret_cast<int *>(static_cast<char *>(s->flags.p) + 32);
+    const MeshGeo g = geo_of(s);
+    const KT *key = P<KT>(s->key_c);
+    k_amr_mark<DIM><<<nb, kBlock, 0, st>>>(E, g, key, P<double>(s->eta_c), tau_refine, P<uint8_t>(s->refine));
+    for (int pass = 0; pass < s->desc.max_depth; pass++)
+        k_amr_close<DIM><<<nb, kBlock, 0, st>>>(E, P<uint32_t>(s->face_c), P<uint8_t>(s->refine));
+    k_amr_coarsen<DIM><<<nb, kBlock, 0, st>>>(E, key, P<double>(s->eta_c), tau_coarsen, P<uint8_t>(s->refine),
+                                               P<uint32_t>(s->face_c), P<uint8_t>(s->cflag));
+    k_amr_count<DIM><<<nb, kBlock, 0, st>>>(E, key, P<uint8_t>(s->refine), P<uint8_t>(s->cflag), P<int>(s->cnt),
+                                             tallies);
+    k_scan_local<<<nb4, kBlock, 0, st>>>(E, P<int>(s->cnt), P<int>(s->off), P<int>(s->bsums));
+    k_scan_sums<<<1, kBlock, 0, st>>>(nb4, P<int>(s->bsums), total);
+    k_scan_add<<<nb4, kBlock, 0, st>>>(E, P<int>(s->off), P<int>(s->bsums));
+    HIP_TRY(hipGetLastError());
+    struct { unsigned long long t[3]; int total; } rb{};
+    HIP_TRY(hipMemcpyAsync(&rb, static_cast<char *>(s->flags.p) + 8, 28, hipMemcpyDeviceToHost, st));
+    MD_TRY(sync(c));
+    const int E_new = rb.total;
+    if (E_new <= 0 || E_new >= (1 << 27)) return MDLTS_EINVAL;
+    MD_TRY(dev_alloc(c, s->key_n, (size_t)E_new * sizeof(KT)));
+    MD_TRY(dev_alloc(c, s->xk, (size_t)E_new));
+    MD_TRY(dev_alloc(c, s->xs, (size_t)E_new * sizeof(int32_t)));
+    MD_TRY(dev_alloc(c, s->xc, (size_t)E_new));
+    k_amr_emit<DIM><<<nb, kBlock, 0, st>>>(E, key, P<uint8_t>(s->refine), P<uint8_t>(s->cflag), P<int>(s->cnt),
+                                            P<int>(s->off), P<KT>(s->key_n), P<uint8_t>(s->xk), P<int32_t>(s->xs),
+                                            P<uint8_t>(s->xc));
+    HIP_TRY(hipGetLastError());
+    if (s->desc.precision == MDLTS_FP64) MD_TRY(run_transfer<double>(s, E, E_new));
+    else MD_TRY(run_transfer<float>(s, E, E_new));
+    std::swap(s->key_c, s->key_n);
+    s->E = (size_t)E_new;
+    s->host_forest_valid = false;
+    s->levels_valid = false;
+    s->eta_valid = false;
+    if (n_refined) *n_refined = (int64_t)rb.t[0];
+    if (n_coarsened) *n_coarsened = (int64_t)rb.t[1];
+    return device_faces(s);  // synchronises
 }
 
 mdlts_status compute_G(mdlts_sim *s)
@@ -922,7 +1059,8 @@ mdlts_status mdlts_sim_destroy(mdlts_sim *s)
     (void)hipStreamSynchronize(c->stream);
     DevBuf *bufs[] = {&s->key_c, &s->face_c, &s->fine_c, &s->u_c, &s->v_c, &s->level_c, &s->cfl_c, &s->eta_c,
                       &s->tmp_u, &s->tmp_v, &s->u_s, &s->v_s, &s->key_s, &s->nbr_s, &s->fine_s, &s->perm,
-                      &s->inv, &s->hist, &s->cnt_ge_d, &s->flags, &s->xk, &s->xs, &s->xc, &s->stage};
+                      &s->inv, &s->hist, &s->cnt_ge_d, &s->flags, &s->xk, &s->xs, &s->xc, &s->stage,
+                      &s->root_start, &s->mkey, &s->refine, &s->cflag, &s->cnt, &s->off, &s->bsums, &s->key_n};
     mdlts_status st = MDLTS_OK;
     for (DevBuf *b : bufs)
         if (dev_free(c, *b) != MDLTS_OK) st = MDLTS_EDEVICE;
@@ -946,6 +1084,7 @@ mdlts_status mdlts_set_tree(mdlts_sim *s, const uint8_t *bits, size_t n_bits)
 mdlts_status mdlts_get_tree(mdlts_sim *s, uint8_t *bits, size_t cap, size_t *n_bits)
 {
     if (!s || !n_bits) return MDLTS_EINVAL;
+    MD_TRY(refresh_host_forest(s));
     std::vector<uint8_t> out;
     s->forest.write_bits(out);
     *n_bits = out.size();
@@ -956,7 +1095,7 @@ mdlts_status mdlts_get_tree(mdlts_sim *s, uint8_t *bits, size_t cap, size_t *n_b
 mdlts_status mdlts_n_leaves(mdlts_sim *s, size_t *n)
 {
     if (!s || !n) return MDLTS_EINVAL;
-    *n = s->forest.size();
+    *n = s->E;
     return MDLTS_OK;
 }
 
@@ -991,9 +1130,10 @@ mdlts_status mdlts_set_stimulus(mdlts_sim *s, const mdlts_stim_box *boxes, int n
 mdlts_status mdlts_set_state(mdlts_sim *s, const double *u, const double *v, size_t n_dof)
 {
     if (!s) return MDLTS_EINVAL;
-    const size_t E = s->forest.size();
+    const size_t E = s->E;
     if (n_dof != E * (size_t)s->np) return MDLTS_EINVAL;
     mdlts_ctx *c = s->ctx;
+    s->eta_valid = false;
     MD_TRY(to_canonical(s));
     MD_TRY(dev_alloc(c, s->stage, n_dof * sizeof(double)));
     const double *src[2] = {u, v};
@@ -1017,7 +1157,7 @@ mdlts_status mdlts_set_state(mdlts_sim *s, const double *u, const double *v, siz
 mdlts_status mdlts_get_state(mdlts_sim *s, double *u, double *v, size_t n_dof)
 {
     if (!s) return MDLTS_EINVAL;
-    const size_t E = s->forest.size();
+    const size_t E = s->E;
     if (n_dof != E * (size_t)s->np) return MDLTS_EINVAL;
     mdlts_ctx *c = s->ctx;
     const bool was_grouped = s->state_grouped;
@@ -1054,7 +1194,7 @@ mdlts_status mdlts_assign_levels(mdlts_sim *s, double dt_barrier, int32_t *level
 {
     if (!s || !(dt_barrier > 0.0) || !std::isfinite(dt_barrier)) return MDLTS_EINVAL;
     mdlts_ctx *c = s->ctx;
-    const int E = (int)s->forest.size();
+    const int E = (int)s->E;
     const int L = s->desc.n_levels;
     const int nb = nblocks(E);
     MD_TRY(to_canonical(s));
@@ -1099,19 +1239,19 @@ mdlts_status mdlts_assign_levels(mdlts_sim *s, double dt_barrier, int32_t *level
     const size_t ksz = s->desc.dim == 2 ? 4 : 8;
     MD_TRY(dev_alloc(c, s->key_s, (size_t)s->cap * ksz));
     MD_TRY(dev_alloc(c, s->nbr_s, (size_t)s->cap * 2 * s->desc.dim * sizeof(uint32_t)));
-    MD_TRY(dev_alloc(c, s->fine_s, std::max<size_t>(1, s->forest.fine.size()) * sizeof(uint32_t)));
+    MD_TRY(dev_alloc(c, s->fine_s, (size_t)s->cap * 2 * s->desc.dim * n_sub(s) * sizeof(uint32_t)));
     if (s->desc.dim == 2)
-        k_remap<uint32_t><<<nb, kBlock, 0, c->stream>>>(E, 4, P<int>(s->perm), P<int>(s->inv), P<uint8_t>(s->level_c),
-                                                         P<uint32_t>(s->key_c), P<uint32_t>(s->face_c),
-                                                         P<uint32_t>(s->key_s), P<uint32_t>(s->nbr_s), s->cap);
+        k_remap<uint32_t, 2><<<nb, kBlock, 0, c->stream>>>(E, 4, P<int>(s->perm), P<int>(s->inv),
+                                                            P<uint8_t>(s->level_c), P<uint32_t>(s->key_c),
+                                                            P<uint32_t>(s->face_c), P<uint32_t>(s->fine_c),
+                                                            P<uint32_t>(s->key_s), P<uint32_t>(s->nbr_s),
+                                                            P<uint32_t>(s->fine_s), s->cap);
     else
-        k_remap<uint64_t><<<nb, kBlock, 0, c->stream>>>(E, 6, P<int>(s->perm), P<int>(s->inv), P<uint8_t>(s->level_c),
-                                                         P<uint64_t>(s->key_c), P<uint32_t>(s->face_c),
-                                                         P<uint64_t>(s->key_s), P<uint32_t>(s->nbr_s), s->cap);
-    const int nfine = (int)s->forest.fine.size();
-    if (nfine)
-        k_remap_fine<<<nblocks(nfine), kBlock, 0, c->stream>>>(nfine, P<uint32_t>(s->fine_c), P<int>(s->inv),
-                                                                P<uint8_t>(s->level_c), P<uint32_t>(s->fine_s));
+        k_remap<uint64_t, 4><<<nb, kBlock, 0, c->stream>>>(E, 6, P<int>(s->perm), P<int>(s->inv),
+                                                            P<uint8_t>(s->level_c), P<uint64_t>(s->key_c),
+                                                            P<uint32_t>(s->face_c), P<uint32_t>(s->fine_c),
+                                                            P<uint64_t>(s->key_s), P<uint32_t>(s->nbr_s),
+                                                            P<uint32_t>(s->fine_s), s->cap);
     const size_t sbytes = (size_t)s->cap * s->np * s->tsize;
     MD_TRY(dev_alloc(c, s->u_s, 2 * sbytes));
     MD_TRY(dev_alloc(c, s->v_s, sbytes));
@@ -1139,7 +1279,7 @@ mdlts_status mdlts_get_levels(mdlts_sim *s, int8_t *level, int32_t *perm, int32_
 {
     if (!s) return MDLTS_EINVAL;
     if (!s->levels_valid) return MDLTS_ESTATE;
-    if (n_leaves != s->forest.size()) return MDLTS_EINVAL;
+    if (n_leaves != s->E) return MDLTS_EINVAL;
     mdlts_ctx *c = s->ctx;
     if (level) HIP_TRY(hipMemcpyAsync(level, s->level_c.p, n_leaves, hipMemcpyDeviceToHost, c->stream));
     if (perm) HIP_TRY(hipMemcpyAsync(perm, s->perm.p, n_leaves * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
@@ -1152,7 +1292,7 @@ mdlts_status mdlts_get_cfl(mdlts_sim *s, double *cfl, size_t n_leaves)
 {
     if (!s || !cfl) return MDLTS_EINVAL;
     if (!s->levels_valid) return MDLTS_ESTATE;
-    if (n_leaves != s->forest.size()) return MDLTS_EINVAL;
+    if (n_leaves != s->E) return MDLTS_EINVAL;
     HIP_TRY(hipMemcpyAsync(cfl, s->cfl_c.p, n_leaves * sizeof(double), hipMemcpyDeviceToHost, s->ctx->stream));
     return sync(s->ctx);
 }
@@ -1161,6 +1301,7 @@ mdlts_status mdlts_step(mdlts_sim *s, int n_barriers)
 {
     if (!s || n_barriers < 0) return MDLTS_EINVAL;
     if (!s->levels_valid || !s->state_grouped) return MDLTS_ESTATE;
+    s->eta_valid = false;
     if (s->desc.precision == MDLTS_FP64) return run_barriers<double>(s, n_barriers);
     return run_barriers<float>(s, n_barriers);
 }
@@ -1168,7 +1309,7 @@ mdlts_status mdlts_step(mdlts_sim *s, int n_barriers)
 mdlts_status mdlts_indicator(mdlts_sim *s, double *eta, size_t n_leaves, double *eta_max)
 {
     if (!s) return MDLTS_EINVAL;
-    const size_t E = s->forest.size();
+    const size_t E = s->E;
     if (eta && n_leaves != E) return MDLTS_EINVAL;
     mdlts_ctx *c = s->ctx;
     const bool was_grouped = s->state_grouped;
@@ -1180,14 +1321,13 @@ mdlts_status mdlts_indicator(mdlts_sim *s, double *eta, size_t n_leaves, double 
     int *nonf = reinterpret_cast<int *>(static_cast<char *>(s->flags.p) + 16);
     if (s->desc.precision == MDLTS_FP64) MD_TRY(run_indicator<double>(s, maxb, nonf));
     else MD_TRY(run_indicator<float>(s, maxb, nonf));
-    s->eta_host.resize(E);
-    HIP_TRY(hipMemcpyAsync(s->eta_host.data(), s->eta_c.p, E * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (eta) HIP_TRY(hipMemcpyAsync(eta, s->eta_c.p, E * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     struct { unsigned long long m; int nf; } fl{};
     HIP_TRY(hipMemcpyAsync(&fl.m, maxb, 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(&fl.nf, nonf, 4, hipMemcpyDeviceToHost, c->stream));
     MD_TRY(sync(c));
     if (was_grouped) s->state_grouped = true;
-    if (eta) std::memcpy(eta, s->eta_host.data(), E * sizeof(double));
+    s->eta_valid = true;
     if (eta_max) {
         double m;
         std::memcpy(&m, &fl.m, 8);
@@ -1200,20 +1340,17 @@ mdlts_status mdlts_adapt(mdlts_sim *s, const double *eta, size_t n_leaves, doubl
                          int64_t *n_refined, int64_t *n_coarsened)
 {
     if (!s) return MDLTS_EINVAL;
-    const size_t E = s->forest.size();
+    const size_t E = s->E;
     if (eta && n_leaves != E) return MDLTS_EINVAL;
-    if (!eta && s->eta_host.size() != E) return MDLTS_ESTATE;
-    const double *ee = eta ? eta : s->eta_host.data();
-    AdaptPlan plan;
-    if (!plan_adapt(s->forest, ee, tau_refine, tau_coarsen, plan)) return MDLTS_EINVAL;
-    if (plan.next.size() >= (1u << 27)) return MDLTS_EINVAL;
+    if (!eta && !s->eta_valid) return MDLTS_ESTATE;
+    mdlts_ctx *c = s->ctx;
+    if (eta) {
+        MD_TRY(copy_h2d(c, s->eta_c, eta, E));
+        MD_TRY(sync(c));
+    }
     MD_TRY(to_canonical(s));
-    if (s->desc.precision == MDLTS_FP64) MD_TRY(run_transfer<double>(s, plan, (int)E));
-    else MD_TRY(run_transfer<float>(s, plan, (int)E));
-    if (n_refined) *n_refined = plan.n_refined;
-    if (n_coarsened) *n_coarsened = plan.n_coarsened;
-    s->eta_host.clear();
-    return set_forest(s, std::move(plan.next));
+    if (s->desc.dim == 2) return device_adapt<2>(s, tau_refine, tau_coarsen, n_refined, n_coarsened);
+    return device_adapt<3>(s, tau_refine, tau_coarsen, n_refined, n_coarsened);
 }
 
 mdlts_status mdlts_counters(mdlts_sim *s, uint64_t *dof_updates, double *t_sim)

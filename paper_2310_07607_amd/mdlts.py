@@ -314,9 +314,13 @@ class Simulation:
     def step(self, n_barriers=1):
         _chk(lib().mdlts_step(self.h, int(n_barriers)), "mdlts_step")
 
-    def indicator(self):
-        eta = np.zeros(self.n_leaves)
+    def indicator(self, download=True):
+        """(eta per leaf or None, max eta); the values stay on the device for adapt()."""
         m = ctypes.c_double()
+        if not download:
+            _chk(lib().mdlts_indicator(self.h, None, 0, ctypes.byref(m)), "mdlts_indicator")
+            return None, m.value
+        eta = np.zeros(self.n_leaves)
         _chk(lib().mdlts_indicator(self.h, _p(eta), eta.size, ctypes.byref(m)), "mdlts_indicator")
         return eta, m.value
 

@@ -188,3 +188,58 @@ def test_single_root_and_ragged_sizes(ctx):
         g.step(2)
         o.step_global(dt, 0.0, 2)
         assert rel_l2(g.get_state()[0], o.get_state()[0]) <= 1e-12
+
+
+def _gap_threshold(vals, lo_q, hi_q):
+    """A threshold in the widest gap of the sorted values between two quantiles."""
+    srt = np.sort(vals)
+    i0, i1 = max(1, int(lo_q * len(srt))), min(len(srt) - 1, int(hi_q * len(srt)))
+    i = max(range(i0, i1 + 1), key=lambda q: srt[q] - srt[q - 1])
+    return 0.5 * (srt[i] + srt[i - 1])
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_device_indicator_drives_device_adaptation(ctx, name):
+    o, g, u, v = _setup(ctx, name, "f64", 1, seed=6)
+    oeta = o.indicator()
+    tau_r = _gap_threshold(oeta, 0.75, 0.9)
+    tau_c = _gap_threshold(oeta, 0.2, 0.4)
+    _, emax = g.indicator(download=False)
+    assert emax == pytest.approx(oeta.max(), rel=1e-12)
+    nr, nc = g.adapt(tau_r, tau_c)
+    assert (nr, nc) == o.adapt(oeta, tau_r, tau_c)
+    assert np.array_equal(g.get_tree(), o.tree_bits())
+    gu, gv = g.get_state()
+    ou, ov = o.get_state()
+    assert rel_l2(gu, ou) <= 1e-13 and rel_l2(gv, ov) <= 1e-13
+
+
+@pytest.mark.parametrize("name", ["q1_2d", "q1_3d"])
+def test_repeated_adaptation_and_stepping(ctx, name):
+    from paper_2310_07607_amd import mdlts
+    o, g, u, v = _setup(ctx, name, "f64", 3, seed=7)
+    # a smooth physical state (rough random fields driven through several
+    # transfers and explicit steps leave the model's physical range)
+    X = o.leaf_nodes()
+    u = 0.5 + 0.45 * np.sin(8 * X[:, 0]) * np.cos(6 * X[:, 1])
+    v = 0.2 + 0.1 * np.cos(5 * X[:, 0])
+    o.set_state(u, v)
+    g.set_state(u, v)
+    for rnd in range(3):
+        eta = inputs.random_eta(70 + rnd, o.n_leaves, frac_hot=0.3)
+        assert g.adapt(0.5, 0.15, eta=eta) == o.adapt(eta, 0.5, 0.15)
+        assert np.array_equal(g.get_tree(), o.tree_bits())
+        assert g.n_leaves == o.n_leaves
+        dt = 4 * o.cfl().min() * (1 - 2 ** -20)
+        g.assign_levels(dt)
+        lv, _ = o.levels(dt, 3)
+        glv, _, _ = g.get_levels()
+        assert np.array_equal(glv, lv)
+        g.set_time(0.1 * rnd)
+        g.step(1)
+        o.lts_barrier(dt, 0.1 * rnd, lv)
+        assert rel_l2(g.get_state()[0], o.get_state()[0]) <= 1e-12
+    # the cached indicator is invalid after stepping
+    with pytest.raises(mdlts.MdltsError) as ei:
+        g.adapt(0.5, 0.15)
+    assert ei.value.status == mdlts.ESTATE
