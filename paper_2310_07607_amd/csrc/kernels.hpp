@@ -35,29 +35,38 @@ struct DevRef {
     double xi[kMaxM];
 };
 
+// Per-assignment constants of the substep kernel, kept in device memory
+// (kernel arguments carry only the per-launch values below).
 template <typename T>
 struct StepArgs {
+    long long slot_stride;
+    int cap;
+    int lmax;
+    int cnt_ge[kMaxLevels];
+    double dt_bar;
+    double h0[3];
+    T inv_h0[3];  // 1/h of a root; 1/h at depth d is inv_h0 * 2^d (exact)
+    T Dk[3];
+    T gamma;
+    T apk, apa, eps0, mu1, mu2;
+    int n_stim;  // all boxes; the kernel checks their time windows
+    double stim[kMaxStim][9];
+    DevRef<T> ref;
+};
+
+// Per-launch kernel arguments (passed by value, so the data pointers are
+// known to address global memory).
+template <typename T>
+struct StepLaunch {
     T *u;
     T *v;
     const void *key;
     const uint32_t *nbr;
     const uint32_t *fine;
-    long long slot_stride;
-    int cap;
-    int n_act;
-    int lmax;
-    int i;
-    int parity;
-    int cnt_ge[kMaxLevels];
-    double dt_bar;
-    double t_i;
-    double h0[3];
-    T Dk[3];
-    T gamma;
-    T apk, apa, eps0, mu1, mu2;
-    int n_stim;
-    double stim[kMaxStim][9];
-    DevRef<T> ref;
+    int i;       // substep index in the barrier interval
+    int n_act;   // active prefix
+    int parity;  // barriers since the level assignment, mod 2
+    double t_i;  // substep start time
 };
 
 template <int DIM>
@@ -160,17 +169,19 @@ __device__ __forceinline__ void tang_apply(const T (&I)[2][kMaxM][kMaxM], int po
 // a neighbour updated at this substep is read from its current slot; one
 // that is not (it is coarser) is linear in time between its two slots.
 template <typename T, int DIM, int P>
-__device__ __forceinline__ void neighbour_trace(const StepArgs<T> &a, uint32_t ent, int k, int side, T *tu, T *tq)
+__device__ __forceinline__ void neighbour_trace(const StepArgs<T> &a, const StepLaunch<T> &L, uint32_t ent, int k,
+                                                int side, T *tu, T *tq)
 {
+    const int si = L.i, parity = L.parity;
     using S = Shape<DIM, P>;
     constexpr int M = S::M;
     const uint32_t id = ent & kIdMask27;
     const int ln = (int)((ent >> 27) & 7);
     const int sh = a.lmax - ln;
-    const int base = ln == 0 ? a.parity : 0;
-    const int cur = base ^ ((a.i >> sh) & 1);
-    const int rem = a.i & ((1 << sh) - 1);
-    const T *p0 = a.u + (long long)cur * a.slot_stride + id;
+    const int base = ln == 0 ? parity : 0;
+    const int cur = base ^ ((si >> sh) & 1);
+    const int rem = si & ((1 << sh) - 1);
+    const T *p0 = L.u + (long long)cur * a.slot_stride + id;
 #pragma unroll
     for (int g = 0; g < S::NF; g++) { tu[g] = 0; tq[g] = 0; }
     if (rem == 0) {
@@ -183,8 +194,8 @@ __device__ __forceinline__ void neighbour_trace(const StepArgs<T> &a, uint32_t e
                 tq[g] += a.ref.G[side][b] * val;
             }
     } else {
-        const T th = (T)rem * (T)ldexp(1.0, -sh);
-        const T *p1 = a.u + (long long)(cur ^ 1) * a.slot_stride + id;
+        const T th = ldexp((T)rem, -sh);
+        const T *p1 = L.u + (long long)(cur ^ 1) * a.slot_stride + id;
 #pragma unroll
         for (int g = 0; g < S::NF; g++)
 #pragma unroll
@@ -203,17 +214,18 @@ __device__ __forceinline__ void neighbour_trace(const StepArgs<T> &a, uint32_t e
 // slots are always loaded (the second from the first's address when not
 // needed) so that the loads of all faces issue together without branches.
 template <typename T, int NP>
-__device__ __forceinline__ void neighbour_values(const StepArgs<T> &a, uint32_t ent, T *val)
+__device__ __forceinline__ void neighbour_values(const StepArgs<T> &a, const StepLaunch<T> &L, uint32_t ent, T *val)
 {
+    const int si = L.i, parity = L.parity;
     const uint32_t id = ent & kIdMask27;
     const int ln = (int)((ent >> 27) & 7);
     const int sh = a.lmax - ln;
-    const int base = ln == 0 ? a.parity : 0;
-    const int cur = base ^ ((a.i >> sh) & 1);
-    const int rem = a.i & ((1 << sh) - 1);
-    const T th = (T)rem * (T)ldexp(1.0, -sh);
-    const T *p0 = a.u + (long long)cur * a.slot_stride + id;
-    const T *p1 = rem ? a.u + (long long)(cur ^ 1) * a.slot_stride + id : p0;
+    const int base = ln == 0 ? parity : 0;
+    const int cur = base ^ ((si >> sh) & 1);
+    const int rem = si & ((1 << sh) - 1);
+    const T th = ldexp((T)rem, -sh);
+    const T *p0 = L.u + (long long)cur * a.slot_stride + id;
+    const T *p1 = rem ? L.u + (long long)(cur ^ 1) * a.slot_stride + id : p0;
 #pragma unroll
     for (int n = 0; n < NP; n++) {
         const T x0 = p0[(long long)n * a.cap];
@@ -233,31 +245,32 @@ __device__ __forceinline__ void neighbour_values(const StepArgs<T> &a, uint32_t 
 // arithmetic, so a wave waits for memory twice; faces with finer neighbours
 // (rare, at refinement interfaces) load their 2^(d-1) neighbours on demand.
 template <int DIM, int P, typename T>
-__global__ __launch_bounds__(256) void k_substep(const StepArgs<T> a)
+__global__ __launch_bounds__(256) void k_substep(const StepArgs<T> *__restrict__ cst, const StepLaunch<T> L)
 {
+    const StepArgs<T> &a = *cst;
     using S = Shape<DIM, P>;
     constexpr int M = S::M, NP = S::NP, NF = S::NF, NS = S::NS;
     constexpr int NFACE = 2 * DIM;
     // prefetch every face's neighbour unless it costs too many registers
     constexpr bool kPrefetch = NFACE * NP <= 64;
     const int j = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (j >= a.n_act) return;
+    if (j >= L.n_act) return;
 
     int lv = 0;
 #pragma unroll
     for (int l = 1; l < kMaxLevels; l++) lv += (j < a.cnt_ge[l]) ? 1 : 0;
     const int sh = a.lmax - lv;
-    const int cur = (lv == 0 ? a.parity : 0) ^ ((a.i >> sh) & 1);
+    const int cur = (lv == 0 ? L.parity : 0) ^ ((L.i >> sh) & 1);
     const T dt = (T)ldexp(a.dt_bar, -lv);
     const uint32_t self_ent = ((uint32_t)lv << 27) | (uint32_t)j;
 
     // ---- loads that depend on nothing but j
     uint32_t ent[NFACE];
 #pragma unroll
-    for (int f = 0; f < NFACE; f++) ent[f] = a.nbr[(long long)f * a.cap + j];
-    const typename KeyOf<DIM>::type kraw = static_cast<const typename KeyOf<DIM>::type *>(a.key)[j];
-    const T *uc = a.u + (long long)cur * a.slot_stride + j;
-    T *vp = a.v + j;
+    for (int f = 0; f < NFACE; f++) ent[f] = L.nbr[(long long)f * a.cap + j];
+    const typename KeyOf<DIM>::type kraw = static_cast<const typename KeyOf<DIM>::type *>(L.key)[j];
+    const T *uc = L.u + (long long)cur * a.slot_stride + j;
+    T *vp = L.v + j;
     T u[NP], vv[NP];
 #pragma unroll
     for (int n = 0; n < NP; n++) {
@@ -271,16 +284,16 @@ __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> a)
         for (int f = 0; f < NFACE; f++) {
             const uint32_t kind = ent[f] >> 30;
             const bool one = kind == kSame || kind == kCoarser;
-            neighbour_values<T, NP>(a, one ? ent[f] : self_ent, nb[f]);
+            neighbour_values<T, NP>(a, L, one ? ent[f] : self_ent, nb[f]);
         }
     }
 
     int depth;
     uint32_t c[3] = {0, 0, 0};
     unpack_key<DIM>(kraw, depth, c);
-    T h[DIM];
+    T ih[DIM];  // 1/h_k of this element
 #pragma unroll
-    for (int k = 0; k < DIM; k++) h[k] = (T)ldexp(a.h0[k], -depth);
+    for (int k = 0; k < DIM; k++) ih[k] = ldexp(a.inv_h0[k], depth);
 
     T r[NP];
 #pragma unroll
@@ -289,7 +302,7 @@ __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> a)
     // element volume: -(4 D_kk / h_k^2) A along each direction
 #pragma unroll
     for (int k = 0; k < DIM; k++) {
-        const T ck = (T)4 * a.Dk[k] / (h[k] * h[k]);
+        const T ck = (T)4 * a.Dk[k] * ih[k] * ih[k];
 #pragma unroll
         for (int g = 0; g < NF; g++)
 #pragma unroll
@@ -304,9 +317,9 @@ __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> a)
     // interior faces
 #pragma unroll
     for (int k = 0; k < DIM; k++) {
-        const T hk = h[k];
-        const T c2 = (T)2 / hk;
+        const T c2 = (T)2 * ih[k];
         const T Dkk = a.Dk[k];
+        const T pen = a.gamma * Dkk * ih[k];  // gamma D / h
         int pos0 = 0, pos1 = 0;  // own position inside a coarser neighbour's face
         {
             int t = 0;
@@ -352,9 +365,9 @@ __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> a)
                         nq[g] = sq;
                     }
                 } else {
-                    neighbour_trace<T, DIM, P>(a, ent[f], k, 1 - s, nu, nq);
+                    neighbour_trace<T, DIM, P>(a, L, ent[f], k, 1 - s, nu, nq);
                 }
-                const T hn = kind == kSame ? hk : (T)2 * hk;
+                const bool co = kind == kCoarser;  // h_nbr = 2h
                 if (kind == kCoarser) {
                     T iu[NF], iq[NF];
                     tang_apply<T, DIM, M>(a.ref.Isub, pos0, pos1, nu, iu);
@@ -362,8 +375,9 @@ __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> a)
 #pragma unroll
                     for (int g = 0; g < NF; g++) { nu[g] = iu[g]; nq[g] = iq[g]; }
                 }
-                const T sigma = a.gamma * (T)0.5 * (Dkk / hk + Dkk / hn);
-                const T qn = ns * Dkk * ((T)2 / hn);
+                // sigma = gamma 1/2 (D/h + D/h_nbr); n.D grad on the neighbour scales by 2/h_nbr
+                const T sigma = co ? (T)0.75 * pen : pen;
+                const T qn = ns * Dkk * (co ? ih[k] : c2);
 #pragma unroll
                 for (int g = 0; g < NF; g++) {
                     const T jmp = tu[g] - nu[g];
@@ -371,21 +385,20 @@ __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> a)
                     Hl[g] = (T)0.5 * jmp;
                 }
             } else {
-                const T hn = (T)0.5 * hk;
-                const T sigma = a.gamma * (T)0.5 * (Dkk / hk + Dkk / hn);
-                const T qn = ns * Dkk * ((T)2 / hn);
+                const T sigma = (T)1.5 * pen;           // h_nbr = h/2
+                const T qn = ns * Dkk * (T)2 * c2;
 #pragma unroll
                 for (int g = 0; g < NF; g++) { Fl[g] = 0; Hl[g] = 0; }
                 uint32_t fe[NS];
 #pragma unroll
-                for (int sub = 0; sub < NS; sub++) fe[sub] = a.fine[((long long)f * a.cap + j) * NS + sub];
+                for (int sub = 0; sub < NS; sub++) fe[sub] = L.fine[((long long)f * a.cap + j) * NS + sub];
 #pragma unroll
                 for (int sub = 0; sub < NS; sub++) {
                     const int p0 = sub & 1, p1 = sub >> 1;
                     T ou[NF], oq[NF], nu[NF], nq[NF], F[NF], H[NF], lf[NF], lh[NF];
                     tang_apply<T, DIM, M>(a.ref.Isub, p0, p1, tu, ou);
                     tang_apply<T, DIM, M>(a.ref.Isub, p0, p1, tq, oq);
-                    neighbour_trace<T, DIM, P>(a, fe[sub], k, 1 - s, nu, nq);
+                    neighbour_trace<T, DIM, P>(a, L, fe[sub], k, 1 - s, nu, nq);
 #pragma unroll
                     for (int g = 0; g < NF; g++) {
                         const T jmp = ou[g] - nu[g];
@@ -408,13 +421,15 @@ __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> a)
     }
 
     // pointwise reaction, stimulus and update
-    T *uo = a.u + (long long)(cur ^ 1) * a.slot_stride + j;
+    T *uo = L.u + (long long)(cur ^ 1) * a.slot_stride + j;
 #pragma unroll
     for (int n = 0; n < NP; n++) {
         const T un = u[n];
         const T vn = vv[n];
         T stim = 0;
-        if (a.n_stim > 0) {
+        bool any = false;
+        for (int b = 0; b < a.n_stim; b++) any = any || (L.t_i >= a.stim[b][6] && L.t_i < a.stim[b][7]);
+        if (any) {
             double X[3];
             int nn = n;
 #pragma unroll
@@ -425,7 +440,7 @@ __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> a)
                 nn /= M;
             }
             for (int b = 0; b < a.n_stim; b++) {
-                bool in = true;
+                bool in = L.t_i >= a.stim[b][6] && L.t_i < a.stim[b][7];
 #pragma unroll
                 for (int k = 0; k < DIM; k++) in = in && X[k] >= a.stim[b][k] && X[k] <= a.stim[b][3 + k];
                 if (in) stim += (T)a.stim[b][8];
@@ -434,10 +449,18 @@ __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> a)
         const T f = -a.apk * un * (un - a.apa) * (un - (T)1) - un * vn;
         T den = un + a.mu2;
         den = den < (T)1e-6 ? (T)1e-6 : den;
-        const T eps = a.eps0 + a.mu1 * vn / den;
         const T vinf = a.apk * un * ((T)1 + a.apa - un);
+        T decay;
+        if constexpr (sizeof(T) == 4) {
+            // FP32 bulk: fast reciprocal division and exponential
+            const T eps = a.eps0 + a.mu1 * __fdividef(vn, den);
+            decay = __expf(-eps * dt);
+        } else {
+            const T eps = a.eps0 + a.mu1 * vn / den;
+            decay = exp(-eps * dt);
+        }
         uo[(long long)n * a.cap] = un + dt * (r[n] + f + stim);
-        vp[(long long)n * a.cap] = vinf + (vn - vinf) * exp(-eps * dt);
+        vp[(long long)n * a.cap] = vinf + (vn - vinf) * decay;
     }
 }
 

@@ -438,6 +438,10 @@ struct mdlts_sim {
     DevBuf key_c, face_c, fine_c, u_c, v_c, level_c, cfl_c, eta_c, tmp_u, tmp_v;
     // grouped device data
     DevBuf u_s, v_s, key_s, nbr_s, fine_s, perm, inv, hist, cnt_ge_d, flags, xk, xs, xc, stage;
+    // substep constants in device memory and their host copy
+    DevBuf step_dev;
+    std::vector<unsigned char> step_host = std::vector<unsigned char>(sizeof(StepArgs<double>));
+    bool step_dirty = true;
     // device mesh management
     DevBuf root_start, mkey, refine, cflag, cnt, off, bsums, key_n;
     int cap = 0;
@@ -737,9 +741,9 @@ mdlts_status set_forest(mdlts_sim *s, Forest &&F)
 
 // ---- substep launch -------------------------------------------------------
 template <int DIM, int P_, typename T>
-void launch_substep(const StepArgs<T> &a, hipStream_t st)
+void launch_substep(const StepArgs<T> *c, const StepLaunch<T> &L, hipStream_t st)
 {
-    k_substep<DIM, P_, T><<<nblocks(a.n_act), kBlock, 0, st>>>(a);
+    k_substep<DIM, P_, T><<<nblocks(L.n_act), kBlock, 0, st>>>(c, L);
 }
 
 mdlts_status drain_events(mdlts_sim *s)
@@ -757,16 +761,13 @@ mdlts_status drain_events(mdlts_sim *s)
 
 constexpr size_t kMaxEventPairs = 4096;
 
+// the per-assignment constants of the substep kernel, uploaded to the device
+// when they change (parameters, levels, buffers)
 template <typename T>
-mdlts_status run_barriers(mdlts_sim *s, int n_barriers)
+mdlts_status upload_step_args(mdlts_sim *s)
 {
-    StepArgs<T> a;
+    StepArgs<T> &a = *reinterpret_cast<StepArgs<T> *>(s->step_host.data());
     std::memset(&a, 0, sizeof(a));
-    a.u = P<T>(s->u_s);
-    a.v = P<T>(s->v_s);
-    a.key = s->key_s.p;
-    a.nbr = P<uint32_t>(s->nbr_s);
-    a.fine = P<uint32_t>(s->fine_s);
     a.slot_stride = (long long)s->np * s->cap;
     a.cap = s->cap;
     a.lmax = s->lmax;
@@ -774,6 +775,7 @@ mdlts_status run_barriers(mdlts_sim *s, int n_barriers)
     a.dt_bar = s->dt_bar;
     for (int k = 0; k < 3; k++) {
         a.h0[k] = s->h0[k];
+        a.inv_h0[k] = (T)(1.0 / s->h0[k]);
         a.Dk[k] = (T)s->Dk[k];
     }
     a.gamma = (T)s->gamma;
@@ -782,28 +784,46 @@ mdlts_status run_barriers(mdlts_sim *s, int n_barriers)
     a.eps0 = (T)s->ap.eps0;
     a.mu1 = (T)s->ap.mu1;
     a.mu2 = (T)s->ap.mu2;
+    a.n_stim = (int)s->stim.size();
+    for (int b = 0; b < a.n_stim; b++) {
+        const mdlts_stim_box &x = s->stim[b];
+        for (int k = 0; k < 3; k++) { a.stim[b][k] = x.lo[k]; a.stim[b][3 + k] = x.hi[k]; }
+        a.stim[b][6] = x.t_on; a.stim[b][7] = x.t_off; a.stim[b][8] = x.amp;
+    }
     fill_ref(s->ref, a.ref);
+    MD_TRY(dev_alloc(s->ctx, s->step_dev, sizeof(StepArgs<T>)));
+    HIP_TRY(hipMemcpyAsync(s->step_dev.p, &a, sizeof(StepArgs<T>), hipMemcpyHostToDevice, s->ctx->stream));
+    MD_TRY(sync(s->ctx));  // the host copy may change right after
+    s->step_dirty = false;
+    return MDLTS_OK;
+}
+
+template <typename T>
+mdlts_status run_barriers(mdlts_sim *s, int n_barriers)
+{
+    if (s->step_dirty) MD_TRY(upload_step_args<T>(s));
+    StepLaunch<T> L;
+    L.u = P<T>(s->u_s);
+    L.v = P<T>(s->v_s);
+    L.key = s->key_s.p;
+    L.nbr = P<uint32_t>(s->nbr_s);
+    L.fine = P<uint32_t>(s->fine_s);
+    const StepArgs<T> *cst = static_cast<const StepArgs<T> *>(s->step_dev.p);
     const long long maxS = 1ll << s->lmax;
     const double h_tick = s->dt_bar / (double)maxS;
     hipStream_t st = s->ctx->stream;
+    const int key = s->desc.dim * 10 + s->desc.order;
     for (int nb = 0; nb < n_barriers; nb++) {
         const double t_n = s->t_start + (double)s->n_bar * s->dt_bar;
-        a.parity = (int)(s->n_since_assign & 1);
+        L.parity = (int)(s->n_since_assign & 1);
         for (long long i = 0; i < maxS; i++) {
             int v2 = 0;
             while (i > 0 && ((i >> v2) & 1) == 0) v2++;
             const int lmin = i == 0 ? 0 : s->lmax - v2;
-            a.i = (int)i;
-            a.n_act = s->cnt_ge[lmin];
-            a.t_i = t_n + (double)i * h_tick;
-            a.n_stim = 0;
-            for (const auto &b : s->stim)
-                if (a.t_i >= b.t_on && a.t_i < b.t_off && a.n_stim < kMaxStim) {
-                    double *q = a.stim[a.n_stim++];
-                    for (int k = 0; k < 3; k++) { q[k] = b.lo[k]; q[3 + k] = b.hi[k]; }
-                    q[6] = b.t_on; q[7] = b.t_off; q[8] = b.amp;
-                }
-            if (a.n_act == 0) continue;
+            L.i = (int)i;
+            L.n_act = s->cnt_ge[lmin];
+            L.t_i = t_n + (double)i * h_tick;
+            if (L.n_act == 0) continue;
             if (s->prof) {
                 if (s->ev_used == kMaxEventPairs) MD_TRY(drain_events(s));
                 while (s->ev.size() < 2 * (s->ev_used + 1)) {
@@ -813,20 +833,19 @@ mdlts_status run_barriers(mdlts_sim *s, int n_barriers)
                 }
                 HIP_TRY(hipEventRecord(s->ev[2 * s->ev_used], st));
             }
-            const int key = s->desc.dim * 10 + s->desc.order;
             switch (key) {
-            case 21: launch_substep<2, 1, T>(a, st); break;
-            case 22: launch_substep<2, 2, T>(a, st); break;
-            case 31: launch_substep<3, 1, T>(a, st); break;
-            case 32: launch_substep<3, 2, T>(a, st); break;
+            case 21: launch_substep<2, 1, T>(cst, L, st); break;
+            case 22: launch_substep<2, 2, T>(cst, L, st); break;
+            case 31: launch_substep<3, 1, T>(cst, L, st); break;
+            case 32: launch_substep<3, 2, T>(cst, L, st); break;
             default: return MDLTS_EINVAL;
             }
-            s->dof_updates += (uint64_t)a.n_act * (uint64_t)s->np;
+            s->dof_updates += (uint64_t)L.n_act * (uint64_t)s->np;
             if (s->prof) {
                 HIP_TRY(hipEventRecord(s->ev[2 * s->ev_used + 1], st));
                 s->ev_used++;
                 s->prof_launches++;
-                s->prof_dof += (uint64_t)a.n_act * (uint64_t)s->np;
+                s->prof_dof += (uint64_t)L.n_act * (uint64_t)s->np;
             }
         }
         HIP_TRY(hipGetLastError());
@@ -1060,7 +1079,8 @@ mdlts_status mdlts_sim_destroy(mdlts_sim *s)
     DevBuf *bufs[] = {&s->key_c, &s->face_c, &s->fine_c, &s->u_c, &s->v_c, &s->level_c, &s->cfl_c, &s->eta_c,
                       &s->tmp_u, &s->tmp_v, &s->u_s, &s->v_s, &s->key_s, &s->nbr_s, &s->fine_s, &s->perm,
                       &s->inv, &s->hist, &s->cnt_ge_d, &s->flags, &s->xk, &s->xs, &s->xc, &s->stage,
-                      &s->root_start, &s->mkey, &s->refine, &s->cflag, &s->cnt, &s->off, &s->bsums, &s->key_n};
+                      &s->root_start, &s->mkey, &s->refine, &s->cflag, &s->cnt, &s->off, &s->bsums, &s->key_n,
+                      &s->step_dev};
     mdlts_status st = MDLTS_OK;
     for (DevBuf *b : bufs)
         if (dev_free(c, *b) != MDLTS_OK) st = MDLTS_EDEVICE;
@@ -1108,6 +1128,7 @@ mdlts_status mdlts_set_conductivity(mdlts_sim *s, const double D_sym[6], double 
     if (!gershgorin_table(s->ref, gamma, G)) return MDLTS_EINVAL;
     for (int k = 0; k < 3; k++) s->Dk[k] = k < s->desc.dim ? Dk[k] : 0.0;
     s->gamma = gamma;
+    s->step_dirty = true;
     std::memcpy(s->G, G, sizeof(G));
     s->levels_valid = s->levels_valid && false;
     return MDLTS_OK;
@@ -1117,6 +1138,7 @@ mdlts_status mdlts_set_ionic(mdlts_sim *s, const mdlts_ap_params *p)
 {
     if (!s || !p) return MDLTS_EINVAL;
     s->ap = *p;
+    s->step_dirty = true;
     return MDLTS_OK;
 }
 
@@ -1124,6 +1146,7 @@ mdlts_status mdlts_set_stimulus(mdlts_sim *s, const mdlts_stim_box *boxes, int n
 {
     if (!s || n_boxes < 0 || n_boxes > kMaxStim || (n_boxes && !boxes)) return MDLTS_EINVAL;
     s->stim.assign(boxes, boxes + n_boxes);
+    s->step_dirty = true;
     return MDLTS_OK;
 }
 
@@ -1271,6 +1294,7 @@ mdlts_status mdlts_assign_levels(mdlts_sim *s, double dt_barrier, int32_t *level
         s->dt_bar = dt_barrier;
     }
     s->levels_valid = true;
+    s->step_dirty = true;
     MD_TRY(to_grouped(s));
     return sync(c);
 }
