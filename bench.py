@@ -144,7 +144,7 @@ def main():
     plain.set_tree(bits)
     plain.set_state(u, v)
     dt_plain = dt / 2 ** (W["n_levels"] - 1)
-    plain.assign_levels(dt_plain)
+    plain.assign_uniform(dt_plain, 0)
     plain.set_time(t_sim1)
     plain.step(5)
     ctx.sync()
@@ -167,7 +167,7 @@ def main():
     ref = setup(ctx, W, args.seed, "f64", n_levels=1)
     ref.set_tree(bits)
     ref.set_state(u, v)
-    ref.assign_levels(dt_plain)
+    ref.assign_uniform(dt_plain, 0)
     ref.set_time(t_sim1)
     nb = 16
     lts.step(nb)

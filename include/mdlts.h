@@ -129,6 +129,12 @@ mdlts_status mdlts_set_time(mdlts_sim *sim, double t);
  * level.  EUNSTABLE if some leaf needs b_e > n_levels-1 (levels are then
  * left unassigned). */
 mdlts_status mdlts_assign_levels(mdlts_sim *sim, double dt_barrier, int32_t *level_hist);
+/* Every leaf on the given level (0 <= level < n_levels): 2^level substeps of
+ * dt_barrier / 2^level per barrier, without the CFL test.  level 0 is the
+ * plain global forward-Euler step of Sec. 2.3 with step dt_barrier, whose
+ * stability (dt * lambda_max < 2) is the caller's responsibility.  The CFL
+ * values are still computed for mdlts_get_cfl. */
+mdlts_status mdlts_assign_uniform(mdlts_sim *sim, double dt_barrier, int level, int32_t *level_hist);
 /* Copies the last assignment: level [n_leaves] (canonical order), perm
  * [n_leaves] (grouped position -> canonical leaf), cnt_ge [n_levels]
  * (number of leaves with level >= l).  Any pointer may be NULL. */

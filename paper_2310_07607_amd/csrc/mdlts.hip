@@ -44,6 +44,7 @@ struct LevelArgs {
     double h0[3];
     double Dk[3];
     double G[4][4];
+    int force_level;  // >= 0: every leaf on this level (no CFL test)
     uint8_t *level;
     double *cfl;
     int *hist;      // [blocks][8]
@@ -71,7 +72,9 @@ __global__ __launch_bounds__(kBlock) void k_levels(const LevelArgs a)
         }
         const double cfl = 1.0 / s;
         int b = 0;
-        while (b < 64 && ldexp(a.dt_bar, -b) > cfl) b++;
+        if (a.force_level >= 0) b = a.force_level;
+        else
+            while (b < 64 && ldexp(a.dt_bar, -b) > cfl) b++;
         if (b > a.n_levels - 1) {
             atomicOr(a.bad, 1);
             b = a.n_levels - 1;
@@ -1213,7 +1216,20 @@ mdlts_status mdlts_set_time(mdlts_sim *s, double t)
     return MDLTS_OK;
 }
 
+static mdlts_status assign_levels_impl(mdlts_sim *s, double dt_barrier, int force_level, int32_t *level_hist);
+
 mdlts_status mdlts_assign_levels(mdlts_sim *s, double dt_barrier, int32_t *level_hist)
+{
+    return assign_levels_impl(s, dt_barrier, -1, level_hist);
+}
+
+mdlts_status mdlts_assign_uniform(mdlts_sim *s, double dt_barrier, int level, int32_t *level_hist)
+{
+    if (!s || level < 0 || level >= s->desc.n_levels) return MDLTS_EINVAL;
+    return assign_levels_impl(s, dt_barrier, level, level_hist);
+}
+
+static mdlts_status assign_levels_impl(mdlts_sim *s, double dt_barrier, int force_level, int32_t *level_hist)
 {
     if (!s || !(dt_barrier > 0.0) || !std::isfinite(dt_barrier)) return MDLTS_EINVAL;
     mdlts_ctx *c = s->ctx;
@@ -1237,6 +1253,7 @@ mdlts_status mdlts_assign_levels(mdlts_sim *s, double dt_barrier, int32_t *level
     la.E = E;
     la.dim = s->desc.dim;
     la.n_levels = L;
+    la.force_level = force_level;
     la.dt_bar = dt_barrier;
     for (int k = 0; k < 3; k++) { la.h0[k] = s->h0[k]; la.Dk[k] = s->Dk[k]; }
     std::memcpy(la.G, s->G, sizeof(la.G));

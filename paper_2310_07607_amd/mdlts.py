@@ -81,6 +81,7 @@ def lib():
         "mdlts_get_state": (I, [P, P, P, S]),
         "mdlts_set_time": (I, [P, D]),
         "mdlts_assign_levels": (I, [P, D, P]),
+        "mdlts_assign_uniform": (I, [P, D, I, P]),
         "mdlts_get_levels": (I, [P, P, P, P, S]),
         "mdlts_get_cfl": (I, [P, P, S]),
         "mdlts_step": (I, [P, I]),
@@ -296,6 +297,12 @@ class Simulation:
     def assign_levels(self, dt_barrier):
         hist = np.zeros(self.n_levels, dtype=np.int32)
         _chk(lib().mdlts_assign_levels(self.h, float(dt_barrier), _p(hist)), "mdlts_assign_levels")
+        return hist
+
+    def assign_uniform(self, dt_barrier, level=0):
+        """Every leaf on `level` (level 0: the plain global step dt_barrier)."""
+        hist = np.zeros(self.n_levels, dtype=np.int32)
+        _chk(lib().mdlts_assign_uniform(self.h, float(dt_barrier), int(level), _p(hist)), "mdlts_assign_uniform")
         return hist
 
     def get_levels(self):

@@ -111,6 +111,18 @@ def test_lts_barrier_against_algorithm1(ctx, name, precision, tol):
         assert rel_l2(gu - ou0, ou - ou0) <= (1e-8 if precision == "f64" else 1e-2)
 
 
+@pytest.mark.parametrize("level", [0, 2])
+def test_uniform_level_equals_global_stepping(ctx, level):
+    o, g, u, v = _setup(ctx, "q1_2d", "f64", 3, seed=8)
+    dt = 0.5 * o.cfl().min() * 2 ** level
+    g.assign_uniform(dt, level)
+    g.set_time(0.0)
+    g.step(3)
+    o.step_global(dt / 2 ** level, 0.0, 3 * 2 ** level)
+    assert rel_l2(g.get_state()[0], o.get_state()[0]) <= 1e-12
+    assert np.all(g.get_levels()[0] == level)
+
+
 @pytest.mark.parametrize("name", ["q1_2d", "q2_2d", "q1_3d"])
 def test_multi_barrier_lts_fp64_trajectory(ctx, name):
     o, g, u, v = _setup(ctx, name, "f64", 3, seed=3)
