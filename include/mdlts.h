@@ -153,6 +153,30 @@ mdlts_status mdlts_get_cfl(mdlts_sim *sim, double *cfl, size_t n_leaves);
  * assigned for the current forest. */
 mdlts_status mdlts_step(mdlts_sim *sim, int n_barriers);
 
+/* ---- many simulations at once -------------------------------------------- */
+/* Advances each simulation of the list (all created on ctx, levels assigned)
+ * by n_barriers barrier intervals, like mdlts_step on each, with one launch
+ * per substep index and element kind (dimension, order, precision) covering
+ * all of them: every simulation runs its own 2^lmax substeps per interval
+ * (Sec. 2.3; the elements of one sweep are independent) with its own
+ * barrier step, parameters and time.  Each result is bitwise the same as
+ * running the simulation alone.  The per-barrier launch sequence is cached
+ * and replayed as a HIP graph until a simulation of the list changes; the
+ * first barriers after a change of the list time the candidate launch
+ * shapes (threads per block, one block per tile or persistent blocks) and
+ * keep the fastest.  Asynchronous on the context stream.  EINVAL for a
+ * repeated or foreign simulation, ESTATE if levels are not assigned. */
+mdlts_status mdlts_batch_step(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sims, int n_barriers);
+/* enable = 0 launches the batch's kernels one by one instead of as a graph. */
+mdlts_status mdlts_set_graphs(mdlts_ctx *ctx, int enable);
+/* Event timing of the batched substep launches (not graph-replayed while
+ * enabled); read returns kernel ms, launches, DoF-updates since the last
+ * read, and the launch shape in use (threads per block; persistent blocks
+ * per CU or 0).  ESTATE before the first mdlts_batch_step. */
+mdlts_status mdlts_batch_profile(mdlts_ctx *ctx, int enable);
+mdlts_status mdlts_batch_profile_read(mdlts_ctx *ctx, double *substep_ms, uint64_t *n_launches,
+                                      uint64_t *dof_updates, int *block, int *per_cu);
+
 /* ---- error indicator and adaptivity (Sec. 2.2, Algorithm 1) -------------- */
 /* Kelly-type indicator eta_e^2 = sum over interior face pieces F of e of
  * h_F/(2p) * W_F^2 * ||[[D grad u . n]]||^2_{L2(F)} at the barrier (FP64

@@ -245,16 +245,13 @@ __device__ __forceinline__ void neighbour_values(const StepArgs<T> &a, const Ste
 // arithmetic, so a wave waits for memory twice; faces with finer neighbours
 // (rare, at refinement interfaces) load their 2^(d-1) neighbours on demand.
 template <int DIM, int P, typename T>
-__global__ __launch_bounds__(256) void k_substep(const StepArgs<T> *__restrict__ cst, const StepLaunch<T> L)
+__device__ __forceinline__ void substep_element(const StepArgs<T> &a, const StepLaunch<T> &L, const int j)
 {
-    const StepArgs<T> &a = *cst;
     using S = Shape<DIM, P>;
     constexpr int M = S::M, NP = S::NP, NF = S::NF, NS = S::NS;
     constexpr int NFACE = 2 * DIM;
     // prefetch every face's neighbour unless it costs too many registers
     constexpr bool kPrefetch = NFACE * NP <= 64;
-    const int j = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (j >= L.n_act) return;
 
     int lv = 0;
 #pragma unroll
@@ -271,11 +268,14 @@ __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> *__restrict__
     const typename KeyOf<DIM>::type kraw = static_cast<const typename KeyOf<DIM>::type *>(L.key)[j];
     const T *uc = L.u + (long long)cur * a.slot_stride + j;
     T *vp = L.v + j;
-    T u[NP], vv[NP];
+    // the gate is needed only at the end; small elements load it with the
+    // first round of loads, large ones after the face phase (registers)
+    constexpr bool kEarlyV = NP <= 16;
+    T u[NP], vv[kEarlyV ? NP : 1];
 #pragma unroll
     for (int n = 0; n < NP; n++) {
         u[n] = uc[(long long)n * a.cap];
-        vv[n] = vp[(long long)n * a.cap];
+        if constexpr (kEarlyV) vv[n] = vp[(long long)n * a.cap];
     }
     // ---- one neighbour per face (same-size or coarser), at the substep time
     T nb[kPrefetch ? NFACE : 1][NP];
@@ -389,16 +389,12 @@ __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> *__restrict__
                 const T qn = ns * Dkk * (T)2 * c2;
 #pragma unroll
                 for (int g = 0; g < NF; g++) { Fl[g] = 0; Hl[g] = 0; }
-                uint32_t fe[NS];
-#pragma unroll
-                for (int sub = 0; sub < NS; sub++) fe[sub] = L.fine[((long long)f * a.cap + j) * NS + sub];
-#pragma unroll
-                for (int sub = 0; sub < NS; sub++) {
+                auto sub_face = [&](int sub) {
                     const int p0 = sub & 1, p1 = sub >> 1;
                     T ou[NF], oq[NF], nu[NF], nq[NF], F[NF], H[NF], lf[NF], lh[NF];
                     tang_apply<T, DIM, M>(a.ref.Isub, p0, p1, tu, ou);
                     tang_apply<T, DIM, M>(a.ref.Isub, p0, p1, tq, oq);
-                    neighbour_trace<T, DIM, P>(a, L, fe[sub], k, 1 - s, nu, nq);
+                    neighbour_trace<T, DIM, P>(a, L, L.fine[((long long)f * a.cap + j) * NS + sub], k, 1 - s, nu, nq);
 #pragma unroll
                     for (int g = 0; g < NF; g++) {
                         const T jmp = ou[g] - nu[g];
@@ -409,6 +405,13 @@ __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> *__restrict__
                     tang_apply<T, DIM, M>(a.ref.Lsub, p0, p1, H, lh);
 #pragma unroll
                     for (int g = 0; g < NF; g++) { Fl[g] += lf[g]; Hl[g] += lh[g]; }
+                };
+                if constexpr (NP <= 16) {
+#pragma unroll
+                    for (int sub = 0; sub < NS; sub++) sub_face(sub);
+                } else {
+#pragma unroll 1
+                    for (int sub = 0; sub < NS; sub++) sub_face(sub);
                 }
             }
             // lift to the own nodes, already multiplied by the inverse mass
@@ -425,7 +428,9 @@ __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> *__restrict__
 #pragma unroll
     for (int n = 0; n < NP; n++) {
         const T un = u[n];
-        const T vn = vv[n];
+        T vn;
+        if constexpr (kEarlyV) vn = vv[n];
+        else vn = vp[(long long)n * a.cap];
         T stim = 0;
         bool any = false;
         for (int b = 0; b < a.n_stim; b++) any = any || (L.t_i >= a.stim[b][6] && L.t_i < a.stim[b][7]);
@@ -462,6 +467,78 @@ __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> *__restrict__
         uo[(long long)n * a.cap] = un + dt * (r[n] + f + stim);
         vp[(long long)n * a.cap] = vinf + (vn - vinf) * decay;
     }
+}
+
+// one simulation: element j of the active prefix [0, n_act)
+template <int DIM, int P, typename T>
+__global__ __launch_bounds__(256) void k_substep(const StepArgs<T> *__restrict__ cst, const StepLaunch<T> L)
+{
+    const int j = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (j >= L.n_act) return;
+    substep_element<DIM, P, T>(*cst, L, j);
+}
+
+// ---- many simulations in one launch ------------------------------------------
+// A tile is up to blockDim.x consecutive active elements of one simulation.
+struct BatchTile {
+    int sim;
+    int start;
+    int count;
+    int pad;
+};
+
+// Everything a batched launch needs about one simulation.  Data locations
+// are byte offsets from the kernel's base pointer so that the kernel derives
+// them from a global-memory kernel argument.
+template <typename T>
+struct BatchSim {
+    StepArgs<T> a;
+    long long off_u, off_v, off_key, off_nbr, off_fine;
+    double t_start, h_tick;
+    long long n_bar;  // barriers since t_start (advanced on the device)
+    int parity;       // barriers since the level assignment, mod 2
+    int pad;
+};
+
+// Substep i of the barrier interval for every tile of the list.  With a
+// grid smaller than the tile count each block walks the tiles of its XCD's
+// contiguous range (persistent form).
+template <int DIM, int P, typename T>
+__global__ __launch_bounds__(256) void k_substep_batch(const BatchSim<T> *__restrict__ sims,
+                                                       const BatchTile *__restrict__ tiles, int n_tiles, int i,
+                                                       char *base)
+{
+    const int x = blockIdx.x & 7, per = (int)(gridDim.x >> 3);
+    const int q = n_tiles >> 3, r = n_tiles & 7;
+    const int t0 = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+    const int t1 = t0 + q + (x < r ? 1 : 0);
+    for (int t = t0 + (int)(blockIdx.x >> 3); t < t1; t += per) {
+        const BatchTile tl = tiles[t];
+        if ((int)threadIdx.x >= tl.count) continue;
+        const BatchSim<T> &d = sims[tl.sim];
+        StepLaunch<T> L;
+        L.u = reinterpret_cast<T *>(base + d.off_u);
+        L.v = reinterpret_cast<T *>(base + d.off_v);
+        L.key = base + d.off_key;
+        L.nbr = reinterpret_cast<const uint32_t *>(base + d.off_nbr);
+        L.fine = reinterpret_cast<const uint32_t *>(base + d.off_fine);
+        L.i = i;
+        L.n_act = 0;
+        L.parity = d.parity;
+        // t = t_start + n dt + i h, rounded like the host (no contraction)
+        L.t_i = __dadd_rn(__dadd_rn(d.t_start, __dmul_rn((double)d.n_bar, d.a.dt_bar)), __dmul_rn((double)i, d.h_tick));
+        substep_element<DIM, P, T>(d.a, L, tl.start + (int)threadIdx.x);
+    }
+}
+
+// end of a barrier interval for every simulation of a batch
+template <typename T>
+__global__ void k_batch_advance(BatchSim<T> *sims, int n)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    sims[s].n_bar += 1;
+    sims[s].parity ^= 1;
 }
 
 }  // namespace mdlts

@@ -414,12 +414,16 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+struct BatchPlan;
+
 struct mdlts_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     mdlts_allocator alloc{};
     bool has_alloc = false;
     int n_sims = 0;  // live simulations; the context outlives them
+    BatchPlan *batch = nullptr;
+    int use_graphs = 1;
 };
 
 struct mdlts_sim {
@@ -445,6 +449,7 @@ struct mdlts_sim {
     DevBuf step_dev;
     std::vector<unsigned char> step_host = std::vector<unsigned char>(sizeof(StepArgs<double>));
     bool step_dirty = true;
+    uint64_t version = 1;  // bumped by every change a batch plan depends on
     // device mesh management
     DevBuf root_start, mkey, refine, cflag, cnt, off, bsums, key_n;
     int cap = 0;
@@ -767,9 +772,8 @@ constexpr size_t kMaxEventPairs = 4096;
 // the per-assignment constants of the substep kernel, uploaded to the device
 // when they change (parameters, levels, buffers)
 template <typename T>
-mdlts_status upload_step_args(mdlts_sim *s)
+void fill_step_args(const mdlts_sim *s, StepArgs<T> &a)
 {
-    StepArgs<T> &a = *reinterpret_cast<StepArgs<T> *>(s->step_host.data());
     std::memset(&a, 0, sizeof(a));
     a.slot_stride = (long long)s->np * s->cap;
     a.cap = s->cap;
@@ -794,6 +798,13 @@ mdlts_status upload_step_args(mdlts_sim *s)
         a.stim[b][6] = x.t_on; a.stim[b][7] = x.t_off; a.stim[b][8] = x.amp;
     }
     fill_ref(s->ref, a.ref);
+}
+
+template <typename T>
+mdlts_status upload_step_args(mdlts_sim *s)
+{
+    StepArgs<T> &a = *reinterpret_cast<StepArgs<T> *>(s->step_host.data());
+    fill_step_args<T>(s, a);
     MD_TRY(dev_alloc(s->ctx, s->step_dev, sizeof(StepArgs<T>)));
     HIP_TRY(hipMemcpyAsync(s->step_dev.p, &a, sizeof(StepArgs<T>), hipMemcpyHostToDevice, s->ctx->stream));
     MD_TRY(sync(s->ctx));  // the host copy may change right after
@@ -988,6 +999,360 @@ mdlts_status compute_G(mdlts_sim *s)
     return MDLTS_OK;
 }
 
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// batches: many simulations advanced by one launch per substep and element
+// kind; tile lists per substep; the barrier interval replayed as a hipGraph
+// ---------------------------------------------------------------------------
+struct BatchGroup {
+    int dim = 2, order = 1, prec = 0;
+    std::vector<int> members;   // indices into BatchPlan::sims
+    DevBuf descs, tiles;
+    std::vector<int> tile_off;  // [2^lmax_all + 1] offsets into tiles per substep
+    char *base = nullptr;
+};
+
+struct BatchPlan {
+    std::vector<mdlts_sim *> sims;
+    std::vector<uint64_t> versions;
+    int lmax_all = 0;
+    int block = 256;
+    int per_cu = 0;  // 0: one block per tile; k: persistent, k blocks per CU
+    bool tuned = false;
+    std::vector<BatchGroup> groups;
+    std::vector<uint64_t> dof_per_barrier;  // per simulation
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int n_cu = 256;
+    // optional event timing of every batched substep launch
+    bool prof = false;
+    std::vector<hipEvent_t> ev;
+    size_t ev_used = 0;
+    double prof_ms = 0.0;
+    uint64_t prof_launches = 0, prof_dof = 0;
+};
+
+namespace {
+
+void free_graph(BatchPlan *P)
+{
+    if (P->exec) (void)hipGraphExecDestroy(P->exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    P->exec = nullptr;
+    P->graph = nullptr;
+}
+
+void free_plan(mdlts_ctx *c)
+{
+    BatchPlan *P = c->batch;
+    if (!P) return;
+    (void)hipStreamSynchronize(c->stream);
+    free_graph(P);
+    for (auto &g : P->groups) {
+        dev_free(c, g.descs);
+        dev_free(c, g.tiles);
+    }
+    for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
+    delete P;
+    c->batch = nullptr;
+}
+
+void *batch_kernel(int dim, int order, int prec)
+{
+    switch (dim * 100 + order * 10 + prec) {
+    case 210: return reinterpret_cast<void *>(&k_substep_batch<2, 1, double>);
+    case 220: return reinterpret_cast<void *>(&k_substep_batch<2, 2, double>);
+    case 310: return reinterpret_cast<void *>(&k_substep_batch<3, 1, double>);
+    case 320: return reinterpret_cast<void *>(&k_substep_batch<3, 2, double>);
+    case 211: return reinterpret_cast<void *>(&k_substep_batch<2, 1, float>);
+    case 221: return reinterpret_cast<void *>(&k_substep_batch<2, 2, float>);
+    case 311: return reinterpret_cast<void *>(&k_substep_batch<3, 1, float>);
+    case 321: return reinterpret_cast<void *>(&k_substep_batch<3, 2, float>);
+    }
+    return nullptr;
+}
+
+template <typename T>
+mdlts_status fill_group(mdlts_ctx *c, BatchPlan &P, BatchGroup &G)
+{
+    const int nm = (int)G.members.size();
+    MD_TRY(dev_alloc(c, G.descs, (size_t)nm * sizeof(BatchSim<T>)));
+    G.base = static_cast<char *>(G.descs.p);
+    std::vector<BatchSim<T>> d(nm);
+    for (int q = 0; q < nm; q++) {
+        mdlts_sim *s = P.sims[G.members[q]];
+        fill_step_args<T>(s, d[q].a);
+        d[q].off_u = static_cast<char *>(s->u_s.p) - G.base;
+        d[q].off_v = static_cast<char *>(s->v_s.p) - G.base;
+        d[q].off_key = static_cast<char *>(s->key_s.p) - G.base;
+        d[q].off_nbr = static_cast<char *>(s->nbr_s.p) - G.base;
+        d[q].off_fine = static_cast<char *>(s->fine_s.p) - G.base;
+        d[q].t_start = s->t_start;
+        d[q].h_tick = s->dt_bar / (double)(1ll << s->lmax);
+        d[q].n_bar = s->n_bar;
+        d[q].parity = (int)(s->n_since_assign & 1);
+        d[q].pad = 0;
+    }
+    // tile lists: substep i of the barrier interval (each simulation runs
+    // its own 2^lmax substeps; shorter schedules idle at the end)
+    const long long nsub = 1ll << P.lmax_all;
+    std::vector<BatchTile> tiles;
+    G.tile_off.assign(nsub + 1, 0);
+    for (long long i = 0; i < nsub; i++) {
+        G.tile_off[i] = (int)tiles.size();
+        for (int q = 0; q < nm; q++) {
+            mdlts_sim *s = P.sims[G.members[q]];
+            if (i >= (1ll << s->lmax)) continue;
+            int v2 = 0;
+            while (i > 0 && ((i >> v2) & 1) == 0) v2++;
+            const int lmin = i == 0 ? 0 : s->lmax - v2;
+            const int n = s->cnt_ge[lmin];
+            for (int st = 0; st < n; st += P.block) tiles.push_back(BatchTile{q, st, std::min(P.block, n - st), 0});
+        }
+    }
+    G.tile_off[nsub] = (int)tiles.size();
+    MD_TRY(dev_alloc(c, G.tiles, std::max<size_t>(1, tiles.size()) * sizeof(BatchTile)));
+    HIP_TRY(hipMemcpyAsync(G.descs.p, d.data(), (size_t)nm * sizeof(BatchSim<T>), hipMemcpyHostToDevice, c->stream));
+    if (!tiles.empty())
+        HIP_TRY(hipMemcpyAsync(G.tiles.p, tiles.data(), tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice,
+                               c->stream));
+    return sync(c);  // host vectors die here
+}
+
+// (re)build descriptors and tile lists for the current launch shape
+mdlts_status build_plan_data(mdlts_ctx *c, BatchPlan &P)
+{
+    free_graph(&P);
+    for (auto &G : P.groups)
+        MD_TRY(G.prec == MDLTS_FP64 ? fill_group<double>(c, P, G) : fill_group<float>(c, P, G));
+    return MDLTS_OK;
+}
+
+int grid_of(const BatchPlan &P, int n_tiles)
+{
+    int grid = (n_tiles + 7) / 8 * 8;
+    if (P.per_cu > 0) grid = std::min(grid, P.per_cu * P.n_cu);
+    return std::max(grid, 8);
+}
+
+// one barrier interval: launches on the stream, or kernel nodes of a graph
+mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, hipGraph_t graph, hipGraphNode_t *last)
+{
+    const long long nsub = 1ll << P.lmax_all;
+    auto add = [&](void *fn, int grid, int block, void **args) -> mdlts_status {
+        if (graph) {
+            hipKernelNodeParams kp{};
+            kp.func = fn;
+            kp.gridDim = dim3(grid);
+            kp.blockDim = dim3(block);
+            kp.sharedMemBytes = 0;
+            kp.kernelParams = args;
+            kp.extra = nullptr;
+            hipGraphNode_t node;
+            HIP_TRY(hipGraphAddKernelNode(&node, graph, *last ? last : nullptr, *last ? 1 : 0, &kp));
+            *last = node;
+        } else {
+            HIP_TRY(hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, c->stream));
+        }
+        return MDLTS_OK;
+    };
+    for (long long i = 0; i < nsub; i++) {
+        for (auto &G : P.groups) {
+            int n_t = G.tile_off[i + 1] - G.tile_off[i];
+            if (n_t == 0) continue;
+            const void *descs = G.descs.p;
+            const BatchTile *tl = static_cast<const BatchTile *>(G.tiles.p) + G.tile_off[i];
+            int ii = (int)i;
+            char *base = G.base;
+            void *args[] = {&descs, &tl, &n_t, &ii, &base};
+            const bool prof = P.prof && !graph;
+            if (prof) {
+                while (P.ev.size() < 2 * (P.ev_used + 1)) {
+                    hipEvent_t e;
+                    HIP_TRY(hipEventCreate(&e));
+                    P.ev.push_back(e);
+                }
+                HIP_TRY(hipEventRecord(P.ev[2 * P.ev_used], c->stream));
+            }
+            MD_TRY(add(batch_kernel(G.dim, G.order, G.prec), grid_of(P, n_t), P.block, args));
+            if (prof) {
+                HIP_TRY(hipEventRecord(P.ev[2 * P.ev_used + 1], c->stream));
+                P.ev_used++;
+                P.prof_launches++;
+            }
+        }
+    }
+    for (auto &G : P.groups) {
+        void *descs = G.descs.p;
+        int nm = (int)G.members.size();
+        void *args[] = {&descs, &nm};
+        void *fn = G.prec == MDLTS_FP64 ? reinterpret_cast<void *>(&k_batch_advance<double>)
+                                        : reinterpret_cast<void *>(&k_batch_advance<float>);
+        MD_TRY(add(fn, (nm + 63) / 64, 64, args));
+    }
+    return MDLTS_OK;
+}
+
+mdlts_status build_graph(mdlts_ctx *c, BatchPlan &P)
+{
+    free_graph(&P);
+    HIP_TRY(hipGraphCreate(&P.graph, 0));
+    hipGraphNode_t last = nullptr;
+    MD_TRY(emit_barrier(c, P, P.graph, &last));
+    HIP_TRY(hipGraphInstantiate(&P.exec, P.graph, nullptr, nullptr, 0));
+    return MDLTS_OK;
+}
+
+// host-side bookkeeping of barriers run by the batch
+void account_barriers(BatchPlan &P, int nb)
+{
+    for (size_t q = 0; q < P.sims.size(); q++) {
+        mdlts_sim *s = P.sims[q];
+        s->n_bar += nb;
+        s->n_since_assign += nb;
+        s->dof_updates += P.dof_per_barrier[q] * (uint64_t)nb;
+        s->eta_valid = false;
+    }
+    if (P.prof)
+        for (size_t q = 0; q < P.sims.size(); q++) P.prof_dof += P.dof_per_barrier[q] * (uint64_t)nb;
+}
+
+mdlts_status drain_batch_events(BatchPlan &P)
+{
+    if (P.ev_used == 0) return MDLTS_OK;
+    HIP_TRY(hipEventSynchronize(P.ev[2 * P.ev_used - 1]));
+    for (size_t q = 0; q < P.ev_used; q++) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, P.ev[2 * q], P.ev[2 * q + 1]));
+        P.prof_ms += ms;
+    }
+    P.ev_used = 0;
+    return MDLTS_OK;
+}
+
+mdlts_status run_batch_barriers(mdlts_ctx *c, BatchPlan &P, int nb)
+{
+    for (int b = 0; b < nb; b++) {
+        if (P.prof) {
+            if (P.ev_used + P.groups.size() * (1u << P.lmax_all) > kMaxEventPairs) MD_TRY(drain_batch_events(P));
+            MD_TRY(emit_barrier(c, P, nullptr, nullptr));
+        } else if (c->use_graphs) {
+            if (!P.exec) MD_TRY(build_graph(c, P));
+            HIP_TRY(hipGraphLaunch(P.exec, c->stream));
+        } else {
+            MD_TRY(emit_barrier(c, P, nullptr, nullptr));
+        }
+        account_barriers(P, 1);
+    }
+    return MDLTS_OK;
+}
+
+// Autotuner: the first barriers of a new plan are run with each candidate
+// launch shape (block size, one block per tile or persistent blocks) and
+// timed with events; the fastest shape is kept.  Per-element arithmetic
+// does not depend on the shape, so results are unchanged.
+mdlts_status autotune(mdlts_ctx *c, BatchPlan &P, int *remaining)
+{
+    struct Cand { int block, per_cu; };
+    const Cand cands[] = {{256, 0}, {128, 0}, {64, 0}, {256, 8}, {128, 16}};
+    const int reps = 2;
+    if (*remaining < (int)(sizeof(cands) / sizeof(cands[0])) * reps) return MDLTS_OK;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best = 1e30f;
+    Cand pick = cands[0];
+    const bool saved_prof = P.prof;
+    P.prof = false;
+    for (const Cand &cd : cands) {
+        P.block = cd.block;
+        P.per_cu = cd.per_cu;
+        MD_TRY(build_plan_data(c, P));
+        MD_TRY(emit_barrier(c, P, nullptr, nullptr));  // warm
+        account_barriers(P, 1);
+        HIP_TRY(hipEventRecord(e0, c->stream));
+        MD_TRY(emit_barrier(c, P, nullptr, nullptr));
+        account_barriers(P, 1);
+        HIP_TRY(hipEventRecord(e1, c->stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+            best = ms;
+            pick = cd;
+        }
+        *remaining -= reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    P.prof = saved_prof;
+    P.block = pick.block;
+    P.per_cu = pick.per_cu;
+    P.tuned = true;
+    return build_plan_data(c, P);
+}
+
+mdlts_status prepare_plan(mdlts_ctx *c, mdlts_sim *const *sims, int n, bool *fresh)
+{
+    *fresh = false;
+    BatchPlan *P = c->batch;
+    bool same = P && (int)P->sims.size() == n;
+    for (int q = 0; same && q < n; q++) same = P->sims[q] == sims[q] && P->versions[q] == sims[q]->version;
+    if (same) return MDLTS_OK;
+    int block = 256, per_cu = 0;
+    bool tuned = false;
+    if (P && (int)P->sims.size() == n) {
+        bool members = true;
+        for (int q = 0; q < n && members; q++) members = P->sims[q] == sims[q];
+        if (members && P->tuned) { block = P->block; per_cu = P->per_cu; tuned = true; }
+    }
+    free_plan(c);
+    P = new (std::nothrow) BatchPlan;
+    if (!P) return MDLTS_ENOMEM;
+    c->batch = P;
+    P->block = block;
+    P->per_cu = per_cu;
+    P->tuned = tuned;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+            P->n_cu = ncu;
+    }
+    for (int q = 0; q < n; q++) {
+        mdlts_sim *s = sims[q];
+        if (s->step_dirty)
+            MD_TRY(s->desc.precision == MDLTS_FP64 ? upload_step_args<double>(s) : upload_step_args<float>(s));
+        P->sims.push_back(s);
+        P->lmax_all = std::max(P->lmax_all, s->lmax);
+        uint64_t dof = 0;
+        for (long long i = 0; i < (1ll << s->lmax); i++) {
+            int v2 = 0;
+            while (i > 0 && ((i >> v2) & 1) == 0) v2++;
+            dof += (uint64_t)s->cnt_ge[i == 0 ? 0 : s->lmax - v2] * (uint64_t)s->np;
+        }
+        P->dof_per_barrier.push_back(dof);
+        int g = -1;
+        for (size_t k = 0; k < P->groups.size(); k++)
+            if (P->groups[k].dim == s->desc.dim && P->groups[k].order == s->desc.order &&
+                P->groups[k].prec == s->desc.precision)
+                g = (int)k;
+        if (g < 0) {
+            P->groups.emplace_back();
+            g = (int)P->groups.size() - 1;
+            P->groups[g].dim = s->desc.dim;
+            P->groups[g].order = s->desc.order;
+            P->groups[g].prec = s->desc.precision;
+        }
+        P->groups[g].members.push_back(q);
+    }
+    for (int q = 0; q < n; q++) P->versions.push_back(sims[q]->version);
+    *fresh = true;
+    return build_plan_data(c, *P);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1033,6 +1398,7 @@ mdlts_status mdlts_ctx_destroy(mdlts_ctx *ctx)
 {
     if (!ctx) return MDLTS_EINVAL;
     if (ctx->n_sims > 0) return MDLTS_EBUSY;
+    free_plan(ctx);
     delete ctx;
     return MDLTS_OK;
 }
@@ -1079,6 +1445,12 @@ mdlts_status mdlts_sim_destroy(mdlts_sim *s)
     if (!s) return MDLTS_EINVAL;
     mdlts_ctx *c = s->ctx;
     (void)hipStreamSynchronize(c->stream);
+    if (c->batch)
+        for (mdlts_sim *m : c->batch->sims)
+            if (m == s) {
+                free_plan(c);
+                break;
+            }
     DevBuf *bufs[] = {&s->key_c, &s->face_c, &s->fine_c, &s->u_c, &s->v_c, &s->level_c, &s->cfl_c, &s->eta_c,
                       &s->tmp_u, &s->tmp_v, &s->u_s, &s->v_s, &s->key_s, &s->nbr_s, &s->fine_s, &s->perm,
                       &s->inv, &s->hist, &s->cnt_ge_d, &s->flags, &s->xk, &s->xs, &s->xc, &s->stage,
@@ -1096,6 +1468,7 @@ mdlts_status mdlts_sim_destroy(mdlts_sim *s)
 mdlts_status mdlts_set_tree(mdlts_sim *s, const uint8_t *bits, size_t n_bits)
 {
     if (!s || (!bits && n_bits)) return MDLTS_EINVAL;
+    s->version++;
     Forest F;
     forest_from_desc(&s->desc, F);
     if (!F.parse_bits(bits, n_bits)) return MDLTS_EINVAL;
@@ -1125,6 +1498,7 @@ mdlts_status mdlts_n_leaves(mdlts_sim *s, size_t *n)
 mdlts_status mdlts_set_conductivity(mdlts_sim *s, const double D_sym[6], double gamma)
 {
     if (!s || !(gamma > 0.0) || !std::isfinite(gamma)) return MDLTS_EINVAL;
+    s->version++;
     double Dk[3];
     if (!diag_of(D_sym, s->desc.dim, Dk)) return MDLTS_EINVAL;
     double G[4][4];
@@ -1140,6 +1514,7 @@ mdlts_status mdlts_set_conductivity(mdlts_sim *s, const double D_sym[6], double 
 mdlts_status mdlts_set_ionic(mdlts_sim *s, const mdlts_ap_params *p)
 {
     if (!s || !p) return MDLTS_EINVAL;
+    s->version++;
     s->ap = *p;
     s->step_dirty = true;
     return MDLTS_OK;
@@ -1148,6 +1523,7 @@ mdlts_status mdlts_set_ionic(mdlts_sim *s, const mdlts_ap_params *p)
 mdlts_status mdlts_set_stimulus(mdlts_sim *s, const mdlts_stim_box *boxes, int n_boxes)
 {
     if (!s || n_boxes < 0 || n_boxes > kMaxStim || (n_boxes && !boxes)) return MDLTS_EINVAL;
+    s->version++;
     s->stim.assign(boxes, boxes + n_boxes);
     s->step_dirty = true;
     return MDLTS_OK;
@@ -1156,6 +1532,7 @@ mdlts_status mdlts_set_stimulus(mdlts_sim *s, const mdlts_stim_box *boxes, int n
 mdlts_status mdlts_set_state(mdlts_sim *s, const double *u, const double *v, size_t n_dof)
 {
     if (!s) return MDLTS_EINVAL;
+    s->version++;
     const size_t E = s->E;
     if (n_dof != E * (size_t)s->np) return MDLTS_EINVAL;
     mdlts_ctx *c = s->ctx;
@@ -1211,6 +1588,7 @@ mdlts_status mdlts_get_state(mdlts_sim *s, double *u, double *v, size_t n_dof)
 mdlts_status mdlts_set_time(mdlts_sim *s, double t)
 {
     if (!s || !std::isfinite(t)) return MDLTS_EINVAL;
+    s->version++;
     s->t_start = t;
     s->n_bar = 0;
     return MDLTS_OK;
@@ -1232,6 +1610,7 @@ mdlts_status mdlts_assign_uniform(mdlts_sim *s, double dt_barrier, int level, in
 static mdlts_status assign_levels_impl(mdlts_sim *s, double dt_barrier, int force_level, int32_t *level_hist)
 {
     if (!s || !(dt_barrier > 0.0) || !std::isfinite(dt_barrier)) return MDLTS_EINVAL;
+    s->version++;
     mdlts_ctx *c = s->ctx;
     const int E = (int)s->E;
     const int L = s->desc.n_levels;
@@ -1341,6 +1720,7 @@ mdlts_status mdlts_get_cfl(mdlts_sim *s, double *cfl, size_t n_leaves)
 mdlts_status mdlts_step(mdlts_sim *s, int n_barriers)
 {
     if (!s || n_barriers < 0) return MDLTS_EINVAL;
+    s->version++;
     if (!s->levels_valid || !s->state_grouped) return MDLTS_ESTATE;
     s->eta_valid = false;
     if (s->desc.precision == MDLTS_FP64) return run_barriers<double>(s, n_barriers);
@@ -1384,6 +1764,7 @@ mdlts_status mdlts_adapt(mdlts_sim *s, const double *eta, size_t n_leaves, doubl
     const size_t E = s->E;
     if (eta && n_leaves != E) return MDLTS_EINVAL;
     if (!eta && !s->eta_valid) return MDLTS_ESTATE;
+    s->version++;
     mdlts_ctx *c = s->ctx;
     if (eta) {
         MD_TRY(copy_h2d(c, s->eta_c, eta, E));
@@ -1421,6 +1802,58 @@ mdlts_status mdlts_profile_read(mdlts_sim *s, double *substep_ms, uint64_t *n_la
     if (dof_updates) *dof_updates = s->prof_dof;
     s->prof_ms = 0.0;
     s->prof_launches = s->prof_dof = 0;
+    return MDLTS_OK;
+}
+
+mdlts_status mdlts_batch_step(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sims, int n_barriers)
+{
+    if (!ctx || !sims || n_sims < 1 || n_barriers < 0) return MDLTS_EINVAL;
+    for (int q = 0; q < n_sims; q++) {
+        if (!sims[q] || sims[q]->ctx != ctx) return MDLTS_EINVAL;
+        for (int r = 0; r < q; r++)
+            if (sims[r] == sims[q]) return MDLTS_EINVAL;
+        if (!sims[q]->levels_valid || !sims[q]->state_grouped) return MDLTS_ESTATE;
+    }
+    bool fresh = false;
+    MD_TRY(prepare_plan(ctx, sims, n_sims, &fresh));
+    BatchPlan &P = *ctx->batch;
+    int remaining = n_barriers;
+    if (!P.tuned) MD_TRY(autotune(ctx, P, &remaining));
+    MD_TRY(run_batch_barriers(ctx, P, remaining));
+    return MDLTS_OK;
+}
+
+mdlts_status mdlts_set_graphs(mdlts_ctx *ctx, int enable)
+{
+    if (!ctx) return MDLTS_EINVAL;
+    ctx->use_graphs = enable != 0;
+    return MDLTS_OK;
+}
+
+mdlts_status mdlts_batch_profile(mdlts_ctx *ctx, int enable)
+{
+    if (!ctx || !ctx->batch) return MDLTS_ESTATE;
+    BatchPlan &P = *ctx->batch;
+    MD_TRY(drain_batch_events(P));
+    P.prof = enable != 0;
+    P.prof_ms = 0.0;
+    P.prof_launches = P.prof_dof = 0;
+    return MDLTS_OK;
+}
+
+mdlts_status mdlts_batch_profile_read(mdlts_ctx *ctx, double *substep_ms, uint64_t *n_launches,
+                                      uint64_t *dof_updates, int *block, int *per_cu)
+{
+    if (!ctx || !ctx->batch) return MDLTS_ESTATE;
+    BatchPlan &P = *ctx->batch;
+    MD_TRY(drain_batch_events(P));
+    if (substep_ms) *substep_ms = P.prof_ms;
+    if (n_launches) *n_launches = P.prof_launches;
+    if (dof_updates) *dof_updates = P.prof_dof;
+    if (block) *block = P.block;
+    if (per_cu) *per_cu = P.per_cu;
+    P.prof_ms = 0.0;
+    P.prof_launches = P.prof_dof = 0;
     return MDLTS_OK;
 }
 

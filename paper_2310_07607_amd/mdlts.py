@@ -89,6 +89,10 @@ def lib():
         "mdlts_adapt": (I, [P, P, S, D, D, P, P]),
         "mdlts_counters": (I, [P, P, P]),
         "mdlts_profile": (I, [P, I]),
+        "mdlts_batch_step": (I, [P, P, I, I]),
+        "mdlts_set_graphs": (I, [P, I]),
+        "mdlts_batch_profile": (I, [P, I]),
+        "mdlts_batch_profile_read": (I, [P, P, P, P, P, P]),
         "mdlts_profile_read": (I, [P, P, P, P]),
         "mdlts_cfl_bound": (I, [P, P, D, I, P]),
         "mdlts_plan_adapt": (I, [P, P, S, P, S, D, D, P, S, P]),
@@ -192,6 +196,26 @@ class Context:
 
     def sync(self):
         _chk(lib().mdlts_sync(self.h), "mdlts_sync")
+
+    def batch_step(self, sims, n_barriers=1):
+        """Advance several simulations together (one launch per substep and kind)."""
+        arr = (ctypes.c_void_p * len(sims))(*[s.h.value for s in sims])
+        _chk(lib().mdlts_batch_step(self.h, arr, len(sims), int(n_barriers)), "mdlts_batch_step")
+
+    def set_graphs(self, enable=True):
+        _chk(lib().mdlts_set_graphs(self.h, 1 if enable else 0), "mdlts_set_graphs")
+
+    def batch_profile(self, enable=True):
+        _chk(lib().mdlts_batch_profile(self.h, 1 if enable else 0), "mdlts_batch_profile")
+
+    def batch_profile_read(self):
+        """(kernel ms, launches, DoF-updates, threads per block, persistent blocks per CU)."""
+        ms = ctypes.c_double()
+        nl, nd = ctypes.c_uint64(), ctypes.c_uint64()
+        blk, pcu = ctypes.c_int(), ctypes.c_int()
+        _chk(lib().mdlts_batch_profile_read(self.h, ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(nd),
+                                            ctypes.byref(blk), ctypes.byref(pcu)), "mdlts_batch_profile_read")
+        return ms.value, nl.value, nd.value, blk.value, pcu.value
 
     def close(self):
         """Destroys the context after closing every simulation created on it."""
