@@ -28,10 +28,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DoF-updates/s (SIPG apply+ionic, LTS) FP32 vs FP64 plain; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per DoF-update of the Q1-2D FP32 substep: read u, v and
-# write u, v (16 B) plus per element a 4 B key and four 4 B face entries over
-# 4 nodes (5 B)
-BYTES_PER_DOF_Q1_2D_F32 = 21.0
+# algorithmic bytes per DoF-update of the FP32 substep: read u, v and write
+# u, v (16 B) plus, per element, the key (4 B in 2-D, 8 B in 3-D) and one
+# 4 B entry per face, shared by the element's nodes
+def bytes_per_dof(dim, p):
+    npe = (p + 1) ** dim
+    return 16.0 + ((4 if dim == 2 else 8) + 4 * 2 * dim) / npe
+
+
+BYTES_PER_DOF_Q1_2D_F32 = bytes_per_dof(2, 1)  # 21 B
 
 
 def parse():
@@ -45,6 +50,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-barriers", type=int, default=200)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-sims", type=int, default=64)
+    ap.add_argument("--batched-barriers", type=int, default=64)
     return ap.parse_args()
 
 
@@ -71,6 +79,80 @@ def interval(sim, W, dt):
     sim.adapt(W["tau_refine"], W["tau_coarsen"])
     sim.assign_levels(dt)
     sim.step(W["amr_every"])
+
+
+def batched_leg(ctx, args):
+    """The batched workload: many simulations advanced together."""
+    from paper_2310_07607_amd import inputs, mdlts
+    specs = inputs.batched_workload(args.seed, args.batched_sims)
+    sims, dts = [], []
+    for w in specs:
+        s = mdlts.Simulation(ctx, w["dim"], w["p"], w["n"], w["length"], w["max_depth"], w["n_levels"], "f32")
+        s.set_conductivity(w["D"], w["gamma"])
+        s.set_ionic(*inputs.AP_PARAMS)
+        s.set_stimulus(inputs.box_array(w["stim"]))
+        desc = mdlts.make_desc(w["dim"], w["p"], w["n"], w["length"], w["max_depth"], w["n_levels"])
+        dt = 2 ** (w["n_levels"] - 1) * mdlts.cfl_bound(desc, w["D"], w["gamma"], w["max_depth"]) * (1 - 2 ** -20)
+        s.assign_levels(dt)
+        s.set_time(0.0)
+        sims.append(s)
+        dts.append(dt)
+    tau_r, tau_c = inputs.WORKLOADS["amr_2d"]["tau_refine"], inputs.WORKLOADS["amr_2d"]["tau_coarsen"]
+    every = 32
+
+    def adapt_all():
+        for s, dt in zip(sims, dts):
+            s.indicator(download=False)
+            s.adapt(tau_r, tau_c)
+            s.assign_levels(dt)
+
+    # warm-up: adaptation intervals from rest through the stimulus
+    for _ in range(3):
+        adapt_all()
+        ctx.batch_step(sims, every)
+    ctx.sync()
+    c0 = [s.counters()[0] for s in sims]
+    w0 = time.perf_counter()
+    ctx.batch_step(sims, args.batched_barriers)
+    ctx.sync()
+    wall = time.perf_counter() - w0
+    c1 = [s.counters()[0] for s in sims]
+    dof = sum(b - a for a, b in zip(c0, c1))
+    bytes_alg = sum((b - a) * bytes_per_dof(w["dim"], w["p"]) for a, b, w in zip(c0, c1, specs))
+    # kernel timing pass
+    ctx.batch_profile(True)
+    c0 = [s.counters()[0] for s in sims]
+    ctx.batch_step(sims, 16)
+    ms, nl, nd, blk, pcu = ctx.batch_profile_read()
+    ctx.batch_profile(False)
+    c1 = [s.counters()[0] for s in sims]
+    kbytes = sum((b - a) * bytes_per_dof(w["dim"], w["p"]) for a, b, w in zip(c0, c1, specs))
+    achieved = kbytes / (ms * 1e-3) / 1e9
+    # one full adaptation interval (indicator + adaptation + levels for every
+    # simulation, then `every` barriers) end to end
+    w1 = time.perf_counter()
+    a0 = sum(s.counters()[0] for s in sims)
+    adapt_all()
+    ctx.batch_step(sims, every)
+    ctx.sync()
+    w_int = time.perf_counter() - w1
+    a1 = sum(s.counters()[0] for s in sims)
+    n_dof = sum(s.n_dof for s in sims)
+    out = {"sims": len(sims), "dof": n_dof, "state_bytes_fp32": 12 * n_dof,
+           "value": dof / wall, "unit": "DoF-updates/s", "barriers": args.batched_barriers,
+           "ms_per_barrier": wall / args.batched_barriers * 1e3,
+           "with_adaptation": {"value": (a1 - a0) / w_int, "interval_ms": w_int * 1e3, "barriers": every},
+           "launch_shape": {"block": blk, "persistent_blocks_per_cu": pcu},
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "kernel": "k_substep_batch<dim,p,float>", "kernel_ms": ms, "launches": nl,
+                        "avg_launch_us": ms * 1e3 / max(nl, 1),
+                        "bytes_per_dof_update": {"q1_2d": bytes_per_dof(2, 1), "q2_2d": bytes_per_dof(2, 2),
+                                                 "q1_3d": bytes_per_dof(3, 1), "q2_3d": bytes_per_dof(3, 2)}},
+           "wall_bytes_per_s": bytes_alg / wall}
+    for s in sims:
+        s.close()
+    return out
 
 
 def cpu_baseline(W, dt, seconds, seed):
@@ -207,11 +289,13 @@ def main():
                      "kernel": "k_substep<2,1,float>", "bytes_per_dof_update": BYTES_PER_DOF_Q1_2D_F32,
                      "avg_launch_us": k_ms * 1e3 / max(k_launch, 1)},
     }
+    for s in (sim, plain, lts, ref):
+        s.close()
+    if not args.no_batched:
+        out["batched"] = batched_leg(ctx, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, dt, args.cpu_seconds, args.seed)
     print(json.dumps(out), flush=True)
-    for s in (sim, plain, lts, ref):
-        s.close()
     ctx.close()
 
 

@@ -330,6 +330,17 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
                 t++;
             }
         }
+        // elements too large to prefetch every face load the two neighbours
+        // of this direction together (one memory round trip per direction)
+        T nbd[2][kPrefetch ? 1 : NP];
+        if constexpr (!kPrefetch) {
+#pragma unroll
+            for (int s = 0; s < 2; s++) {
+                const uint32_t kind = ent[2 * k + s] >> 30;
+                const bool one = kind == kSame || kind == kCoarser;
+                neighbour_values<T, NP>(a, L, one ? ent[2 * k + s] : self_ent, nbd[s]);
+            }
+        }
 #pragma unroll
         for (int s = 0; s < 2; s++) {
             const int f = 2 * k + s;
@@ -352,6 +363,19 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
             T Fl[NF], Hl[NF];
             if (kind != kFiner) {
                 T nu[NF], nq[NF];
+                auto trace_from = [&](const T *nv) {
+#pragma unroll
+                    for (int g = 0; g < NF; g++) {
+                        T su = 0, sq = 0;
+#pragma unroll
+                        for (int b = 0; b < M; b++) {
+                            su += a.ref.B[1 - s][b] * nv[fnode<DIM, M>(k, g, b)];
+                            sq += a.ref.G[1 - s][b] * nv[fnode<DIM, M>(k, g, b)];
+                        }
+                        nu[g] = su;
+                        nq[g] = sq;
+                    }
+                };
                 if constexpr (kPrefetch) {
 #pragma unroll
                     for (int g = 0; g < NF; g++) {
@@ -365,7 +389,7 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
                         nq[g] = sq;
                     }
                 } else {
-                    neighbour_trace<T, DIM, P>(a, L, ent[f], k, 1 - s, nu, nq);
+                    trace_from(nbd[s]);
                 }
                 const bool co = kind == kCoarser;  // h_nbr = 2h
                 if (kind == kCoarser) {

@@ -39,6 +39,32 @@ WORKLOADS = {
 }
 
 
+def batched_workload(seed=0, n_sims=64):
+    """The batched workload: n_sims independent simulations drawn from a
+    seeded generator.  dim 2 or 3 and degree 1 or 2 with probability 1/2
+    each; roots N^2 with N log-uniform in [32, 256] (2-D) or N^3 with N
+    log-uniform in [16, 64] (3-D); root size 1/64 cm; D = c 1e-3 I with c
+    uniform in [0.5, 2]; a 0.1 cm stimulus box at a uniform site for 1 ms;
+    refinement depth 1 and 3 LTS levels; FP32."""
+    r = rng(seed)
+    out = []
+    for _ in range(n_sims):
+        dim = int(r.integers(2, 4))
+        p = int(r.integers(1, 3))
+        lo, hi = (32, 256) if dim == 2 else (16, 64)
+        N = int(round(np.exp(r.uniform(np.log(lo), np.log(hi)))))
+        h0 = 1.0 / 64
+        c = r.uniform(0.5, 2.0)
+        length = tuple([N * h0] * dim)
+        site = [r.uniform(0.05, N * h0 - 0.05) for _ in range(dim)]
+        lo_b = tuple(x - 0.05 for x in site)
+        hi_b = tuple(x + 0.05 for x in site)
+        out.append(dict(dim=dim, p=p, n=tuple([N] * dim), length=length, max_depth=1, n_levels=3,
+                        D=tuple([c * 1e-3] * dim), gamma=2.0 if p == 1 else 4.0,
+                        stim=[(lo_b, hi_b, 0.0, 1.0, 1.0)], fp="f32"))
+    return out
+
+
 def rng(seed):
     return np.random.default_rng(seed)
 
