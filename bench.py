@@ -17,8 +17,8 @@ substep kernel's average duration (roofline) from a following pass of
 Prints one JSON line (rank 0, N = 1).
 """
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -38,6 +38,29 @@ def bytes_per_dof(dim, p):
 
 BYTES_PER_DOF_Q1_2D_F32 = bytes_per_dof(2, 1)  # 21 B
 
+# Measured HBM traffic of the substep kernels per algorithmic byte: rocprofv3
+# FETCH_SIZE and WRITE_SIZE summed over every dispatch of a kernel in a run of
+# this script, each counter scaled by what it reads for a plain device copy of
+# known size (`--copy-probe`), divided by the algorithmic bytes of the same
+# dispatches (the "dispatch_totals" this script prints).  An entry is used only
+# while the kernel source still has the digest it was measured with.
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2310_07607_amd", "csrc", "kernels.hpp")
+FETCH_SCALE = 2.0   # copy of 256 MiB: FETCH_SIZE reads 128.0 MiB
+WRITE_SCALE = 1.0   # copy of 256 MiB: WRITE_SIZE reads 256.0 MiB
+MEASURED_TRAFFIC = {}
+
+
+def kernel_digest():
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_per_launch(kernel, alg_bytes_per_launch):
+    m = MEASURED_TRAFFIC.get(kernel)
+    if m is None or m["digest"] != kernel_digest():
+        return None
+    return m["hbm_over_algorithmic"] * alg_bytes_per_launch
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -53,7 +76,26 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-sims", type=int, default=64)
     ap.add_argument("--batched-barriers", type=int, default=64)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-rates", default="10,50,200", help="Poisson arrival rates, requests/s")
+    ap.add_argument("--serve-requests", type=int, default=32, help="requests per rate")
+    ap.add_argument("--serve-time-scale", type=float, default=0.02,
+                    help="simulated time per request = U[20, 100] ms times this")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 256 MiB on the device 5 times (calibrates the HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_probe():
+    import torch
+    n = 64 << 20
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe": {"bytes_read_per_copy": 4 * n, "bytes_written_per_copy": 4 * n,
+                                     "copies": 5}}), flush=True)
 
 
 def setup(ctx, W, seed, precision, n_levels=None):
@@ -128,6 +170,7 @@ def batched_leg(ctx, args):
     c1 = [s.counters()[0] for s in sims]
     kbytes = sum((b - a) * bytes_per_dof(w["dim"], w["p"]) for a, b, w in zip(c0, c1, specs))
     achieved = kbytes / (ms * 1e-3) / 1e9
+    traffic = traffic_per_launch("k_substep_batch", kbytes / max(nl, 1))
     # one full adaptation interval (indicator + adaptation + levels for every
     # simulation, then `every` barriers) end to end
     w1 = time.perf_counter()
@@ -138,20 +181,56 @@ def batched_leg(ctx, args):
     w_int = time.perf_counter() - w1
     a1 = sum(s.counters()[0] for s in sims)
     n_dof = sum(s.n_dof for s in sims)
+    totals = {}
+    for s, w in zip(sims, specs):
+        key = f"k_substep_batch<{w['dim']},{w['p']},float>"
+        totals[key] = totals.get(key, 0) + s.counters()[0]
     out = {"sims": len(sims), "dof": n_dof, "state_bytes_fp32": 12 * n_dof,
            "value": dof / wall, "unit": "DoF-updates/s", "barriers": args.batched_barriers,
            "ms_per_barrier": wall / args.batched_barriers * 1e3,
            "with_adaptation": {"value": (a1 - a0) / w_int, "interval_ms": w_int * 1e3, "barriers": every},
            "launch_shape": {"block": blk, "persistent_blocks_per_cu": pcu},
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                        "traffic_unit": "HBM bytes per launch",
+                        "algorithmic_bytes_per_launch": kbytes / max(nl, 1),
                         "kernel": "k_substep_batch<dim,p,float>", "kernel_ms": ms, "launches": nl,
                         "avg_launch_us": ms * 1e3 / max(nl, 1),
                         "bytes_per_dof_update": {"q1_2d": bytes_per_dof(2, 1), "q2_2d": bytes_per_dof(2, 2),
                                                  "q1_3d": bytes_per_dof(3, 1), "q2_3d": bytes_per_dof(3, 2)}},
-           "wall_bytes_per_s": bytes_alg / wall}
+           "wall_bytes_per_s": bytes_alg / wall,
+           "dispatch_totals": {"unit": "DoF-updates since creation", **totals}}
     for s in sims:
         s.close()
+    return out
+
+
+def serving_leg(ctx, args):
+    """Continuous batching: Poisson arrivals of solves from the batched
+    distribution plus 5 % of the 3-D slab, admitted by device memory."""
+    import torch
+    from paper_2310_07607_amd import inputs
+    from paper_2310_07607_amd.serving import MdltsBackend, Request, Server, summarize
+    W = inputs.WORKLOADS["amr_2d"]
+    large = {"max_depth": 1, "n_levels": 3}
+    free, total = torch.cuda.mem_get_info()
+    budget = int(0.5 * free)
+    out = {"budget_bytes": budget, "amr_every": 32, "time_scale": args.serve_time_scale,
+           "large_request": "128x48x24 Q2 slab, refinement depth 1, 3 LTS levels", "rates": {}}
+    for k, rate in enumerate(float(x) for x in args.serve_rates.split(",")):
+        reqs = inputs.serving_requests(args.seed + 100 * k, args.serve_requests, rate, args.serve_time_scale,
+                                       large_overrides=large)
+        be = MdltsBackend(ctx, W["tau_refine"], W["tau_coarsen"], amr_every=32, keep_state=False)
+        srv = Server(be, budget)
+        rs = [Request(i, s, t, a) for i, (s, t, a) in enumerate(reqs)]
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        done = srv.run(rs, realtime=True)
+        wall = time.perf_counter() - w0
+        res = summarize(done, wall, be.device_ms)
+        res.update({"peak_resident": srv.peak_resident, "ticks": srv.ticks,
+                    "large_requests": sum(1 for s, _, _ in reqs if s["dim"] == 3 and s["n"][0] == 128)})
+        out["rates"][f"{rate:g}"] = res
     return out
 
 
@@ -183,6 +262,9 @@ def cpu_baseline(W, dt, seconds, seed):
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in DESIGN.md "
                                    "but not built", "n_gpus": args.gpus}))
@@ -259,6 +341,10 @@ def main():
     err = float(np.linalg.norm(ul - ur) / np.linalg.norm(ur))
 
     achieved = BYTES_PER_DOF_Q1_2D_F32 * k_dof / (k_ms * 1e-3) / 1e9 if k_ms > 0 else 0.0
+    alg_per_launch = BYTES_PER_DOF_Q1_2D_F32 * k_dof / max(k_launch, 1)
+    totals = {"unit": "DoF-updates since creation",
+              "k_substep<2,1,float>": sim.counters()[0] + lts.counters()[0],
+              "k_substep<2,1,double>": plain.counters()[0] + ref.counters()[0]}
     out = {
         "metric": METRIC,
         "value": value,
@@ -285,14 +371,19 @@ def main():
                        "lts_fp32_sim_ms_per_s": args.steps * W["amr_every"] * dt / wall,
                        "rel_l2_fp32_lts_vs_fp64_plain": err, "window_ms": nb * dt},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic_per_launch("k_substep<2,1,float>", alg_per_launch),
+                     "traffic_unit": "HBM bytes per launch", "algorithmic_bytes_per_launch": alg_per_launch,
                      "kernel": "k_substep<2,1,float>", "bytes_per_dof_update": BYTES_PER_DOF_Q1_2D_F32,
                      "avg_launch_us": k_ms * 1e3 / max(k_launch, 1)},
+        "dispatch_totals": totals,
     }
     for s in (sim, plain, lts, ref):
         s.close()
     if not args.no_batched:
         out["batched"] = batched_leg(ctx, args)
+    if not args.no_serving:
+        out["serving"] = serving_leg(ctx, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, dt, args.cpu_seconds, args.seed)
     print(json.dumps(out), flush=True)

@@ -226,6 +226,15 @@ mdlts_status mdlts_plan_adapt(const mdlts_mesh_desc *desc, const uint8_t *bits, 
 mdlts_status mdlts_plan_levels(const mdlts_mesh_desc *desc, const uint8_t *bits, size_t n_bits, const double D_sym[6],
                                double gamma, double dt_barrier, int8_t *level, int32_t *perm, int32_t *cnt_ge,
                                double *cfl, size_t n_leaves);
+/* Upper bound, in bytes, of the device memory one simulation of this shape
+ * holds while it never has more than max_leaves leaves: both state layouts,
+ * the transfer and staging buffers, face, level and adaptation tables, and its
+ * share of a batch plan.  A request loop that admits solves by device memory
+ * (continuous batching of many simulations, as in the batched form of the
+ * LTS step) reserves this for the worst-case leaf count of a request, i.e.
+ * every root refined to max_depth.  Host only; no device call.
+ * EINVAL: bad descriptor, max_leaves < 1 or >= 2^27, bytes NULL. */
+mdlts_status mdlts_memory_bound(const mdlts_mesh_desc *desc, int64_t max_leaves, uint64_t *bytes);
 
 #ifdef __cplusplus
 }

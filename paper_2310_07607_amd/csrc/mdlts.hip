@@ -424,6 +424,14 @@ struct mdlts_ctx {
     int n_sims = 0;  // live simulations; the context outlives them
     BatchPlan *batch = nullptr;
     int use_graphs = 1;
+    // launch shape chosen by the autotuner, per mix of kernel variants
+    // (bit 4*(dim-2) + 2*(order-1) + precision); -1 = not tuned yet
+    int tuned_block[256];
+    int tuned_per_cu[256];
+    mdlts_ctx()
+    {
+        for (int k = 0; k < 256; k++) tuned_block[k] = tuned_per_cu[k] = -1;
+    }
 };
 
 struct mdlts_sim {
@@ -1023,6 +1031,7 @@ struct BatchPlan {
     bool tuned = false;
     std::vector<BatchGroup> groups;
     std::vector<uint64_t> dof_per_barrier;  // per simulation
+    int variant_mask = 0;                   // kernel variants present
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int n_cu = 256;
@@ -1291,6 +1300,8 @@ mdlts_status autotune(mdlts_ctx *c, BatchPlan &P, int *remaining)
     P.block = pick.block;
     P.per_cu = pick.per_cu;
     P.tuned = true;
+    c->tuned_block[P.variant_mask] = pick.block;
+    c->tuned_per_cu[P.variant_mask] = pick.per_cu;
     return build_plan_data(c, P);
 }
 
@@ -1301,20 +1312,10 @@ mdlts_status prepare_plan(mdlts_ctx *c, mdlts_sim *const *sims, int n, bool *fre
     bool same = P && (int)P->sims.size() == n;
     for (int q = 0; same && q < n; q++) same = P->sims[q] == sims[q] && P->versions[q] == sims[q]->version;
     if (same) return MDLTS_OK;
-    int block = 256, per_cu = 0;
-    bool tuned = false;
-    if (P && (int)P->sims.size() == n) {
-        bool members = true;
-        for (int q = 0; q < n && members; q++) members = P->sims[q] == sims[q];
-        if (members && P->tuned) { block = P->block; per_cu = P->per_cu; tuned = true; }
-    }
     free_plan(c);
     P = new (std::nothrow) BatchPlan;
     if (!P) return MDLTS_ENOMEM;
     c->batch = P;
-    P->block = block;
-    P->per_cu = per_cu;
-    P->tuned = tuned;
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess) {
         int ncu = 0;
@@ -1349,6 +1350,14 @@ mdlts_status prepare_plan(mdlts_ctx *c, mdlts_sim *const *sims, int n, bool *fre
         P->groups[g].members.push_back(q);
     }
     for (int q = 0; q < n; q++) P->versions.push_back(sims[q]->version);
+    for (const BatchGroup &g : P->groups)
+        P->variant_mask |= 1 << (4 * (g.dim - 2) + 2 * (g.order - 1) + (g.prec == MDLTS_FP32 ? 1 : 0));
+    // a mix of variants tuned before keeps its launch shape
+    if (c->tuned_block[P->variant_mask] > 0) {
+        P->block = c->tuned_block[P->variant_mask];
+        P->per_cu = c->tuned_per_cu[P->variant_mask];
+        P->tuned = true;
+    }
     *fresh = true;
     return build_plan_data(c, *P);
 }
@@ -1906,6 +1915,34 @@ mdlts_status mdlts_plan_adapt(const mdlts_mesh_desc *desc, const uint8_t *bits, 
     plan.next.write_bits(out);
     *n_out = out.size();
     if (out_bits && cap >= out.size()) std::memcpy(out_bits, out.data(), out.size());
+    return MDLTS_OK;
+}
+
+mdlts_status mdlts_memory_bound(const mdlts_mesh_desc *desc, int64_t max_leaves, uint64_t *bytes)
+{
+    if (!valid_desc(desc) || max_leaves < 1 || max_leaves >= (1 << 27) || !bytes) return MDLTS_EINVAL;
+    const uint64_t d = (uint64_t)desc->dim;
+    const uint64_t np = desc->dim == 2 ? (uint64_t)(desc->order + 1) * (desc->order + 1)
+                                       : (uint64_t)(desc->order + 1) * (desc->order + 1) * (desc->order + 1);
+    const uint64_t T = desc->precision == MDLTS_FP64 ? 8 : 4;
+    const uint64_t ksz = desc->dim == 2 ? 4 : 8;
+    const uint64_t ns = desc->dim == 2 ? 2 : 4;
+    const uint64_t nsub = 1ull << (desc->n_levels - 1);
+    // every buffer a simulation holds is sized by its largest leaf count
+    const uint64_t per_leaf =
+        7 * np * T                  // u and v canonical, transfer copies, two u slots and v grouped
+        + 8 * np                    // FP64 staging of uploads and readbacks
+        + 3 * ksz + 4               // canonical, new and grouped keys; Morton keys
+        + 2 * (2 * d * 4)           // face tables, canonical and grouped
+        + 2 * (2 * d * ns * 4)      // sub-face tables, canonical and grouped
+        + 1 + 1 + 4 + 4 + 4 + 1     // refine and coarsen flags, counts, offsets, root offsets, scan sums
+        + 1 + 4 + 1                 // transfer kind, source and child
+        + 1 + 8 + 4 + 4 + 8 + 1     // level, CFL, permutation both ways, indicator, histogram share
+        + (nsub * 16 + 31) / 32;    // batch tiles: per substep one per 64 leaves (blocks of >= 64 threads)
+    const uint64_t fixed = 64 * 512         // allocator rounding of every buffer
+                           + 4 * 4096       // flags, step constants, batch descriptor, small scans
+                           + nsub * 16 * 2; // tile list heads
+    *bytes = per_leaf * (uint64_t)max_leaves + fixed;
     return MDLTS_OK;
 }
 

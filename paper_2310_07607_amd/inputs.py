@@ -65,6 +65,31 @@ def batched_workload(seed=0, n_sims=64):
     return out
 
 
+def serving_requests(seed, n_requests, rate, t_scale=1.0, large_frac=0.05, large_overrides=None):
+    """Requests of the serving workload: Poisson arrivals at `rate` per second
+    (exponential gaps, the first at time 0); each solve is a draw of the
+    batched workload, or with probability `large_frac` the 3-D slab
+    (128x48x24 Q2, anisotropic D, corner stimulus), with `large_overrides`
+    applied to it; simulated time uniform in [20, 100] ms times `t_scale`.
+    Returns [(spec, t_sim_ms, arrival_s)]."""
+    r = rng(seed)
+    gaps = r.exponential(1.0 / rate, size=n_requests)
+    gaps[0] = 0.0
+    arrivals = np.cumsum(gaps)
+    small = batched_workload(seed + 1, n_requests)
+    out = []
+    for q in range(n_requests):
+        if r.uniform() < large_frac:
+            w = dict(WORKLOADS["amr_3d"])
+            w.update(large_overrides or {})
+            spec = dict(dim=3, p=w["p"], n=tuple(w["n"]), length=tuple(w["length"]), max_depth=w["max_depth"],
+                        n_levels=w["n_levels"], D=tuple(w["D"]), gamma=w["gamma"], stim=list(w["stim"]), fp="f32")
+        else:
+            spec = small[q]
+        out.append((spec, r.uniform(20.0, 100.0) * t_scale, float(arrivals[q])))
+    return out
+
+
 def rng(seed):
     return np.random.default_rng(seed)
 

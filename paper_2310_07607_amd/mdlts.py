@@ -97,6 +97,7 @@ def lib():
         "mdlts_cfl_bound": (I, [P, P, D, I, P]),
         "mdlts_plan_adapt": (I, [P, P, S, P, S, D, D, P, S, P]),
         "mdlts_plan_levels": (I, [P, P, S, P, D, D, P, P, P, P, S]),
+        "mdlts_memory_bound": (I, [P, ctypes.c_int64, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -404,6 +405,19 @@ def plan_adapt(desc, bits, eta, tau_refine, tau_coarsen):
     _chk(lib().mdlts_plan_adapt(ctypes.byref(desc), _p(b), b.size, _p(e), e.size, float(tau_refine),
                                 float(tau_coarsen), _p(out), out.size, ctypes.byref(n)), "mdlts_plan_adapt")
     return out
+
+
+def memory_bound(desc, max_leaves):
+    """Device bytes a simulation of this shape holds with at most max_leaves leaves."""
+    out = ctypes.c_uint64()
+    _chk(lib().mdlts_memory_bound(ctypes.byref(desc), int(max_leaves), ctypes.byref(out)), "mdlts_memory_bound")
+    return out.value
+
+
+def max_leaves(desc):
+    """Leaves of the forest with every root refined to max_depth."""
+    roots = desc.n[0] * desc.n[1] * (desc.n[2] if desc.dim == 3 else 1)
+    return roots << (desc.dim * desc.max_depth)
 
 
 def plan_levels(desc, bits, n_leaves, D, gamma, dt_barrier):

@@ -103,3 +103,21 @@ def test_cfl_bound_is_the_worst_leaf(dim, p, gamma):
     u.set_params(np.diag(list(D) + [0.0] * (3 - dim)), gamma)
     desc0 = mdlts.make_desc(dim, p, n, length, 0, 1)
     assert mdlts.cfl_bound(desc0, D, gamma, 0) == pytest.approx(u.cfl().min(), rel=1e-13)
+
+
+@pytest.mark.parametrize("dim,p", [(2, 1), (2, 2), (3, 1), (3, 2)])
+def test_memory_bound_is_affine_in_leaves_and_covers_the_state(dim, p):
+    n = (8,) * dim
+    d32 = mdlts.make_desc(dim, p, n, (1.0,) * dim, max_depth=2, n_levels=4, precision="f32")
+    d64 = mdlts.make_desc(dim, p, n, (1.0,) * dim, max_depth=2, n_levels=4, precision="f64")
+    E = mdlts.max_leaves(d32)
+    assert E == 8 ** dim * (1 << (dim * 2))
+    b1, b2, b3 = (mdlts.memory_bound(d32, k) for k in (E, 2 * E, 3 * E))
+    assert b3 - b2 == b2 - b1 > 0  # affine in the leaf count
+    per_leaf = b2 - b1
+    npe = (p + 1) ** dim
+    # at least: two u slots and v grouped, u and v canonical, in the bulk precision
+    assert per_leaf >= 5 * npe * 4
+    assert mdlts.memory_bound(d64, E) > b1
+    with pytest.raises(mdlts.MdltsError):
+        mdlts.memory_bound(d32, 0)
