@@ -127,7 +127,10 @@ mdlts_status mdlts_set_time(mdlts_sim *sim, double t);
  * are then grouped by level, finest first, stable in canonical order.  Runs on
  * the device.  level_hist (optional, [n_levels]) receives the counts per
  * level.  EUNSTABLE if some leaf needs b_e > n_levels-1 (levels are then
- * left unassigned). */
+ * left unassigned).  ENOMEM if the two time slots of u would exceed 4 GiB
+ * (2 * n_leaves * (p+1)^d * bytes per value; e.g. 19.8M Q2 hexahedra in
+ * FP32), the limit of the substep kernels' 32-bit offsets; this also applies
+ * to mdlts_assign_uniform. */
 mdlts_status mdlts_assign_levels(mdlts_sim *sim, double dt_barrier, int32_t *level_hist);
 /* Every leaf on the given level (0 <= level < n_levels): 2^level substeps of
  * dt_barrier / 2^level per barrier, without the CFL test.  level 0 is the

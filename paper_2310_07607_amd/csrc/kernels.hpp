@@ -40,6 +40,8 @@ struct DevRef {
 template <typename T>
 struct StepArgs {
     long long slot_stride;
+    uint32_t slot_bytes;  // slot_stride * sizeof(T); both slots fit in 4 GiB
+    uint32_t node_bytes;  // cap * sizeof(T)
     int cap;
     int lmax;
     int cnt_ge[kMaxLevels];
@@ -129,6 +131,36 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
     return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
+// Arrays are read and written through raw buffer resources: a descriptor
+// (scalar registers) holds the array's base and byte size, and each access
+// adds a per-lane 32-bit byte offset and a uniform one (node or face
+// stride), so no address arithmetic runs on the vector unit.  An offset past
+// the end reads 0 and drops the write instead of touching other memory.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_of(const void *p, uint32_t bytes)
+{
+    // dword 3 of a gfx9 raw buffer descriptor: 32-bit data format, no swizzle
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, T x)
+{
+    if constexpr (sizeof(T) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, (int)voff, (int)soff, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(HIP_vector_base<uint32_t, 2>::Native_vec_, x), r,
+                                              (int)voff, (int)soff, 0);
+}
+
 // out = (I[pos0] (x) I[pos1]) in over the tangential points of a face
 template <typename T, int DIM, int M>
 __device__ __forceinline__ void tang_apply(const T (&I)[2][kMaxM][kMaxM], int pos0, int pos1, const T *in, T *out)
@@ -169,8 +201,9 @@ __device__ __forceinline__ void tang_apply(const T (&I)[2][kMaxM][kMaxM], int po
 // a neighbour updated at this substep is read from its current slot; one
 // that is not (it is coarser) is linear in time between its two slots.
 template <typename T, int DIM, int P>
-__device__ __forceinline__ void neighbour_trace(const StepArgs<T> &a, const StepLaunch<T> &L, uint32_t ent, int k,
-                                                int side, T *tu, T *tq)
+__device__ __forceinline__ void neighbour_trace(const StepArgs<T> &a, const StepLaunch<T> &L,
+                                                __amdgpu_buffer_rsrc_t ru, uint32_t ent, int k, int side, T *tu,
+                                                T *tq)
 {
     const int si = L.i, parity = L.parity;
     using S = Shape<DIM, P>;
@@ -181,7 +214,7 @@ __device__ __forceinline__ void neighbour_trace(const StepArgs<T> &a, const Step
     const int base = ln == 0 ? parity : 0;
     const int cur = base ^ ((si >> sh) & 1);
     const int rem = si & ((1 << sh) - 1);
-    const T *p0 = L.u + (long long)cur * a.slot_stride + id;
+    const uint32_t o0 = (uint32_t)cur * a.slot_bytes + id * (uint32_t)sizeof(T);
 #pragma unroll
     for (int g = 0; g < S::NF; g++) { tu[g] = 0; tq[g] = 0; }
     if (rem == 0) {
@@ -189,19 +222,19 @@ __device__ __forceinline__ void neighbour_trace(const StepArgs<T> &a, const Step
         for (int g = 0; g < S::NF; g++)
 #pragma unroll
             for (int b = 0; b < M; b++) {
-                const T val = p0[(long long)fnode<DIM, M>(k, g, b) * a.cap];
+                const T val = buf_ld<T>(ru, o0, (uint32_t)fnode<DIM, M>(k, g, b) * a.node_bytes);
                 tu[g] += a.ref.B[side][b] * val;
                 tq[g] += a.ref.G[side][b] * val;
             }
     } else {
         const T th = ldexp((T)rem, -sh);
-        const T *p1 = L.u + (long long)(cur ^ 1) * a.slot_stride + id;
+        const uint32_t o1 = (uint32_t)(cur ^ 1) * a.slot_bytes + id * (uint32_t)sizeof(T);
 #pragma unroll
         for (int g = 0; g < S::NF; g++)
 #pragma unroll
             for (int b = 0; b < M; b++) {
-                const long long o = (long long)fnode<DIM, M>(k, g, b) * a.cap;
-                const T val = ((T)1 - th) * p0[o] + th * p1[o];
+                const uint32_t so = (uint32_t)fnode<DIM, M>(k, g, b) * a.node_bytes;
+                const T val = ((T)1 - th) * buf_ld<T>(ru, o0, so) + th * buf_ld<T>(ru, o1, so);
                 tu[g] += a.ref.B[side][b] * val;
                 tq[g] += a.ref.G[side][b] * val;
             }
@@ -210,11 +243,14 @@ __device__ __forceinline__ void neighbour_trace(const StepArgs<T> &a, const Step
 
 // Value of a neighbour's nodes at substep i (packed entry: level | id): a
 // neighbour updated at this substep is read from its current slot; one that
-// is not (it is coarser) is linear in time between its two slots.  Both
-// slots are always loaded (the second from the first's address when not
-// needed) so that the loads of all faces issue together without branches.
-template <typename T, int NP>
-__device__ __forceinline__ void neighbour_values(const StepArgs<T> &a, const StepLaunch<T> &L, uint32_t ent, T *val)
+// is not (it is coarser) is linear in time between its two slots.  Small
+// elements (kBranchless) always load both slots, the second from the
+// first's address when not needed, so that the loads of all faces issue
+// together without branches; large ones load the second slot only for
+// lanes whose neighbour needs it.
+template <typename T, int NP, bool kBranchless>
+__device__ __forceinline__ void neighbour_values(const StepArgs<T> &a, const StepLaunch<T> &L,
+                                                 __amdgpu_buffer_rsrc_t ru, uint32_t ent, T *val)
 {
     const int si = L.i, parity = L.parity;
     const uint32_t id = ent & kIdMask27;
@@ -224,13 +260,26 @@ __device__ __forceinline__ void neighbour_values(const StepArgs<T> &a, const Ste
     const int cur = base ^ ((si >> sh) & 1);
     const int rem = si & ((1 << sh) - 1);
     const T th = ldexp((T)rem, -sh);
-    const T *p0 = L.u + (long long)cur * a.slot_stride + id;
-    const T *p1 = rem ? L.u + (long long)(cur ^ 1) * a.slot_stride + id : p0;
+    const uint32_t o0 = (uint32_t)cur * a.slot_bytes + id * (uint32_t)sizeof(T);
+    const uint32_t o1 = (uint32_t)(cur ^ 1) * a.slot_bytes + id * (uint32_t)sizeof(T);
+    if constexpr (kBranchless) {
+        const uint32_t o1s = rem ? o1 : o0;
 #pragma unroll
-    for (int n = 0; n < NP; n++) {
-        const T x0 = p0[(long long)n * a.cap];
-        const T x1 = p1[(long long)n * a.cap];
-        val[n] = x0 + th * (x1 - x0);
+        for (int n = 0; n < NP; n++) {
+            const T x0 = buf_ld<T>(ru, o0, (uint32_t)n * a.node_bytes);
+            const T x1 = buf_ld<T>(ru, o1s, (uint32_t)n * a.node_bytes);
+            val[n] = x0 + th * (x1 - x0);
+        }
+    } else {
+#pragma unroll
+        for (int n = 0; n < NP; n++) val[n] = buf_ld<T>(ru, o0, (uint32_t)n * a.node_bytes);
+        if (rem) {
+#pragma unroll
+            for (int n = 0; n < NP; n++) {
+                const T x1 = buf_ld<T>(ru, o1, (uint32_t)n * a.node_bytes);
+                val[n] = val[n] + th * (x1 - val[n]);
+            }
+        }
     }
 }
 
@@ -245,7 +294,8 @@ __device__ __forceinline__ void neighbour_values(const StepArgs<T> &a, const Ste
 // arithmetic, so a wave waits for memory twice; faces with finer neighbours
 // (rare, at refinement interfaces) load their 2^(d-1) neighbours on demand.
 template <int DIM, int P, typename T>
-__device__ __forceinline__ void substep_element(const StepArgs<T> &a, const StepLaunch<T> &L, const int j)
+__device__ __forceinline__ void substep_element(const StepArgs<T> &a, const StepLaunch<T> &L, const int j,
+                                                const int lv)
 {
     using S = Shape<DIM, P>;
     constexpr int M = S::M, NP = S::NP, NF = S::NF, NS = S::NS;
@@ -253,29 +303,31 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
     // prefetch every face's neighbour unless it costs too many registers
     constexpr bool kPrefetch = NFACE * NP <= 64;
 
-    int lv = 0;
-#pragma unroll
-    for (int l = 1; l < kMaxLevels; l++) lv += (j < a.cnt_ge[l]) ? 1 : 0;
     const int sh = a.lmax - lv;
     const int cur = (lv == 0 ? L.parity : 0) ^ ((L.i >> sh) & 1);
     const T dt = (T)ldexp(a.dt_bar, -lv);
     const uint32_t self_ent = ((uint32_t)lv << 27) | (uint32_t)j;
 
     // ---- loads that depend on nothing but j
+    using KT = typename KeyOf<DIM>::type;
+    const uint32_t oj = (uint32_t)j * 4u;                   // 32-bit tables
+    const uint32_t ojt = (uint32_t)j * (uint32_t)sizeof(T);  // bulk arrays
+    const __amdgpu_buffer_rsrc_t ru = buf_of(L.u, 2u * a.slot_bytes);
+    const __amdgpu_buffer_rsrc_t rv = buf_of(L.v, a.slot_bytes);
+    const __amdgpu_buffer_rsrc_t rn = buf_of(L.nbr, (uint32_t)NFACE * (uint32_t)a.cap * 4u);
     uint32_t ent[NFACE];
 #pragma unroll
-    for (int f = 0; f < NFACE; f++) ent[f] = L.nbr[(long long)f * a.cap + j];
-    const typename KeyOf<DIM>::type kraw = static_cast<const typename KeyOf<DIM>::type *>(L.key)[j];
-    const T *uc = L.u + (long long)cur * a.slot_stride + j;
-    T *vp = L.v + j;
+    for (int f = 0; f < NFACE; f++) ent[f] = buf_ld<uint32_t>(rn, oj, (uint32_t)f * (uint32_t)a.cap * 4u);
+    const KT kraw = buf_ld<KT>(buf_of(L.key, (uint32_t)a.cap * (uint32_t)sizeof(KT)), (uint32_t)j * sizeof(KT), 0);
+    const uint32_t ou = (uint32_t)cur * a.slot_bytes + ojt;
     // the gate is needed only at the end; small elements load it with the
     // first round of loads, large ones after the face phase (registers)
     constexpr bool kEarlyV = NP <= 16;
     T u[NP], vv[kEarlyV ? NP : 1];
 #pragma unroll
     for (int n = 0; n < NP; n++) {
-        u[n] = uc[(long long)n * a.cap];
-        if constexpr (kEarlyV) vv[n] = vp[(long long)n * a.cap];
+        u[n] = buf_ld<T>(ru, ou, (uint32_t)n * a.node_bytes);
+        if constexpr (kEarlyV) vv[n] = buf_ld<T>(rv, ojt, (uint32_t)n * a.node_bytes);
     }
     // ---- one neighbour per face (same-size or coarser), at the substep time
     T nb[kPrefetch ? NFACE : 1][NP];
@@ -284,7 +336,7 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
         for (int f = 0; f < NFACE; f++) {
             const uint32_t kind = ent[f] >> 30;
             const bool one = kind == kSame || kind == kCoarser;
-            neighbour_values<T, NP>(a, L, one ? ent[f] : self_ent, nb[f]);
+            neighbour_values<T, NP, true>(a, L, ru, one ? ent[f] : self_ent, nb[f]);
         }
     }
 
@@ -338,7 +390,7 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
             for (int s = 0; s < 2; s++) {
                 const uint32_t kind = ent[2 * k + s] >> 30;
                 const bool one = kind == kSame || kind == kCoarser;
-                neighbour_values<T, NP>(a, L, one ? ent[2 * k + s] : self_ent, nbd[s]);
+                neighbour_values<T, NP, false>(a, L, ru, one ? ent[2 * k + s] : self_ent, nbd[s]);
             }
         }
 #pragma unroll
@@ -418,7 +470,10 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
                     T ou[NF], oq[NF], nu[NF], nq[NF], F[NF], H[NF], lf[NF], lh[NF];
                     tang_apply<T, DIM, M>(a.ref.Isub, p0, p1, tu, ou);
                     tang_apply<T, DIM, M>(a.ref.Isub, p0, p1, tq, oq);
-                    neighbour_trace<T, DIM, P>(a, L, L.fine[((long long)f * a.cap + j) * NS + sub], k, 1 - s, nu, nq);
+                    const uint32_t fe = buf_ld<uint32_t>(buf_of(L.fine, (uint32_t)NFACE * (uint32_t)a.cap * NS * 4u),
+                                                         (uint32_t)(j * NS + sub) * 4u,
+                                                         (uint32_t)f * (uint32_t)a.cap * NS * 4u);
+                    neighbour_trace<T, DIM, P>(a, L, ru, fe, k, 1 - s, nu, nq);
 #pragma unroll
                     for (int g = 0; g < NF; g++) {
                         const T jmp = ou[g] - nu[g];
@@ -448,13 +503,13 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
     }
 
     // pointwise reaction, stimulus and update
-    T *uo = L.u + (long long)(cur ^ 1) * a.slot_stride + j;
+    const uint32_t ouo = (uint32_t)(cur ^ 1) * a.slot_bytes + ojt;
 #pragma unroll
     for (int n = 0; n < NP; n++) {
         const T un = u[n];
         T vn;
         if constexpr (kEarlyV) vn = vv[n];
-        else vn = vp[(long long)n * a.cap];
+        else vn = buf_ld<T>(rv, ojt, (uint32_t)n * a.node_bytes);
         T stim = 0;
         bool any = false;
         for (int b = 0; b < a.n_stim; b++) any = any || (L.t_i >= a.stim[b][6] && L.t_i < a.stim[b][7]);
@@ -481,15 +536,15 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
         const T vinf = a.apk * un * ((T)1 + a.apa - un);
         T decay;
         if constexpr (sizeof(T) == 4) {
-            // FP32 bulk: fast reciprocal division and exponential
-            const T eps = a.eps0 + a.mu1 * __fdividef(vn, den);
+            // FP32 bulk: hardware reciprocal (1 ulp) and exponential
+            const T eps = a.eps0 + a.mu1 * (vn * __builtin_amdgcn_rcpf(den));
             decay = __expf(-eps * dt);
         } else {
             const T eps = a.eps0 + a.mu1 * vn / den;
             decay = exp(-eps * dt);
         }
-        uo[(long long)n * a.cap] = un + dt * (r[n] + f + stim);
-        vp[(long long)n * a.cap] = vinf + (vn - vinf) * decay;
+        buf_st<T>(ru, ouo, (uint32_t)n * a.node_bytes, un + dt * (r[n] + f + stim));
+        buf_st<T>(rv, ojt, (uint32_t)n * a.node_bytes, vinf + (vn - vinf) * decay);
     }
 }
 
@@ -499,16 +554,21 @@ __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> *__restrict__
 {
     const int j = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (j >= L.n_act) return;
-    substep_element<DIM, P, T>(*cst, L, j);
+    const StepArgs<T> &a = *cst;
+    int lv = 0;  // elements are grouped finest level first
+#pragma unroll
+    for (int l = 1; l < kMaxLevels; l++) lv += (j < a.cnt_ge[l]) ? 1 : 0;
+    substep_element<DIM, P, T>(a, L, j, lv);
 }
 
 // ---- many simulations in one launch ------------------------------------------
-// A tile is up to blockDim.x consecutive active elements of one simulation.
+// A tile is up to blockDim.x consecutive active elements of one simulation,
+// all of one level.
 struct BatchTile {
     int sim;
     int start;
     int count;
-    int pad;
+    int level;
 };
 
 // Everything a batched launch needs about one simulation.  Data locations
@@ -519,7 +579,13 @@ struct BatchSim {
     StepArgs<T> a;
     long long off_u, off_v, off_key, off_nbr, off_fine;
     double t_start, h_tick;
-    long long n_bar;  // barriers since t_start (advanced on the device)
+};
+
+// Barrier counter of a simulation in a batch.  Two copies alternate: the
+// launches of a barrier read one, and the first substep's launch writes the
+// next barrier's values into the other, so no launch writes what it reads.
+struct BatchClock {
+    long long n_bar;  // barriers since t_start
     int parity;       // barriers since the level assignment, mod 2
     int pad;
 };
@@ -530,7 +596,8 @@ struct BatchSim {
 template <int DIM, int P, typename T>
 __global__ __launch_bounds__(256) void k_substep_batch(const BatchSim<T> *__restrict__ sims,
                                                        const BatchTile *__restrict__ tiles, int n_tiles, int i,
-                                                       char *base)
+                                                       char *base, const BatchClock *__restrict__ clk,
+                                                       BatchClock *__restrict__ clk_next)
 {
     const int x = blockIdx.x & 7, per = (int)(gridDim.x >> 3);
     const int q = n_tiles >> 3, r = n_tiles & 7;
@@ -538,6 +605,16 @@ __global__ __launch_bounds__(256) void k_substep_batch(const BatchSim<T> *__rest
     const int t1 = t0 + q + (x < r ? 1 : 0);
     for (int t = t0 + (int)(blockIdx.x >> 3); t < t1; t += per) {
         const BatchTile tl = tiles[t];
+        const BatchClock ck = clk[tl.sim];
+        // every simulation has a tile at start 0 in substep 0: it advances
+        // the simulation's clock for the next barrier
+        if (i == 0 && tl.start == 0 && threadIdx.x == 0) {
+            BatchClock nx;
+            nx.n_bar = ck.n_bar + 1;
+            nx.parity = ck.parity ^ 1;
+            nx.pad = 0;
+            clk_next[tl.sim] = nx;
+        }
         if ((int)threadIdx.x >= tl.count) continue;
         const BatchSim<T> &d = sims[tl.sim];
         StepLaunch<T> L;
@@ -548,21 +625,11 @@ __global__ __launch_bounds__(256) void k_substep_batch(const BatchSim<T> *__rest
         L.fine = reinterpret_cast<const uint32_t *>(base + d.off_fine);
         L.i = i;
         L.n_act = 0;
-        L.parity = d.parity;
+        L.parity = ck.parity;
         // t = t_start + n dt + i h, rounded like the host (no contraction)
-        L.t_i = __dadd_rn(__dadd_rn(d.t_start, __dmul_rn((double)d.n_bar, d.a.dt_bar)), __dmul_rn((double)i, d.h_tick));
-        substep_element<DIM, P, T>(d.a, L, tl.start + (int)threadIdx.x);
+        L.t_i = __dadd_rn(__dadd_rn(d.t_start, __dmul_rn((double)ck.n_bar, d.a.dt_bar)), __dmul_rn((double)i, d.h_tick));
+        substep_element<DIM, P, T>(d.a, L, tl.start + (int)threadIdx.x, tl.level);
     }
-}
-
-// end of a barrier interval for every simulation of a batch
-template <typename T>
-__global__ void k_batch_advance(BatchSim<T> *sims, int n)
-{
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    sims[s].n_bar += 1;
-    sims[s].parity ^= 1;
 }
 
 }  // namespace mdlts

@@ -468,6 +468,7 @@ struct mdlts_sim {
     double dt_bar = 0.0;
     double t_start = 0.0;
     long long n_bar = 0;  // barriers since t_start (time bookkeeping)
+    BatchPlan *solo = nullptr;  // graph plan of mdlts_step
     long long n_since_assign = 0;
     uint64_t dof_updates = 0;
     bool eta_valid = false;  // eta_c holds the indicator of the current forest
@@ -784,6 +785,8 @@ void fill_step_args(const mdlts_sim *s, StepArgs<T> &a)
 {
     std::memset(&a, 0, sizeof(a));
     a.slot_stride = (long long)s->np * s->cap;
+    a.slot_bytes = (uint32_t)(a.slot_stride * (long long)sizeof(T));
+    a.node_bytes = (uint32_t)((long long)s->cap * (long long)sizeof(T));
     a.cap = s->cap;
     a.lmax = s->lmax;
     for (int l = 0; l < kMaxLevels; l++) a.cnt_ge[l] = l < (int)s->cnt_ge.size() && l <= s->lmax ? s->cnt_ge[l] : 0;
@@ -1017,7 +1020,8 @@ mdlts_status compute_G(mdlts_sim *s)
 struct BatchGroup {
     int dim = 2, order = 1, prec = 0;
     std::vector<int> members;   // indices into BatchPlan::sims
-    DevBuf descs, tiles;
+    DevBuf descs, tiles, clocks;  // clocks: [2][members] BatchClock
+    std::vector<BatchClock> hclk;  // host source of the clock uploads
     std::vector<int> tile_off;  // [2^lmax_all + 1] offsets into tiles per substep
     char *base = nullptr;
 };
@@ -1031,9 +1035,11 @@ struct BatchPlan {
     bool tuned = false;
     std::vector<BatchGroup> groups;
     std::vector<uint64_t> dof_per_barrier;  // per simulation
+    std::vector<long long> n_bar;           // per simulation, as the device clocks hold it
     int variant_mask = 0;                   // kernel variants present
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    int phase = 0;                          // clock copy the next barrier reads
+    hipGraph_t graph[2] = {nullptr, nullptr};  // one barrier, per phase
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
     int n_cu = 256;
     // optional event timing of every batched substep launch
     bool prof = false;
@@ -1047,25 +1053,29 @@ namespace {
 
 void free_graph(BatchPlan *P)
 {
-    if (P->exec) (void)hipGraphExecDestroy(P->exec);
-    if (P->graph) (void)hipGraphDestroy(P->graph);
-    P->exec = nullptr;
-    P->graph = nullptr;
+    for (int k = 0; k < 2; k++) {
+        if (P->exec[k]) (void)hipGraphExecDestroy(P->exec[k]);
+        if (P->graph[k]) (void)hipGraphDestroy(P->graph[k]);
+        P->exec[k] = nullptr;
+        P->graph[k] = nullptr;
+    }
 }
 
-void free_plan(mdlts_ctx *c)
+// frees a plan (the context's batch plan or a simulation's step plan)
+void free_plan(mdlts_ctx *c, BatchPlan *&slot)
 {
-    BatchPlan *P = c->batch;
+    BatchPlan *P = slot;
     if (!P) return;
     (void)hipStreamSynchronize(c->stream);
     free_graph(P);
     for (auto &g : P->groups) {
         dev_free(c, g.descs);
         dev_free(c, g.tiles);
+        dev_free(c, g.clocks);
     }
     for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
     delete P;
-    c->batch = nullptr;
+    slot = nullptr;
 }
 
 void *batch_kernel(int dim, int order, int prec)
@@ -1081,6 +1091,20 @@ void *batch_kernel(int dim, int order, int prec)
     case 321: return reinterpret_cast<void *>(&k_substep_batch<3, 2, float>);
     }
     return nullptr;
+}
+
+// both clock copies from the host's barrier counts (the next barrier reads
+// copy 0)
+mdlts_status upload_clocks(mdlts_ctx *c, BatchPlan &P, BatchGroup &G)
+{
+    const size_t nm = G.members.size();
+    G.hclk.resize(2 * nm);
+    for (size_t q = 0; q < nm; q++) {
+        const mdlts_sim *s = P.sims[G.members[q]];
+        G.hclk[q] = G.hclk[nm + q] = BatchClock{s->n_bar, (int)(s->n_since_assign & 1), 0};
+    }
+    HIP_TRY(hipMemcpyAsync(G.clocks.p, G.hclk.data(), 2 * nm * sizeof(BatchClock), hipMemcpyHostToDevice, c->stream));
+    return MDLTS_OK;
 }
 
 template <typename T>
@@ -1100,9 +1124,6 @@ mdlts_status fill_group(mdlts_ctx *c, BatchPlan &P, BatchGroup &G)
         d[q].off_fine = static_cast<char *>(s->fine_s.p) - G.base;
         d[q].t_start = s->t_start;
         d[q].h_tick = s->dt_bar / (double)(1ll << s->lmax);
-        d[q].n_bar = s->n_bar;
-        d[q].parity = (int)(s->n_since_assign & 1);
-        d[q].pad = 0;
     }
     // tile lists: substep i of the barrier interval (each simulation runs
     // its own 2^lmax substeps; shorter schedules idle at the end)
@@ -1117,13 +1138,20 @@ mdlts_status fill_group(mdlts_ctx *c, BatchPlan &P, BatchGroup &G)
             int v2 = 0;
             while (i > 0 && ((i >> v2) & 1) == 0) v2++;
             const int lmin = i == 0 ? 0 : s->lmax - v2;
-            const int n = s->cnt_ge[lmin];
-            for (int st = 0; st < n; st += P.block) tiles.push_back(BatchTile{q, st, std::min(P.block, n - st), 0});
+            // active levels lmax..lmin occupy [0, cnt_ge[lmin]), finest first;
+            // tiles do not straddle levels
+            for (int l = s->lmax; l >= lmin; l--) {
+                const int lo = l == s->lmax ? 0 : s->cnt_ge[l + 1], hi = s->cnt_ge[l];
+                for (int st = lo; st < hi; st += P.block)
+                    tiles.push_back(BatchTile{q, st, std::min(P.block, hi - st), l});
+            }
         }
     }
     G.tile_off[nsub] = (int)tiles.size();
     MD_TRY(dev_alloc(c, G.tiles, std::max<size_t>(1, tiles.size()) * sizeof(BatchTile)));
     HIP_TRY(hipMemcpyAsync(G.descs.p, d.data(), (size_t)nm * sizeof(BatchSim<T>), hipMemcpyHostToDevice, c->stream));
+    MD_TRY(dev_alloc(c, G.clocks, 2 * (size_t)nm * sizeof(BatchClock)));
+    MD_TRY(upload_clocks(c, P, G));
     if (!tiles.empty())
         HIP_TRY(hipMemcpyAsync(G.tiles.p, tiles.data(), tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice,
                                c->stream));
@@ -1136,6 +1164,9 @@ mdlts_status build_plan_data(mdlts_ctx *c, BatchPlan &P)
     free_graph(&P);
     for (auto &G : P.groups)
         MD_TRY(G.prec == MDLTS_FP64 ? fill_group<double>(c, P, G) : fill_group<float>(c, P, G));
+    P.phase = 0;
+    P.n_bar.resize(P.sims.size());
+    for (size_t q = 0; q < P.sims.size(); q++) P.n_bar[q] = P.sims[q]->n_bar;
     return MDLTS_OK;
 }
 
@@ -1146,10 +1177,13 @@ int grid_of(const BatchPlan &P, int n_tiles)
     return std::max(grid, 8);
 }
 
-// one barrier interval: launches on the stream, or kernel nodes of a graph
-mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, hipGraph_t graph, hipGraphNode_t *last)
+// one barrier interval reading clock copy `phase`: launches on the stream,
+// or kernel nodes of a graph (the launches of one substep, one per kernel
+// variant, depend on all launches of the previous substep, not on each other)
+mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, int phase, hipGraph_t graph)
 {
     const long long nsub = 1ll << P.lmax_all;
+    std::vector<hipGraphNode_t> prev, cur;
     auto add = [&](void *fn, int grid, int block, void **args) -> mdlts_status {
         if (graph) {
             hipKernelNodeParams kp{};
@@ -1160,14 +1194,15 @@ mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, hipGraph_t graph, hipGraph
             kp.kernelParams = args;
             kp.extra = nullptr;
             hipGraphNode_t node;
-            HIP_TRY(hipGraphAddKernelNode(&node, graph, *last ? last : nullptr, *last ? 1 : 0, &kp));
-            *last = node;
+            HIP_TRY(hipGraphAddKernelNode(&node, graph, prev.empty() ? nullptr : prev.data(), prev.size(), &kp));
+            cur.push_back(node);
         } else {
             HIP_TRY(hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, c->stream));
         }
         return MDLTS_OK;
     };
     for (long long i = 0; i < nsub; i++) {
+        cur.clear();
         for (auto &G : P.groups) {
             int n_t = G.tile_off[i + 1] - G.tile_off[i];
             if (n_t == 0) continue;
@@ -1175,7 +1210,10 @@ mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, hipGraph_t graph, hipGraph
             const BatchTile *tl = static_cast<const BatchTile *>(G.tiles.p) + G.tile_off[i];
             int ii = (int)i;
             char *base = G.base;
-            void *args[] = {&descs, &tl, &n_t, &ii, &base};
+            const int nm = (int)G.members.size();
+            const BatchClock *ck = static_cast<const BatchClock *>(G.clocks.p) + (size_t)phase * nm;
+            BatchClock *ck_next = static_cast<BatchClock *>(G.clocks.p) + (size_t)(phase ^ 1) * nm;
+            void *args[] = {&descs, &tl, &n_t, &ii, &base, &ck, &ck_next};
             const bool prof = P.prof && !graph;
             if (prof) {
                 while (P.ev.size() < 2 * (P.ev_used + 1)) {
@@ -1192,14 +1230,7 @@ mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, hipGraph_t graph, hipGraph
                 P.prof_launches++;
             }
         }
-    }
-    for (auto &G : P.groups) {
-        void *descs = G.descs.p;
-        int nm = (int)G.members.size();
-        void *args[] = {&descs, &nm};
-        void *fn = G.prec == MDLTS_FP64 ? reinterpret_cast<void *>(&k_batch_advance<double>)
-                                        : reinterpret_cast<void *>(&k_batch_advance<float>);
-        MD_TRY(add(fn, (nm + 63) / 64, 64, args));
+        if (!cur.empty()) prev.swap(cur);
     }
     return MDLTS_OK;
 }
@@ -1207,14 +1238,16 @@ mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, hipGraph_t graph, hipGraph
 mdlts_status build_graph(mdlts_ctx *c, BatchPlan &P)
 {
     free_graph(&P);
-    HIP_TRY(hipGraphCreate(&P.graph, 0));
-    hipGraphNode_t last = nullptr;
-    MD_TRY(emit_barrier(c, P, P.graph, &last));
-    HIP_TRY(hipGraphInstantiate(&P.exec, P.graph, nullptr, nullptr, 0));
+    for (int k = 0; k < 2; k++) {
+        HIP_TRY(hipGraphCreate(&P.graph[k], 0));
+        MD_TRY(emit_barrier(c, P, k, P.graph[k]));
+        HIP_TRY(hipGraphInstantiate(&P.exec[k], P.graph[k], nullptr, nullptr, 0));
+    }
     return MDLTS_OK;
 }
 
-// host-side bookkeeping of barriers run by the batch
+// host-side bookkeeping of barriers run by the batch (one at a time: the
+// clock copies alternate)
 void account_barriers(BatchPlan &P, int nb)
 {
     for (size_t q = 0; q < P.sims.size(); q++) {
@@ -1223,7 +1256,9 @@ void account_barriers(BatchPlan &P, int nb)
         s->n_since_assign += nb;
         s->dof_updates += P.dof_per_barrier[q] * (uint64_t)nb;
         s->eta_valid = false;
+        P.n_bar[q] = s->n_bar;
     }
+    P.phase ^= nb & 1;
     if (P.prof)
         for (size_t q = 0; q < P.sims.size(); q++) P.prof_dof += P.dof_per_barrier[q] * (uint64_t)nb;
 }
@@ -1246,12 +1281,12 @@ mdlts_status run_batch_barriers(mdlts_ctx *c, BatchPlan &P, int nb)
     for (int b = 0; b < nb; b++) {
         if (P.prof) {
             if (P.ev_used + P.groups.size() * (1u << P.lmax_all) > kMaxEventPairs) MD_TRY(drain_batch_events(P));
-            MD_TRY(emit_barrier(c, P, nullptr, nullptr));
+            MD_TRY(emit_barrier(c, P, P.phase, nullptr));
         } else if (c->use_graphs) {
-            if (!P.exec) MD_TRY(build_graph(c, P));
-            HIP_TRY(hipGraphLaunch(P.exec, c->stream));
+            if (!P.exec[0]) MD_TRY(build_graph(c, P));
+            HIP_TRY(hipGraphLaunch(P.exec[P.phase], c->stream));
         } else {
-            MD_TRY(emit_barrier(c, P, nullptr, nullptr));
+            MD_TRY(emit_barrier(c, P, P.phase, nullptr));
         }
         account_barriers(P, 1);
     }
@@ -1279,10 +1314,10 @@ mdlts_status autotune(mdlts_ctx *c, BatchPlan &P, int *remaining)
         P.block = cd.block;
         P.per_cu = cd.per_cu;
         MD_TRY(build_plan_data(c, P));
-        MD_TRY(emit_barrier(c, P, nullptr, nullptr));  // warm
+        MD_TRY(emit_barrier(c, P, P.phase, nullptr));  // warm
         account_barriers(P, 1);
         HIP_TRY(hipEventRecord(e0, c->stream));
-        MD_TRY(emit_barrier(c, P, nullptr, nullptr));
+        MD_TRY(emit_barrier(c, P, P.phase, nullptr));
         account_barriers(P, 1);
         HIP_TRY(hipEventRecord(e1, c->stream));
         HIP_TRY(hipEventSynchronize(e1));
@@ -1305,17 +1340,30 @@ mdlts_status autotune(mdlts_ctx *c, BatchPlan &P, int *remaining)
     return build_plan_data(c, P);
 }
 
-mdlts_status prepare_plan(mdlts_ctx *c, mdlts_sim *const *sims, int n, bool *fresh)
+// The plan in `slot` for these simulations, rebuilt when the set or any
+// simulation's levels, buffers or parameters changed; when only barrier
+// counts moved (the simulations were stepped by another plan) the clocks
+// are uploaded again.
+mdlts_status prepare_plan(mdlts_ctx *c, BatchPlan *&slot, mdlts_sim *const *sims, int n, bool *fresh)
 {
     *fresh = false;
-    BatchPlan *P = c->batch;
+    BatchPlan *P = slot;
     bool same = P && (int)P->sims.size() == n;
     for (int q = 0; same && q < n; q++) same = P->sims[q] == sims[q] && P->versions[q] == sims[q]->version;
-    if (same) return MDLTS_OK;
-    free_plan(c);
+    if (same) {
+        bool moved = false;
+        for (int q = 0; q < n; q++) moved = moved || P->n_bar[q] != sims[q]->n_bar;
+        if (moved) {
+            for (auto &G : P->groups) MD_TRY(upload_clocks(c, *P, G));
+            P->phase = 0;
+            for (int q = 0; q < n; q++) P->n_bar[q] = sims[q]->n_bar;
+        }
+        return MDLTS_OK;
+    }
+    free_plan(c, slot);
     P = new (std::nothrow) BatchPlan;
     if (!P) return MDLTS_ENOMEM;
-    c->batch = P;
+    slot = P;
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess) {
         int ncu = 0;
@@ -1407,7 +1455,7 @@ mdlts_status mdlts_ctx_destroy(mdlts_ctx *ctx)
 {
     if (!ctx) return MDLTS_EINVAL;
     if (ctx->n_sims > 0) return MDLTS_EBUSY;
-    free_plan(ctx);
+    free_plan(ctx, ctx->batch);
     delete ctx;
     return MDLTS_OK;
 }
@@ -1457,9 +1505,10 @@ mdlts_status mdlts_sim_destroy(mdlts_sim *s)
     if (c->batch)
         for (mdlts_sim *m : c->batch->sims)
             if (m == s) {
-                free_plan(c);
+                free_plan(c, c->batch);
                 break;
             }
+    free_plan(c, s->solo);
     DevBuf *bufs[] = {&s->key_c, &s->face_c, &s->fine_c, &s->u_c, &s->v_c, &s->level_c, &s->cfl_c, &s->eta_c,
                       &s->tmp_u, &s->tmp_v, &s->u_s, &s->v_s, &s->key_s, &s->nbr_s, &s->fine_s, &s->perm,
                       &s->inv, &s->hist, &s->cnt_ge_d, &s->flags, &s->xk, &s->xs, &s->xc, &s->stage,
@@ -1619,6 +1668,8 @@ mdlts_status mdlts_assign_uniform(mdlts_sim *s, double dt_barrier, int level, in
 static mdlts_status assign_levels_impl(mdlts_sim *s, double dt_barrier, int force_level, int32_t *level_hist)
 {
     if (!s || !(dt_barrier > 0.0) || !std::isfinite(dt_barrier)) return MDLTS_EINVAL;
+    // the substep kernels address both u slots with 32-bit byte offsets
+    if ((uint64_t)2 * s->np * (uint64_t)s->E * s->tsize > 0xffffffffull) return MDLTS_ENOMEM;
     s->version++;
     mdlts_ctx *c = s->ctx;
     const int E = (int)s->E;
@@ -1729,11 +1780,25 @@ mdlts_status mdlts_get_cfl(mdlts_sim *s, double *cfl, size_t n_leaves)
 mdlts_status mdlts_step(mdlts_sim *s, int n_barriers)
 {
     if (!s || n_barriers < 0) return MDLTS_EINVAL;
-    s->version++;
     if (!s->levels_valid || !s->state_grouped) return MDLTS_ESTATE;
     s->eta_valid = false;
-    if (s->desc.precision == MDLTS_FP64) return run_barriers<double>(s, n_barriers);
-    return run_barriers<float>(s, n_barriers);
+    mdlts_ctx *c = s->ctx;
+    if (!c->use_graphs) {
+        if (s->desc.precision == MDLTS_FP64) return run_barriers<double>(s, n_barriers);
+        return run_barriers<float>(s, n_barriers);
+    }
+    // a one-simulation plan: each barrier is one graph launch (or, while
+    // profiling, the same launches on the stream between events)
+    bool fresh = false;
+    MD_TRY(prepare_plan(c, s->solo, &s, 1, &fresh));
+    BatchPlan &P = *s->solo;
+    if (P.prof != s->prof) {
+        MD_TRY(drain_batch_events(P));
+        P.prof = s->prof;
+    }
+    int remaining = n_barriers;
+    if (!P.tuned) MD_TRY(autotune(c, P, &remaining));
+    return run_batch_barriers(c, P, remaining);
 }
 
 mdlts_status mdlts_indicator(mdlts_sim *s, double *eta, size_t n_leaves, double *eta_max)
@@ -1792,10 +1857,25 @@ mdlts_status mdlts_counters(mdlts_sim *s, uint64_t *dof_updates, double *t_sim)
     return MDLTS_OK;
 }
 
+// event times of the step plan's launches, added to the simulation's
+static mdlts_status drain_solo(mdlts_sim *s)
+{
+    if (!s->solo) return MDLTS_OK;
+    BatchPlan &P = *s->solo;
+    MD_TRY(drain_batch_events(P));
+    s->prof_ms += P.prof_ms;
+    s->prof_launches += P.prof_launches;
+    s->prof_dof += P.prof_dof;
+    P.prof_ms = 0.0;
+    P.prof_launches = P.prof_dof = 0;
+    return MDLTS_OK;
+}
+
 mdlts_status mdlts_profile(mdlts_sim *s, int enable)
 {
     if (!s) return MDLTS_EINVAL;
     MD_TRY(drain_events(s));
+    MD_TRY(drain_solo(s));
     s->prof = enable != 0;
     s->prof_ms = 0.0;
     s->prof_launches = s->prof_dof = 0;
@@ -1806,6 +1886,7 @@ mdlts_status mdlts_profile_read(mdlts_sim *s, double *substep_ms, uint64_t *n_la
 {
     if (!s) return MDLTS_EINVAL;
     MD_TRY(drain_events(s));
+    MD_TRY(drain_solo(s));
     if (substep_ms) *substep_ms = s->prof_ms;
     if (n_launches) *n_launches = s->prof_launches;
     if (dof_updates) *dof_updates = s->prof_dof;
@@ -1824,7 +1905,7 @@ mdlts_status mdlts_batch_step(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sims
         if (!sims[q]->levels_valid || !sims[q]->state_grouped) return MDLTS_ESTATE;
     }
     bool fresh = false;
-    MD_TRY(prepare_plan(ctx, sims, n_sims, &fresh));
+    MD_TRY(prepare_plan(ctx, ctx->batch, sims, n_sims, &fresh));
     BatchPlan &P = *ctx->batch;
     int remaining = n_barriers;
     if (!P.tuned) MD_TRY(autotune(ctx, P, &remaining));
