@@ -26,6 +26,104 @@ constexpr uint32_t kIdMask30 = 0x3fffffffu;
 constexpr int kMaxStim = 8;
 constexpr int kMaxLevels = 8;
 
+// 1-D reference tables of degree p (Sec. 2.1: Lagrange basis at the p+1
+// Gauss-Legendre nodes, quadrature on the same nodes), evaluated by the
+// compiler so that the substep kernel carries them as instruction
+// constants.  Same construction as the host tables (barycentric weights).
+struct RefConst {
+    int m;
+    double xi[kMaxM], w[kMaxM], winv[kMaxM], lam[kMaxM];
+    double D1[kMaxM][kMaxM];       // D1[a][b] = l_b'(xi_a)
+    double A[kMaxM][kMaxM];        // (1/w_a) sum_q w_q D1[q][a] D1[q][b]
+    double B[2][kMaxM];            // l_b(-1), l_b(+1)
+    double G[2][kMaxM];            // l_b'(-1), l_b'(+1)
+    double Isub[2][kMaxM][kMaxM];  // l_b((xi_g + 2 pos - 1) / 2)
+    double Lsub[2][kMaxM][kMaxM];  // w_g Isub[pos][g][a] / (2 w_a)
+};
+
+constexpr double csqrt(double x)
+{
+    double r = x > 1.0 ? x : 1.0;
+    for (int k = 0; k < 200; k++) {
+        const double n = 0.5 * (r + x / r);
+        if (n == r) break;
+        r = n;
+    }
+    return r;
+}
+
+constexpr double clagrange(const RefConst &T, int b, double x)
+{
+    double v = T.lam[b];
+    for (int k = 0; k < T.m; k++)
+        if (k != b) v *= (x - T.xi[k]);
+    return v;
+}
+
+constexpr double clagrange_deriv(const RefConst &T, int b, double x)
+{
+    double s = 0.0;
+    for (int k = 0; k < T.m; k++) {
+        if (k == b) continue;
+        double v = T.lam[b];
+        for (int q = 0; q < T.m; q++)
+            if (q != b && q != k) v *= (x - T.xi[q]);
+        s += v;
+    }
+    return s;
+}
+
+constexpr RefConst ref_const(int p)
+{
+    RefConst T{};
+    if (p == 1) {
+        T.m = 2;
+        const double r = 1.0 / csqrt(3.0);
+        T.xi[0] = -r; T.xi[1] = r;
+        T.w[0] = 1.0; T.w[1] = 1.0;
+    } else {
+        T.m = 3;
+        const double r = csqrt(0.6);
+        T.xi[0] = -r; T.xi[1] = 0.0; T.xi[2] = r;
+        T.w[0] = 5.0 / 9.0; T.w[1] = 8.0 / 9.0; T.w[2] = 5.0 / 9.0;
+    }
+    const int m = T.m;
+    for (int j = 0; j < m; j++) {
+        double d = 1.0;
+        for (int k = 0; k < m; k++)
+            if (k != j) d *= (T.xi[j] - T.xi[k]);
+        T.lam[j] = 1.0 / d;
+        T.winv[j] = 1.0 / T.w[j];
+    }
+    for (int a = 0; a < m; a++) {
+        double diag = 0.0;
+        for (int b = 0; b < m; b++) {
+            if (a == b) continue;
+            T.D1[a][b] = (T.lam[b] / T.lam[a]) / (T.xi[a] - T.xi[b]);
+            diag -= T.D1[a][b];
+        }
+        T.D1[a][a] = diag;
+    }
+    for (int a = 0; a < m; a++)
+        for (int b = 0; b < m; b++) {
+            double s = 0.0;
+            for (int q = 0; q < m; q++) s += T.w[q] * T.D1[q][a] * T.D1[q][b];
+            T.A[a][b] = s / T.w[a];
+        }
+    for (int s = 0; s < 2; s++)
+        for (int b = 0; b < m; b++) {
+            T.B[s][b] = clagrange(T, b, s ? 1.0 : -1.0);
+            T.G[s][b] = clagrange_deriv(T, b, s ? 1.0 : -1.0);
+        }
+    for (int pos = 0; pos < 2; pos++)
+        for (int g = 0; g < m; g++)
+            for (int b = 0; b < m; b++) T.Isub[pos][g][b] = clagrange(T, b, 0.5 * (T.xi[g] + 2.0 * pos - 1.0));
+    for (int pos = 0; pos < 2; pos++)
+        for (int a = 0; a < m; a++)
+            for (int g = 0; g < m; g++) T.Lsub[pos][a][g] = T.w[g] * T.Isub[pos][g][a] / (2.0 * T.w[a]);
+    return T;
+}
+
 template <typename T>
 struct DevRef {
     T A[kMaxM][kMaxM];
@@ -65,10 +163,14 @@ struct StepLaunch {
     const void *key;
     const uint32_t *nbr;
     const uint32_t *fine;
-    int i;       // substep index in the barrier interval
-    int n_act;   // active prefix
-    int parity;  // barriers since the level assignment, mod 2
-    double t_i;  // substep start time
+    uint32_t node_bytes;  // cap * sizeof(T): stride between nodes of u and v
+    uint32_t slot_bytes;  // np * node_bytes: stride between the two u slots
+    int cap;              // elements per table column
+    int lmax;             // finest level present
+    int i;                // substep index in the barrier interval
+    int n_act;            // active prefix
+    int parity;           // barriers since the level assignment, mod 2
+    double t_i;           // substep start time
 };
 
 template <int DIM>
@@ -163,14 +265,15 @@ __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t voff, 
 
 // out = (I[pos0] (x) I[pos1]) in over the tangential points of a face
 template <typename T, int DIM, int M>
-__device__ __forceinline__ void tang_apply(const T (&I)[2][kMaxM][kMaxM], int pos0, int pos1, const T *in, T *out)
+__device__ __forceinline__ void tang_apply(const double (&I)[2][kMaxM][kMaxM], int pos0, int pos1, const T *in,
+                                           T *out)
 {
     if constexpr (DIM == 2) {
 #pragma unroll
         for (int g = 0; g < M; g++) {
             T s = 0;
 #pragma unroll
-            for (int q = 0; q < M; q++) s += (pos0 ? I[1][g][q] : I[0][g][q]) * in[q];
+            for (int q = 0; q < M; q++) s += (pos0 ? (T)I[1][g][q] : (T)I[0][g][q]) * in[q];
             out[g] = s;
         }
     } else {
@@ -181,7 +284,7 @@ __device__ __forceinline__ void tang_apply(const T (&I)[2][kMaxM][kMaxM], int po
             for (int g0 = 0; g0 < M; g0++) {
                 T s = 0;
 #pragma unroll
-                for (int q = 0; q < M; q++) s += (pos0 ? I[1][g0][q] : I[0][g0][q]) * in[q + M * g1];
+                for (int q = 0; q < M; q++) s += (pos0 ? (T)I[1][g0][q] : (T)I[0][g0][q]) * in[q + M * g1];
                 tmp[g0 + M * g1] = s;
             }
 #pragma unroll
@@ -190,7 +293,7 @@ __device__ __forceinline__ void tang_apply(const T (&I)[2][kMaxM][kMaxM], int po
             for (int g0 = 0; g0 < M; g0++) {
                 T s = 0;
 #pragma unroll
-                for (int q = 0; q < M; q++) s += (pos1 ? I[1][g1][q] : I[0][g1][q]) * tmp[g0 + M * q];
+                for (int q = 0; q < M; q++) s += (pos1 ? (T)I[1][g1][q] : (T)I[0][g1][q]) * tmp[g0 + M * q];
                 out[g0 + M * g1] = s;
             }
     }
@@ -208,13 +311,14 @@ __device__ __forceinline__ void neighbour_trace(const StepArgs<T> &a, const Step
     const int si = L.i, parity = L.parity;
     using S = Shape<DIM, P>;
     constexpr int M = S::M;
+    constexpr RefConst R = ref_const(P);
     const uint32_t id = ent & kIdMask27;
     const int ln = (int)((ent >> 27) & 7);
-    const int sh = a.lmax - ln;
+    const int sh = L.lmax - ln;
     const int base = ln == 0 ? parity : 0;
     const int cur = base ^ ((si >> sh) & 1);
     const int rem = si & ((1 << sh) - 1);
-    const uint32_t o0 = (uint32_t)cur * a.slot_bytes + id * (uint32_t)sizeof(T);
+    const uint32_t o0 = (uint32_t)cur * L.slot_bytes + id * (uint32_t)sizeof(T);
 #pragma unroll
     for (int g = 0; g < S::NF; g++) { tu[g] = 0; tq[g] = 0; }
     if (rem == 0) {
@@ -222,21 +326,21 @@ __device__ __forceinline__ void neighbour_trace(const StepArgs<T> &a, const Step
         for (int g = 0; g < S::NF; g++)
 #pragma unroll
             for (int b = 0; b < M; b++) {
-                const T val = buf_ld<T>(ru, o0, (uint32_t)fnode<DIM, M>(k, g, b) * a.node_bytes);
-                tu[g] += a.ref.B[side][b] * val;
-                tq[g] += a.ref.G[side][b] * val;
+                const T val = buf_ld<T>(ru, o0, (uint32_t)fnode<DIM, M>(k, g, b) * L.node_bytes);
+                tu[g] += (T)R.B[side][b] * val;
+                tq[g] += (T)R.G[side][b] * val;
             }
     } else {
         const T th = ldexp((T)rem, -sh);
-        const uint32_t o1 = (uint32_t)(cur ^ 1) * a.slot_bytes + id * (uint32_t)sizeof(T);
+        const uint32_t o1 = (uint32_t)(cur ^ 1) * L.slot_bytes + id * (uint32_t)sizeof(T);
 #pragma unroll
         for (int g = 0; g < S::NF; g++)
 #pragma unroll
             for (int b = 0; b < M; b++) {
-                const uint32_t so = (uint32_t)fnode<DIM, M>(k, g, b) * a.node_bytes;
+                const uint32_t so = (uint32_t)fnode<DIM, M>(k, g, b) * L.node_bytes;
                 const T val = ((T)1 - th) * buf_ld<T>(ru, o0, so) + th * buf_ld<T>(ru, o1, so);
-                tu[g] += a.ref.B[side][b] * val;
-                tq[g] += a.ref.G[side][b] * val;
+                tu[g] += (T)R.B[side][b] * val;
+                tq[g] += (T)R.G[side][b] * val;
             }
     }
 }
@@ -255,28 +359,28 @@ __device__ __forceinline__ void neighbour_values(const StepArgs<T> &a, const Ste
     const int si = L.i, parity = L.parity;
     const uint32_t id = ent & kIdMask27;
     const int ln = (int)((ent >> 27) & 7);
-    const int sh = a.lmax - ln;
+    const int sh = L.lmax - ln;
     const int base = ln == 0 ? parity : 0;
     const int cur = base ^ ((si >> sh) & 1);
     const int rem = si & ((1 << sh) - 1);
     const T th = ldexp((T)rem, -sh);
-    const uint32_t o0 = (uint32_t)cur * a.slot_bytes + id * (uint32_t)sizeof(T);
-    const uint32_t o1 = (uint32_t)(cur ^ 1) * a.slot_bytes + id * (uint32_t)sizeof(T);
+    const uint32_t o0 = (uint32_t)cur * L.slot_bytes + id * (uint32_t)sizeof(T);
+    const uint32_t o1 = (uint32_t)(cur ^ 1) * L.slot_bytes + id * (uint32_t)sizeof(T);
     if constexpr (kBranchless) {
         const uint32_t o1s = rem ? o1 : o0;
 #pragma unroll
         for (int n = 0; n < NP; n++) {
-            const T x0 = buf_ld<T>(ru, o0, (uint32_t)n * a.node_bytes);
-            const T x1 = buf_ld<T>(ru, o1s, (uint32_t)n * a.node_bytes);
+            const T x0 = buf_ld<T>(ru, o0, (uint32_t)n * L.node_bytes);
+            const T x1 = buf_ld<T>(ru, o1s, (uint32_t)n * L.node_bytes);
             val[n] = x0 + th * (x1 - x0);
         }
     } else {
 #pragma unroll
-        for (int n = 0; n < NP; n++) val[n] = buf_ld<T>(ru, o0, (uint32_t)n * a.node_bytes);
+        for (int n = 0; n < NP; n++) val[n] = buf_ld<T>(ru, o0, (uint32_t)n * L.node_bytes);
         if (rem) {
 #pragma unroll
             for (int n = 0; n < NP; n++) {
-                const T x1 = buf_ld<T>(ru, o1, (uint32_t)n * a.node_bytes);
+                const T x1 = buf_ld<T>(ru, o1, (uint32_t)n * L.node_bytes);
                 val[n] = val[n] + th * (x1 - val[n]);
             }
         }
@@ -303,7 +407,8 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
     // prefetch every face's neighbour unless it costs too many registers
     constexpr bool kPrefetch = NFACE * NP <= 64;
 
-    const int sh = a.lmax - lv;
+    constexpr RefConst R = ref_const(P);
+    const int sh = L.lmax - lv;
     const int cur = (lv == 0 ? L.parity : 0) ^ ((L.i >> sh) & 1);
     const T dt = (T)ldexp(a.dt_bar, -lv);
     const uint32_t self_ent = ((uint32_t)lv << 27) | (uint32_t)j;
@@ -312,22 +417,22 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
     using KT = typename KeyOf<DIM>::type;
     const uint32_t oj = (uint32_t)j * 4u;                   // 32-bit tables
     const uint32_t ojt = (uint32_t)j * (uint32_t)sizeof(T);  // bulk arrays
-    const __amdgpu_buffer_rsrc_t ru = buf_of(L.u, 2u * a.slot_bytes);
-    const __amdgpu_buffer_rsrc_t rv = buf_of(L.v, a.slot_bytes);
-    const __amdgpu_buffer_rsrc_t rn = buf_of(L.nbr, (uint32_t)NFACE * (uint32_t)a.cap * 4u);
+    const __amdgpu_buffer_rsrc_t ru = buf_of(L.u, 2u * L.slot_bytes);
+    const __amdgpu_buffer_rsrc_t rv = buf_of(L.v, L.slot_bytes);
+    const __amdgpu_buffer_rsrc_t rn = buf_of(L.nbr, (uint32_t)NFACE * (uint32_t)L.cap * 4u);
     uint32_t ent[NFACE];
 #pragma unroll
-    for (int f = 0; f < NFACE; f++) ent[f] = buf_ld<uint32_t>(rn, oj, (uint32_t)f * (uint32_t)a.cap * 4u);
-    const KT kraw = buf_ld<KT>(buf_of(L.key, (uint32_t)a.cap * (uint32_t)sizeof(KT)), (uint32_t)j * sizeof(KT), 0);
-    const uint32_t ou = (uint32_t)cur * a.slot_bytes + ojt;
+    for (int f = 0; f < NFACE; f++) ent[f] = buf_ld<uint32_t>(rn, oj, (uint32_t)f * (uint32_t)L.cap * 4u);
+    const KT kraw = buf_ld<KT>(buf_of(L.key, (uint32_t)L.cap * (uint32_t)sizeof(KT)), (uint32_t)j * sizeof(KT), 0);
+    const uint32_t ou = (uint32_t)cur * L.slot_bytes + ojt;
     // the gate is needed only at the end; small elements load it with the
     // first round of loads, large ones after the face phase (registers)
     constexpr bool kEarlyV = NP <= 16;
     T u[NP], vv[kEarlyV ? NP : 1];
 #pragma unroll
     for (int n = 0; n < NP; n++) {
-        u[n] = buf_ld<T>(ru, ou, (uint32_t)n * a.node_bytes);
-        if constexpr (kEarlyV) vv[n] = buf_ld<T>(rv, ojt, (uint32_t)n * a.node_bytes);
+        u[n] = buf_ld<T>(ru, ou, (uint32_t)n * L.node_bytes);
+        if constexpr (kEarlyV) vv[n] = buf_ld<T>(rv, ojt, (uint32_t)n * L.node_bytes);
     }
     // ---- one neighbour per face (same-size or coarser), at the substep time
     T nb[kPrefetch ? NFACE : 1][NP];
@@ -361,7 +466,7 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
             for (int aa = 0; aa < M; aa++) {
                 T s = 0;
 #pragma unroll
-                for (int b = 0; b < M; b++) s += a.ref.A[aa][b] * u[fnode<DIM, M>(k, g, b)];
+                for (int b = 0; b < M; b++) s += (T)R.A[aa][b] * u[fnode<DIM, M>(k, g, b)];
                 r[fnode<DIM, M>(k, g, aa)] -= ck * s;
             }
     }
@@ -406,8 +511,8 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
                 T su = 0, sq = 0;
 #pragma unroll
                 for (int b = 0; b < M; b++) {
-                    su += a.ref.B[s][b] * u[fnode<DIM, M>(k, g, b)];
-                    sq += a.ref.G[s][b] * u[fnode<DIM, M>(k, g, b)];
+                    su += (T)R.B[s][b] * u[fnode<DIM, M>(k, g, b)];
+                    sq += (T)R.G[s][b] * u[fnode<DIM, M>(k, g, b)];
                 }
                 tu[g] = su;
                 tq[g] = sq;
@@ -421,8 +526,8 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
                         T su = 0, sq = 0;
 #pragma unroll
                         for (int b = 0; b < M; b++) {
-                            su += a.ref.B[1 - s][b] * nv[fnode<DIM, M>(k, g, b)];
-                            sq += a.ref.G[1 - s][b] * nv[fnode<DIM, M>(k, g, b)];
+                            su += (T)R.B[1 - s][b] * nv[fnode<DIM, M>(k, g, b)];
+                            sq += (T)R.G[1 - s][b] * nv[fnode<DIM, M>(k, g, b)];
                         }
                         nu[g] = su;
                         nq[g] = sq;
@@ -434,8 +539,8 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
                         T su = 0, sq = 0;
 #pragma unroll
                         for (int b = 0; b < M; b++) {
-                            su += a.ref.B[1 - s][b] * nb[f][fnode<DIM, M>(k, g, b)];
-                            sq += a.ref.G[1 - s][b] * nb[f][fnode<DIM, M>(k, g, b)];
+                            su += (T)R.B[1 - s][b] * nb[f][fnode<DIM, M>(k, g, b)];
+                            sq += (T)R.G[1 - s][b] * nb[f][fnode<DIM, M>(k, g, b)];
                         }
                         nu[g] = su;
                         nq[g] = sq;
@@ -446,8 +551,8 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
                 const bool co = kind == kCoarser;  // h_nbr = 2h
                 if (kind == kCoarser) {
                     T iu[NF], iq[NF];
-                    tang_apply<T, DIM, M>(a.ref.Isub, pos0, pos1, nu, iu);
-                    tang_apply<T, DIM, M>(a.ref.Isub, pos0, pos1, nq, iq);
+                    tang_apply<T, DIM, M>(R.Isub, pos0, pos1, nu, iu);
+                    tang_apply<T, DIM, M>(R.Isub, pos0, pos1, nq, iq);
 #pragma unroll
                     for (int g = 0; g < NF; g++) { nu[g] = iu[g]; nq[g] = iq[g]; }
                 }
@@ -468,11 +573,11 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
                 auto sub_face = [&](int sub) {
                     const int p0 = sub & 1, p1 = sub >> 1;
                     T ou[NF], oq[NF], nu[NF], nq[NF], F[NF], H[NF], lf[NF], lh[NF];
-                    tang_apply<T, DIM, M>(a.ref.Isub, p0, p1, tu, ou);
-                    tang_apply<T, DIM, M>(a.ref.Isub, p0, p1, tq, oq);
-                    const uint32_t fe = buf_ld<uint32_t>(buf_of(L.fine, (uint32_t)NFACE * (uint32_t)a.cap * NS * 4u),
+                    tang_apply<T, DIM, M>(R.Isub, p0, p1, tu, ou);
+                    tang_apply<T, DIM, M>(R.Isub, p0, p1, tq, oq);
+                    const uint32_t fe = buf_ld<uint32_t>(buf_of(L.fine, (uint32_t)NFACE * (uint32_t)L.cap * NS * 4u),
                                                          (uint32_t)(j * NS + sub) * 4u,
-                                                         (uint32_t)f * (uint32_t)a.cap * NS * 4u);
+                                                         (uint32_t)f * (uint32_t)L.cap * NS * 4u);
                     neighbour_trace<T, DIM, P>(a, L, ru, fe, k, 1 - s, nu, nq);
 #pragma unroll
                     for (int g = 0; g < NF; g++) {
@@ -480,8 +585,8 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
                         F[g] = (T)0.5 * (qs * oq[g] + qn * nq[g]) - sigma * jmp;
                         H[g] = (T)0.5 * jmp;
                     }
-                    tang_apply<T, DIM, M>(a.ref.Lsub, p0, p1, F, lf);
-                    tang_apply<T, DIM, M>(a.ref.Lsub, p0, p1, H, lh);
+                    tang_apply<T, DIM, M>(R.Lsub, p0, p1, F, lf);
+                    tang_apply<T, DIM, M>(R.Lsub, p0, p1, H, lh);
 #pragma unroll
                     for (int g = 0; g < NF; g++) { Fl[g] += lf[g]; Hl[g] += lh[g]; }
                 };
@@ -498,21 +603,23 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
             for (int g = 0; g < NF; g++)
 #pragma unroll
                 for (int b = 0; b < M; b++)
-                    r[fnode<DIM, M>(k, g, b)] += c2 * a.ref.winv[b] * (Fl[g] * a.ref.B[s][b] + Hl[g] * qs * a.ref.G[s][b]);
+                    r[fnode<DIM, M>(k, g, b)] += c2 * (T)R.winv[b] * (Fl[g] * (T)R.B[s][b] + Hl[g] * qs * (T)R.G[s][b]);
         }
     }
 
-    // pointwise reaction, stimulus and update
-    const uint32_t ouo = (uint32_t)(cur ^ 1) * a.slot_bytes + ojt;
+    // pointwise reaction, stimulus and update; the parameters are read
+    // before the first store (the stores could alias them for the compiler)
+    const uint32_t ouo = (uint32_t)(cur ^ 1) * L.slot_bytes + ojt;
+    const T apk = a.apk, apa = a.apa, eps0 = a.eps0, mu1 = a.mu1, mu2 = a.mu2;
+    bool any = false;  // some stimulus box is on at t_i
+    for (int b = 0; b < a.n_stim; b++) any = any || (L.t_i >= a.stim[b][6] && L.t_i < a.stim[b][7]);
 #pragma unroll
     for (int n = 0; n < NP; n++) {
         const T un = u[n];
         T vn;
         if constexpr (kEarlyV) vn = vv[n];
-        else vn = buf_ld<T>(rv, ojt, (uint32_t)n * a.node_bytes);
+        else vn = buf_ld<T>(rv, ojt, (uint32_t)n * L.node_bytes);
         T stim = 0;
-        bool any = false;
-        for (int b = 0; b < a.n_stim; b++) any = any || (L.t_i >= a.stim[b][6] && L.t_i < a.stim[b][7]);
         if (any) {
             double X[3];
             int nn = n;
@@ -520,7 +627,7 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
             for (int k = 0; k < DIM; k++) {
                 const double hk = ldexp(a.h0[k], -depth);
                 const double lo = (double)c[k] * hk;
-                X[k] = lo + 0.5 * (a.ref.xi[nn % M] + 1.0) * hk;
+                X[k] = lo + 0.5 * (R.xi[nn % M] + 1.0) * hk;
                 nn /= M;
             }
             for (int b = 0; b < a.n_stim; b++) {
@@ -530,21 +637,21 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
                 if (in) stim += (T)a.stim[b][8];
             }
         }
-        const T f = -a.apk * un * (un - a.apa) * (un - (T)1) - un * vn;
-        T den = un + a.mu2;
+        const T f = -apk * un * (un - apa) * (un - (T)1) - un * vn;
+        T den = un + mu2;
         den = den < (T)1e-6 ? (T)1e-6 : den;
-        const T vinf = a.apk * un * ((T)1 + a.apa - un);
+        const T vinf = apk * un * ((T)1 + apa - un);
         T decay;
         if constexpr (sizeof(T) == 4) {
             // FP32 bulk: hardware reciprocal (1 ulp) and exponential
-            const T eps = a.eps0 + a.mu1 * (vn * __builtin_amdgcn_rcpf(den));
+            const T eps = eps0 + mu1 * (vn * __builtin_amdgcn_rcpf(den));
             decay = __expf(-eps * dt);
         } else {
-            const T eps = a.eps0 + a.mu1 * vn / den;
+            const T eps = eps0 + mu1 * vn / den;
             decay = exp(-eps * dt);
         }
-        buf_st<T>(ru, ouo, (uint32_t)n * a.node_bytes, un + dt * (r[n] + f + stim));
-        buf_st<T>(rv, ojt, (uint32_t)n * a.node_bytes, vinf + (vn - vinf) * decay);
+        buf_st<T>(ru, ouo, (uint32_t)n * L.node_bytes, un + dt * (r[n] + f + stim));
+        buf_st<T>(rv, ojt, (uint32_t)n * L.node_bytes, vinf + (vn - vinf) * decay);
     }
 }
 
@@ -565,11 +672,16 @@ __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> *__restrict__
 // A tile is up to blockDim.x consecutive active elements of one simulation,
 // all of one level.
 struct BatchTile {
+    // the simulation's arrays as byte offsets from the kernel's base pointer
+    long long off_u, off_v, off_key, off_nbr, off_fine;
     int sim;
     int start;
     int count;
-    int level;
+    int packed;           // level | parity << 4 | lmax << 8 (parity of the tile list's barrier)
+    uint32_t node_bytes;  // as in StepLaunch
+    uint32_t slot_bytes;
 };
+static_assert(sizeof(BatchTile) == 64, "one scalar load per tile");
 
 // Everything a batched launch needs about one simulation.  Data locations
 // are byte offsets from the kernel's base pointer so that the kernel derives
@@ -577,17 +689,15 @@ struct BatchTile {
 template <typename T>
 struct BatchSim {
     StepArgs<T> a;
-    long long off_u, off_v, off_key, off_nbr, off_fine;
     double t_start, h_tick;
 };
 
 // Barrier counter of a simulation in a batch.  Two copies alternate: the
 // launches of a barrier read one, and the first substep's launch writes the
-// next barrier's values into the other, so no launch writes what it reads.
+// next barrier's count into the other, so no launch writes what it reads.
+// (Each copy has its own tile list, which carries the barrier's parity.)
 struct BatchClock {
     long long n_bar;  // barriers since t_start
-    int parity;       // barriers since the level assignment, mod 2
-    int pad;
 };
 
 // Substep i of the barrier interval for every tile of the list.  With a
@@ -604,31 +714,37 @@ __global__ __launch_bounds__(256) void k_substep_batch(const BatchSim<T> *__rest
     const int t0 = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
     const int t1 = t0 + q + (x < r ? 1 : 0);
     for (int t = t0 + (int)(blockIdx.x >> 3); t < t1; t += per) {
-        const BatchTile tl = tiles[t];
+        // everything the first loads need comes with the tile, read as one
+        // 64-byte value (a single scalar load)
+        typedef int TileWords __attribute__((ext_vector_type(16)));
+        const BatchTile tl = __builtin_bit_cast(BatchTile, *reinterpret_cast<const TileWords *>(tiles + t));
         const BatchClock ck = clk[tl.sim];
         // every simulation has a tile at start 0 in substep 0: it advances
-        // the simulation's clock for the next barrier
-        if (i == 0 && tl.start == 0 && threadIdx.x == 0) {
-            BatchClock nx;
-            nx.n_bar = ck.n_bar + 1;
-            nx.parity = ck.parity ^ 1;
-            nx.pad = 0;
-            clk_next[tl.sim] = nx;
+        // the simulation's clock for the next barrier (after its own work,
+        // so that the element loads do not wait for the clock)
+        const bool advance = i == 0 && tl.start == 0 && threadIdx.x == 0;
+        if ((int)threadIdx.x >= tl.count) {
+            if (advance) clk_next[tl.sim] = BatchClock{ck.n_bar + 1};
+            continue;
         }
-        if ((int)threadIdx.x >= tl.count) continue;
         const BatchSim<T> &d = sims[tl.sim];
         StepLaunch<T> L;
-        L.u = reinterpret_cast<T *>(base + d.off_u);
-        L.v = reinterpret_cast<T *>(base + d.off_v);
-        L.key = base + d.off_key;
-        L.nbr = reinterpret_cast<const uint32_t *>(base + d.off_nbr);
-        L.fine = reinterpret_cast<const uint32_t *>(base + d.off_fine);
+        L.u = reinterpret_cast<T *>(base + tl.off_u);
+        L.v = reinterpret_cast<T *>(base + tl.off_v);
+        L.key = base + tl.off_key;
+        L.nbr = reinterpret_cast<const uint32_t *>(base + tl.off_nbr);
+        L.fine = reinterpret_cast<const uint32_t *>(base + tl.off_fine);
+        L.node_bytes = tl.node_bytes;
+        L.slot_bytes = tl.slot_bytes;
+        L.cap = (int)(tl.node_bytes / (uint32_t)sizeof(T));
+        L.lmax = (tl.packed >> 8) & 15;
         L.i = i;
         L.n_act = 0;
-        L.parity = ck.parity;
+        L.parity = (tl.packed >> 4) & 1;
         // t = t_start + n dt + i h, rounded like the host (no contraction)
         L.t_i = __dadd_rn(__dadd_rn(d.t_start, __dmul_rn((double)ck.n_bar, d.a.dt_bar)), __dmul_rn((double)i, d.h_tick));
-        substep_element<DIM, P, T>(d.a, L, tl.start + (int)threadIdx.x, tl.level);
+        substep_element<DIM, P, T>(d.a, L, tl.start + (int)threadIdx.x, tl.packed & 15);
+        if (advance) clk_next[tl.sim] = BatchClock{ck.n_bar + 1};
     }
 }
 

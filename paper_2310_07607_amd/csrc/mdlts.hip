@@ -833,6 +833,10 @@ mdlts_status run_barriers(mdlts_sim *s, int n_barriers)
     L.key = s->key_s.p;
     L.nbr = P<uint32_t>(s->nbr_s);
     L.fine = P<uint32_t>(s->fine_s);
+    L.node_bytes = (uint32_t)((size_t)s->cap * sizeof(T));
+    L.slot_bytes = (uint32_t)((size_t)s->np * s->cap * sizeof(T));
+    L.cap = s->cap;
+    L.lmax = s->lmax;
     const StepArgs<T> *cst = static_cast<const StepArgs<T> *>(s->step_dev.p);
     const long long maxS = 1ll << s->lmax;
     const double h_tick = s->dt_bar / (double)maxS;
@@ -1023,6 +1027,7 @@ struct BatchGroup {
     DevBuf descs, tiles, clocks;  // clocks: [2][members] BatchClock
     std::vector<BatchClock> hclk;  // host source of the clock uploads
     std::vector<int> tile_off;  // [2^lmax_all + 1] offsets into tiles per substep
+    int n_tiles = 0;            // tiles per barrier; the device list holds two copies (phases)
     char *base = nullptr;
 };
 
@@ -1101,7 +1106,7 @@ mdlts_status upload_clocks(mdlts_ctx *c, BatchPlan &P, BatchGroup &G)
     G.hclk.resize(2 * nm);
     for (size_t q = 0; q < nm; q++) {
         const mdlts_sim *s = P.sims[G.members[q]];
-        G.hclk[q] = G.hclk[nm + q] = BatchClock{s->n_bar, (int)(s->n_since_assign & 1), 0};
+        G.hclk[q] = G.hclk[nm + q] = BatchClock{s->n_bar};
     }
     HIP_TRY(hipMemcpyAsync(G.clocks.p, G.hclk.data(), 2 * nm * sizeof(BatchClock), hipMemcpyHostToDevice, c->stream));
     return MDLTS_OK;
@@ -1117,11 +1122,6 @@ mdlts_status fill_group(mdlts_ctx *c, BatchPlan &P, BatchGroup &G)
     for (int q = 0; q < nm; q++) {
         mdlts_sim *s = P.sims[G.members[q]];
         fill_step_args<T>(s, d[q].a);
-        d[q].off_u = static_cast<char *>(s->u_s.p) - G.base;
-        d[q].off_v = static_cast<char *>(s->v_s.p) - G.base;
-        d[q].off_key = static_cast<char *>(s->key_s.p) - G.base;
-        d[q].off_nbr = static_cast<char *>(s->nbr_s.p) - G.base;
-        d[q].off_fine = static_cast<char *>(s->fine_s.p) - G.base;
         d[q].t_start = s->t_start;
         d[q].h_tick = s->dt_bar / (double)(1ll << s->lmax);
     }
@@ -1138,16 +1138,38 @@ mdlts_status fill_group(mdlts_ctx *c, BatchPlan &P, BatchGroup &G)
             int v2 = 0;
             while (i > 0 && ((i >> v2) & 1) == 0) v2++;
             const int lmin = i == 0 ? 0 : s->lmax - v2;
+            BatchTile tt{};
+            tt.off_u = static_cast<char *>(s->u_s.p) - G.base;
+            tt.off_v = static_cast<char *>(s->v_s.p) - G.base;
+            tt.off_key = static_cast<char *>(s->key_s.p) - G.base;
+            tt.off_nbr = static_cast<char *>(s->nbr_s.p) - G.base;
+            tt.off_fine = static_cast<char *>(s->fine_s.p) - G.base;
+            tt.sim = q;
+            tt.node_bytes = (uint32_t)((size_t)s->cap * sizeof(T));
+            tt.slot_bytes = (uint32_t)((size_t)s->np * s->cap * sizeof(T));
+            const int parity = (int)(s->n_since_assign & 1);
             // active levels lmax..lmin occupy [0, cnt_ge[lmin]), finest first;
             // tiles do not straddle levels
             for (int l = s->lmax; l >= lmin; l--) {
                 const int lo = l == s->lmax ? 0 : s->cnt_ge[l + 1], hi = s->cnt_ge[l];
-                for (int st = lo; st < hi; st += P.block)
-                    tiles.push_back(BatchTile{q, st, std::min(P.block, hi - st), l});
+                for (int st = lo; st < hi; st += P.block) {
+                    tt.start = st;
+                    tt.count = std::min(P.block, hi - st);
+                    tt.packed = l | parity << 4 | s->lmax << 8;
+                    tiles.push_back(tt);
+                }
             }
         }
     }
     G.tile_off[nsub] = (int)tiles.size();
+    // the tile list of the barrier after: same tiles, the other parity
+    const size_t nt = tiles.size();
+    G.n_tiles = (int)nt;
+    for (size_t k = 0; k < nt; k++) {
+        BatchTile tt = tiles[k];
+        tt.packed ^= 1 << 4;
+        tiles.push_back(tt);
+    }
     MD_TRY(dev_alloc(c, G.tiles, std::max<size_t>(1, tiles.size()) * sizeof(BatchTile)));
     HIP_TRY(hipMemcpyAsync(G.descs.p, d.data(), (size_t)nm * sizeof(BatchSim<T>), hipMemcpyHostToDevice, c->stream));
     MD_TRY(dev_alloc(c, G.clocks, 2 * (size_t)nm * sizeof(BatchClock)));
@@ -1207,7 +1229,7 @@ mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, int phase, hipGraph_t grap
             int n_t = G.tile_off[i + 1] - G.tile_off[i];
             if (n_t == 0) continue;
             const void *descs = G.descs.p;
-            const BatchTile *tl = static_cast<const BatchTile *>(G.tiles.p) + G.tile_off[i];
+            const BatchTile *tl = static_cast<const BatchTile *>(G.tiles.p) + (size_t)phase * G.n_tiles + G.tile_off[i];
             int ii = (int)i;
             char *base = G.base;
             const int nm = (int)G.members.size();
@@ -1353,11 +1375,8 @@ mdlts_status prepare_plan(mdlts_ctx *c, BatchPlan *&slot, mdlts_sim *const *sims
     if (same) {
         bool moved = false;
         for (int q = 0; q < n; q++) moved = moved || P->n_bar[q] != sims[q]->n_bar;
-        if (moved) {
-            for (auto &G : P->groups) MD_TRY(upload_clocks(c, *P, G));
-            P->phase = 0;
-            for (int q = 0; q < n; q++) P->n_bar[q] = sims[q]->n_bar;
-        }
+        // clocks and the tiles' parities from the host's counts
+        if (moved) MD_TRY(build_plan_data(c, *P));
         return MDLTS_OK;
     }
     free_plan(c, slot);
