@@ -148,11 +148,15 @@ def batched_leg(ctx, args):
             s.adapt(tau_r, tau_c)
             s.assign_levels(dt)
 
-    # warm-up: adaptation intervals from rest through the stimulus
-    for _ in range(3):
+    # warm-up: adaptation intervals from rest until every stimulus (1 ms) is
+    # over, so that the timed region is the propagation phase
+    warm = 0
+    while warm < 3 or (min(s.counters()[1] for s in sims) < 1.2 and warm < 60):
         adapt_all()
         ctx.batch_step(sims, every)
+        warm += 1
     ctx.sync()
+    t_warm = [s.counters()[1] for s in sims]
     c0 = [s.counters()[0] for s in sims]
     w0 = time.perf_counter()
     ctx.batch_step(sims, args.batched_barriers)
@@ -186,6 +190,7 @@ def batched_leg(ctx, args):
         key = f"k_substep_batch<{w['dim']},{w['p']},float>"
         totals[key] = totals.get(key, 0) + s.counters()[0]
     out = {"sims": len(sims), "dof": n_dof, "state_bytes_fp32": 12 * n_dof,
+           "warmup_intervals": warm, "t_sim_ms_after_warmup": [min(t_warm), max(t_warm)],
            "value": dof / wall, "unit": "DoF-updates/s", "barriers": args.batched_barriers,
            "ms_per_barrier": wall / args.batched_barriers * 1e3,
            "with_adaptation": {"value": (a1 - a0) / w_int, "interval_ms": w_int * 1e3, "barriers": every},

@@ -387,6 +387,42 @@ __device__ __forceinline__ void neighbour_values(const StepArgs<T> &a, const Ste
     }
 }
 
+// The two halves of neighbour_values for software pipelining: the current
+// slot's values, then (at use) the interpolation towards the other slot for
+// lanes whose neighbour is coarser and not updated at this substep.
+template <typename T, int NP>
+__device__ __forceinline__ void neighbour_slot0(const StepLaunch<T> &L, __amdgpu_buffer_rsrc_t ru, uint32_t ent,
+                                                T *val)
+{
+    const uint32_t id = ent & kIdMask27;
+    const int ln = (int)((ent >> 27) & 7);
+    const int sh = L.lmax - ln;
+    const int cur = (ln == 0 ? L.parity : 0) ^ ((L.i >> sh) & 1);
+    const uint32_t o0 = (uint32_t)cur * L.slot_bytes + id * (uint32_t)sizeof(T);
+#pragma unroll
+    for (int n = 0; n < NP; n++) val[n] = buf_ld<T>(ru, o0, (uint32_t)n * L.node_bytes);
+}
+
+template <typename T, int NP>
+__device__ __forceinline__ void neighbour_interp(const StepLaunch<T> &L, __amdgpu_buffer_rsrc_t ru, uint32_t ent,
+                                                 T *val)
+{
+    const uint32_t id = ent & kIdMask27;
+    const int ln = (int)((ent >> 27) & 7);
+    const int sh = L.lmax - ln;
+    const int cur = (ln == 0 ? L.parity : 0) ^ ((L.i >> sh) & 1);
+    const int rem = L.i & ((1 << sh) - 1);
+    if (rem) {
+        const T th = ldexp((T)rem, -sh);
+        const uint32_t o1 = (uint32_t)(cur ^ 1) * L.slot_bytes + id * (uint32_t)sizeof(T);
+#pragma unroll
+        for (int n = 0; n < NP; n++) {
+            const T x1 = buf_ld<T>(ru, o1, (uint32_t)n * L.node_bytes);
+            val[n] = val[n] + th * (x1 - val[n]);
+        }
+    }
+}
+
 // One substep (Sec. 2.3, Algorithm 1) for the active prefix of the
 // level-grouped elements: element-volume diffusion, SIPG face fluxes
 // (Sec. 2.1), inverse diagonal mass, Aliev-Panfilov reaction + stimulus,
@@ -471,7 +507,19 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
             }
     }
 
-    // interior faces
+    // interior faces.  Elements too large to prefetch every face keep the
+    // neighbours of two faces in flight: face f+2's loads are issued as soon
+    // as face f is done (double buffer), so memory overlaps the arithmetic.
+    T nbuf[2][kPrefetch ? 1 : NP];
+    auto issue = [&](int f, T *dst) {
+        const uint32_t kind = ent[f] >> 30;
+        const bool one = kind == kSame || kind == kCoarser;
+        neighbour_slot0<T, NP>(L, ru, one ? ent[f] : self_ent, dst);
+    };
+    if constexpr (!kPrefetch) {
+        issue(0, nbuf[0]);
+        issue(1, nbuf[1]);
+    }
 #pragma unroll
     for (int k = 0; k < DIM; k++) {
         const T c2 = (T)2 * ih[k];
@@ -487,22 +535,11 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
                 t++;
             }
         }
-        // elements too large to prefetch every face load the two neighbours
-        // of this direction together (one memory round trip per direction)
-        T nbd[2][kPrefetch ? 1 : NP];
-        if constexpr (!kPrefetch) {
-#pragma unroll
-            for (int s = 0; s < 2; s++) {
-                const uint32_t kind = ent[2 * k + s] >> 30;
-                const bool one = kind == kSame || kind == kCoarser;
-                neighbour_values<T, NP, false>(a, L, ru, one ? ent[2 * k + s] : self_ent, nbd[s]);
-            }
-        }
 #pragma unroll
         for (int s = 0; s < 2; s++) {
             const int f = 2 * k + s;
             const uint32_t kind = ent[f] >> 30;
-            if (kind == kBoundary) continue;
+            if (kind != kBoundary) {
             const T ns = s ? (T)1 : (T)-1;
             const T qs = ns * Dkk * c2;
             T tu[NF], tq[NF];
@@ -546,7 +583,8 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
                         nq[g] = sq;
                     }
                 } else {
-                    trace_from(nbd[s]);
+                    neighbour_interp<T, NP>(L, ru, ent[f], nbuf[s]);
+                    trace_from(nbuf[s]);
                 }
                 const bool co = kind == kCoarser;  // h_nbr = 2h
                 if (kind == kCoarser) {
@@ -556,14 +594,19 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
 #pragma unroll
                     for (int g = 0; g < NF; g++) { nu[g] = iu[g]; nq[g] = iq[g]; }
                 }
-                // sigma = gamma 1/2 (D/h + D/h_nbr); n.D grad on the neighbour scales by 2/h_nbr
+                // sigma = gamma 1/2 (D/h + D/h_nbr); n.D grad on the neighbour
+                // scales by 2/h_nbr.  Fl and Hl are formed already scaled for
+                // the lift (by c2 and by c2 qs): F = 1/2 (qs tq + qn nq) - sigma [u],
+                // H = 1/2 [u].
                 const T sigma = co ? (T)0.75 * pen : pen;
                 const T qn = ns * Dkk * (co ? ih[k] : c2);
+                const T cf_q = (T)0.5 * c2 * qs, cf_n = (T)0.5 * c2 * qn, cf_j = c2 * sigma;
+                const T ch = (T)0.5 * c2 * qs;
 #pragma unroll
                 for (int g = 0; g < NF; g++) {
                     const T jmp = tu[g] - nu[g];
-                    Fl[g] = (T)0.5 * (qs * tq[g] + qn * nq[g]) - sigma * jmp;
-                    Hl[g] = (T)0.5 * jmp;
+                    Fl[g] = cf_q * tq[g] + cf_n * nq[g] - cf_j * jmp;
+                    Hl[g] = ch * jmp;
                 }
             } else {
                 const T sigma = (T)1.5 * pen;           // h_nbr = h/2
@@ -597,13 +640,20 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
 #pragma unroll 1
                     for (int sub = 0; sub < NS; sub++) sub_face(sub);
                 }
+                const T chq = c2 * qs;
+#pragma unroll
+                for (int g = 0; g < NF; g++) { Fl[g] *= c2; Hl[g] *= chq; }
             }
-            // lift to the own nodes, already multiplied by the inverse mass
+            // lift to the own nodes, already multiplied by the inverse mass:
+            // r += c2 winv (F B + qs H G), with c2 and c2 qs already in Fl, Hl
 #pragma unroll
             for (int g = 0; g < NF; g++)
 #pragma unroll
                 for (int b = 0; b < M; b++)
-                    r[fnode<DIM, M>(k, g, b)] += c2 * (T)R.winv[b] * (Fl[g] * (T)R.B[s][b] + Hl[g] * qs * (T)R.G[s][b]);
+                    r[fnode<DIM, M>(k, g, b)] += Fl[g] * (T)(R.winv[b] * R.B[s][b]) + Hl[g] * (T)(R.winv[b] * R.G[s][b]);
+            }
+            if constexpr (!kPrefetch)
+                if (f + 2 < NFACE) issue(f + 2, nbuf[s]);
         }
     }
 
@@ -613,6 +663,22 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
     const T apk = a.apk, apa = a.apa, eps0 = a.eps0, mu1 = a.mu1, mu2 = a.mu2;
     bool any = false;  // some stimulus box is on at t_i
     for (int b = 0; b < a.n_stim; b++) any = any || (L.t_i >= a.stim[b][6] && L.t_i < a.stim[b][7]);
+    // Nodes lie inside the element's box [lo, lo + h] (also after rounding:
+    // lo + f h with 0 < f < 1 rounds into [lo, fl(lo + h)]), so an element
+    // whose box misses every active stimulus box tests no node.
+    bool hit = false;
+    if (any) {
+        for (int b = 0; b < a.n_stim; b++) {
+            bool h = L.t_i >= a.stim[b][6] && L.t_i < a.stim[b][7];
+#pragma unroll
+            for (int k = 0; k < DIM; k++) {
+                const double hk = ldexp(a.h0[k], -depth);
+                const double lo = (double)c[k] * hk;
+                h = h && lo <= a.stim[b][3 + k] && lo + hk >= a.stim[b][k];
+            }
+            hit = hit || h;
+        }
+    }
 #pragma unroll
     for (int n = 0; n < NP; n++) {
         const T un = u[n];
@@ -620,7 +686,7 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
         if constexpr (kEarlyV) vn = vv[n];
         else vn = buf_ld<T>(rv, ojt, (uint32_t)n * L.node_bytes);
         T stim = 0;
-        if (any) {
+        if (hit) {
             double X[3];
             int nn = n;
 #pragma unroll
