@@ -433,9 +433,16 @@ __device__ __forceinline__ void neighbour_interp(const StepLaunch<T> &L, __amdgp
 // same-size or coarser faces) one neighbour per face are loaded before any
 // arithmetic, so a wave waits for memory twice; faces with finer neighbours
 // (rare, at refinement interfaces) load their 2^(d-1) neighbours on demand.
+// Large FP32 elements stage the gate v through LDS: its loads go straight
+// to LDS at the start (no registers held) and are read at the update.
+template <int DIM, int P, typename T>
+constexpr bool kGateInLds = Shape<DIM, P>::NP > 16 && sizeof(T) == 4;
+template <int DIM, int P, typename T>
+constexpr int kGateLdsWords = kGateInLds<DIM, P, T> ? 4 * Shape<DIM, P>::NP * 64 : 1;  // 4 waves per block
+
 template <int DIM, int P, typename T>
 __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const StepLaunch<T> &L, const int j,
-                                                const int lv)
+                                                const int lv, float *gate_lds)
 {
     using S = Shape<DIM, P>;
     constexpr int M = S::M, NP = S::NP, NF = S::NF, NS = S::NS;
@@ -464,11 +471,16 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
     // the gate is needed only at the end; small elements load it with the
     // first round of loads, large ones after the face phase (registers)
     constexpr bool kEarlyV = NP <= 16;
+    constexpr bool kLdsV = kGateInLds<DIM, P, T>;
+    // this wave's slice of the gate staging area: [node][lane]
+    float *gv = gate_lds + (threadIdx.x >> 6) * (NP * 64);
     T u[NP], vv[kEarlyV ? NP : 1];
 #pragma unroll
     for (int n = 0; n < NP; n++) {
         u[n] = buf_ld<T>(ru, ou, (uint32_t)n * L.node_bytes);
         if constexpr (kEarlyV) vv[n] = buf_ld<T>(rv, ojt, (uint32_t)n * L.node_bytes);
+        if constexpr (kLdsV)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rv, gv + n * 64, 4, ojt, (uint32_t)n * L.node_bytes, 0, 0);
     }
     // ---- one neighbour per face (same-size or coarser), at the substep time
     T nb[kPrefetch ? NFACE : 1][NP];
@@ -683,8 +695,16 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
     for (int n = 0; n < NP; n++) {
         const T un = u[n];
         T vn;
-        if constexpr (kEarlyV) vn = vv[n];
-        else vn = buf_ld<T>(rv, ojt, (uint32_t)n * L.node_bytes);
+        if constexpr (kEarlyV) {
+            vn = vv[n];
+        } else if constexpr (kLdsV) {
+            // the LDS writes of the staging loads complete with vmcnt, which
+            // the compiler does not track for them: wait before the first read
+            if (n == 0) __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0)
+            vn = gv[n * 64 + (threadIdx.x & 63)];
+        } else {
+            vn = buf_ld<T>(rv, ojt, (uint32_t)n * L.node_bytes);
+        }
         T stim = 0;
         if (hit) {
             double X[3];
@@ -731,7 +751,8 @@ __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> *__restrict__
     int lv = 0;  // elements are grouped finest level first
 #pragma unroll
     for (int l = 1; l < kMaxLevels; l++) lv += (j < a.cnt_ge[l]) ? 1 : 0;
-    substep_element<DIM, P, T>(a, L, j, lv);
+    __shared__ float gate[kGateLdsWords<DIM, P, T>];
+    substep_element<DIM, P, T>(a, L, j, lv, gate);
 }
 
 // ---- many simulations in one launch ------------------------------------------
@@ -809,7 +830,8 @@ __global__ __launch_bounds__(256) void k_substep_batch(const BatchSim<T> *__rest
         L.parity = (tl.packed >> 4) & 1;
         // t = t_start + n dt + i h, rounded like the host (no contraction)
         L.t_i = __dadd_rn(__dadd_rn(d.t_start, __dmul_rn((double)ck.n_bar, d.a.dt_bar)), __dmul_rn((double)i, d.h_tick));
-        substep_element<DIM, P, T>(d.a, L, tl.start + (int)threadIdx.x, tl.packed & 15);
+        __shared__ float gate[kGateLdsWords<DIM, P, T>];
+        substep_element<DIM, P, T>(d.a, L, tl.start + (int)threadIdx.x, tl.packed & 15, gate);
         if (advance) clk_next[tl.sim] = BatchClock{ck.n_bar + 1};
     }
 }
