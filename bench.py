@@ -11,8 +11,14 @@ One step = one adaptation interval, all on the device: indicator, adaptation
 and grouping, then `amr_every` barrier intervals of substeps.  Warm-up steps
 start at t = 0 from the resting state; the front is established before
 timing starts.  `value` comes from an uninstrumented timed region; the
-substep kernel's average duration (roofline) from a following pass of
-`--profile-steps` steps with HIP events around every substep launch.
+substep kernel's average launch duration (roofline) from a following pass
+of `--profile-steps` intervals whose graph-replayed barriers are bracketed
+by HIP events on the library's stream (only substep launches run between
+the events), divided by the launches they contain.
+
+Further legs: the plain FP64 global step on the same mesh and state, the
+FP32 LTS error against it, the batched workload (64 simulations), the
+serving loop (Poisson arrivals) and the FP64 oracle on the host cores.
 
 Prints one JSON line (rank 0, N = 1).
 """
@@ -47,7 +53,12 @@ BYTES_PER_DOF_Q1_2D_F32 = bytes_per_dof(2, 1)  # 21 B
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2310_07607_amd", "csrc", "kernels.hpp")
 FETCH_SCALE = 2.0   # copy of 256 MiB: FETCH_SIZE reads 128.0 MiB
 WRITE_SCALE = 1.0   # copy of 256 MiB: WRITE_SIZE reads 256.0 MiB
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    # amr_2d workload, all dispatches of the kernel in a 100 + 20 + 5 interval run
+    "k_substep_batch<2,1,float>": {"digest": "4514c560528d4739", "hbm_over_algorithmic": 1.280},
+    # batched workload, the four FP32 variants weighted by algorithmic bytes
+    "k_substep_batch": {"digest": "4514c560528d4739", "hbm_over_algorithmic": 1.069},
+}
 
 
 def kernel_digest():
@@ -74,6 +85,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-barriers", type=int, default=200)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the batched leg and print its object (for counter runs)")
     ap.add_argument("--batched-sims", type=int, default=64)
     ap.add_argument("--batched-barriers", type=int, default=64)
     ap.add_argument("--no-serving", action="store_true")
@@ -114,6 +127,31 @@ def barrier_step(W):
     desc = mdlts.make_desc(W["dim"], W["p"], W["n"], W["length"], W["max_depth"], W["n_levels"])
     b = mdlts.cfl_bound(desc, W["D"][: W["dim"]], W["gamma"], W["max_depth"])
     return 2 ** (W["n_levels"] - 1) * b * (1 - 2 ** -20)
+
+
+def launches_per_barrier(sim):
+    """Substep launches of one barrier of a simulation stepped alone: every
+    substep of 2^lmax has active elements (cnt_ge is non-increasing)."""
+    _, _, cnt = sim.get_levels()
+    lmax = max(l for l in range(len(cnt)) if cnt[l] > 0)
+    return 2 ** lmax
+
+
+def timed_barriers(ctx, fn, n, count):
+    """(device ms, DoF-updates) of n barriers run by fn(n) on the context's
+    stream, after one untimed barrier that builds the plan's graphs; count()
+    returns the DoF-updates so far."""
+    import torch
+    fn(1)
+    c0 = count()
+    st = ctx._torch_stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    fn(n)
+    e1.record(st)
+    e1.synchronize()
+    return e0.elapsed_time(e1), count() - c0
 
 
 def interval(sim, W, dt):
@@ -165,14 +203,18 @@ def batched_leg(ctx, args):
     c1 = [s.counters()[0] for s in sims]
     dof = sum(b - a for a, b in zip(c0, c1))
     bytes_alg = sum((b - a) * bytes_per_dof(w["dim"], w["p"]) for a, b, w in zip(c0, c1, specs))
-    # kernel timing pass
+    # kernel timing: HIP events around graph-replayed barriers (only substep
+    # launches run between them); launches per barrier: one per kernel
+    # variant and substep of the longest schedule in that variant
     ctx.batch_profile(True)
-    c0 = [s.counters()[0] for s in sims]
-    ctx.batch_step(sims, 16)
-    ms, nl, nd, blk, pcu = ctx.batch_profile_read()
+    ctx.batch_step(sims, 1)
+    _, nl1, _, blk, pcu = ctx.batch_profile_read()
     ctx.batch_profile(False)
-    c1 = [s.counters()[0] for s in sims]
-    kbytes = sum((b - a) * bytes_per_dof(w["dim"], w["p"]) for a, b, w in zip(c0, c1, specs))
+    nb_k = 16
+    bpd = [bytes_per_dof(w["dim"], w["p"]) for w in specs]
+    ms, kbytes = timed_barriers(ctx, lambda n: ctx.batch_step(sims, n), nb_k,
+                                lambda: sum(s.counters()[0] * b for s, b in zip(sims, bpd)))
+    nl = nl1 * nb_k
     achieved = kbytes / (ms * 1e-3) / 1e9
     traffic = traffic_per_launch("k_substep_batch", kbytes / max(nl, 1))
     # one full adaptation interval (indicator + adaptation + levels for every
@@ -278,6 +320,11 @@ def main():
     import torch
     from paper_2310_07607_amd import inputs, mdlts
 
+    if args.batched_only:
+        ctx = mdlts.Context(0)
+        print(json.dumps({"batched": batched_leg(ctx, args)}), flush=True)
+        ctx.close()
+        return
     W = dict(inputs.WORKLOADS[args.workload])
     dt = barrier_step(W)
     ctx = mdlts.Context(0)
@@ -296,12 +343,18 @@ def main():
     n1, t_sim1 = sim.counters()
     dof = n1 - n0
     value = dof / wall
-    # kernel timing pass: HIP events around every substep launch
-    sim.profile(True)
+    # kernel timing pass: HIP events around the graph-replayed barriers of
+    # each interval (only substep launches run between them)
+    k_ms, k_launch, k_dof = 0.0, 0, 0
     for _ in range(args.profile_steps):
-        interval(sim, W, dt)
-    k_ms, k_launch, k_dof = sim.profile_read()
-    sim.profile(False)
+        sim.indicator(download=False)
+        sim.adapt(W["tau_refine"], W["tau_coarsen"])
+        sim.assign_levels(dt)
+        nb_k = W["amr_every"] - 1
+        ms, nd = timed_barriers(ctx, lambda n: sim.step(n), nb_k, lambda: sim.counters()[0])
+        k_ms += ms
+        k_dof += nd
+        k_launch += launches_per_barrier(sim) * nb_k
     _, t_sim1 = sim.counters()
     leaves = sim.n_leaves
     hist = sim.assign_levels(dt)
@@ -318,14 +371,14 @@ def main():
     plain.step(5)
     ctx.sync()
     p0, _ = plain.counters()
-    plain.profile(True)
     wp = time.perf_counter()
     plain.step(args.plain_barriers)
     ctx.sync()
     wplain = time.perf_counter() - wp
-    p_ms, p_launch, p_dof = plain.profile_read()
     p1, _ = plain.counters()
     plain_rate = (p1 - p0) / wplain
+    p_ms, _ = timed_barriers(ctx, lambda n: plain.step(n), 50, lambda: plain.counters()[0])
+    p_launch = 50
 
     # FP32 LTS vs FP64 plain over the same simulated window (frozen mesh)
     lts = setup(ctx, W, args.seed, "f32")
@@ -348,8 +401,8 @@ def main():
     achieved = BYTES_PER_DOF_Q1_2D_F32 * k_dof / (k_ms * 1e-3) / 1e9 if k_ms > 0 else 0.0
     alg_per_launch = BYTES_PER_DOF_Q1_2D_F32 * k_dof / max(k_launch, 1)
     totals = {"unit": "DoF-updates since creation",
-              "k_substep<2,1,float>": sim.counters()[0] + lts.counters()[0],
-              "k_substep<2,1,double>": plain.counters()[0] + ref.counters()[0]}
+              "k_substep_batch<2,1,float>": sim.counters()[0] + lts.counters()[0],
+              "k_substep_batch<2,1,double>": plain.counters()[0] + ref.counters()[0]}
     out = {
         "metric": METRIC,
         "value": value,
@@ -377,9 +430,9 @@ def main():
                        "rel_l2_fp32_lts_vs_fp64_plain": err, "window_ms": nb * dt},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic_per_launch("k_substep<2,1,float>", alg_per_launch),
+                     "traffic": traffic_per_launch("k_substep_batch<2,1,float>", alg_per_launch),
                      "traffic_unit": "HBM bytes per launch", "algorithmic_bytes_per_launch": alg_per_launch,
-                     "kernel": "k_substep<2,1,float>", "bytes_per_dof_update": BYTES_PER_DOF_Q1_2D_F32,
+                     "kernel": "k_substep_batch<2,1,float>", "bytes_per_dof_update": BYTES_PER_DOF_Q1_2D_F32,
                      "avg_launch_us": k_ms * 1e3 / max(k_launch, 1)},
         "dispatch_totals": totals,
     }
