@@ -155,9 +155,9 @@ def timed_barriers(ctx, fn, n, count):
 
 
 def interval(sim, W, dt):
-    sim.indicator(download=False)
-    sim.adapt(W["tau_refine"], W["tau_coarsen"])
-    sim.assign_levels(dt)
+    """Indicator, adaptation, levels (one call, two host synchronisations),
+    then amr_every barriers."""
+    sim.ctx.batch_adapt([sim], W["tau_refine"], W["tau_coarsen"], [dt])
     sim.step(W["amr_every"])
 
 
@@ -181,10 +181,7 @@ def batched_leg(ctx, args):
     every = 32
 
     def adapt_all():
-        for s, dt in zip(sims, dts):
-            s.indicator(download=False)
-            s.adapt(tau_r, tau_c)
-            s.assign_levels(dt)
+        ctx.batch_adapt(sims, tau_r, tau_c, dts)
 
     # warm-up: adaptation intervals from rest until every stimulus (1 ms) is
     # over, so that the timed region is the propagation phase
@@ -347,9 +344,7 @@ def main():
     # each interval (only substep launches run between them)
     k_ms, k_launch, k_dof = 0.0, 0, 0
     for _ in range(args.profile_steps):
-        sim.indicator(download=False)
-        sim.adapt(W["tau_refine"], W["tau_coarsen"])
-        sim.assign_levels(dt)
+        sim.ctx.batch_adapt([sim], W["tau_refine"], W["tau_coarsen"], [dt])
         nb_k = W["amr_every"] - 1
         ms, nd = timed_barriers(ctx, lambda n: sim.step(n), nb_k, lambda: sim.counters()[0])
         k_ms += ms

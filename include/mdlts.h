@@ -170,6 +170,17 @@ mdlts_status mdlts_step(mdlts_sim *sim, int n_barriers);
  * keep the fastest.  Asynchronous on the context stream.  EINVAL for a
  * repeated or foreign simulation, ESTATE if levels are not assigned. */
 mdlts_status mdlts_batch_step(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sims, int n_barriers);
+/* Error indicator, adaptation and level assignment of several simulations
+ * (Algorithm 1's adaptation step at a barrier): for each simulation the same
+ * work and results as mdlts_indicator (no readback), mdlts_adapt (with the
+ * device indicator) and mdlts_assign_levels(dt_barrier[q]) in sequence, with
+ * two host synchronisations for all simulations together instead of several
+ * per simulation.  sims as for mdlts_batch_step; dt_barrier [n_sims].
+ * Returns the first error of any simulation (EUNSTABLE: non-finite
+ * indicator or a leaf beyond the levels; that simulation's levels are then
+ * invalid); the others are still processed. */
+mdlts_status mdlts_batch_adapt(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sims, double tau_refine,
+                               double tau_coarsen, const double *dt_barrier);
 /* enable = 0 launches the batch's kernels one by one instead of as a graph. */
 mdlts_status mdlts_set_graphs(mdlts_ctx *ctx, int enable);
 /* Event timing of the batched substep launches (not graph-replayed while

@@ -434,8 +434,22 @@ struct mdlts_ctx {
     }
 };
 
+// Host-visible staging of a simulation's small readbacks (pinned memory, so
+// the copies into it are asynchronous and one synchronisation can cover the
+// readbacks of many simulations).
+struct PinnedReadback {
+    unsigned long long tallies[3];  // adaptation: refined, coarsened, (spare)
+    int total;                      // adaptation: number of new leaves
+    int face_bad;                   // face tables: inconsistent mesh
+    int level_bad;                  // levels: a leaf needs more levels than configured
+    int eta_nonfinite;              // indicator: non-finite values
+    unsigned long long eta_max_bits;
+    int cnt_ge[kMaxLevels];
+};
+
 struct mdlts_sim {
     mdlts_ctx *ctx = nullptr;
+    PinnedReadback *pin = nullptr;
     mdlts_mesh_desc desc{};
     int np = 0;
     size_t tsize = 8;  // bytes of the bulk precision
@@ -599,7 +613,8 @@ MeshGeo geo_of(const mdlts_sim *s)
 
 int n_sub(const mdlts_sim *s) { return s->desc.dim == 2 ? 2 : 4; }
 
-// face tables of the canonical leaves in key_c, built on the device
+// face tables of the canonical leaves in key_c, built on the device; the
+// consistency flag arrives in pin->face_bad after the next synchronisation
 mdlts_status device_faces(mdlts_sim *s)
 {
     mdlts_ctx *c = s->ctx;
@@ -627,10 +642,16 @@ mdlts_status device_faces(mdlts_sim *s)
                                                                P<uint32_t>(s->fine_c), P<int>(s->flags));
     }
     HIP_TRY(hipGetLastError());
-    int bad = 0;
-    HIP_TRY(hipMemcpyAsync(&bad, s->flags.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    MD_TRY(sync(c));
-    return bad ? MDLTS_EINVAL : MDLTS_OK;
+    HIP_TRY(hipMemcpyAsync(&s->pin->face_bad, s->flags.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    return MDLTS_OK;
+}
+
+// face tables and their consistency check, synchronously
+mdlts_status device_faces_sync(mdlts_sim *s)
+{
+    MD_TRY(device_faces(s));
+    MD_TRY(sync(s->ctx));
+    return s->pin->face_bad ? MDLTS_EINVAL : MDLTS_OK;
 }
 
 // upload the leaf keys of the host forest and build the face tables
@@ -652,7 +673,7 @@ mdlts_status upload_forest(mdlts_sim *s)
         MD_TRY(copy_h2d(c, s->key_c, key.data(), E));
         MD_TRY(sync(c));
     }
-    return device_faces(s);
+    return device_faces_sync(s);
 }
 
 // refresh the host mirror of the leaves from the device keys
@@ -948,12 +969,13 @@ mdlts_status run_transfer(mdlts_sim *s, int E_old, int E_new)
     return MDLTS_OK;
 }
 
-// Algorithm 1's adaptation on the device: mark (eta >= tau_refine), close
-// the 2:1 balance, flag coarsenable sibling groups, count and scan the new
-// leaves, emit keys and the transfer map, transfer u and v, rebuild faces.
+// Algorithm 1's adaptation on the device, in two halves so that several
+// simulations can share the synchronisation between them.
+// First half: mark (eta >= tau_refine), close the 2:1 balance, flag
+// coarsenable sibling groups, count and scan the new leaves; the counts
+// arrive in pin->tallies / pin->total after the next synchronisation.
 template <int DIM>
-mdlts_status device_adapt(mdlts_sim *s, double tau_refine, double tau_coarsen, int64_t *n_refined,
-                          int64_t *n_coarsened)
+mdlts_status adapt_count(mdlts_sim *s, double tau_refine, double tau_coarsen)
 {
     using KT = typename KeyOf<DIM>::type;
     mdlts_ctx *c = s->ctx;
@@ -983,18 +1005,31 @@ mdlts_status device_adapt(mdlts_sim *s, double tau_refine, double tau_coarsen, i
     k_scan_sums<<<1, kBlock, 0, st>>>(nb4, P<int>(s->bsums), total);
     k_scan_add<<<nb4, kBlock, 0, st>>>(E, P<int>(s->off), P<int>(s->bsums));
     HIP_TRY(hipGetLastError());
-    struct { unsigned long long t[3]; int total; } rb{};
-    HIP_TRY(hipMemcpyAsync(&rb, static_cast<char *>(s->flags.p) + 8, 28, hipMemcpyDeviceToHost, st));
-    MD_TRY(sync(c));
-    const int E_new = rb.total;
+    HIP_TRY(hipMemcpyAsync(s->pin->tallies, tallies, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&s->pin->total, total, sizeof(int), hipMemcpyDeviceToHost, st));
+    return MDLTS_OK;
+}
+
+// Second half, after the counts are on the host: emit keys and the transfer
+// map, transfer u and v, rebuild the face tables (their consistency flag
+// arrives in pin->face_bad after the next synchronisation).
+template <int DIM>
+mdlts_status adapt_emit(mdlts_sim *s)
+{
+    using KT = typename KeyOf<DIM>::type;
+    mdlts_ctx *c = s->ctx;
+    hipStream_t st = c->stream;
+    const int E = (int)s->E;
+    const int nb = nblocks(E);
+    const int E_new = s->pin->total;
     if (E_new <= 0 || E_new >= (1 << 27)) return MDLTS_EINVAL;
     MD_TRY(dev_alloc(c, s->key_n, (size_t)E_new * sizeof(KT)));
     MD_TRY(dev_alloc(c, s->xk, (size_t)E_new));
     MD_TRY(dev_alloc(c, s->xs, (size_t)E_new * sizeof(int32_t)));
     MD_TRY(dev_alloc(c, s->xc, (size_t)E_new));
-    k_amr_emit<DIM><<<nb, kBlock, 0, st>>>(E, key, P<uint8_t>(s->refine), P<uint8_t>(s->cflag), P<int>(s->cnt),
-                                            P<int>(s->off), P<KT>(s->key_n), P<uint8_t>(s->xk), P<int32_t>(s->xs),
-                                            P<uint8_t>(s->xc));
+    k_amr_emit<DIM><<<nb, kBlock, 0, st>>>(E, P<KT>(s->key_c), P<uint8_t>(s->refine), P<uint8_t>(s->cflag),
+                                            P<int>(s->cnt), P<int>(s->off), P<KT>(s->key_n), P<uint8_t>(s->xk),
+                                            P<int32_t>(s->xs), P<uint8_t>(s->xc));
     HIP_TRY(hipGetLastError());
     if (s->desc.precision == MDLTS_FP64) MD_TRY(run_transfer<double>(s, E, E_new));
     else MD_TRY(run_transfer<float>(s, E, E_new));
@@ -1003,9 +1038,7 @@ mdlts_status device_adapt(mdlts_sim *s, double tau_refine, double tau_coarsen, i
     s->host_forest_valid = false;
     s->levels_valid = false;
     s->eta_valid = false;
-    if (n_refined) *n_refined = (int64_t)rb.t[0];
-    if (n_coarsened) *n_coarsened = (int64_t)rb.t[1];
-    return device_faces(s);  // synchronises
+    return device_faces(s);
 }
 
 mdlts_status compute_G(mdlts_sim *s)
@@ -1493,6 +1526,13 @@ mdlts_status mdlts_sim_create(mdlts_ctx *ctx, const mdlts_mesh_desc *desc, mdlts
     if (!s) return MDLTS_ENOMEM;
     s->ctx = ctx;
     ctx->n_sims++;
+    if (hipHostMalloc(reinterpret_cast<void **>(&s->pin), sizeof(PinnedReadback), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        s->pin = nullptr;
+        mdlts_sim_destroy(s);
+        return MDLTS_ENOMEM;
+    }
+    std::memset(s->pin, 0, sizeof(PinnedReadback));
     s->desc = *desc;
     if (desc->dim == 2) { s->desc.n[2] = 1; s->desc.len[2] = 1.0; }
     s->np = 1;
@@ -1537,6 +1577,7 @@ mdlts_status mdlts_sim_destroy(mdlts_sim *s)
     for (DevBuf *b : bufs)
         if (dev_free(c, *b) != MDLTS_OK) st = MDLTS_EDEVICE;
     for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+    if (s->pin) (void)hipHostFree(s->pin);
     c->n_sims--;
     delete s;
     return st;
@@ -1684,12 +1725,17 @@ mdlts_status mdlts_assign_uniform(mdlts_sim *s, double dt_barrier, int level, in
     return assign_levels_impl(s, dt_barrier, level, level_hist);
 }
 
-static mdlts_status assign_levels_impl(mdlts_sim *s, double dt_barrier, int force_level, int32_t *level_hist)
+// Level assignment in two halves (so that several simulations can share the
+// synchronisation): the CFL levels, grouping, grouped tables and the state
+// permutation are enqueued; the level counts and the stability flag arrive
+// in pin->cnt_ge / pin->level_bad after the next synchronisation.
+static mdlts_status levels_enqueue(mdlts_sim *s, double dt_barrier, int force_level)
 {
-    if (!s || !(dt_barrier > 0.0) || !std::isfinite(dt_barrier)) return MDLTS_EINVAL;
+    if (!(dt_barrier > 0.0) || !std::isfinite(dt_barrier)) return MDLTS_EINVAL;
     // the substep kernels address both u slots with 32-bit byte offsets
     if ((uint64_t)2 * s->np * (uint64_t)s->E * s->tsize > 0xffffffffull) return MDLTS_ENOMEM;
     s->version++;
+    s->levels_valid = false;
     mdlts_ctx *c = s->ctx;
     const int E = (int)s->E;
     const int L = s->desc.n_levels;
@@ -1722,13 +1768,9 @@ static mdlts_status assign_levels_impl(mdlts_sim *s, double dt_barrier, int forc
     if (s->desc.dim == 2) k_levels<2><<<nb, kBlock, 0, c->stream>>>(la);
     else k_levels<3><<<nb, kBlock, 0, c->stream>>>(la);
     HIP_TRY(hipGetLastError());
-    int bad = 0;
-    HIP_TRY(hipMemcpyAsync(&bad, s->flags.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    MD_TRY(sync(c));
-    if (bad) {
-        s->levels_valid = false;
-        return MDLTS_EUNSTABLE;
-    }
+    HIP_TRY(hipMemcpyAsync(&s->pin->level_bad, s->flags.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    // (levels above the cap are clamped by k_levels, so what follows stays
+    // well defined; the flag makes the assignment invalid afterwards)
     k_level_scan<<<1, kBlock, 0, c->stream>>>(P<int>(s->hist), nb, L, P<int>(s->cnt_ge_d));
     k_level_scatter<<<nb, kBlock, 0, c->stream>>>(P<uint8_t>(s->level_c), E, P<int>(s->hist), P<int>(s->perm),
                                                    P<int>(s->inv));
@@ -1754,10 +1796,16 @@ static mdlts_status assign_levels_impl(mdlts_sim *s, double dt_barrier, int forc
     MD_TRY(dev_alloc(c, s->u_s, 2 * sbytes));
     MD_TRY(dev_alloc(c, s->v_s, sbytes));
     HIP_TRY(hipGetLastError());
-    std::vector<int32_t> cnt(kMaxLevels, 0);
-    HIP_TRY(hipMemcpyAsync(cnt.data(), s->cnt_ge_d.p, kMaxLevels * sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    MD_TRY(sync(c));
-    s->cnt_ge.assign(cnt.begin(), cnt.begin() + L);
+    HIP_TRY(hipMemcpyAsync(s->pin->cnt_ge, s->cnt_ge_d.p, kMaxLevels * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    return to_grouped(s);
+}
+
+// after the synchronisation: level counts on the host, time base, validity
+static mdlts_status levels_finish(mdlts_sim *s, double dt_barrier, int32_t *level_hist)
+{
+    if (s->pin->level_bad) return MDLTS_EUNSTABLE;
+    const int L = s->desc.n_levels;
+    s->cnt_ge.assign(s->pin->cnt_ge, s->pin->cnt_ge + L);
     s->lmax = 0;
     for (int l = 0; l < L; l++)
         if (s->cnt_ge[l] > 0) s->lmax = l;
@@ -1770,8 +1818,15 @@ static mdlts_status assign_levels_impl(mdlts_sim *s, double dt_barrier, int forc
     }
     s->levels_valid = true;
     s->step_dirty = true;
-    MD_TRY(to_grouped(s));
-    return sync(c);
+    return MDLTS_OK;
+}
+
+static mdlts_status assign_levels_impl(mdlts_sim *s, double dt_barrier, int force_level, int32_t *level_hist)
+{
+    if (!s) return MDLTS_EINVAL;
+    MD_TRY(levels_enqueue(s, dt_barrier, force_level));
+    MD_TRY(sync(s->ctx));
+    return levels_finish(s, dt_barrier, level_hist);
 }
 
 mdlts_status mdlts_get_levels(mdlts_sim *s, int8_t *level, int32_t *perm, int32_t *cnt_ge, size_t n_leaves)
@@ -1820,12 +1875,12 @@ mdlts_status mdlts_step(mdlts_sim *s, int n_barriers)
     return run_batch_barriers(c, P, remaining);
 }
 
-mdlts_status mdlts_indicator(mdlts_sim *s, double *eta, size_t n_leaves, double *eta_max)
+// the indicator on the device (canonical state, FP64 eta in eta_c); its
+// maximum and non-finite flag arrive in pin after the next synchronisation
+static mdlts_status indicator_enqueue(mdlts_sim *s)
 {
-    if (!s) return MDLTS_EINVAL;
-    const size_t E = s->E;
-    if (eta && n_leaves != E) return MDLTS_EINVAL;
     mdlts_ctx *c = s->ctx;
+    const size_t E = s->E;
     const bool was_grouped = s->state_grouped;
     MD_TRY(to_canonical(s));
     MD_TRY(dev_alloc(c, s->eta_c, E * sizeof(double)));
@@ -1835,19 +1890,25 @@ mdlts_status mdlts_indicator(mdlts_sim *s, double *eta, size_t n_leaves, double 
     int *nonf = reinterpret_cast<int *>(static_cast<char *>(s->flags.p) + 16);
     if (s->desc.precision == MDLTS_FP64) MD_TRY(run_indicator<double>(s, maxb, nonf));
     else MD_TRY(run_indicator<float>(s, maxb, nonf));
-    if (eta) HIP_TRY(hipMemcpyAsync(eta, s->eta_c.p, E * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    struct { unsigned long long m; int nf; } fl{};
-    HIP_TRY(hipMemcpyAsync(&fl.m, maxb, 8, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipMemcpyAsync(&fl.nf, nonf, 4, hipMemcpyDeviceToHost, c->stream));
-    MD_TRY(sync(c));
+    HIP_TRY(hipMemcpyAsync(&s->pin->eta_max_bits, maxb, 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(&s->pin->eta_nonfinite, nonf, 4, hipMemcpyDeviceToHost, c->stream));
+    // the grouped copy of the state is untouched
     if (was_grouped) s->state_grouped = true;
     s->eta_valid = true;
-    if (eta_max) {
-        double m;
-        std::memcpy(&m, &fl.m, 8);
-        *eta_max = m;
-    }
-    return fl.nf ? MDLTS_EUNSTABLE : MDLTS_OK;
+    return MDLTS_OK;
+}
+
+mdlts_status mdlts_indicator(mdlts_sim *s, double *eta, size_t n_leaves, double *eta_max)
+{
+    if (!s) return MDLTS_EINVAL;
+    const size_t E = s->E;
+    if (eta && n_leaves != E) return MDLTS_EINVAL;
+    mdlts_ctx *c = s->ctx;
+    MD_TRY(indicator_enqueue(s));
+    if (eta) HIP_TRY(hipMemcpyAsync(eta, s->eta_c.p, E * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    MD_TRY(sync(c));
+    if (eta_max) std::memcpy(eta_max, &s->pin->eta_max_bits, 8);
+    return s->pin->eta_nonfinite ? MDLTS_EUNSTABLE : MDLTS_OK;
 }
 
 mdlts_status mdlts_adapt(mdlts_sim *s, const double *eta, size_t n_leaves, double tau_refine, double tau_coarsen,
@@ -1864,8 +1925,15 @@ mdlts_status mdlts_adapt(mdlts_sim *s, const double *eta, size_t n_leaves, doubl
         MD_TRY(sync(c));
     }
     MD_TRY(to_canonical(s));
-    if (s->desc.dim == 2) return device_adapt<2>(s, tau_refine, tau_coarsen, n_refined, n_coarsened);
-    return device_adapt<3>(s, tau_refine, tau_coarsen, n_refined, n_coarsened);
+    if (s->desc.dim == 2) MD_TRY(adapt_count<2>(s, tau_refine, tau_coarsen));
+    else MD_TRY(adapt_count<3>(s, tau_refine, tau_coarsen));
+    MD_TRY(sync(c));
+    if (n_refined) *n_refined = (int64_t)s->pin->tallies[0];
+    if (n_coarsened) *n_coarsened = (int64_t)s->pin->tallies[1];
+    if (s->desc.dim == 2) MD_TRY(adapt_emit<2>(s));
+    else MD_TRY(adapt_emit<3>(s));
+    MD_TRY(sync(c));
+    return s->pin->face_bad ? MDLTS_EINVAL : MDLTS_OK;
 }
 
 mdlts_status mdlts_counters(mdlts_sim *s, uint64_t *dof_updates, double *t_sim)
@@ -1930,6 +1998,44 @@ mdlts_status mdlts_batch_step(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sims
     if (!P.tuned) MD_TRY(autotune(ctx, P, &remaining));
     MD_TRY(run_batch_barriers(ctx, P, remaining));
     return MDLTS_OK;
+}
+
+mdlts_status mdlts_batch_adapt(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sims, double tau_refine,
+                               double tau_coarsen, const double *dt_barrier)
+{
+    if (!ctx || !sims || n_sims < 1 || !dt_barrier) return MDLTS_EINVAL;
+    for (int q = 0; q < n_sims; q++) {
+        if (!sims[q] || sims[q]->ctx != ctx) return MDLTS_EINVAL;
+        for (int r = 0; r < q; r++)
+            if (sims[r] == sims[q]) return MDLTS_EINVAL;
+        if (!(dt_barrier[q] > 0.0) || !std::isfinite(dt_barrier[q])) return MDLTS_EINVAL;
+    }
+    // indicator and the counting half of the adaptation, all simulations
+    for (int q = 0; q < n_sims; q++) {
+        mdlts_sim *s = sims[q];
+        s->version++;
+        MD_TRY(indicator_enqueue(s));
+        MD_TRY(to_canonical(s));
+        if (s->desc.dim == 2) MD_TRY(adapt_count<2>(s, tau_refine, tau_coarsen));
+        else MD_TRY(adapt_count<3>(s, tau_refine, tau_coarsen));
+    }
+    MD_TRY(sync(ctx));
+    // new leaves, transfer, faces and levels, all simulations
+    for (int q = 0; q < n_sims; q++) {
+        mdlts_sim *s = sims[q];
+        if (s->desc.dim == 2) MD_TRY(adapt_emit<2>(s));
+        else MD_TRY(adapt_emit<3>(s));
+        MD_TRY(levels_enqueue(s, dt_barrier[q], -1));
+    }
+    MD_TRY(sync(ctx));
+    mdlts_status first = MDLTS_OK;
+    for (int q = 0; q < n_sims; q++) {
+        mdlts_sim *s = sims[q];
+        mdlts_status st = s->pin->face_bad ? MDLTS_EINVAL : levels_finish(s, dt_barrier[q], nullptr);
+        if (st == MDLTS_OK && s->pin->eta_nonfinite) st = MDLTS_EUNSTABLE;
+        if (first == MDLTS_OK) first = st;
+    }
+    return first;
 }
 
 mdlts_status mdlts_set_graphs(mdlts_ctx *ctx, int enable)

@@ -90,6 +90,7 @@ def lib():
         "mdlts_counters": (I, [P, P, P]),
         "mdlts_profile": (I, [P, I]),
         "mdlts_batch_step": (I, [P, P, I, I]),
+        "mdlts_batch_adapt": (I, [P, P, I, D, D, P]),
         "mdlts_set_graphs": (I, [P, I]),
         "mdlts_batch_profile": (I, [P, I]),
         "mdlts_batch_profile_read": (I, [P, P, P, P, P, P]),
@@ -202,6 +203,16 @@ class Context:
         """Advance several simulations together (one launch per substep and kind)."""
         arr = (ctypes.c_void_p * len(sims))(*[s.h.value for s in sims])
         _chk(lib().mdlts_batch_step(self.h, arr, len(sims), int(n_barriers)), "mdlts_batch_step")
+
+    def batch_adapt(self, sims, tau_refine, tau_coarsen, dt_barrier):
+        """Indicator, adaptation and levels of several simulations with two
+        synchronisations in all; dt_barrier: one per simulation."""
+        arr = (ctypes.c_void_p * len(sims))(*[s.h.value for s in sims])
+        dts = np.ascontiguousarray(dt_barrier, dtype=np.float64)
+        if dts.size != len(sims):
+            raise ValueError("one dt_barrier per simulation")
+        _chk(lib().mdlts_batch_adapt(self.h, arr, len(sims), float(tau_refine), float(tau_coarsen), _p(dts)),
+             "mdlts_batch_adapt")
 
     def set_graphs(self, enable=True):
         _chk(lib().mdlts_set_graphs(self.h, 1 if enable else 0), "mdlts_set_graphs")

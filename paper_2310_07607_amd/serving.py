@@ -88,10 +88,10 @@ class MdltsBackend:
         s._dt_barrier = self.dt_barrier(spec)
         return s
 
-    def adapt(self, s):
-        s.indicator(download=False)
-        s.adapt(self.tau_refine, self.tau_coarsen)
-        s.assign_levels(s._dt_barrier)
+    def adapt(self, sims):
+        """Indicator, adaptation and levels of every resident solve, with two
+        host synchronisations in all."""
+        self.ctx.batch_adapt(sims, self.tau_refine, self.tau_coarsen, [s._dt_barrier for s in sims])
 
     def advance(self, sims):
         import torch
@@ -165,9 +165,9 @@ class Server:
         self.active.extend(joining)
         if not self.active:
             return []
-        for r in self.active:
-            self.be.adapt(r.handle)
-        self.be.advance([r.handle for r in self.active])
+        handles = [r.handle for r in self.active]
+        self.be.adapt(handles)
+        self.be.advance(handles)
         self.ticks += 1
         self.peak_resident = max(self.peak_resident, len(self.active))
         self.peak_reserved = max(self.peak_reserved, self.reserved)

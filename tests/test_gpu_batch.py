@@ -90,3 +90,46 @@ def test_batch_against_oracle(ctx):
     assert nl > 0 and ms > 0 and nd > 0 and blk in (64, 128, 256)
     g.close()
     g2.close()
+
+
+def test_batch_adapt_equals_per_simulation_calls(ctx):
+    """mdlts_batch_adapt = indicator, adapt and assign_levels per simulation,
+    bitwise (trees, levels, states, and the steps that follow)."""
+    from paper_2310_07607_amd import mdlts
+
+    def build():
+        out = []
+        for k, case in enumerate(CASES):
+            dim, p, n, length, depth, D, gamma, seeds, L, prec = case
+            o, g, _, _, u, v = _make(ctx, case, 40 + k)
+            # a barrier step that keeps every leaf the adaptation can make
+            # within the levels
+            desc = mdlts.make_desc(dim, p, n, length, depth, L)
+            dt = 2 ** (L - 1) * mdlts.cfl_bound(desc, D, gamma, depth) * (1 - 2 ** -20)
+            g.assign_levels(dt)
+            out.append((g, dt))
+        return out
+
+    a = build()
+    for g, dt in a:
+        g.step(3)
+        g.indicator(download=False)
+        g.adapt(2e-9, 1e-10)
+        g.assign_levels(dt)
+        g.step(2)
+    b = build()
+    for g, dt in b:
+        g.step(3)
+    ctx.batch_adapt([g for g, _ in b], 2e-9, 1e-10, [dt for _, dt in b])
+    for g, dt in b:
+        g.step(2)
+    for (ga, _), (gb, _) in zip(a, b):
+        assert np.array_equal(ga.get_tree(), gb.get_tree())
+        la, pa, ca = ga.get_levels()
+        lb, pb, cb = gb.get_levels()
+        assert np.array_equal(la, lb) and np.array_equal(pa, pb) and np.array_equal(ca, cb)
+        ua, va = ga.get_state()
+        ub, vb = gb.get_state()
+        assert np.array_equal(ua, ub) and np.array_equal(va, vb)
+        ga.close()
+        gb.close()

@@ -31,8 +31,9 @@ class FakeBackend:
         self.open_now.add(rid)
         return rid
 
-    def adapt(self, h):
-        self.adapts[h] = self.adapts.get(h, 0) + 1
+    def adapt(self, hs):
+        for h in hs:
+            self.adapts[h] = self.adapts.get(h, 0) + 1
 
     def advance(self, hs):
         assert set(hs) <= self.open_now
