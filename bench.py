@@ -310,8 +310,8 @@ def main():
         copy_probe()
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in DESIGN.md "
-                                   "but not built", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this library runs on one GPU; sharding over several GPUs is a design, "
+                                   "not built", "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
     import torch

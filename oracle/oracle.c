@@ -14,8 +14,8 @@
  *            the gate, Gershgorin CFL per element block, substeps 2^b,
  *            Algorithm 1 (multi-queue synchronous LTS with linear time
  *            interpolation of coarser neighbours).
- * Readings where the paper is silent or garbled are listed in the design doc and
- * repeated next to the code they affect.
+ * Where the paper is silent or garbled, the reading taken is stated next to
+ * the code it affects.
  *
  * The ionic model is the two-variable Aliev-Panfilov model (the workloads'
  * model; the paper's PCG model is not specified in the paper).
@@ -789,6 +789,77 @@ int or_levels(or_sim *S, double dt_barrier, int n_levels, int8_t *level)
         level[e] = (int8_t)(b > 127 ? 127 : b);
     }
     free(cfl);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* RV-T temporal indicator and the b^cell substeps (Sec. 2.3)           */
+/* ------------------------------------------------------------------ */
+/* The indicator of element e over a barrier [t_a, t_b] (Sec. 2.3, Ratti-
+ * Veroni temporal indicator): the L2 norms over [t_a, t_b] x e of the
+ * changes of the ionic current I and of the gating right-hand side g since
+ * t_a, each divided by t_b - t_a, combined as a root sum of squares.
+ * Readings: the time integrals use the midpoint rule (as the paper states)
+ * at the state linear in time between the barrier's end values (the S-LTS
+ * representation of a coarse element between its updates); I(u, v, t) is
+ * the whole non-diffusive right-hand side of du/dt, f(u, v) + s(x, t); the
+ * L2(e) norm uses the element's own quadrature (the diagonal mass).  So
+ *   eta^2 = [ |I(m, t_m) - I(a, t_a)|^2 + |g(m) - g(a)|^2 ]_{L2(e)} / (t_b - t_a).
+ * The state at t_b is the oracle's current state. */
+static double ap_current(const or_sim *S, double u, double v)
+{
+    return -S->apk * u * (u - S->apa) * (u - 1.0) - u * v;
+}
+
+static double ap_gate_rate(const or_sim *S, double u, double v)
+{
+    double den = u + S->mu2;
+    if (den < 1e-6) den = 1e-6;
+    const double eps = S->eps0 + S->mu1 * v / den;
+    const double vinf = S->apk * u * (1.0 + S->apa - u);
+    return eps * (vinf - v);
+}
+
+int or_rvt_indicator(or_sim *S, const double *u_a, const double *v_a, double t_a, double t_b, double *eta_t)
+{
+    if (or_assemble(S) != OR_OK || !(t_b > t_a)) return OR_EINVAL;
+    const double span = t_b - t_a, t_m = 0.5 * (t_a + t_b);
+    const int np = S->np;
+    for (int64_t e = 0; e < S->n_leaves; e++) {
+        double sum = 0.0;
+        for (int i = 0; i < np; i++) {
+            const size_t q = (size_t)e * np + i;
+            double X[3];
+            node_xyz(S, S->leaf[e], i, X);
+            const double um = 0.5 * (u_a[q] + S->u[q]), vm = 0.5 * (v_a[q] + S->v[q]);
+            const double dI = (ap_current(S, um, vm) + stimulus_at(S, X, t_m)) -
+                              (ap_current(S, u_a[q], v_a[q]) + stimulus_at(S, X, t_a));
+            const double dg = ap_gate_rate(S, um, vm) - ap_gate_rate(S, u_a[q], v_a[q]);
+            sum += S->Mii[q] * (dI * dI + dg * dg);
+        }
+        eta_t[e] = sqrt(sum / span);
+    }
+    return OR_OK;
+}
+
+/* Levels with both criteria of Sec. 2.3: b_e = max(b^CFL_e, b^cell_e), with
+ * b^cell_e = ceil(log2(dt_barrier / dt_cell)) where eta_t[e] > tau_cell and
+ * 0 elsewhere.  The ceiling is taken as the smallest b >= 0 with
+ * dt_barrier 2^-b <= dt_cell (exact scaling, as for b^CFL). */
+int or_levels_cell(or_sim *S, double dt_barrier, int n_levels, const double *eta_t, double tau_cell,
+                   double dt_cell, int8_t *level)
+{
+    if (!(dt_cell > 0.0)) return OR_EINVAL;
+    int rc = or_levels(S, dt_barrier, n_levels, level);
+    if (rc != OR_OK && rc != OR_EUNSTABLE) return rc;
+    int b_cell = 0;
+    while (b_cell < 100 && ldexp(dt_barrier, -b_cell) > dt_cell) b_cell++;
+    for (int64_t e = 0; e < S->n_leaves; e++) {
+        int b = level[e];
+        if (eta_t[e] > tau_cell && b_cell > b) b = b_cell;
+        if (b > n_levels - 1) rc = OR_EUNSTABLE;
+        level[e] = (int8_t)(b > 127 ? 127 : b);
+    }
     return rc;
 }
 

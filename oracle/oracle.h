@@ -62,6 +62,13 @@ int or_apply_K(or_sim *S, const double *u, double *Ku);
 int or_step_global(or_sim *S, double dt, double t0, int64_t n_steps);
 int or_cfl(or_sim *S, double *cfl);
 int or_levels(or_sim *S, double dt_barrier, int n_levels, int8_t *level);
+/* RV-T temporal indicator of every leaf over [t_a, t_b]: the state at t_a
+ * is given (u_a, v_a), the state at t_b is the current one. */
+int or_rvt_indicator(or_sim *S, const double *u_a, const double *v_a, double t_a, double t_b, double *eta_t);
+/* levels from max(b^CFL, b^cell): b^cell = ceil(log2(dt_barrier/dt_cell))
+ * where eta_t > tau_cell, else 0 */
+int or_levels_cell(or_sim *S, double dt_barrier, int n_levels, const double *eta_t, double tau_cell,
+                   double dt_cell, int8_t *level);
 void or_bucket(int64_t E, const int8_t *level, int n_levels, int32_t *perm, int32_t *cnt_ge);
 /* mode 0: Algorithm 1 with explicit queues; mode 1: two-slot level-bucket form.
  * trace (optional, capacity trace_cap rows of 4 doubles): substep, element,

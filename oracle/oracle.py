@@ -56,6 +56,8 @@ def lib():
             "or_step_global": (I32, [P, D, D, I64]),
             "or_cfl": (I32, [P, P]),
             "or_levels": (I32, [P, D, I32, P]),
+            "or_rvt_indicator": (I32, [P, P, P, D, D, P]),
+            "or_levels_cell": (I32, [P, D, I32, P, D, D, P]),
             "or_bucket": (None, [I64, P, I32, P, P]),
             "or_lts_barrier": (I32, [P, D, D, P, I32, P, I64, P, P]),
             "or_indicator": (I32, [P, P]),
@@ -192,6 +194,25 @@ class Oracle:
         rc = lib().or_levels(self.h, float(dt_barrier), int(n_levels), _p(out))
         if rc not in (OK, EUNSTABLE):
             _check(rc, "or_levels")
+        return out, rc
+
+    def rvt_indicator(self, u_a, v_a, t_a, t_b):
+        """RV-T temporal indicator per leaf over [t_a, t_b] (current state = t_b)."""
+        n = self.n_leaves * self.np_
+        ua = np.ascontiguousarray(u_a, dtype=np.float64)
+        va = np.ascontiguousarray(v_a, dtype=np.float64)
+        assert ua.size == n and va.size == n
+        out = np.zeros(self.n_leaves)
+        _check(lib().or_rvt_indicator(self.h, _p(ua), _p(va), float(t_a), float(t_b), _p(out)), "or_rvt_indicator")
+        return out
+
+    def levels_cell(self, dt_barrier, n_levels, eta_t, tau_cell, dt_cell):
+        out = np.zeros(self.n_leaves, dtype=np.int8)
+        e = np.ascontiguousarray(eta_t, dtype=np.float64)
+        rc = lib().or_levels_cell(self.h, float(dt_barrier), int(n_levels), _p(e), float(tau_cell), float(dt_cell),
+                                  _p(out))
+        if rc not in (OK, EUNSTABLE):
+            _check(rc, "or_levels_cell")
         return out, rc
 
     @staticmethod

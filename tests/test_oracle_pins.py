@@ -501,3 +501,98 @@ def test_point_evaluation_reproduces_nodal_values_and_linears():
     np.testing.assert_allclose(o.eval_points(X[:, :2]), u, atol=1e-14)
     pts = inputs.rng(9).uniform([0, 0], [0.3, 0.2], (50, 2))
     np.testing.assert_allclose(o.eval_points(pts), 1.0 + 2.0 * pts[:, 0] - 3.0 * pts[:, 1], atol=1e-13)
+
+
+# ---- RV-T temporal indicator and b^cell (Sec. 2.3) --------------------------
+
+def _rvt_mesh(depth_bits=None, n=(4, 4), length=(0.4, 0.4), p=1):
+    o = Oracle(2, p, n, length, 1)
+    o.set_params(np.diag([1e-3, 1e-3, 0.0]), 2.0, inputs.AP_PARAMS)
+    if depth_bits is not None:
+        o.set_tree(depth_bits)
+    return o
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_rvt_zero_for_a_state_constant_in_time(p):
+    o = _rvt_mesh(p=p)
+    u, v = inputs.random_state(3, o.n_leaves * o.np_, u_range=(0.0, 1.0), v_range=(0.0, 1.0))
+    o.set_state(u, v)
+    eta = o.rvt_indicator(u, v, 0.3, 0.7)
+    assert np.all(eta == 0.0)
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_rvt_stimulus_switching_on_closed_form(p):
+    """u = v = 0 at both ends (no ionic change); a stimulus of amplitude A
+    switches on between t_a and the midpoint: inside it the change of I is A
+    at every node, so eta = A sqrt(|e| / (t_b - t_a)) for elements inside the
+    box and 0 for elements outside."""
+    o = _rvt_mesh(p=p)
+    A, t_a, t_b = 0.7, 1.0, 1.5
+    box = ((0.0, 0.0, 0.0), (0.2, 0.2, 1.0), 1.1, 5.0, A)  # on from 1.1 (t_a < 1.1 <= t_m = 1.25)
+    o.set_stimulus(inputs.box_array([box]))
+    z = np.zeros(o.n_leaves * o.np_)
+    o.set_state(z, z)
+    eta = o.rvt_indicator(z, z, t_a, t_b)
+    depth, c = o.leaf_info()
+    h = 0.1
+    inside = (c[:, 0] < 2) & (c[:, 1] < 2)
+    assert np.allclose(eta[inside], A * math.sqrt(h * h / (t_b - t_a)), rtol=1e-14)
+    assert np.all(eta[~inside] == 0.0)
+
+
+def test_rvt_gate_rate_at_the_cubic_root():
+    """v = 0, u from 0 to 2a (so the midpoint is u = a): the cubic current is
+    zero at u = 0 and u = a, and the gate rate is eps0 v_inf(a) = eps0 k a, so
+    eta = eps0 k a sqrt(|e| / (t_b - t_a))."""
+    o = _rvt_mesh()
+    k, a, eps0 = inputs.AP_PARAMS[0], inputs.AP_PARAMS[1], inputs.AP_PARAMS[2]
+    N = o.n_leaves * o.np_
+    o.set_state(np.full(N, 2 * a), np.zeros(N))
+    t_a, t_b = 0.0, 0.04
+    eta = o.rvt_indicator(np.zeros(N), np.zeros(N), t_a, t_b)
+    assert np.allclose(eta, eps0 * k * a * math.sqrt(0.01 / (t_b - t_a)), rtol=1e-13)
+
+
+def test_rvt_is_an_l2_norm_over_the_element():
+    """The same uniform states on a mesh refined once: each child carries a
+    quarter of the area, so its indicator is half the parent's."""
+    u0, u1 = 0.1, 0.6
+    coarse = _rvt_mesh()
+    N = coarse.n_leaves * coarse.np_
+    coarse.set_state(np.full(N, u1), np.full(N, 0.2))
+    ec = coarse.rvt_indicator(np.full(N, u0), np.full(N, 0.05), 0.0, 0.1)
+    fine = _rvt_mesh(depth_bits=inputs.uniform_tree_bits(16, 1, 2))
+    N = fine.n_leaves * fine.np_
+    fine.set_state(np.full(N, u1), np.full(N, 0.2))
+    ef = fine.rvt_indicator(np.full(N, u0), np.full(N, 0.05), 0.0, 0.1)
+    assert ec.min() > 0
+    assert np.allclose(ef, 0.5 * ec[0], rtol=1e-13)
+    # and it scales with 1 / sqrt(t_b - t_a)
+    e4 = coarse.rvt_indicator(np.full(16 * 4, u0), np.full(16 * 4, 0.05), 0.0, 0.4)
+    assert np.allclose(e4, 0.5 * ec, rtol=1e-13)
+
+
+def test_levels_with_the_cell_criterion():
+    """b = max(b^CFL, b^cell), b^cell = ceil(log2(dt / dt_cell)) above
+    tau_cell: dt/dt_cell = 3 gives 2, a power of two 4 gives 2 (a tie is
+    satisfied), 5 gives 3; below the threshold only the CFL level remains."""
+    o = _rvt_mesh()
+    cfl = o.cfl()
+    dt = 0.5 * cfl.min()  # every leaf at CFL level 0
+    base, rc = o.levels(dt, 4)
+    assert rc == 0 and np.all(base == 0)
+    eta = np.zeros(o.n_leaves)
+    eta[::3] = 2.0
+    for ratio, b_cell in ((3.0, 2), (4.0, 2), (5.0, 3), (1.0, 0), (0.7, 0)):
+        lv, rc = o.levels_cell(dt, 4, eta, 1.0, dt / ratio)
+        assert rc == 0
+        assert np.all(lv[eta > 1.0] == b_cell) and np.all(lv[eta <= 1.0] == 0)
+    lv, rc = o.levels_cell(dt, 3, eta, 1.0, dt / 5.0)
+    assert rc == EUNSTABLE  # b^cell = 3 needs four levels
+    # the CFL level wins where it is larger
+    dt2 = 4.0 * cfl.min()
+    lv_cfl, _ = o.levels(dt2, 4)
+    lv, rc = o.levels_cell(dt2, 4, eta, 1.0, dt2 / 2.0)
+    assert np.array_equal(lv, np.maximum(lv_cfl, np.where(eta > 1.0, 1, 0)))
