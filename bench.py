@@ -154,6 +154,30 @@ def timed_barriers(ctx, fn, n, count):
     return e0.elapsed_time(e1), count() - c0
 
 
+def rvt_leg(ctx, sim, dt, reps=20):
+    """The RV-T temporal indicator over one barrier at the workload's current
+    mesh: device time of the call (state gather, indicator kernel, maximum),
+    HIP events on the library's stream; algorithmic bytes of the indicator
+    kernel: both states (u, v) at both ends plus the key, and eta."""
+    import torch
+    sim.rvt_snapshot()
+    sim.step(1)
+    sim.rvt_indicator(download=False)  # warm
+    st = ctx._torch_stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        _, m = sim.rvt_indicator(download=False)
+    e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    n_dof = sim.n_dof
+    nbytes = n_dof * 16 + sim.n_leaves * (4 + 8)
+    return {"call_ms": ms, "dof": n_dof, "eta_t_max": m, "bytes_per_call": nbytes,
+            "achieved_GBps_lower_bound": nbytes / (ms * 1e-3) / 1e9}
+
+
 def interval(sim, W, dt):
     """Indicator, adaptation, levels (one call, two host synchronisations),
     then amr_every barriers."""
@@ -357,6 +381,7 @@ def main():
     # plain FP64 global step on the same mesh and state (frozen mesh)
     u, v = sim.get_state()
     bits = sim.get_tree()
+    rvt = rvt_leg(ctx, sim, dt)
     plain = setup(ctx, W, args.seed, "f64", n_levels=1)
     plain.set_tree(bits)
     plain.set_state(u, v)
@@ -430,6 +455,7 @@ def main():
                      "kernel": "k_substep_batch<2,1,float>", "bytes_per_dof_update": BYTES_PER_DOF_Q1_2D_F32,
                      "avg_launch_us": k_ms * 1e3 / max(k_launch, 1)},
         "dispatch_totals": totals,
+        "rvt_indicator": rvt,
     }
     for s in (sim, plain, lts, ref):
         s.close()

@@ -138,6 +138,26 @@ mdlts_status mdlts_assign_levels(mdlts_sim *sim, double dt_barrier, int32_t *lev
  * stability (dt * lambda_max < 2) is the caller's responsibility.  The CFL
  * values are still computed for mdlts_get_cfl. */
 mdlts_status mdlts_assign_uniform(mdlts_sim *sim, double dt_barrier, int level, int32_t *level_hist);
+/* ---- RV-T temporal indicator and the cell criterion (Sec. 2.3) ------------ */
+/* Saves the current state and time as the start t_a of the interval the RV-T
+ * indicator will cover (device copy; valid until the leaves change). */
+mdlts_status mdlts_rvt_snapshot(mdlts_sim *sim);
+/* RV-T indicator per leaf over [t_a, t_now]: the L2 norms over the interval
+ * and the element of the changes of the ionic current (stimulus included) and
+ * of the gate rate since t_a, divided by t_now - t_a; the time integrals by
+ * the midpoint rule at the state linear in time between the two end states.
+ * FP64 on the device, kept there for mdlts_assign_levels_cell; eta_t
+ * [n_leaves] (canonical order, may be NULL) and eta_t_max (may be NULL)
+ * receive copies.  ESTATE without a snapshot on the current leaves or if no
+ * time has passed since it.  Synchronises. */
+mdlts_status mdlts_rvt_indicator(mdlts_sim *sim, double *eta_t, size_t n_leaves, double *eta_t_max);
+/* mdlts_assign_levels with both criteria: b_e = max(b^CFL_e, b^cell_e), with
+ * b^cell_e = ceil(log2(dt_barrier / dt_cell)) where the last RV-T indicator
+ * exceeds tau_cell and 0 elsewhere (ceiling by exact scaling, ties
+ * satisfied).  ESTATE if the indicator was not computed on the current
+ * leaves; EUNSTABLE as mdlts_assign_levels. */
+mdlts_status mdlts_assign_levels_cell(mdlts_sim *sim, double dt_barrier, double tau_cell, double dt_cell,
+                                      int32_t *level_hist);
 /* Copies the last assignment: level [n_leaves] (canonical order), perm
  * [n_leaves] (grouped position -> canonical leaf), cnt_ge [n_levels]
  * (number of leaves with level >= l).  Any pointer may be NULL. */

@@ -45,6 +45,9 @@ struct LevelArgs {
     double Dk[3];
     double G[4][4];
     int force_level;  // >= 0: every leaf on this level (no CFL test)
+    const double *eta_t;  // RV-T indicator per leaf, or null: no cell criterion
+    double tau_cell;      // threshold of the cell criterion
+    int b_cell;           // level the criterion asks for
     uint8_t *level;
     double *cfl;
     int *hist;      // [blocks][8]
@@ -75,6 +78,8 @@ __global__ __launch_bounds__(kBlock) void k_levels(const LevelArgs a)
         if (a.force_level >= 0) b = a.force_level;
         else
             while (b < 64 && ldexp(a.dt_bar, -b) > cfl) b++;
+        // the cell criterion (RV-T indicator above its threshold)
+        if (a.eta_t && a.force_level < 0 && a.eta_t[e] > a.tau_cell && a.b_cell > b) b = a.b_cell;
         if (b > a.n_levels - 1) {
             atomicOr(a.bad, 1);
             b = a.n_levels - 1;
@@ -354,6 +359,97 @@ __global__ __launch_bounds__(kBlock) void k_indicator(const IndArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// RV-T temporal indicator (Sec. 2.3): per element, over a barrier [t_a, t_b],
+// the L2 norms over [t_a, t_b] x e of the changes of the ionic current I and
+// of the gate rate g since t_a, divided by t_b - t_a.  The time integrals use
+// the midpoint rule at the state linear in time between the barrier's end
+// values (the S-LTS representation of a coarse element between its
+// updates); I includes the stimulus.  FP64 from the bulk-precision states.
+// ---------------------------------------------------------------------------
+struct RvtArgs {
+    const void *u_a, *v_a;  // canonical [np][E], bulk precision: state at t_a
+    const void *u_b, *v_b;  // the same at t_b
+    const void *key;
+    int E;
+    double h0[3];
+    double apk, apa, eps0, mu1, mu2;
+    double t_a, t_b;
+    int n_stim;
+    double stim[kMaxStim][9];
+    double *eta;
+    unsigned long long *eta_max_bits;
+};
+
+__device__ __forceinline__ double rvt_current(const RvtArgs &a, double u, double v)
+{
+    return -a.apk * u * (u - a.apa) * (u - 1.0) - u * v;
+}
+
+__device__ __forceinline__ double rvt_gate_rate(const RvtArgs &a, double u, double v)
+{
+    double den = u + a.mu2;
+    den = den < 1e-6 ? 1e-6 : den;
+    const double eps = a.eps0 + a.mu1 * v / den;
+    return eps * (a.apk * u * (1.0 + a.apa - u) - v);
+}
+
+__device__ __forceinline__ double rvt_stimulus(const RvtArgs &a, const double *X, int dim, double t)
+{
+    double s = 0.0;
+    for (int b = 0; b < a.n_stim; b++) {
+        bool in = t >= a.stim[b][6] && t < a.stim[b][7];
+        for (int k = 0; k < dim; k++) in = in && X[k] >= a.stim[b][k] && X[k] <= a.stim[b][3 + k];
+        if (in) s += a.stim[b][8];
+    }
+    return s;
+}
+
+template <int DIM, int P, typename T>
+__global__ __launch_bounds__(kBlock) void k_rvt(const RvtArgs a)
+{
+    using S = Shape<DIM, P>;
+    constexpr int M = S::M, NP = S::NP;
+    constexpr RefConst R = ref_const(P);
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    double eta = 0.0;
+    if (e < a.E) {
+        int depth;
+        uint32_t c[3] = {0, 0, 0};
+        unpack_key<DIM>(static_cast<const typename KeyOf<DIM>::type *>(a.key)[e], depth, c);
+        double h[3] = {1, 1, 1}, lo[3] = {0, 0, 0};
+        for (int k = 0; k < DIM; k++) {
+            h[k] = ldexp(a.h0[k], -depth);
+            lo[k] = (double)c[k] * h[k];
+        }
+        const double t_m = 0.5 * (a.t_a + a.t_b);
+        const T *ua = static_cast<const T *>(a.u_a), *va = static_cast<const T *>(a.v_a);
+        const T *ub = static_cast<const T *>(a.u_b), *vb = static_cast<const T *>(a.v_b);
+        double sum = 0.0;
+        for (int n = 0; n < NP; n++) {
+            const long long q = (long long)n * a.E + e;
+            const double u0 = (double)ua[q], v0 = (double)va[q];
+            const double um = 0.5 * (u0 + (double)ub[q]), vm = 0.5 * (v0 + (double)vb[q]);
+            double X[3] = {0, 0, 0}, w = 1.0;
+            int nn = n;
+            for (int k = 0; k < DIM; k++) {
+                X[k] = lo[k] + 0.5 * (R.xi[nn % M] + 1.0) * h[k];
+                w *= R.w[nn % M] * 0.5 * h[k];  // diagonal mass: GL weight x |J|
+                nn /= M;
+            }
+            const double dI = (rvt_current(a, um, vm) + rvt_stimulus(a, X, DIM, t_m)) -
+                              (rvt_current(a, u0, v0) + rvt_stimulus(a, X, DIM, a.t_a));
+            const double dg = rvt_gate_rate(a, um, vm) - rvt_gate_rate(a, u0, v0);
+            sum += w * (dI * dI + dg * dg);
+        }
+        eta = sqrt(sum / (a.t_b - a.t_a));
+        a.eta[e] = eta;
+    }
+    double m = isfinite(eta) ? eta : 0.0;
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(a.eta_max_bits, (unsigned long long)__double_as_longlong(m));
+}
+
+// ---------------------------------------------------------------------------
 // refinement transfer: copy, prolongation by evaluation, L2 restriction
 // ---------------------------------------------------------------------------
 struct XferArgs {
@@ -482,6 +578,12 @@ struct mdlts_sim {
     double dt_bar = 0.0;
     double t_start = 0.0;
     long long n_bar = 0;  // barriers since t_start (time bookkeeping)
+    // RV-T temporal indicator: state snapshot at t_a and the indicator, each
+    // valid for the tree revision it was taken on
+    uint64_t tree_rev = 1;  // bumped whenever the leaves change
+    DevBuf snap_u, snap_v, eta_t_c;
+    double snap_t = 0.0;
+    uint64_t snap_rev = 0, eta_t_rev = 0;
     BatchPlan *solo = nullptr;  // graph plan of mdlts_step
     long long n_since_assign = 0;
     uint64_t dof_updates = 0;
@@ -771,6 +873,7 @@ mdlts_status to_grouped(mdlts_sim *s)
 
 mdlts_status set_forest(mdlts_sim *s, Forest &&F)
 {
+    s->tree_rev++;
     s->forest = std::move(F);
     s->levels_valid = false;
     s->eta_valid = false;
@@ -1035,6 +1138,7 @@ mdlts_status adapt_emit(mdlts_sim *s)
     else MD_TRY(run_transfer<float>(s, E, E_new));
     std::swap(s->key_c, s->key_n);
     s->E = (size_t)E_new;
+    s->tree_rev++;
     s->host_forest_valid = false;
     s->levels_valid = false;
     s->eta_valid = false;
@@ -1572,7 +1676,7 @@ mdlts_status mdlts_sim_destroy(mdlts_sim *s)
                       &s->tmp_u, &s->tmp_v, &s->u_s, &s->v_s, &s->key_s, &s->nbr_s, &s->fine_s, &s->perm,
                       &s->inv, &s->hist, &s->cnt_ge_d, &s->flags, &s->xk, &s->xs, &s->xc, &s->stage,
                       &s->root_start, &s->mkey, &s->refine, &s->cflag, &s->cnt, &s->off, &s->bsums, &s->key_n,
-                      &s->step_dev};
+                      &s->step_dev, &s->snap_u, &s->snap_v, &s->eta_t_c};
     mdlts_status st = MDLTS_OK;
     for (DevBuf *b : bufs)
         if (dev_free(c, *b) != MDLTS_OK) st = MDLTS_EDEVICE;
@@ -1729,7 +1833,8 @@ mdlts_status mdlts_assign_uniform(mdlts_sim *s, double dt_barrier, int level, in
 // synchronisation): the CFL levels, grouping, grouped tables and the state
 // permutation are enqueued; the level counts and the stability flag arrive
 // in pin->cnt_ge / pin->level_bad after the next synchronisation.
-static mdlts_status levels_enqueue(mdlts_sim *s, double dt_barrier, int force_level)
+static mdlts_status levels_enqueue(mdlts_sim *s, double dt_barrier, int force_level, const double *eta_t = nullptr,
+                                   double tau_cell = 0.0, int b_cell = 0)
 {
     if (!(dt_barrier > 0.0) || !std::isfinite(dt_barrier)) return MDLTS_EINVAL;
     // the substep kernels address both u slots with 32-bit byte offsets
@@ -1759,6 +1864,9 @@ static mdlts_status levels_enqueue(mdlts_sim *s, double dt_barrier, int force_le
     la.n_levels = L;
     la.force_level = force_level;
     la.dt_bar = dt_barrier;
+    la.eta_t = eta_t;
+    la.tau_cell = tau_cell;
+    la.b_cell = b_cell;
     for (int k = 0; k < 3; k++) { la.h0[k] = s->h0[k]; la.Dk[k] = s->Dk[k]; }
     std::memcpy(la.G, s->G, sizeof(la.G));
     la.level = P<uint8_t>(s->level_c);
@@ -1825,6 +1933,91 @@ static mdlts_status assign_levels_impl(mdlts_sim *s, double dt_barrier, int forc
 {
     if (!s) return MDLTS_EINVAL;
     MD_TRY(levels_enqueue(s, dt_barrier, force_level));
+    MD_TRY(sync(s->ctx));
+    return levels_finish(s, dt_barrier, level_hist);
+}
+
+mdlts_status mdlts_rvt_snapshot(mdlts_sim *s)
+{
+    if (!s) return MDLTS_EINVAL;
+    mdlts_ctx *c = s->ctx;
+    const bool was_grouped = s->state_grouped;
+    MD_TRY(to_canonical(s));
+    const size_t bytes = s->E * s->np * s->tsize;
+    MD_TRY(dev_alloc(c, s->snap_u, bytes));
+    MD_TRY(dev_alloc(c, s->snap_v, bytes));
+    HIP_TRY(hipMemcpyAsync(s->snap_u.p, s->u_c.p, bytes, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(s->snap_v.p, s->v_c.p, bytes, hipMemcpyDeviceToDevice, c->stream));
+    if (was_grouped) s->state_grouped = true;  // the grouped copy is untouched
+    s->snap_t = s->t_start + (double)s->n_bar * s->dt_bar;
+    s->snap_rev = s->tree_rev;
+    return MDLTS_OK;
+}
+
+mdlts_status mdlts_rvt_indicator(mdlts_sim *s, double *eta_t, size_t n_leaves, double *eta_t_max)
+{
+    if (!s) return MDLTS_EINVAL;
+    const size_t E = s->E;
+    if (eta_t && n_leaves != E) return MDLTS_EINVAL;
+    const double t_b = s->t_start + (double)s->n_bar * s->dt_bar;
+    if (s->snap_rev != s->tree_rev || !(t_b > s->snap_t)) return MDLTS_ESTATE;
+    mdlts_ctx *c = s->ctx;
+    const bool was_grouped = s->state_grouped;
+    MD_TRY(to_canonical(s));
+    MD_TRY(dev_alloc(c, s->eta_t_c, E * sizeof(double)));
+    MD_TRY(dev_alloc(c, s->flags, 64));
+    HIP_TRY(hipMemsetAsync(s->flags.p, 0, 64, c->stream));
+    RvtArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.u_a = s->snap_u.p;
+    a.v_a = s->snap_v.p;
+    a.u_b = s->u_c.p;
+    a.v_b = s->v_c.p;
+    a.key = s->key_c.p;
+    a.E = (int)E;
+    for (int k = 0; k < 3; k++) a.h0[k] = s->h0[k];
+    a.apk = s->ap.k; a.apa = s->ap.a; a.eps0 = s->ap.eps0; a.mu1 = s->ap.mu1; a.mu2 = s->ap.mu2;
+    a.t_a = s->snap_t;
+    a.t_b = t_b;
+    a.n_stim = (int)s->stim.size();
+    for (int b = 0; b < a.n_stim; b++) {
+        const mdlts_stim_box &B = s->stim[b];
+        for (int k = 0; k < 3; k++) { a.stim[b][k] = B.lo[k]; a.stim[b][3 + k] = B.hi[k]; }
+        a.stim[b][6] = B.t_on; a.stim[b][7] = B.t_off; a.stim[b][8] = B.amp;
+    }
+    a.eta = P<double>(s->eta_t_c);
+    a.eta_max_bits = reinterpret_cast<unsigned long long *>(static_cast<char *>(s->flags.p) + 8);
+    const int nb = nblocks((int)E);
+    hipStream_t st = c->stream;
+    switch (s->desc.dim * 100 + s->desc.order * 10 + (s->desc.precision == MDLTS_FP32 ? 1 : 0)) {
+    case 210: k_rvt<2, 1, double><<<nb, kBlock, 0, st>>>(a); break;
+    case 220: k_rvt<2, 2, double><<<nb, kBlock, 0, st>>>(a); break;
+    case 310: k_rvt<3, 1, double><<<nb, kBlock, 0, st>>>(a); break;
+    case 320: k_rvt<3, 2, double><<<nb, kBlock, 0, st>>>(a); break;
+    case 211: k_rvt<2, 1, float><<<nb, kBlock, 0, st>>>(a); break;
+    case 221: k_rvt<2, 2, float><<<nb, kBlock, 0, st>>>(a); break;
+    case 311: k_rvt<3, 1, float><<<nb, kBlock, 0, st>>>(a); break;
+    case 321: k_rvt<3, 2, float><<<nb, kBlock, 0, st>>>(a); break;
+    default: return MDLTS_EINVAL;
+    }
+    HIP_TRY(hipGetLastError());
+    if (eta_t) HIP_TRY(hipMemcpyAsync(eta_t, s->eta_t_c.p, E * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&s->pin->eta_max_bits, a.eta_max_bits, 8, hipMemcpyDeviceToHost, st));
+    MD_TRY(sync(c));
+    if (was_grouped) s->state_grouped = true;
+    if (eta_t_max) std::memcpy(eta_t_max, &s->pin->eta_max_bits, 8);
+    s->eta_t_rev = s->tree_rev;
+    return MDLTS_OK;
+}
+
+mdlts_status mdlts_assign_levels_cell(mdlts_sim *s, double dt_barrier, double tau_cell, double dt_cell,
+                                      int32_t *level_hist)
+{
+    if (!s || !(dt_cell > 0.0) || !std::isfinite(dt_cell) || !(dt_barrier > 0.0)) return MDLTS_EINVAL;
+    if (s->eta_t_rev != s->tree_rev) return MDLTS_ESTATE;
+    int b_cell = 0;  // ceil(log2(dt_barrier / dt_cell)) by exact scaling
+    while (b_cell < 64 && std::ldexp(dt_barrier, -b_cell) > dt_cell) b_cell++;
+    MD_TRY(levels_enqueue(s, dt_barrier, -1, P<double>(s->eta_t_c), tau_cell, b_cell));
     MD_TRY(sync(s->ctx));
     return levels_finish(s, dt_barrier, level_hist);
 }
@@ -2136,14 +2329,14 @@ mdlts_status mdlts_memory_bound(const mdlts_mesh_desc *desc, int64_t max_leaves,
     const uint64_t nsub = 1ull << (desc->n_levels - 1);
     // every buffer a simulation holds is sized by its largest leaf count
     const uint64_t per_leaf =
-        7 * np * T                  // u and v canonical, transfer copies, two u slots and v grouped
+        9 * np * T                  // u and v canonical, transfer copies, two u slots and v grouped, RV-T snapshot
         + 8 * np                    // FP64 staging of uploads and readbacks
         + 3 * ksz + 4               // canonical, new and grouped keys; Morton keys
         + 2 * (2 * d * 4)           // face tables, canonical and grouped
         + 2 * (2 * d * ns * 4)      // sub-face tables, canonical and grouped
         + 1 + 1 + 4 + 4 + 4 + 1     // refine and coarsen flags, counts, offsets, root offsets, scan sums
         + 1 + 4 + 1                 // transfer kind, source and child
-        + 1 + 8 + 4 + 4 + 8 + 1     // level, CFL, permutation both ways, indicator, histogram share
+        + 1 + 8 + 4 + 4 + 8 + 8 + 1 // level, CFL, permutation both ways, indicators, histogram share
         + (nsub * 16 + 31) / 32;    // batch tiles: per substep one per 64 leaves (blocks of >= 64 threads)
     const uint64_t fixed = 64 * 512         // allocator rounding of every buffer
                            + 4 * 4096       // flags, step constants, batch descriptor, small scans

@@ -99,6 +99,9 @@ def lib():
         "mdlts_plan_adapt": (I, [P, P, S, P, S, D, D, P, S, P]),
         "mdlts_plan_levels": (I, [P, P, S, P, D, D, P, P, P, P, S]),
         "mdlts_memory_bound": (I, [P, ctypes.c_int64, P]),
+        "mdlts_rvt_snapshot": (I, [P]),
+        "mdlts_rvt_indicator": (I, [P, P, S, P]),
+        "mdlts_assign_levels_cell": (I, [P, D, D, D, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -339,6 +342,27 @@ class Simulation:
         """Every leaf on `level` (level 0: the plain global step dt_barrier)."""
         hist = np.zeros(self.n_levels, dtype=np.int32)
         _chk(lib().mdlts_assign_uniform(self.h, float(dt_barrier), int(level), _p(hist)), "mdlts_assign_uniform")
+        return hist
+
+    def rvt_snapshot(self):
+        """Start of the interval the RV-T temporal indicator covers."""
+        _chk(lib().mdlts_rvt_snapshot(self.h), "mdlts_rvt_snapshot")
+
+    def rvt_indicator(self, download=True):
+        """(eta_t per leaf or None, max eta_t) over [snapshot time, now]."""
+        m = ctypes.c_double()
+        if not download:
+            _chk(lib().mdlts_rvt_indicator(self.h, None, 0, ctypes.byref(m)), "mdlts_rvt_indicator")
+            return None, m.value
+        eta = np.zeros(self.n_leaves)
+        _chk(lib().mdlts_rvt_indicator(self.h, _p(eta), eta.size, ctypes.byref(m)), "mdlts_rvt_indicator")
+        return eta, m.value
+
+    def assign_levels_cell(self, dt_barrier, tau_cell, dt_cell):
+        """Levels from max(b^CFL, b^cell) with the last RV-T indicator."""
+        hist = np.zeros(self.n_levels, dtype=np.int32)
+        _chk(lib().mdlts_assign_levels_cell(self.h, float(dt_barrier), float(tau_cell), float(dt_cell), _p(hist)),
+             "mdlts_assign_levels_cell")
         return hist
 
     def get_levels(self):
