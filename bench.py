@@ -178,6 +178,51 @@ def rvt_leg(ctx, sim, dt, reps=20):
             "achieved_GBps_lower_bound": nbytes / (ms * 1e-3) / 1e9}
 
 
+def auto_levels_leg(ctx, W, seed, u, v, bits, t0, barriers=20):
+    """The same mesh and state with 8 levels and the barrier step chosen from
+    the leaves (mdlts_assign_levels_auto: coarse leaves step near their own
+    CFL limit): stepping rate in simulated time, and the FP32 error over one
+    barrier against FP64 stepping every leaf at the finest substep."""
+    import numpy as np
+    L = 8
+    sim = setup(ctx, W, seed, "f32", n_levels=L)
+    sim.set_tree(bits)
+    sim.set_state(u, v)
+    dt, hist = sim.assign_levels_auto()
+    sim.set_time(t0)
+    sim.step(1)
+    ctx.sync()
+    c0, s0 = sim.counters()
+    w0 = time.perf_counter()
+    sim.step(barriers)
+    ctx.sync()
+    wall = time.perf_counter() - w0
+    c1, s1 = sim.counters()
+    # accuracy over one barrier from the same state
+    lts = setup(ctx, W, seed, "f32", n_levels=L)
+    lts.set_tree(bits)
+    lts.set_state(u, v)
+    lts.assign_levels(dt)
+    lts.set_time(t0)
+    ref = setup(ctx, W, seed, "f64", n_levels=L)
+    ref.set_tree(bits)
+    ref.set_state(u, v)
+    ref.assign_uniform(dt, L - 1)
+    ref.set_time(t0)
+    lts.step(1)
+    ref.step(1)
+    ul, _ = lts.get_state()
+    ur, _ = ref.get_state()
+    err = float(np.linalg.norm(ul - ur) / np.linalg.norm(ur))
+    out = {"n_levels": L, "dt_barrier_ms": dt, "level_hist": hist.tolist(),
+           "value": (c1 - c0) / wall, "unit": "DoF-updates/s", "sim_ms_per_s": (s1 - s0) / wall,
+           "dof_updates_per_sim_ms": (c1 - c0) / (s1 - s0),
+           "rel_l2_fp32_vs_fp64_finest_substep": err, "window_ms": dt}
+    for g in (sim, lts, ref):
+        g.close()
+    return out
+
+
 def interval(sim, W, dt):
     """Indicator, adaptation, levels (one call, two host synchronisations),
     then amr_every barriers."""
@@ -382,6 +427,7 @@ def main():
     u, v = sim.get_state()
     bits = sim.get_tree()
     rvt = rvt_leg(ctx, sim, dt)
+    auto = auto_levels_leg(ctx, W, args.seed, u, v, bits, t_sim1)
     plain = setup(ctx, W, args.seed, "f64", n_levels=1)
     plain.set_tree(bits)
     plain.set_state(u, v)
@@ -447,6 +493,8 @@ def main():
                        "kernel_ms_per_launch": p_ms / max(p_launch, 1),
                        "sim_ms_per_s": args.plain_barriers * dt_plain / wplain,
                        "lts_fp32_sim_ms_per_s": args.steps * W["amr_every"] * dt / wall,
+                       "lts_fp32_dof_updates_per_sim_ms": dof / (args.steps * W["amr_every"] * dt),
+                       "plain_dof_updates_per_sim_ms": (p1 - p0) / (args.plain_barriers * dt_plain),
                        "rel_l2_fp32_lts_vs_fp64_plain": err, "window_ms": nb * dt},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
@@ -456,6 +504,7 @@ def main():
                      "avg_launch_us": k_ms * 1e3 / max(k_launch, 1)},
         "dispatch_totals": totals,
         "rvt_indicator": rvt,
+        "auto_levels": auto,
     }
     for s in (sim, plain, lts, ref):
         s.close()

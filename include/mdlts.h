@@ -138,6 +138,15 @@ mdlts_status mdlts_assign_levels(mdlts_sim *sim, double dt_barrier, int32_t *lev
  * stability (dt * lambda_max < 2) is the caller's responsibility.  The CFL
  * values are still computed for mdlts_get_cfl. */
 mdlts_status mdlts_assign_uniform(mdlts_sim *sim, double dt_barrier, int level, int32_t *level_hist);
+/* The barrier step chosen from the current leaves (Sec. 2.3 leaves the
+ * barrier step to the user): dt_barrier = 2^(n_levels-1) * min_e CFL_e *
+ * (1 - 2^-20), the largest step that keeps every leaf within the configured
+ * levels (off the power-of-two ties), then mdlts_assign_levels with it.
+ * *dt_barrier receives the step.  With n_levels up to 8 this is the paper's
+ * form: the coarsest leaves step near their own CFL limit instead of at the
+ * finest level's.  Synchronises. */
+mdlts_status mdlts_assign_levels_auto(mdlts_sim *sim, double *dt_barrier, int32_t *level_hist);
+
 /* ---- RV-T temporal indicator and the cell criterion (Sec. 2.3) ------------ */
 /* Saves the current state and time as the start t_a of the interval the RV-T
  * indicator will cover (device copy; valid until the leaves change). */

@@ -347,43 +347,27 @@ __device__ __forceinline__ void neighbour_trace(const StepArgs<T> &a, const Step
 
 // Value of a neighbour's nodes at substep i (packed entry: level | id): a
 // neighbour updated at this substep is read from its current slot; one that
-// is not (it is coarser) is linear in time between its two slots.  Small
-// elements (kBranchless) always load both slots, the second from the
-// first's address when not needed, so that the loads of all faces issue
-// together without branches; large ones load the second slot only for
-// lanes whose neighbour needs it.
-template <typename T, int NP, bool kBranchless>
-__device__ __forceinline__ void neighbour_values(const StepArgs<T> &a, const StepLaunch<T> &L,
-                                                 __amdgpu_buffer_rsrc_t ru, uint32_t ent, T *val)
+// is not (it is coarser) is linear in time between its two slots.  Both
+// slots are always loaded (the second from the first's address when not
+// needed), so that the loads of all faces of a small element issue together
+// without branches and the wave waits for memory once.
+template <typename T, int NP>
+__device__ __forceinline__ void neighbour_values(const StepLaunch<T> &L, __amdgpu_buffer_rsrc_t ru, uint32_t ent,
+                                                 T *val)
 {
-    const int si = L.i, parity = L.parity;
     const uint32_t id = ent & kIdMask27;
     const int ln = (int)((ent >> 27) & 7);
     const int sh = L.lmax - ln;
-    const int base = ln == 0 ? parity : 0;
-    const int cur = base ^ ((si >> sh) & 1);
-    const int rem = si & ((1 << sh) - 1);
+    const int cur = (ln == 0 ? L.parity : 0) ^ ((L.i >> sh) & 1);
+    const int rem = L.i & ((1 << sh) - 1);
     const T th = ldexp((T)rem, -sh);
     const uint32_t o0 = (uint32_t)cur * L.slot_bytes + id * (uint32_t)sizeof(T);
-    const uint32_t o1 = (uint32_t)(cur ^ 1) * L.slot_bytes + id * (uint32_t)sizeof(T);
-    if constexpr (kBranchless) {
-        const uint32_t o1s = rem ? o1 : o0;
+    const uint32_t o1 = rem ? (uint32_t)(cur ^ 1) * L.slot_bytes + id * (uint32_t)sizeof(T) : o0;
 #pragma unroll
-        for (int n = 0; n < NP; n++) {
-            const T x0 = buf_ld<T>(ru, o0, (uint32_t)n * L.node_bytes);
-            const T x1 = buf_ld<T>(ru, o1s, (uint32_t)n * L.node_bytes);
-            val[n] = x0 + th * (x1 - x0);
-        }
-    } else {
-#pragma unroll
-        for (int n = 0; n < NP; n++) val[n] = buf_ld<T>(ru, o0, (uint32_t)n * L.node_bytes);
-        if (rem) {
-#pragma unroll
-            for (int n = 0; n < NP; n++) {
-                const T x1 = buf_ld<T>(ru, o1, (uint32_t)n * L.node_bytes);
-                val[n] = val[n] + th * (x1 - val[n]);
-            }
-        }
+    for (int n = 0; n < NP; n++) {
+        const T x0 = buf_ld<T>(ru, o0, (uint32_t)n * L.node_bytes);
+        const T x1 = buf_ld<T>(ru, o1, (uint32_t)n * L.node_bytes);
+        val[n] = x0 + th * (x1 - x0);
     }
 }
 
@@ -489,7 +473,7 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
         for (int f = 0; f < NFACE; f++) {
             const uint32_t kind = ent[f] >> 30;
             const bool one = kind == kSame || kind == kCoarser;
-            neighbour_values<T, NP, true>(a, L, ru, one ? ent[f] : self_ent, nb[f]);
+            neighbour_values<T, NP>(L, ru, one ? ent[f] : self_ent, nb[f]);
         }
     }
 

@@ -92,6 +92,16 @@ __global__ __launch_bounds__(kBlock) void k_levels(const LevelArgs a)
     if (threadIdx.x < kMaxLevels) a.hist[blockIdx.x * kMaxLevels + threadIdx.x] = sh[threadIdx.x];
 }
 
+// smallest of n positive doubles: wavefront minimum, one atomic per wave
+// (for positive doubles the bit patterns order like the values)
+__global__ __launch_bounds__(kBlock) void k_min_positive(int n, const double *x, unsigned long long *min_bits)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    double m = i < n ? x[i] : 1.0e308;
+    for (int off = 32; off > 0; off >>= 1) m = fmin(m, __shfl_down(m, off, 64));
+    if ((threadIdx.x & 63) == 0) atomicMin(min_bits, (unsigned long long)__double_as_longlong(m));
+}
+
 // exclusive offsets of every (block, level) in the finest-first order
 __global__ __launch_bounds__(kBlock) void k_level_scan(int *hist, int nb, int n_levels, int *cnt_ge)
 {
@@ -1935,6 +1945,30 @@ static mdlts_status assign_levels_impl(mdlts_sim *s, double dt_barrier, int forc
     MD_TRY(levels_enqueue(s, dt_barrier, force_level));
     MD_TRY(sync(s->ctx));
     return levels_finish(s, dt_barrier, level_hist);
+}
+
+mdlts_status mdlts_assign_levels_auto(mdlts_sim *s, double *dt_barrier, int32_t *level_hist)
+{
+    if (!s || !dt_barrier) return MDLTS_EINVAL;
+    mdlts_ctx *c = s->ctx;
+    const int E = (int)s->E;
+    // CFL of every leaf (the level pass with every leaf forced to level 0),
+    // then its minimum
+    MD_TRY(levels_enqueue(s, 1.0, 0));
+    unsigned long long *mb = reinterpret_cast<unsigned long long *>(static_cast<char *>(s->flags.p) + 16);
+    const unsigned long long init = 0x7fefffffffffffffull;  // largest finite double
+    HIP_TRY(hipMemcpyAsync(mb, &init, 8, hipMemcpyHostToDevice, c->stream));
+    k_min_positive<<<nblocks(E), kBlock, 0, c->stream>>>(E, P<double>(s->cfl_c), mb);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(&s->pin->eta_max_bits, mb, 8, hipMemcpyDeviceToHost, c->stream));
+    MD_TRY(sync(c));
+    double cfl_min;
+    std::memcpy(&cfl_min, &s->pin->eta_max_bits, 8);
+    if (!(cfl_min > 0.0) || !std::isfinite(cfl_min)) return MDLTS_EUNSTABLE;
+    // every leaf within the configured levels, off the power-of-two ties
+    const double dt = std::ldexp(cfl_min, s->desc.n_levels - 1) * (1.0 - std::ldexp(1.0, -20));
+    *dt_barrier = dt;
+    return assign_levels_impl(s, dt, -1, level_hist);
 }
 
 mdlts_status mdlts_rvt_snapshot(mdlts_sim *s)

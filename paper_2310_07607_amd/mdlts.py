@@ -100,6 +100,7 @@ def lib():
         "mdlts_plan_levels": (I, [P, P, S, P, D, D, P, P, P, P, S]),
         "mdlts_memory_bound": (I, [P, ctypes.c_int64, P]),
         "mdlts_rvt_snapshot": (I, [P]),
+        "mdlts_assign_levels_auto": (I, [P, P, P]),
         "mdlts_rvt_indicator": (I, [P, P, S, P]),
         "mdlts_assign_levels_cell": (I, [P, D, D, D, P]),
     }
@@ -343,6 +344,14 @@ class Simulation:
         hist = np.zeros(self.n_levels, dtype=np.int32)
         _chk(lib().mdlts_assign_uniform(self.h, float(dt_barrier), int(level), _p(hist)), "mdlts_assign_uniform")
         return hist
+
+    def assign_levels_auto(self):
+        """(dt_barrier, level histogram): the largest barrier step that keeps
+        every current leaf within the configured levels."""
+        dt = ctypes.c_double()
+        hist = np.zeros(self.n_levels, dtype=np.int32)
+        _chk(lib().mdlts_assign_levels_auto(self.h, ctypes.byref(dt), _p(hist)), "mdlts_assign_levels_auto")
+        return dt.value, hist
 
     def rvt_snapshot(self):
         """Start of the interval the RV-T temporal indicator covers."""

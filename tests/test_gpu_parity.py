@@ -255,3 +255,24 @@ def test_repeated_adaptation_and_stepping(ctx, name):
     with pytest.raises(mdlts.MdltsError) as ei:
         g.adapt(0.5, 0.15)
     assert ei.value.status == mdlts.ESTATE
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_automatic_barrier_step(ctx, name):
+    """dt_barrier = 2^(L-1) min CFL (1 - 2^-20) from the current leaves, and the
+    levels it gives, against the oracle's CFL and levels; then one barrier."""
+    L = 8
+    o, g, u, v = _setup(ctx, name, "f64", L, seed=9)
+    dt, hist = g.assign_levels_auto()
+    dt_o = np.ldexp(o.cfl().min(), L - 1) * (1 - 2.0 ** -20)
+    assert dt == pytest.approx(dt_o, rel=1e-12)
+    lv_o, rc = o.levels(dt, L)
+    assert rc == 0
+    level, _, _ = g.get_levels()
+    assert np.array_equal(level, lv_o)
+    assert hist[-1] > 0 or level.max() < L - 1
+    g.set_time(0.0)
+    g.step(1)
+    o.lts_barrier(dt, 0.0, lv_o)
+    assert rel_l2(g.get_state()[0], o.get_state()[0]) <= 1e-12
+    g.close()
