@@ -55,9 +55,9 @@ FETCH_SCALE = 2.0   # copy of 256 MiB: FETCH_SIZE reads 128.0 MiB
 WRITE_SCALE = 1.0   # copy of 256 MiB: WRITE_SIZE reads 256.0 MiB
 MEASURED_TRAFFIC = {
     # amr_2d workload, all dispatches of the kernel in a 100 + 20 + 5 interval run
-    "k_substep_batch<2,1,float>": {"digest": "4514c560528d4739", "hbm_over_algorithmic": 1.280},
+    "k_substep_batch<2,1,float>": {"digest": "b4049e7dec2e2504", "hbm_over_algorithmic": 1.290},
     # batched workload, the four FP32 variants weighted by algorithmic bytes
-    "k_substep_batch": {"digest": "4514c560528d4739", "hbm_over_algorithmic": 1.069},
+    "k_substep_batch": {"digest": "b4049e7dec2e2504", "hbm_over_algorithmic": 1.073},
 }
 
 
@@ -217,7 +217,8 @@ def auto_levels_leg(ctx, W, seed, u, v, bits, t0, barriers=20):
     out = {"n_levels": L, "dt_barrier_ms": dt, "level_hist": hist.tolist(),
            "value": (c1 - c0) / wall, "unit": "DoF-updates/s", "sim_ms_per_s": (s1 - s0) / wall,
            "dof_updates_per_sim_ms": (c1 - c0) / (s1 - s0),
-           "rel_l2_fp32_vs_fp64_finest_substep": err, "window_ms": dt}
+           "rel_l2_fp32_vs_fp64_finest_substep": err, "window_ms": dt,
+           "dof_updates_f32": sim.counters()[0] + lts.counters()[0], "dof_updates_f64": ref.counters()[0]}
     for g in (sim, lts, ref):
         g.close()
     return out
@@ -467,8 +468,8 @@ def main():
     achieved = BYTES_PER_DOF_Q1_2D_F32 * k_dof / (k_ms * 1e-3) / 1e9 if k_ms > 0 else 0.0
     alg_per_launch = BYTES_PER_DOF_Q1_2D_F32 * k_dof / max(k_launch, 1)
     totals = {"unit": "DoF-updates since creation",
-              "k_substep_batch<2,1,float>": sim.counters()[0] + lts.counters()[0],
-              "k_substep_batch<2,1,double>": plain.counters()[0] + ref.counters()[0]}
+              "k_substep_batch<2,1,float>": sim.counters()[0] + lts.counters()[0] + auto["dof_updates_f32"],
+              "k_substep_batch<2,1,double>": plain.counters()[0] + ref.counters()[0] + auto["dof_updates_f64"]}
     out = {
         "metric": METRIC,
         "value": value,
