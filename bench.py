@@ -55,7 +55,7 @@ FETCH_SCALE = 2.0   # copy of 256 MiB: FETCH_SIZE reads 128.0 MiB
 WRITE_SCALE = 1.0   # copy of 256 MiB: WRITE_SIZE reads 256.0 MiB
 MEASURED_TRAFFIC = {
     # amr_2d workload, all dispatches of the kernel in a 100 + 20 + 5 interval run
-    "k_substep_batch<2,1,float>": {"digest": "b4049e7dec2e2504", "hbm_over_algorithmic": 1.290},
+    "k_substep_batch<2,1,float,false>": {"digest": "b4049e7dec2e2504", "hbm_over_algorithmic": 1.290},
     # batched workload, the four FP32 variants weighted by algorithmic bytes
     "k_substep_batch": {"digest": "b4049e7dec2e2504", "hbm_over_algorithmic": 1.073},
 }
@@ -224,6 +224,50 @@ def auto_levels_leg(ctx, W, seed, u, v, bits, t0, barriers=20):
     return out
 
 
+def full_tensor_leg(ctx, W, seed, u, v, bits, t0, barriers=50):
+    """The same mesh and state under a full diffusion tensor (fibres at 30
+    degrees, eigenvalues 1.6e-3 and 0.4e-3 cm^2/ms: the trace of the
+    isotropic tensor, anisotropy 4): the barrier step from the leaves with the
+    configured levels, graph-timed substep launches, and the FP32 error over
+    one barrier against FP64 on the same levels."""
+    import numpy as np
+    th = np.pi / 6
+    R = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+    D = R @ np.diag([1.6e-3, 0.4e-3]) @ R.T
+    sims = {}
+    for prec in ("f32", "f64"):
+        g = setup(ctx, W, seed, prec)
+        g.set_conductivity(D, W["gamma"])
+        g.set_tree(bits)
+        g.set_state(u, v)
+        sims[prec] = g
+    g = sims["f32"]
+    dt, hist = g.assign_levels_auto()
+    g.set_time(t0)
+    ms, nd = timed_barriers(ctx, lambda n: g.step(n), barriers, lambda: g.counters()[0])
+    n_launch = launches_per_barrier(g) * barriers
+    # accuracy over one barrier from the same state, same levels
+    a, b = sims["f32"], sims["f64"]
+    a.set_state(u, v)
+    a.assign_levels(dt)
+    a.set_time(t0)
+    b.assign_levels(dt)
+    b.set_time(t0)
+    a.step(1)
+    b.step(1)
+    err = float(np.linalg.norm(a.get_state()[0] - b.get_state()[0]) / np.linalg.norm(b.get_state()[0]))
+    achieved = BYTES_PER_DOF_Q1_2D_F32 * nd / (ms * 1e-3) / 1e9
+    out = {"D": [[float(x) for x in r] for r in D], "dt_barrier_ms": dt, "level_hist": hist.tolist(),
+           "kernel_only": {"value": nd / (ms * 1e-3), "unit": "DoF-updates/s", "avg_launch_us": ms * 1e3 / n_launch,
+                           "achieved_GBps": achieved, "frac": achieved / HBM_PEAK_GBS},
+           "kernel": "k_substep_batch<2,1,float,true>",
+           "rel_l2_fp32_vs_fp64_one_barrier": err,
+           "dof_updates_f32": a.counters()[0], "dof_updates_f64": b.counters()[0]}
+    for q in sims.values():
+        q.close()
+    return out
+
+
 def interval(sim, W, dt):
     """Indicator, adaptation, levels (one call, two host synchronisations),
     then amr_every barriers."""
@@ -296,7 +340,7 @@ def batched_leg(ctx, args):
     n_dof = sum(s.n_dof for s in sims)
     totals = {}
     for s, w in zip(sims, specs):
-        key = f"k_substep_batch<{w['dim']},{w['p']},float>"
+        key = f"k_substep_batch<{w['dim']},{w['p']},float,false>"
         totals[key] = totals.get(key, 0) + s.counters()[0]
     out = {"sims": len(sims), "dof": n_dof, "state_bytes_fp32": 12 * n_dof,
            "warmup_intervals": warm, "t_sim_ms_after_warmup": [min(t_warm), max(t_warm)],
@@ -308,7 +352,7 @@ def batched_leg(ctx, args):
                         "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                         "traffic_unit": "HBM bytes per launch",
                         "algorithmic_bytes_per_launch": kbytes / max(nl, 1),
-                        "kernel": "k_substep_batch<dim,p,float>", "kernel_ms": ms, "launches": nl,
+                        "kernel": "k_substep_batch<dim,p,float,false>", "kernel_ms": ms, "launches": nl,
                         "avg_launch_us": ms * 1e3 / max(nl, 1),
                         "bytes_per_dof_update": {"q1_2d": bytes_per_dof(2, 1), "q2_2d": bytes_per_dof(2, 2),
                                                  "q1_3d": bytes_per_dof(3, 1), "q2_3d": bytes_per_dof(3, 2)}},
@@ -429,6 +473,7 @@ def main():
     bits = sim.get_tree()
     rvt = rvt_leg(ctx, sim, dt)
     auto = auto_levels_leg(ctx, W, args.seed, u, v, bits, t_sim1)
+    full = full_tensor_leg(ctx, W, args.seed, u, v, bits, t_sim1)
     plain = setup(ctx, W, args.seed, "f64", n_levels=1)
     plain.set_tree(bits)
     plain.set_state(u, v)
@@ -468,8 +513,10 @@ def main():
     achieved = BYTES_PER_DOF_Q1_2D_F32 * k_dof / (k_ms * 1e-3) / 1e9 if k_ms > 0 else 0.0
     alg_per_launch = BYTES_PER_DOF_Q1_2D_F32 * k_dof / max(k_launch, 1)
     totals = {"unit": "DoF-updates since creation",
-              "k_substep_batch<2,1,float>": sim.counters()[0] + lts.counters()[0] + auto["dof_updates_f32"],
-              "k_substep_batch<2,1,double>": plain.counters()[0] + ref.counters()[0] + auto["dof_updates_f64"]}
+              "k_substep_batch<2,1,float,false>": sim.counters()[0] + lts.counters()[0] + auto["dof_updates_f32"],
+              "k_substep_batch<2,1,double,false>": plain.counters()[0] + ref.counters()[0] + auto["dof_updates_f64"],
+              "k_substep_batch<2,1,float,true>": full["dof_updates_f32"],
+              "k_substep_batch<2,1,double,true>": full["dof_updates_f64"]}
     out = {
         "metric": METRIC,
         "value": value,
@@ -499,13 +546,14 @@ def main():
                        "rel_l2_fp32_lts_vs_fp64_plain": err, "window_ms": nb * dt},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic_per_launch("k_substep_batch<2,1,float>", alg_per_launch),
+                     "traffic": traffic_per_launch("k_substep_batch<2,1,float,false>", alg_per_launch),
                      "traffic_unit": "HBM bytes per launch", "algorithmic_bytes_per_launch": alg_per_launch,
-                     "kernel": "k_substep_batch<2,1,float>", "bytes_per_dof_update": BYTES_PER_DOF_Q1_2D_F32,
+                     "kernel": "k_substep_batch<2,1,float,false>", "bytes_per_dof_update": BYTES_PER_DOF_Q1_2D_F32,
                      "avg_launch_us": k_ms * 1e3 / max(k_launch, 1)},
         "dispatch_totals": totals,
         "rvt_indicator": rvt,
         "auto_levels": auto,
+        "full_tensor": full,
     }
     for s in (sim, plain, lts, ref):
         s.close()

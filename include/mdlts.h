@@ -106,10 +106,13 @@ mdlts_status mdlts_set_tree(mdlts_sim *sim, const uint8_t *refine_bits, size_t n
 mdlts_status mdlts_get_tree(mdlts_sim *sim, uint8_t *bits, size_t cap, size_t *n_bits);
 mdlts_status mdlts_n_leaves(mdlts_sim *sim, size_t *n_leaves);
 /* Diffusion tensor D (Sec. 2: D = kappa/(chi C_m)) as Dxx,Dyy,Dzz,Dxy,Dxz,Dyz
- * [cm^2/ms] and the SIPG penalty gamma (Sec. 2.1).  This library supports a
- * diagonal D (axis-aligned fibres); EINVAL for off-diagonal entries, a
- * non-positive diagonal, or a gamma for which the element blocks lose their
- * negative diagonal. */
+ * [cm^2/ms] and the SIPG penalty gamma (Sec. 2.1; sigma_F uses n.D n).  D
+ * must be symmetric positive definite; off-diagonal entries (fibres not
+ * along the axes) select kernels with the mixed-derivative volume terms and
+ * the tangential parts of the face fluxes, and a CFL bound from the full own
+ * element block.  In 2-D, Dzz is ignored and Dxz, Dyz must be 0.  EINVAL for
+ * a tensor that is not accepted, or a gamma for which some element block
+ * loses its negative diagonal. */
 mdlts_status mdlts_set_conductivity(mdlts_sim *sim, const double D_sym[6], double gamma);
 mdlts_status mdlts_set_ionic(mdlts_sim *sim, const mdlts_ap_params *p);
 /* At most 8 boxes. */
@@ -253,8 +256,8 @@ mdlts_status mdlts_profile_read(mdlts_sim *sim, double *substep_ms, uint64_t *n_
 
 /* ---- host-only planning utilities (no device work) ---------------------- */
 /* Lower bound on CFL_e over the leaves of the given depth (worst face kinds
- * per direction that a 2:1-balanced forest allows; attained on uniform
- * meshes).  A barrier step of 2^(L-1) * bound(max_depth) keeps every leaf
+ * per direction that a 2:1-balanced forest allows, jointly over all faces
+ * for a full tensor; attained on uniform meshes).  A barrier step of 2^(L-1) * bound(max_depth) keeps every leaf
  * within L levels. */
 mdlts_status mdlts_cfl_bound(const mdlts_mesh_desc *desc, const double D_sym[6], double gamma, int depth,
                              double *cfl_min);

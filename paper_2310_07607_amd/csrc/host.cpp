@@ -130,6 +130,150 @@ bool gershgorin_table(const RefTables &T, double gamma, double out[4][4])
     return true;
 }
 
+bool parse_conductivity(const double D_sym[6], int dim, Conductivity &C)
+{
+    if (!D_sym) return false;
+    for (int q = 0; q < 6; q++)
+        if (!std::isfinite(D_sym[q])) return false;
+    C = Conductivity{};
+    for (int k = 0; k < 3; k++) C.Dk[k] = D_sym[k];
+    for (int q = 0; q < 3; q++) C.Dx[q] = D_sym[3 + q];
+    if (dim == 2 && (C.Dx[1] != 0.0 || C.Dx[2] != 0.0)) return false;
+    // positive definite: positive leading principal minors of the dim x dim tensor
+    const double a = C.Dk[0], b = C.Dk[1], c = C.Dk[2], xy = C.Dx[0], xz = C.Dx[1], yz = C.Dx[2];
+    for (int k = 0; k < dim; k++)
+        if (!(C.Dk[k] > 0.0)) return false;
+    if (!(a * b - xy * xy > 0.0)) return false;
+    if (dim == 3 && !(a * (b * c - yz * yz) - xy * (xy * c - yz * xz) + xz * (xy * yz - b * xz) > 0.0)) return false;
+    C.full = xy != 0.0 || xz != 0.0 || yz != 0.0;
+    return true;
+}
+
+bool own_block_table(const RefTables &T, int dim, const double h0[3], const Conductivity &C, double gamma,
+                     std::vector<double> &out)
+{
+    const int m = T.m;
+    const int np = dim == 2 ? m * m : m * m * m;
+    const int nfaces = 2 * dim;
+    const double D[3][3] = {{C.Dk[0], C.Dx[0], C.Dx[1]}, {C.Dx[0], C.Dk[1], C.Dx[2]}, {C.Dx[1], C.Dx[2], C.Dk[2]}};
+    auto digit = [&](int i, int k) {
+        for (int q = 0; q < k; q++) i /= m;
+        return i % m;
+    };
+    std::vector<double> Mi(np);
+    for (int i = 0; i < np; i++) {
+        double v = 1.0;
+        for (int k = 0; k < dim; k++) v *= T.w[digit(i, k)] * 0.5 * h0[k];
+        Mi[i] = v;
+    }
+    // value and physical gradient of basis function j at a point given by
+    // the 1-D basis values val1[k][b] and derivatives der1[k][b] there
+    // (tensor products of the 1-D factors)
+    auto grad_at = [&](int j, const double *val1, const double *der1, double *g, double &val) {
+        val = 1.0;
+        for (int k = 0; k < dim; k++) val *= val1[k * kMaxM + digit(j, k)];
+        for (int l = 0; l < dim; l++) {
+            double v = 2.0 / h0[l] * der1[l * kMaxM + digit(j, l)];
+            for (int k = 0; k < dim; k++)
+                if (k != l) v *= val1[k * kMaxM + digit(j, k)];
+            g[l] = v;
+        }
+    };
+    // volume: -int D grad(l_j) . grad(l_i), GL rule at the nodes
+    std::vector<double> V((size_t)np * np, 0.0);
+    std::vector<double> gq((size_t)np * 3), vq(np);
+    for (int q = 0; q < np; q++) {
+        int qi[3] = {0, 0, 0};
+        double val1[3 * kMaxM] = {}, der1[3 * kMaxM] = {};
+        double Wq = 1.0;
+        for (int k = 0; k < dim; k++) {
+            qi[k] = digit(q, k);
+            Wq *= T.w[qi[k]] * 0.5 * h0[k];
+            for (int b = 0; b < m; b++) {
+                val1[k * kMaxM + b] = b == qi[k] ? 1.0 : 0.0;
+                der1[k * kMaxM + b] = T.D1[qi[k]][b];
+            }
+        }
+        for (int j = 0; j < np; j++) grad_at(j, val1, der1, &gq[(size_t)j * 3], vq[j]);
+        for (int i = 0; i < np; i++)
+            for (int j = 0; j < np; j++) {
+                double a = 0.0;
+                for (int x = 0; x < dim; x++)
+                    for (int y = 0; y < dim; y++) a += gq[(size_t)i * 3 + x] * D[x][y] * gq[(size_t)j * 3 + y];
+                V[(size_t)i * np + j] -= Wq * a / Mi[i];
+            }
+    }
+    // own-side terms of face f with the neighbour frozen at zero:
+    // consistency and symmetry (Cf) and the penalty without sigma (Pf)
+    std::vector<double> Cf((size_t)nfaces * np * np, 0.0), Pf((size_t)nfaces * np * np, 0.0);
+    const int nf = np / m;
+    for (int f = 0; f < nfaces; f++) {
+        const int k = f / 2, s = f % 2;
+        const double ns = s ? 1.0 : -1.0;
+        for (int g = 0; g < nf; g++) {
+            int qi[3] = {0, 0, 0};
+            double val1[3 * kMaxM] = {}, der1[3 * kMaxM] = {};
+            double Wg = 1.0;
+            int gg = g;
+            for (int t = 0; t < dim; t++) {
+                if (t == k) {
+                    for (int b = 0; b < m; b++) {
+                        val1[t * kMaxM + b] = T.B[s][b];
+                        der1[t * kMaxM + b] = T.G[s][b];
+                    }
+                    continue;
+                }
+                qi[t] = gg % m;
+                gg /= m;
+                Wg *= T.w[qi[t]] * 0.5 * h0[t];
+                for (int b = 0; b < m; b++) {
+                    val1[t * kMaxM + b] = b == qi[t] ? 1.0 : 0.0;
+                    der1[t * kMaxM + b] = T.D1[qi[t]][b];
+                }
+            }
+            for (int j = 0; j < np; j++) grad_at(j, val1, der1, &gq[(size_t)j * 3], vq[j]);
+            for (int i = 0; i < np; i++) {
+                double dni = 0.0;
+                for (int y = 0; y < dim; y++) dni += D[k][y] * gq[(size_t)i * 3 + y];
+                dni *= ns;
+                for (int j = 0; j < np; j++) {
+                    double dnj = 0.0;
+                    for (int y = 0; y < dim; y++) dnj += D[k][y] * gq[(size_t)j * 3 + y];
+                    dnj *= ns;
+                    const size_t o = ((size_t)f * np + i) * np + j;
+                    Cf[o] += Wg * (0.5 * dnj * vq[i] + 0.5 * vq[j] * dni) / Mi[i];
+                    Pf[o] += Wg * vq[j] * vq[i] / Mi[i];
+                }
+            }
+        }
+    }
+    // penalty sigma = gamma 1/2 (D_kk/h + D_kk/h_nbr) per kind
+    const double factor[4] = {0.0, 1.0, 0.75, 1.5};
+    const int n_combo = 1 << (2 * nfaces);
+    out.assign((size_t)n_combo, 0.0);
+    std::vector<double> L((size_t)np * np);
+    for (int combo = 0; combo < n_combo; combo++) {
+        L = V;
+        for (int f = 0; f < nfaces; f++) {
+            const int kind = (combo >> (2 * f)) & 3;
+            if (kind == kBoundary) continue;
+            const int k = f / 2;
+            const double sigma = gamma * D[k][k] / h0[k] * factor[kind];
+            const double *cf = &Cf[(size_t)f * np * np], *pf = &Pf[(size_t)f * np * np];
+            for (size_t o = 0; o < (size_t)np * np; o++) L[o] += cf[o] - sigma * pf[o];
+        }
+        double worst = 0.0;
+        for (int i = 0; i < np; i++) {
+            if (!(L[(size_t)i * np + i] < 0.0)) return false;
+            double r = 0.0;
+            for (int j = 0; j < np; j++) r += std::fabs(L[(size_t)i * np + j]);
+            if (r > worst) worst = r;
+        }
+        out[(size_t)combo] = worst;
+    }
+    return true;
+}
+
 // ---------------------------------------------------------------------------
 // linear forest
 // ---------------------------------------------------------------------------
@@ -447,6 +591,16 @@ void host_cfl(const Forest &F, const double h0[3], const double Dk[3], const dou
             s += Dk[k] / (h * h) * G[lo][hi];
         }
         cfl[e] = 1.0 / s;
+    }
+}
+
+void host_cfl_full(const Forest &F, const std::vector<double> &table, double *cfl)
+{
+    const size_t E = F.size();
+    for (size_t e = 0; e < E; e++) {
+        uint32_t idx = 0;
+        for (int f = 0; f < 2 * F.dim; f++) idx |= (F.face[(size_t)f * E + e] >> 30) << (2 * f);
+        cfl[e] = 1.0 / (table[idx] * std::ldexp(1.0, 2 * (int)F.leaves[e].depth));
     }
 }
 

@@ -35,6 +35,26 @@ bool make_ref_tables(int p, RefTables &T);
 // Returns false if some diagonal entry is not negative (gamma too small).
 bool gershgorin_table(const RefTables &T, double gamma, double out[4][4]);
 
+// A diffusion tensor D (Sec. 2: D = kappa / (chi C_m)) as the library keeps
+// it: diagonal and off-diagonal entries.  Accepted are symmetric positive
+// definite tensors; in 2-D the z row and column must be zero.
+struct Conductivity {
+    double Dk[3] = {0, 0, 0};  // Dxx, Dyy, Dzz
+    double Dx[3] = {0, 0, 0};  // Dxy, Dxz, Dyz
+    bool full = false;         // some off-diagonal entry is nonzero
+};
+// D_sym = Dxx, Dyy, Dzz, Dxy, Dxz, Dyz; false if not accepted
+bool parse_conductivity(const double D_sym[6], int dim, Conductivity &C);
+
+// Gershgorin row-sum bound max_i sum_j |(M_e^-1 K_ee)_ij| of the own block of
+// a root element (box h0) under a full tensor, for every combination of the
+// kinds of its 2 dim faces: out[sum_f kind_f 4^f], face f = 2k + s.  The
+// block of a leaf at depth d is 4^d times the root's.  Assembled from the
+// tensor-product basis at the GL nodes; returns false if some block has a
+// diagonal entry that is not negative (gamma too small).
+bool own_block_table(const RefTables &T, int dim, const double h0[3], const Conductivity &C, double gamma,
+                     std::vector<double> &out);
+
 struct Leaf {
     uint8_t depth;
     uint32_t c[3];  // cell index in the level-`depth` grid of the whole box
@@ -82,6 +102,8 @@ bool plan_adapt(const Forest &cur, const double *eta, double tau_refine, double 
 // Per-leaf CFL with the separable Gershgorin bound (host reference of the
 // device level kernel) and the resulting level.
 void host_cfl(const Forest &F, const double h0[3], const double Dk[3], const double G[4][4], double *cfl);
+// The same from the full-tensor table of own_block_table.
+void host_cfl_full(const Forest &F, const std::vector<double> &table, double *cfl);
 int level_of(double dt_barrier, double cfl);
 
 }  // namespace mdlts

@@ -35,6 +35,7 @@ struct RefConst {
     double xi[kMaxM], w[kMaxM], winv[kMaxM], lam[kMaxM];
     double D1[kMaxM][kMaxM];       // D1[a][b] = l_b'(xi_a)
     double A[kMaxM][kMaxM];        // (1/w_a) sum_q w_q D1[q][a] D1[q][b]
+    double W1[kMaxM][kMaxM];       // w_q D1[q][a] / w_a: weak derivative, A = W1 D1
     double B[2][kMaxM];            // l_b(-1), l_b(+1)
     double G[2][kMaxM];            // l_b'(-1), l_b'(+1)
     double Isub[2][kMaxM][kMaxM];  // l_b((xi_g + 2 pos - 1) / 2)
@@ -109,6 +110,7 @@ constexpr RefConst ref_const(int p)
             double s = 0.0;
             for (int q = 0; q < m; q++) s += T.w[q] * T.D1[q][a] * T.D1[q][b];
             T.A[a][b] = s / T.w[a];
+            T.W1[a][b] = T.w[b] * T.D1[b][a] / T.w[a];
         }
     for (int s = 0; s < 2; s++)
         for (int b = 0; b < m; b++) {
@@ -147,6 +149,8 @@ struct StepArgs {
     double h0[3];
     T inv_h0[3];  // 1/h of a root; 1/h at depth d is inv_h0 * 2^d (exact)
     T Dk[3];
+    T Dx[3];   // off-diagonal Dxy, Dxz, Dyz
+    int full;  // some off-diagonal entry is nonzero
     T gamma;
     T apk, apa, eps0, mu1, mu2;
     int n_stim;  // all boxes; the kernel checks their time windows
@@ -299,6 +303,43 @@ __device__ __forceinline__ void tang_apply(const double (&I)[2][kMaxM][kMaxM], i
     }
 }
 
+// out = Op applied along direction k of an element array (lines of M nodes)
+template <typename T, int DIM, int M>
+__device__ __forceinline__ void line_apply(const double (&Op)[kMaxM][kMaxM], int k, const T *in, T *out)
+{
+    constexpr int NF = DIM == 2 ? M : M * M;
+#pragma unroll
+    for (int g = 0; g < NF; g++)
+#pragma unroll
+        for (int aa = 0; aa < M; aa++) {
+            T s = 0;
+#pragma unroll
+            for (int b = 0; b < M; b++) s += (T)Op[aa][b] * in[fnode<DIM, M>(k, g, b)];
+            out[fnode<DIM, M>(k, g, aa)] = s;
+        }
+}
+
+// out = Op applied along tangential axis tau (0: g0, 1: g1) of a face array
+// of points g0 + M g1
+template <typename T, int DIM, int M>
+__device__ __forceinline__ void face_line(const double (&Op)[kMaxM][kMaxM], int tau, const T *in, T *out)
+{
+    constexpr int NF = DIM == 2 ? M : M * M;
+#pragma unroll
+    for (int g = 0; g < NF; g++) {
+        const int g0 = g % M, g1 = g / M;
+        T s = 0;
+#pragma unroll
+        for (int c = 0; c < M; c++) s += (T)Op[tau ? g1 : g0][c] * in[tau ? g0 + M * c : c + M * g1];
+        out[g] = s;
+    }
+}
+
+// the direction of tangential axis tau of a face normal to k, and the slot
+// of D_kt among the off-diagonal entries (xy, xz, yz)
+__device__ __forceinline__ constexpr int tang_dir(int k, int tau) { return tau + (tau >= k ? 1 : 0); }
+__device__ __forceinline__ constexpr int off_slot(int k, int t) { return k + t - 1; }
+
 // Trace (value and reference normal derivative) of a neighbour on its face
 // `side` normal to k, at the neighbour's interpolated time for substep i:
 // a neighbour updated at this substep is read from its current slot; one
@@ -424,7 +465,9 @@ constexpr bool kGateInLds = Shape<DIM, P>::NP > 16 && sizeof(T) == 4;
 template <int DIM, int P, typename T>
 constexpr int kGateLdsWords = kGateInLds<DIM, P, T> ? 4 * Shape<DIM, P>::NP * 64 : 1;  // 4 waves per block
 
-template <int DIM, int P, typename T>
+// FULL: the diffusion tensor has off-diagonal entries (separate kernels, so
+// that the diagonal case keeps its register budget)
+template <int DIM, int P, typename T, bool FULL>
 __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const StepLaunch<T> &L, const int j,
                                                 const int lv, float *gate_lds)
 {
@@ -500,6 +543,25 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
 #pragma unroll
                 for (int b = 0; b < M; b++) s += (T)R.A[aa][b] * u[fnode<DIM, M>(k, g, b)];
                 r[fnode<DIM, M>(k, g, aa)] -= ck * s;
+            }
+    }
+
+    // off-diagonal D: -(4 D_kl / (h_k h_l)) (W1_k D1_l + W1_l D1_k) u per pair k < l
+    if constexpr (FULL) {
+#pragma unroll
+        for (int k = 0; k < DIM; k++)
+#pragma unroll
+            for (int l = k + 1; l < DIM; l++) {
+                const T ckl = (T)4 * a.Dx[off_slot(k, l)] * ih[k] * ih[l];
+                T d1[NP], wd[NP];
+                line_apply<T, DIM, M>(R.D1, l, u, d1);
+                line_apply<T, DIM, M>(R.W1, k, d1, wd);
+#pragma unroll
+                for (int n = 0; n < NP; n++) r[n] -= ckl * wd[n];
+                line_apply<T, DIM, M>(R.D1, k, u, d1);
+                line_apply<T, DIM, M>(R.W1, l, d1, wd);
+#pragma unroll
+                for (int n = 0; n < NP; n++) r[n] -= ckl * wd[n];
             }
     }
 
@@ -604,11 +666,29 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
                     Fl[g] = cf_q * tq[g] + cf_n * nq[g] - cf_j * jmp;
                     Hl[g] = ch * jmp;
                 }
+                if constexpr (FULL) {
+                    // tangential parts of n.D grad u on both sides (their
+                    // mean) and of n.D grad l_i (against the jump), both
+                    // lifted with c2 ns D_kt / h_t
+                    T sm[NF], df[NF], t0[NF], t1[NF];
+#pragma unroll
+                    for (int g = 0; g < NF; g++) { sm[g] = tu[g] + nu[g]; df[g] = tu[g] - nu[g]; }
+#pragma unroll
+                    for (int tau = 0; tau < DIM - 1; tau++) {
+                        const int t = tang_dir(k, tau);
+                        const T cc = ns * c2 * a.Dx[off_slot(k, t)] * ih[t];
+                        face_line<T, DIM, M>(R.D1, tau, sm, t0);
+                        face_line<T, DIM, M>(R.W1, tau, df, t1);
+#pragma unroll
+                        for (int g = 0; g < NF; g++) Fl[g] += cc * (t0[g] + t1[g]);
+                    }
+                }
             } else {
                 const T sigma = (T)1.5 * pen;           // h_nbr = h/2
                 const T qn = ns * Dkk * (T)2 * c2;
+                T Jl[NF];  // full tensors: jumps lifted from the sub-faces
 #pragma unroll
-                for (int g = 0; g < NF; g++) { Fl[g] = 0; Hl[g] = 0; }
+                for (int g = 0; g < NF; g++) { Fl[g] = 0; Hl[g] = 0; Jl[g] = 0; }
                 auto sub_face = [&](int sub) {
                     const int p0 = sub & 1, p1 = sub >> 1;
                     T ou[NF], oq[NF], nu[NF], nq[NF], F[NF], H[NF], lf[NF], lh[NF];
@@ -624,6 +704,26 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
                         F[g] = (T)0.5 * (qs * oq[g] + qn * nq[g]) - sigma * jmp;
                         H[g] = (T)0.5 * jmp;
                     }
+                    if constexpr (FULL) {
+                        // tangential derivatives on the sub-face (h_t / 2):
+                        // the mean of both sides into F; the jump is lifted
+                        // to the face and differentiated there (below)
+                        T sm[NF], t0[NF];
+#pragma unroll
+                        for (int g = 0; g < NF; g++) sm[g] = ou[g] + nu[g];
+#pragma unroll
+                        for (int tau = 0; tau < DIM - 1; tau++) {
+                            const int t = tang_dir(k, tau);
+                            const T cf = (T)2 * ns * a.Dx[off_slot(k, t)] * ih[t];
+                            face_line<T, DIM, M>(R.D1, tau, sm, t0);
+#pragma unroll
+                            for (int g = 0; g < NF; g++) F[g] += cf * t0[g];
+                        }
+                        T lj[NF];
+                        tang_apply<T, DIM, M>(R.Lsub, p0, p1, H, lj);
+#pragma unroll
+                        for (int g = 0; g < NF; g++) Jl[g] += lj[g];
+                    }
                     tang_apply<T, DIM, M>(R.Lsub, p0, p1, F, lf);
                     tang_apply<T, DIM, M>(R.Lsub, p0, p1, H, lh);
 #pragma unroll
@@ -635,6 +735,18 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
                 } else {
 #pragma unroll 1
                     for (int sub = 0; sub < NS; sub++) sub_face(sub);
+                }
+                if constexpr (FULL) {
+                    // n.D grad l_i along the face against the lifted jumps
+                    T t1[NF];
+#pragma unroll
+                    for (int tau = 0; tau < DIM - 1; tau++) {
+                        const int t = tang_dir(k, tau);
+                        const T cj = (T)2 * ns * a.Dx[off_slot(k, t)] * ih[t];
+                        face_line<T, DIM, M>(R.W1, tau, Jl, t1);
+#pragma unroll
+                        for (int g = 0; g < NF; g++) Fl[g] += cj * t1[g];
+                    }
                 }
                 const T chq = c2 * qs;
 #pragma unroll
@@ -726,7 +838,7 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
 }
 
 // one simulation: element j of the active prefix [0, n_act)
-template <int DIM, int P, typename T>
+template <int DIM, int P, typename T, bool FULL>
 __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> *__restrict__ cst, const StepLaunch<T> L)
 {
     const int j = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
@@ -736,7 +848,7 @@ __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> *__restrict__
 #pragma unroll
     for (int l = 1; l < kMaxLevels; l++) lv += (j < a.cnt_ge[l]) ? 1 : 0;
     __shared__ float gate[kGateLdsWords<DIM, P, T>];
-    substep_element<DIM, P, T>(a, L, j, lv, gate);
+    substep_element<DIM, P, T, FULL>(a, L, j, lv, gate);
 }
 
 // ---- many simulations in one launch ------------------------------------------
@@ -774,7 +886,7 @@ struct BatchClock {
 // Substep i of the barrier interval for every tile of the list.  With a
 // grid smaller than the tile count each block walks the tiles of its XCD's
 // contiguous range (persistent form).
-template <int DIM, int P, typename T>
+template <int DIM, int P, typename T, bool FULL>
 __global__ __launch_bounds__(256) void k_substep_batch(const BatchSim<T> *__restrict__ sims,
                                                        const BatchTile *__restrict__ tiles, int n_tiles, int i,
                                                        char *base, const BatchClock *__restrict__ clk,
@@ -815,7 +927,7 @@ __global__ __launch_bounds__(256) void k_substep_batch(const BatchSim<T> *__rest
         // t = t_start + n dt + i h, rounded like the host (no contraction)
         L.t_i = __dadd_rn(__dadd_rn(d.t_start, __dmul_rn((double)ck.n_bar, d.a.dt_bar)), __dmul_rn((double)i, d.h_tick));
         __shared__ float gate[kGateLdsWords<DIM, P, T>];
-        substep_element<DIM, P, T>(d.a, L, tl.start + (int)threadIdx.x, tl.packed & 15, gate);
+        substep_element<DIM, P, T, FULL>(d.a, L, tl.start + (int)threadIdx.x, tl.packed & 15, gate);
         if (advance) clk_next[tl.sim] = BatchClock{ck.n_bar + 1};
     }
 }

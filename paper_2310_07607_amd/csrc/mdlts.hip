@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -44,6 +45,7 @@ struct LevelArgs {
     double h0[3];
     double Dk[3];
     double G[4][4];
+    const double *otab;  // full tensors: root bound per face-kind combination, else null
     int force_level;  // >= 0: every leaf on this level (no CFL test)
     const double *eta_t;  // RV-T indicator per leaf, or null: no cell criterion
     double tau_cell;      // threshold of the cell criterion
@@ -67,11 +69,19 @@ __global__ __launch_bounds__(kBlock) void k_levels(const LevelArgs a)
         uint32_t c[3];
         unpack_key<DIM>(static_cast<const typename KeyOf<DIM>::type *>(a.key)[e], depth, c);
         double s = 0.0;
-        for (int k = 0; k < DIM; k++) {
-            const double h = ldexp(a.h0[k], -depth);
-            const uint32_t lo = a.face[(long long)(2 * k) * a.E + e] >> 30;
-            const uint32_t hi = a.face[(long long)(2 * k + 1) * a.E + e] >> 30;
-            s += a.Dk[k] / (h * h) * a.G[lo][hi];
+        if (a.otab) {
+            // full tensor: the own block couples the directions; its bound
+            // is the root's for these face kinds, times 4^depth (exact)
+            uint32_t idx = 0;
+            for (int f = 0; f < 2 * DIM; f++) idx |= (a.face[(long long)f * a.E + e] >> 30) << (2 * f);
+            s = a.otab[idx] * ldexp(1.0, 2 * depth);
+        } else {
+            for (int k = 0; k < DIM; k++) {
+                const double h = ldexp(a.h0[k], -depth);
+                const uint32_t lo = a.face[(long long)(2 * k) * a.E + e] >> 30;
+                const uint32_t hi = a.face[(long long)(2 * k + 1) * a.E + e] >> 30;
+                s += a.Dk[k] / (h * h) * a.G[lo][hi];
+            }
         }
         const double cfl = 1.0 / s;
         int b = 0;
@@ -260,6 +270,8 @@ struct IndArgs {
     int p;
     double h0[3];
     double Dk[3];
+    double Dx[3];  // off-diagonal Dxy, Dxz, Dyz
+    int full;      // some off-diagonal entry is nonzero
     DevRef<double> ref;
     double *eta;
     unsigned long long *eta_max_bits;
@@ -285,11 +297,33 @@ __device__ __forceinline__ void canon_trace(const IndArgs &a, uint32_t id, int k
     }
 }
 
-template <int DIM, int P, typename T>
+// Tangential part of the jump of n.D grad u at the face points: with a full
+// tensor, n.D grad u = ns sum_t D_kt d/dx_t u + the normal part.  The traces
+// are given at the points of the (sub-)face, whose reference coordinates
+// scale by `scale` / h_t (2 on a face, 4 on a half-size sub-face).
+template <int DIM, int M, bool FULL>
+__device__ __forceinline__ void tangential_jump(const IndArgs &a, const RefConst &R, int k, double ns, double scale,
+                                                const double *h, const double *tu, const double *nu, double *tj)
+{
+    constexpr int NF = DIM == 2 ? M : M * M;
+    for (int g = 0; g < NF; g++) tj[g] = 0.0;
+    if constexpr (!FULL) return;
+    double df[NF], d[NF];
+    for (int g = 0; g < NF; g++) df[g] = tu[g] - nu[g];
+    for (int tau = 0; tau < DIM - 1; tau++) {
+        const int t = tang_dir(k, tau);
+        face_line<double, DIM, M>(R.D1, tau, df, d);
+        const double c = ns * a.Dx[off_slot(k, t)] * scale / h[t];
+        for (int g = 0; g < NF; g++) tj[g] += c * d[g];
+    }
+}
+
+template <int DIM, int P, typename T, bool FULL>
 __global__ __launch_bounds__(kBlock) void k_indicator(const IndArgs a)
 {
     using S = Shape<DIM, P>;
     constexpr int M = S::M, NF = S::NF, NS = S::NS;
+    constexpr RefConst R = ref_const(P);
     const int e = blockIdx.x * kBlock + threadIdx.x;
     double eta = 0.0;
     if (e < a.E) {
@@ -328,14 +362,17 @@ __global__ __launch_bounds__(kBlock) void k_indicator(const IndArgs a)
                     canon_trace<DIM, P, T>(a, ent & kIdMask30, k, 1 - s, nu, nq);
                     const double hn = kind == kSame ? h[k] : 2.0 * h[k];
                     if (kind == kCoarser) {
-                        double iq[NF];
+                        double iq[NF], iu[NF];
                         tang_apply<double, DIM, M>(a.ref.Isub, pos0, pos1, nq, iq);
-                        for (int g = 0; g < NF; g++) nq[g] = iq[g];
+                        tang_apply<double, DIM, M>(a.ref.Isub, pos0, pos1, nu, iu);
+                        for (int g = 0; g < NF; g++) { nq[g] = iq[g]; nu[g] = iu[g]; }
                     }
                     const double qn = ns * a.Dk[k] * 2.0 / hn;
+                    double tj[NF];
+                    tangential_jump<DIM, M, FULL>(a, R, k, ns, 2.0, h, tu, nu, tj);
                     double integral = 0.0;
                     for (int g = 0; g < NF; g++) {
-                        const double jmp = qs * tq[g] - qn * nq[g];
+                        const double jmp = qs * tq[g] - qn * nq[g] + tj[g];
                         integral += om[g] * area * jmp * jmp;
                     }
                     const double hF = DIM == 2 ? area : sqrt(area);
@@ -345,12 +382,14 @@ __global__ __launch_bounds__(kBlock) void k_indicator(const IndArgs a)
                     const double hF = DIM == 2 ? sarea : sqrt(sarea);
                     const double qn = ns * a.Dk[k] * 2.0 / (0.5 * h[k]);
                     for (int sub = 0; sub < NS; sub++) {
-                        double oq[NF], nu[NF], nq[NF];
+                        double oq[NF], ou[NF], nu[NF], nq[NF], tj[NF];
                         tang_apply<double, DIM, M>(a.ref.Isub, sub & 1, sub >> 1, tq, oq);
+                        tang_apply<double, DIM, M>(a.ref.Isub, sub & 1, sub >> 1, tu, ou);
                         canon_trace<DIM, P, T>(a, a.fine[((long long)(2 * k + s) * a.E + e) * NS + sub], k, 1 - s, nu, nq);
+                        tangential_jump<DIM, M, FULL>(a, R, k, ns, 4.0, h, ou, nu, tj);
                         double integral = 0.0;
                         for (int g = 0; g < NF; g++) {
-                            const double jmp = qs * oq[g] - qn * nq[g];
+                            const double jmp = qs * oq[g] - qn * nq[g] + tj[g];
                             integral += om[g] * sarea * jmp * jmp;
                         }
                         acc += hF / (2.0 * a.p) * sarea * sarea * integral;
@@ -531,13 +570,8 @@ struct mdlts_ctx {
     BatchPlan *batch = nullptr;
     int use_graphs = 1;
     // launch shape chosen by the autotuner, per mix of kernel variants
-    // (bit 4*(dim-2) + 2*(order-1) + precision); -1 = not tuned yet
-    int tuned_block[256];
-    int tuned_per_cu[256];
-    mdlts_ctx()
-    {
-        for (int k = 0; k < 256; k++) tuned_block[k] = tuned_per_cu[k] = -1;
-    }
+    // (bit 8*full + 4*(dim-2) + 2*(order-1) + precision)
+    std::map<int, std::pair<int, int>> tuned;  // mask -> (block, blocks per CU)
 };
 
 // Host-visible staging of a simulation's small readbacks (pinned memory, so
@@ -565,8 +599,15 @@ struct mdlts_sim {
     RefTables ref{};
     double h0[3] = {1, 1, 1};
     double Dk[3] = {1e-3, 1e-3, 1e-3};
+    double Dx[3] = {0.0, 0.0, 0.0};  // off-diagonal Dxy, Dxz, Dyz
+    bool dfull = false;              // some off-diagonal entry is nonzero
     double gamma = 2.0;
     double G[4][4] = {};
+    // full tensors: own-block Gershgorin bound of a root per face-kind
+    // combination (own_block_table), and its device copy
+    std::vector<double> otab;
+    bool otab_dirty = false;
+    DevBuf otab_d;
     mdlts_ap_params ap{8.0, 0.15, 0.002, 0.2, 0.3};
     std::vector<mdlts_stim_box> stim;
     // canonical device data
@@ -687,17 +728,6 @@ void forest_from_desc(const mdlts_mesh_desc *d, Forest &F)
     F.dim = d->dim;
     F.max_depth = d->max_depth;
     for (int k = 0; k < 3; k++) F.n[k] = k < d->dim ? d->n[k] : 1;
-}
-
-bool diag_of(const double D_sym[6], int dim, double Dk[3])
-{
-    if (!D_sym) return false;
-    for (int q = 3; q < 6; q++)
-        if (D_sym[q] != 0.0) return false;
-    for (int k = 0; k < 3; k++) Dk[k] = D_sym[k];
-    for (int k = 0; k < dim; k++)
-        if (!(Dk[k] > 0.0) || !std::isfinite(Dk[k])) return false;
-    return true;
 }
 
 mdlts_status sync(mdlts_ctx *c)
@@ -892,9 +922,10 @@ mdlts_status set_forest(mdlts_sim *s, Forest &&F)
 
 // ---- substep launch -------------------------------------------------------
 template <int DIM, int P_, typename T>
-void launch_substep(const StepArgs<T> *c, const StepLaunch<T> &L, hipStream_t st)
+void launch_substep(const StepArgs<T> *c, const StepLaunch<T> &L, bool full, hipStream_t st)
 {
-    k_substep<DIM, P_, T><<<nblocks(L.n_act), kBlock, 0, st>>>(c, L);
+    if (full) k_substep<DIM, P_, T, true><<<nblocks(L.n_act), kBlock, 0, st>>>(c, L);
+    else k_substep<DIM, P_, T, false><<<nblocks(L.n_act), kBlock, 0, st>>>(c, L);
 }
 
 mdlts_status drain_events(mdlts_sim *s)
@@ -929,7 +960,9 @@ void fill_step_args(const mdlts_sim *s, StepArgs<T> &a)
         a.h0[k] = s->h0[k];
         a.inv_h0[k] = (T)(1.0 / s->h0[k]);
         a.Dk[k] = (T)s->Dk[k];
+        a.Dx[k] = (T)s->Dx[k];
     }
+    a.full = s->dfull ? 1 : 0;
     a.gamma = (T)s->gamma;
     a.apk = (T)s->ap.k;
     a.apa = (T)s->ap.a;
@@ -997,10 +1030,10 @@ mdlts_status run_barriers(mdlts_sim *s, int n_barriers)
                 HIP_TRY(hipEventRecord(s->ev[2 * s->ev_used], st));
             }
             switch (key) {
-            case 21: launch_substep<2, 1, T>(cst, L, st); break;
-            case 22: launch_substep<2, 2, T>(cst, L, st); break;
-            case 31: launch_substep<3, 1, T>(cst, L, st); break;
-            case 32: launch_substep<3, 2, T>(cst, L, st); break;
+            case 21: launch_substep<2, 1, T>(cst, L, s->dfull, st); break;
+            case 22: launch_substep<2, 2, T>(cst, L, s->dfull, st); break;
+            case 31: launch_substep<3, 1, T>(cst, L, s->dfull, st); break;
+            case 32: launch_substep<3, 2, T>(cst, L, s->dfull, st); break;
             default: return MDLTS_EINVAL;
             }
             s->dof_updates += (uint64_t)L.n_act * (uint64_t)s->np;
@@ -1018,6 +1051,13 @@ mdlts_status run_barriers(mdlts_sim *s, int n_barriers)
     return MDLTS_OK;
 }
 
+template <int DIM, int P_, typename T>
+void launch_indicator(const IndArgs &a, int E, hipStream_t st)
+{
+    if (a.full) k_indicator<DIM, P_, T, true><<<nblocks(E), kBlock, 0, st>>>(a);
+    else k_indicator<DIM, P_, T, false><<<nblocks(E), kBlock, 0, st>>>(a);
+}
+
 template <typename T>
 mdlts_status run_indicator(mdlts_sim *s, unsigned long long *max_bits, int *nonfinite)
 {
@@ -1030,17 +1070,18 @@ mdlts_status run_indicator(mdlts_sim *s, unsigned long long *max_bits, int *nonf
     a.fine = P<uint32_t>(s->fine_c);
     a.E = E;
     a.p = s->desc.order;
-    for (int k = 0; k < 3; k++) { a.h0[k] = s->h0[k]; a.Dk[k] = s->Dk[k]; }
+    for (int k = 0; k < 3; k++) { a.h0[k] = s->h0[k]; a.Dk[k] = s->Dk[k]; a.Dx[k] = s->Dx[k]; }
+    a.full = s->dfull ? 1 : 0;
     fill_ref(s->ref, a.ref);
     a.eta = P<double>(s->eta_c);
     a.eta_max_bits = max_bits;
     a.nonfinite = nonfinite;
     hipStream_t st = s->ctx->stream;
     switch (s->desc.dim * 10 + s->desc.order) {
-    case 21: k_indicator<2, 1, T><<<nblocks(E), kBlock, 0, st>>>(a); break;
-    case 22: k_indicator<2, 2, T><<<nblocks(E), kBlock, 0, st>>>(a); break;
-    case 31: k_indicator<3, 1, T><<<nblocks(E), kBlock, 0, st>>>(a); break;
-    case 32: k_indicator<3, 2, T><<<nblocks(E), kBlock, 0, st>>>(a); break;
+    case 21: launch_indicator<2, 1, T>(a, E, st); break;
+    case 22: launch_indicator<2, 2, T>(a, E, st); break;
+    case 31: launch_indicator<3, 1, T>(a, E, st); break;
+    case 32: launch_indicator<3, 2, T>(a, E, st); break;
     default: return MDLTS_EINVAL;
     }
     HIP_TRY(hipGetLastError());
@@ -1170,6 +1211,7 @@ mdlts_status compute_G(mdlts_sim *s)
 // ---------------------------------------------------------------------------
 struct BatchGroup {
     int dim = 2, order = 1, prec = 0;
+    bool full = false;  // off-diagonal diffusion tensors (their own kernels)
     std::vector<int> members;   // indices into BatchPlan::sims
     DevBuf descs, tiles, clocks;  // clocks: [2][members] BatchClock
     std::vector<BatchClock> hclk;  // host source of the clock uploads
@@ -1230,19 +1272,25 @@ void free_plan(mdlts_ctx *c, BatchPlan *&slot)
     slot = nullptr;
 }
 
-void *batch_kernel(int dim, int order, int prec)
+template <bool FULL>
+void *batch_kernel_of(int dim, int order, int prec)
 {
     switch (dim * 100 + order * 10 + prec) {
-    case 210: return reinterpret_cast<void *>(&k_substep_batch<2, 1, double>);
-    case 220: return reinterpret_cast<void *>(&k_substep_batch<2, 2, double>);
-    case 310: return reinterpret_cast<void *>(&k_substep_batch<3, 1, double>);
-    case 320: return reinterpret_cast<void *>(&k_substep_batch<3, 2, double>);
-    case 211: return reinterpret_cast<void *>(&k_substep_batch<2, 1, float>);
-    case 221: return reinterpret_cast<void *>(&k_substep_batch<2, 2, float>);
-    case 311: return reinterpret_cast<void *>(&k_substep_batch<3, 1, float>);
-    case 321: return reinterpret_cast<void *>(&k_substep_batch<3, 2, float>);
+    case 210: return reinterpret_cast<void *>(&k_substep_batch<2, 1, double, FULL>);
+    case 220: return reinterpret_cast<void *>(&k_substep_batch<2, 2, double, FULL>);
+    case 310: return reinterpret_cast<void *>(&k_substep_batch<3, 1, double, FULL>);
+    case 320: return reinterpret_cast<void *>(&k_substep_batch<3, 2, double, FULL>);
+    case 211: return reinterpret_cast<void *>(&k_substep_batch<2, 1, float, FULL>);
+    case 221: return reinterpret_cast<void *>(&k_substep_batch<2, 2, float, FULL>);
+    case 311: return reinterpret_cast<void *>(&k_substep_batch<3, 1, float, FULL>);
+    case 321: return reinterpret_cast<void *>(&k_substep_batch<3, 2, float, FULL>);
     }
     return nullptr;
+}
+
+void *batch_kernel(int dim, int order, int prec, bool full)
+{
+    return full ? batch_kernel_of<true>(dim, order, prec) : batch_kernel_of<false>(dim, order, prec);
 }
 
 // both clock copies from the host's barrier counts (the next barrier reads
@@ -1392,7 +1440,7 @@ mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, int phase, hipGraph_t grap
                 }
                 HIP_TRY(hipEventRecord(P.ev[2 * P.ev_used], c->stream));
             }
-            MD_TRY(add(batch_kernel(G.dim, G.order, G.prec), grid_of(P, n_t), P.block, args));
+            MD_TRY(add(batch_kernel(G.dim, G.order, G.prec, G.full), grid_of(P, n_t), P.block, args));
             if (prof) {
                 HIP_TRY(hipEventRecord(P.ev[2 * P.ev_used + 1], c->stream));
                 P.ev_used++;
@@ -1504,8 +1552,7 @@ mdlts_status autotune(mdlts_ctx *c, BatchPlan &P, int *remaining)
     P.block = pick.block;
     P.per_cu = pick.per_cu;
     P.tuned = true;
-    c->tuned_block[P.variant_mask] = pick.block;
-    c->tuned_per_cu[P.variant_mask] = pick.per_cu;
+    c->tuned[P.variant_mask] = {pick.block, pick.per_cu};
     return build_plan_data(c, P);
 }
 
@@ -1552,7 +1599,7 @@ mdlts_status prepare_plan(mdlts_ctx *c, BatchPlan *&slot, mdlts_sim *const *sims
         int g = -1;
         for (size_t k = 0; k < P->groups.size(); k++)
             if (P->groups[k].dim == s->desc.dim && P->groups[k].order == s->desc.order &&
-                P->groups[k].prec == s->desc.precision)
+                P->groups[k].prec == s->desc.precision && P->groups[k].full == s->dfull)
                 g = (int)k;
         if (g < 0) {
             P->groups.emplace_back();
@@ -1560,16 +1607,18 @@ mdlts_status prepare_plan(mdlts_ctx *c, BatchPlan *&slot, mdlts_sim *const *sims
             P->groups[g].dim = s->desc.dim;
             P->groups[g].order = s->desc.order;
             P->groups[g].prec = s->desc.precision;
+            P->groups[g].full = s->dfull;
         }
         P->groups[g].members.push_back(q);
     }
     for (int q = 0; q < n; q++) P->versions.push_back(sims[q]->version);
     for (const BatchGroup &g : P->groups)
-        P->variant_mask |= 1 << (4 * (g.dim - 2) + 2 * (g.order - 1) + (g.prec == MDLTS_FP32 ? 1 : 0));
+        P->variant_mask |= 1 << (8 * (g.full ? 1 : 0) + 4 * (g.dim - 2) + 2 * (g.order - 1) + (g.prec == MDLTS_FP32 ? 1 : 0));
     // a mix of variants tuned before keeps its launch shape
-    if (c->tuned_block[P->variant_mask] > 0) {
-        P->block = c->tuned_block[P->variant_mask];
-        P->per_cu = c->tuned_per_cu[P->variant_mask];
+    const auto tk = c->tuned.find(P->variant_mask);
+    if (tk != c->tuned.end()) {
+        P->block = tk->second.first;
+        P->per_cu = tk->second.second;
         P->tuned = true;
     }
     *fresh = true;
@@ -1686,7 +1735,7 @@ mdlts_status mdlts_sim_destroy(mdlts_sim *s)
                       &s->tmp_u, &s->tmp_v, &s->u_s, &s->v_s, &s->key_s, &s->nbr_s, &s->fine_s, &s->perm,
                       &s->inv, &s->hist, &s->cnt_ge_d, &s->flags, &s->xk, &s->xs, &s->xc, &s->stage,
                       &s->root_start, &s->mkey, &s->refine, &s->cflag, &s->cnt, &s->off, &s->bsums, &s->key_n,
-                      &s->step_dev, &s->snap_u, &s->snap_v, &s->eta_t_c};
+                      &s->step_dev, &s->snap_u, &s->snap_v, &s->eta_t_c, &s->otab_d};
     mdlts_status st = MDLTS_OK;
     for (DevBuf *b : bufs)
         if (dev_free(c, *b) != MDLTS_OK) st = MDLTS_EDEVICE;
@@ -1731,11 +1780,19 @@ mdlts_status mdlts_set_conductivity(mdlts_sim *s, const double D_sym[6], double 
 {
     if (!s || !(gamma > 0.0) || !std::isfinite(gamma)) return MDLTS_EINVAL;
     s->version++;
-    double Dk[3];
-    if (!diag_of(D_sym, s->desc.dim, Dk)) return MDLTS_EINVAL;
+    Conductivity C;
+    if (!parse_conductivity(D_sym, s->desc.dim, C)) return MDLTS_EINVAL;
     double G[4][4];
     if (!gershgorin_table(s->ref, gamma, G)) return MDLTS_EINVAL;
-    for (int k = 0; k < 3; k++) s->Dk[k] = k < s->desc.dim ? Dk[k] : 0.0;
+    std::vector<double> otab;
+    if (C.full && !own_block_table(s->ref, s->desc.dim, s->h0, C, gamma, otab)) return MDLTS_EINVAL;
+    for (int k = 0; k < 3; k++) {
+        s->Dk[k] = k < s->desc.dim ? C.Dk[k] : 0.0;
+        s->Dx[k] = C.Dx[k];
+    }
+    s->dfull = C.full;
+    s->otab = std::move(otab);
+    s->otab_dirty = C.full;
     s->gamma = gamma;
     s->step_dirty = true;
     std::memcpy(s->G, G, sizeof(G));
@@ -1879,6 +1936,15 @@ static mdlts_status levels_enqueue(mdlts_sim *s, double dt_barrier, int force_le
     la.b_cell = b_cell;
     for (int k = 0; k < 3; k++) { la.h0[k] = s->h0[k]; la.Dk[k] = s->Dk[k]; }
     std::memcpy(la.G, s->G, sizeof(la.G));
+    if (s->dfull) {
+        if (s->otab_dirty || !s->otab_d.p) {
+            MD_TRY(dev_alloc(c, s->otab_d, s->otab.size() * sizeof(double)));
+            HIP_TRY(hipMemcpyAsync(s->otab_d.p, s->otab.data(), s->otab.size() * sizeof(double), hipMemcpyHostToDevice,
+                                   c->stream));
+            s->otab_dirty = false;
+        }
+        la.otab = P<double>(s->otab_d);
+    }
     la.level = P<uint8_t>(s->level_c);
     la.cfl = P<double>(s->cfl_c);
     la.hist = P<int>(s->hist);
@@ -2303,8 +2369,8 @@ mdlts_status mdlts_cfl_bound(const mdlts_mesh_desc *desc, const double D_sym[6],
                              double *cfl_min)
 {
     if (!valid_desc(desc) || !cfl_min || depth < 0 || depth > desc->max_depth || !(gamma > 0.0)) return MDLTS_EINVAL;
-    double Dk[3];
-    if (!diag_of(D_sym, desc->dim, Dk)) return MDLTS_EINVAL;
+    Conductivity C;
+    if (!parse_conductivity(D_sym, desc->dim, C)) return MDLTS_EINVAL;
     RefTables R;
     make_ref_tables(desc->order, R);
     double G[4][4];
@@ -2327,7 +2393,28 @@ mdlts_status mdlts_cfl_bound(const mdlts_mesh_desc *desc, const double D_sym[6],
                 if (ok) worst = std::max(worst, G[lo][hi]);
             }
         const double h = std::ldexp(desc->len[k] / (double)desc->n[k], -depth);
-        s += Dk[k] / (h * h) * worst;
+        s += C.Dk[k] / (h * h) * worst;
+    }
+    if (C.full) {
+        // the worst admissible combination of the kinds of all faces
+        double h0[3];
+        for (int k = 0; k < 3; k++) h0[k] = k < desc->dim ? desc->len[k] / (double)desc->n[k] : 1.0;
+        std::vector<double> tab;
+        if (!own_block_table(R, desc->dim, h0, C, gamma, tab)) return MDLTS_EINVAL;
+        double worst = 0.0;
+        for (size_t idx = 0; idx < tab.size(); idx++) {
+            bool ok = true;
+            for (int k = 0; k < desc->dim && ok; k++) {
+                const uint32_t lo = (uint32_t)(idx >> (4 * k)) & 3, hi = (uint32_t)(idx >> (4 * k + 2)) & 3;
+                if ((lo == kFiner || hi == kFiner) && depth == desc->max_depth) ok = false;
+                if ((lo == kCoarser || hi == kCoarser) && depth == 0) ok = false;
+                if (lo == kBoundary && hi == kBoundary && !(depth == 0 && desc->n[k] == 1)) ok = false;
+                const bool sib_lo = lo == kSame || lo == kFiner, sib_hi = hi == kSame || hi == kFiner;
+                if (depth > 0 && !sib_lo && !sib_hi) ok = false;
+            }
+            if (ok) worst = std::max(worst, tab[idx]);
+        }
+        s = worst * std::ldexp(1.0, 2 * depth);
     }
     *cfl_min = 1.0 / s;
     return MDLTS_OK;
@@ -2374,6 +2461,7 @@ mdlts_status mdlts_memory_bound(const mdlts_mesh_desc *desc, int64_t max_leaves,
         + (nsub * 16 + 31) / 32;    // batch tiles: per substep one per 64 leaves (blocks of >= 64 threads)
     const uint64_t fixed = 64 * 512         // allocator rounding of every buffer
                            + 4 * 4096       // flags, step constants, batch descriptor, small scans
+                           + 8 * 4096       // own-block bounds of a full diffusion tensor
                            + nsub * 16 * 2; // tile list heads
     *bytes = per_leaf * (uint64_t)max_leaves + fixed;
     return MDLTS_OK;
@@ -2384,8 +2472,8 @@ mdlts_status mdlts_plan_levels(const mdlts_mesh_desc *desc, const uint8_t *bits,
                                double *cfl, size_t n_leaves)
 {
     if (!valid_desc(desc) || !(dt_barrier > 0.0) || !(gamma > 0.0)) return MDLTS_EINVAL;
-    double Dk[3];
-    if (!diag_of(D_sym, desc->dim, Dk)) return MDLTS_EINVAL;
+    Conductivity C;
+    if (!parse_conductivity(D_sym, desc->dim, C)) return MDLTS_EINVAL;
     Forest F;
     forest_from_desc(desc, F);
     if (!F.parse_bits(bits, n_bits)) return MDLTS_EINVAL;
@@ -2397,7 +2485,13 @@ mdlts_status mdlts_plan_levels(const mdlts_mesh_desc *desc, const uint8_t *bits,
     double h0[3];
     for (int k = 0; k < 3; k++) h0[k] = k < desc->dim ? desc->len[k] / (double)desc->n[k] : 1.0;
     std::vector<double> c(n_leaves);
-    host_cfl(F, h0, Dk, G, c.data());
+    if (C.full) {
+        std::vector<double> tab;
+        if (!own_block_table(R, desc->dim, h0, C, gamma, tab)) return MDLTS_EINVAL;
+        host_cfl_full(F, tab, c.data());
+    } else {
+        host_cfl(F, h0, C.Dk, G, c.data());
+    }
     std::vector<int> lv(n_leaves);
     mdlts_status st = MDLTS_OK;
     for (size_t e = 0; e < n_leaves; e++) {

@@ -6,8 +6,14 @@ from paper_2310_07607_amd import inputs
 
 
 def diag3(D):
-    D = list(D) + [0.0] * (3 - len(D))
-    return np.diag(D)
+    """3x3 tensor from the diagonal (a sequence) or a dim x dim matrix."""
+    D = np.asarray(D, dtype=np.float64)
+    out = np.zeros((3, 3))
+    if D.ndim == 2:
+        out[: D.shape[0], : D.shape[1]] = D
+    else:
+        out[np.arange(D.size), np.arange(D.size)] = D
+    return out
 
 
 def oracle_mesh(dim, p, n, length, depth, D, gamma, seeds=(), frac=0.25):

@@ -15,6 +15,10 @@ CASES = [
     (2, 2, (7, 6), (0.07, 0.06), 2, (0.8e-3, 0.8e-3), 4.0, (4, 5), 4, "f32"),
     (3, 1, (5, 4, 3), (0.05, 0.04, 0.03), 1, (1.3e-3, 0.33e-3, 0.33e-3), 2.0, (6,), 3, "f32"),
     (3, 2, (4, 3, 3), (0.04, 0.03, 0.03), 1, (1e-3, 1e-3, 1e-3), 4.0, (7,), 3, "f32"),
+    # full diffusion tensors: kernels of their own in the same launches
+    (2, 2, (6, 5), (0.06, 0.05), 1, ((1.3e-3, 0.4e-3), (0.4e-3, 0.8e-3)), 4.0, (12,), 3, "f32"),
+    (3, 1, (5, 4, 3), (0.05, 0.04, 0.03), 1,
+     ((1.3e-3, 0.3e-3, 0.1e-3), (0.3e-3, 0.8e-3, 0.2e-3), (0.1e-3, 0.2e-3, 0.6e-3)), 2.0, (13,), 3, "f32"),
     (2, 1, (13, 9), (0.13, 0.09), 2, (1e-3, 1e-3), 2.0, (8, 9), 3, "f64"),
 ]
 

@@ -13,12 +13,20 @@ from tests.gpu_common import gpu_sim, oracle_mesh, rel_l2
 
 pytestmark = pytest.mark.gpu
 
+FULL_2D = np.array([[1.3e-3, 0.4e-3], [0.4e-3, 0.8e-3]])
+FULL_3D = np.array([[1.3e-3, 0.3e-3, 0.1e-3], [0.3e-3, 0.8e-3, 0.2e-3], [0.1e-3, 0.2e-3, 0.6e-3]])
+
 MESHES = {
     # dim, p, n, length, depth, D, gamma, refinement seeds
     "q1_2d": (2, 1, (13, 9), (0.65, 0.45), 2, (1e-3, 1e-3), 2.0, (1, 2)),
     "q2_2d": (2, 2, (7, 6), (0.35, 0.3), 2, (1.3e-3, 0.4e-3), 4.0, (3, 4)),
     "q1_3d": (3, 1, (5, 4, 3), (0.25, 0.2, 0.15), 2, (1.3e-3, 0.33e-3, 0.33e-3), 2.0, (5,)),
     "q2_3d": (3, 2, (4, 3, 3), (0.2, 0.15, 0.15), 1, (1.3e-3, 0.33e-3, 0.33e-3), 4.0, (6,)),
+    # full diffusion tensors (fibres not along the axes)
+    "q1_2d_full": (2, 1, (11, 8), (0.55, 0.4), 2, FULL_2D, 2.0, (7, 8)),
+    "q2_2d_full": (2, 2, (6, 5), (0.3, 0.25), 2, FULL_2D, 4.0, (9,)),
+    "q1_3d_full": (3, 1, (5, 4, 3), (0.25, 0.2, 0.15), 2, FULL_3D, 2.0, (10,)),
+    "q2_3d_full": (3, 2, (4, 3, 3), (0.2, 0.15, 0.15), 1, FULL_3D, 4.0, (11,)),
 }
 
 

@@ -27,17 +27,34 @@ def test_strerror_and_invalid_descriptors():
         mdlts.cfl_bound(bad, [1e-3, 1e-3, 1e-3], 2.0, 0)
     assert ei.value.status == mdlts.EINVAL
     good = mdlts.make_desc(2, 1, (4, 4), (1, 1), max_depth=2, n_levels=3)
-    with pytest.raises(mdlts.MdltsError):                       # off-diagonal D
-        mdlts.cfl_bound(good, [1e-3, 1e-3, 0, 1e-4, 0, 0], 2.0, 0)
+    with pytest.raises(mdlts.MdltsError):                       # D not positive definite
+        mdlts.cfl_bound(good, [1e-3, 1e-3, 0, 1.5e-3, 0, 0], 2.0, 0)
+    with pytest.raises(mdlts.MdltsError):                       # a z coupling in 2-D
+        mdlts.cfl_bound(good, [1e-3, 1e-3, 0, 1e-4, 1e-4, 0], 2.0, 0)
+    assert mdlts.cfl_bound(good, [1e-3, 1e-3, 0, 1e-4, 0, 0], 2.0, 0) > 0   # full tensor accepted
     with pytest.raises(mdlts.MdltsError):                       # depth above the cap
         mdlts.cfl_bound(good, [1e-3, 1e-3, 0], 2.0, 3)
     with pytest.raises(mdlts.MdltsError):                       # Q2 penalty without negative diagonals
         mdlts.cfl_bound(mdlts.make_desc(2, 2, (4, 4), (1, 1)), [1e-3, 1e-3, 0], 0.1, 0)
 
 
+def _dmat(D):
+    D = np.asarray(D, dtype=np.float64)
+    out = np.zeros((3, 3))
+    if D.ndim == 2:
+        out[: D.shape[0], : D.shape[1]] = D
+    else:
+        out[np.arange(D.size), np.arange(D.size)] = D
+    return out
+
+
+FULL_2D = ((1.3e-3, 0.4e-3), (0.4e-3, 0.8e-3))
+FULL_3D = ((1.3e-3, 0.3e-3, 0.1e-3), (0.3e-3, 0.8e-3, 0.2e-3), (0.1e-3, 0.2e-3, 0.6e-3))
+
+
 def _oracle_mesh(dim, p, n, length, depth, seeds, D, gamma):
     o = Oracle(dim, p, n, length, depth)
-    o.set_params(np.diag(list(D) + [0.0] * (3 - len(D))), gamma)
+    o.set_params(_dmat(D), gamma)
     for s in seeds:
         o.adapt(inputs.random_eta(s, o.n_leaves, frac_hot=0.25), 0.5, -1.0)
     return o
@@ -48,6 +65,10 @@ CASES = [
     (2, 2, (4, 6), (0.4, 0.6), 2, (1.3e-3, 0.4e-3), 4.0),
     (3, 1, (3, 3, 2), (0.3, 0.3, 0.2), 2, (1.3e-3, 0.33e-3, 0.33e-3), 2.0),
     (3, 2, (3, 2, 2), (0.3, 0.2, 0.2), 2, (1e-3, 1e-3, 1e-3), 4.0),
+    (2, 1, (7, 5), (0.7, 0.5), 3, FULL_2D, 2.0),
+    (2, 2, (4, 6), (0.4, 0.6), 2, FULL_2D, 4.0),
+    (3, 1, (3, 3, 2), (0.3, 0.3, 0.2), 2, FULL_3D, 2.0),
+    (3, 2, (3, 2, 2), (0.3, 0.2, 0.2), 2, FULL_3D, 4.0),
 ]
 
 
@@ -86,10 +107,11 @@ def test_plan_levels_matches_oracle_bitwise(dim, p, n, length, depth, D, gamma):
 
 
 @pytest.mark.parametrize("dim,p,gamma", [(2, 1, 2.0), (2, 2, 4.0), (3, 1, 2.0), (3, 2, 4.0)])
-def test_cfl_bound_is_the_worst_leaf(dim, p, gamma):
+@pytest.mark.parametrize("full", [False, True])
+def test_cfl_bound_is_the_worst_leaf(dim, p, gamma, full):
     n = (4, 4, 3)[:dim]
     length = (0.4, 0.4, 0.3)[:dim]
-    D = (1.3e-3, 0.5e-3, 0.4e-3)[:dim]
+    D = ((FULL_2D if dim == 2 else FULL_3D) if full else (1.3e-3, 0.5e-3, 0.4e-3)[:dim])
     desc = mdlts.make_desc(dim, p, n, length, 2, 4)
     o = _oracle_mesh(dim, p, n, length, 2, (5, 6), D, gamma)
     depth, _ = o.leaf_info()
@@ -100,7 +122,7 @@ def test_cfl_bound_is_the_worst_leaf(dim, p, gamma):
             assert b <= cfl[depth == d].min() * (1 + 1e-13)
     # on a uniform root mesh the bound is attained (a boundary leaf)
     u = Oracle(dim, p, n, length, 0)
-    u.set_params(np.diag(list(D) + [0.0] * (3 - dim)), gamma)
+    u.set_params(_dmat(D), gamma)
     desc0 = mdlts.make_desc(dim, p, n, length, 0, 1)
     assert mdlts.cfl_bound(desc0, D, gamma, 0) == pytest.approx(u.cfl().min(), rel=1e-13)
 

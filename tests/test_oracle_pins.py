@@ -175,6 +175,74 @@ def test_linear_fields_are_stationary_away_from_the_boundary(dim, p):
     assert np.abs(o.indicator()).max() < 1e-12
 
 
+# full diffusion tensors (fibres not along the axes; Sec. 2: D symmetric
+# positive definite, not necessarily diagonal)
+FULL_D = {2: np.array([[1.3e-3, 0.4e-3, 0.0], [0.4e-3, 0.8e-3, 0.0], [0.0, 0.0, 0.0]]),
+          3: np.array([[1.3e-3, 0.3e-3, 0.1e-3], [0.3e-3, 0.8e-3, 0.2e-3], [0.1e-3, 0.2e-3, 0.6e-3]])}
+
+
+@pytest.mark.parametrize("dim,p,gamma", [(2, 1, 2.0), (2, 2, 4.0), (3, 1, 2.0), (3, 2, 4.0)])
+def test_full_tensor_operator_symmetric_zero_on_constants_negative_semidefinite(dim, p, gamma):
+    o = make(dim, p, [3, 2, 2][:dim], [0.3, 0.2, 0.2][:dim], depth=2, D=FULL_D[dim], gamma=gamma)
+    refine_some(o, rounds=1 if dim == 3 else 2)
+    K, _ = o.dense_operators()
+    scale = np.abs(K).max()
+    assert np.abs(K - K.T).max() <= 1e-13 * scale
+    assert np.abs(K @ np.ones(K.shape[0])).max() <= 1e-13 * scale
+    assert np.linalg.eigvalsh(-0.5 * (K + K.T)).min() >= -1e-12 * scale
+
+
+@pytest.mark.parametrize("dim,p", [(2, 1), (2, 2), (3, 1), (3, 2)])
+def test_bilinear_field_gives_the_mixed_second_derivatives(dim, p):
+    # u = xy (2-D) or xy + 2yz - xz (3-D) lies in Q1: its Hessian has only
+    # mixed entries, so div(D grad u) = 2 Dxy (+ 4 Dyz - 2 Dxz) is a constant
+    # made by the off-diagonal entries alone.  SIPG consistency with exact GL
+    # quadrature and the diagonal GL mass give M^-1 K u = that constant at
+    # every node of an element without a boundary face (also across
+    # non-conforming faces); the normal flux is continuous, so the face-jump
+    # indicator vanishes.  Dropping or transposing an off-diagonal term in
+    # the volume or in the face fluxes breaks it.
+    D = FULL_D[dim]
+    n = [4, 4, 3][:dim]
+    o = make(dim, p, n, [0.4, 0.4, 0.3][:dim], depth=2, D=D)
+    refine_some(o, rounds=1)
+    X = o.leaf_nodes()
+    if dim == 2:
+        u = X[:, 0] * X[:, 1]
+        c = 2 * D[0, 1]
+    else:
+        u = X[:, 0] * X[:, 1] + 2 * X[:, 1] * X[:, 2] - X[:, 0] * X[:, 2]
+        c = 2 * D[0, 1] + 4 * D[1, 2] - 2 * D[0, 2]
+    _, M = o.dense_operators()
+    Lu = (o.apply_K(u) / np.diag(M)).reshape(o.n_leaves, -1)
+    depth, coords = o.leaf_info()
+    n_int = 0
+    for e in range(o.n_leaves):
+        if all(0 < coords[e, k] < n[k] * 2 ** depth[e] - 1 for k in range(dim)):
+            assert np.abs(Lu[e] - c).max() <= 1e-11 * abs(c), (e, Lu[e], c)
+            n_int += 1
+    assert n_int > 0
+    o.set_state(u, np.zeros_like(u))
+    assert np.abs(o.indicator()).max() < 1e-12
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_indicator_closed_form_for_a_kink_under_a_full_tensor(p):
+    # u = |x - x0|: on the faces normal to x the normal flux is Dxx sign(x - x0)
+    # (jump 2 Dxx at x0 only); on the faces normal to y it is Dxy sign(x - x0),
+    # equal on both sides.  So eta is the diagonal closed form with Dxx.
+    h = 0.1
+    D = FULL_D[2]
+    o = make(2, p, [4, 3], [0.4, 0.3], D=D)
+    X = o.leaf_nodes()
+    u = np.abs(X[:, 0] - 0.2)
+    o.set_state(u, np.zeros_like(u))
+    eta = o.indicator().reshape(3, 4)
+    expect = math.sqrt(h / (2 * p) * h ** 2 * h * (2 * D[0, 0]) ** 2)
+    np.testing.assert_allclose(eta[:, 1:3], expect, rtol=1e-12)
+    assert np.abs(eta[:, [0, 3]]).max() < 1e-15
+
+
 @pytest.mark.parametrize("p,ratio_min,sizes", [(1, 3.7, (8, 16)), (2, 15.0, (4, 8))])
 def test_smallest_eigenvalue_converges_to_laplacian_mode(p, ratio_min, sizes):
     # -M^-1 K has smallest non-zero eigenvalue -> pi^2 D / Lx^2 (Neumann box)
