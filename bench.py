@@ -268,6 +268,33 @@ def full_tensor_leg(ctx, W, seed, u, v, bits, t0, barriers=50):
     return out
 
 
+def degree3_leg(ctx, barriers=40):
+    """Degree 3 on uniform root meshes in FP32 (a 2 x 2 cm square of 256 x 256
+    elements, 1.05M DoF, and a 1 x 0.75 x 0.375 cm slab of 64 x 48 x 24
+    elements, 4.7M DoF; D = 1e-3 I, gamma 8): one level at the barrier step
+    from the leaves, graph-timed substep launches."""
+    from paper_2310_07607_amd import inputs, mdlts
+    out = {}
+    for name, dim, n, length in (("q3_2d", 2, (256, 256), (2.0, 2.0)),
+                                 ("q3_3d", 3, (64, 48, 24), (1.0, 0.75, 0.375))):
+        g = mdlts.Simulation(ctx, dim, 3, n, length, 0, 1, "f32")
+        g.set_conductivity((1e-3,) * dim, 8.0)
+        g.set_ionic(*inputs.AP_PARAMS)
+        u, v = inputs.random_state(5, g.n_dof, u_range=(0.0, 0.3), v_range=(0.0, 0.1))
+        g.set_state(u, v)
+        dt, _ = g.assign_levels_auto()
+        g.set_time(0.0)
+        ms, nd = timed_barriers(ctx, lambda k: g.step(k), barriers, lambda: g.counters()[0])
+        bpd = bytes_per_dof(dim, 3)
+        achieved = bpd * nd / (ms * 1e-3) / 1e9
+        out[name] = {"dof": g.n_dof, "dt_ms": dt, "value": nd / (ms * 1e-3), "unit": "DoF-updates/s",
+                     "avg_launch_us": ms * 1e3 / barriers, "bytes_per_dof_update": bpd,
+                     "achieved_GBps": achieved, "frac": achieved / HBM_PEAK_GBS,
+                     "kernel": f"k_substep_batch<{dim},3,float,false>", "dof_updates": g.counters()[0]}
+        g.close()
+    return out
+
+
 def interval(sim, W, dt):
     """Indicator, adaptation, levels (one call, two host synchronisations),
     then amr_every barriers."""
@@ -474,6 +501,7 @@ def main():
     rvt = rvt_leg(ctx, sim, dt)
     auto = auto_levels_leg(ctx, W, args.seed, u, v, bits, t_sim1)
     full = full_tensor_leg(ctx, W, args.seed, u, v, bits, t_sim1)
+    deg3 = degree3_leg(ctx)
     plain = setup(ctx, W, args.seed, "f64", n_levels=1)
     plain.set_tree(bits)
     plain.set_state(u, v)
@@ -554,6 +582,7 @@ def main():
         "rvt_indicator": rvt,
         "auto_levels": auto,
         "full_tensor": full,
+        "degree3": deg3,
     }
     for s in (sim, plain, lts, ref):
         s.close()

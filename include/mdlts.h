@@ -66,7 +66,7 @@ typedef struct {
 
 typedef struct {
     int dim;          /* 2 or 3 */
-    int order;        /* polynomial degree p: 1 or 2 */
+    int order;        /* polynomial degree p: 1, 2 or 3 */
     int n[3];         /* root grid (n[2] ignored for dim 2) */
     double len[3];    /* box edge lengths [cm] */
     int max_depth;    /* refinement depth cap, 0..8 */
@@ -95,7 +95,8 @@ mdlts_status mdlts_sync(mdlts_ctx *ctx);
 
 /* ---- simulation: mesh and parameters (Sec. 2, Sec. 2.2) ------------------ */
 /* Creates a simulation on the root mesh (all roots leaves, u = v = 0, t = 0,
- * D = 1e-3 I, gamma = 2, standard Aliev-Panfilov constants, no stimulus). */
+ * D = 1e-3 I, gamma = 2 / 4 / 8 for degree 1 / 2 / 3, standard Aliev-Panfilov
+ * constants, no stimulus). */
 mdlts_status mdlts_sim_create(mdlts_ctx *ctx, const mdlts_mesh_desc *desc, mdlts_sim **out);
 mdlts_status mdlts_sim_destroy(mdlts_sim *sim);
 /* Replaces the forest (refine-bit stream, see above).  The state is reset to

@@ -26,16 +26,33 @@ def _run(cmd):
     subprocess.run(cmd, check=True)
 
 
+def _run_all(cmds):
+    """Run the compile commands concurrently; raise if any fails."""
+    procs = []
+    for cmd in cmds:
+        print(" ".join(cmd), flush=True)
+        procs.append((cmd, subprocess.Popen(cmd)))
+    failed = [cmd for cmd, p in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
+
+
 def build(verbose=True):
     os.makedirs(LIBDIR, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
     host_o = os.path.join(LIBDIR, "host.o")
-    _run(["g++", "-std=c++17", "-O2", "-fPIC", "-ffp-contract=off", "-Wall", *inc, "-c",
-          os.path.join(CSRC, "host.cpp"), "-o", host_o])
     dev_o = os.path.join(LIBDIR, "mdlts.o")
-    _run([HIPCC, *HIP_FLAGS, *inc, "-c", os.path.join(CSRC, "mdlts.hip"), "-o", dev_o])
+    # the substep kernels, one translation unit per polynomial degree
+    var_o = [os.path.join(LIBDIR, f"variants_p{p}.o") for p in (1, 2, 3)]
+    cmds = [["g++", "-std=c++17", "-O2", "-fPIC", "-ffp-contract=off", "-Wall", *inc, "-c",
+             os.path.join(CSRC, "host.cpp"), "-o", host_o],
+            [HIPCC, *HIP_FLAGS, *inc, "-c", os.path.join(CSRC, "mdlts.hip"), "-o", dev_o]]
+    for p, o in zip((1, 2, 3), var_o):
+        cmds.append([HIPCC, *HIP_FLAGS, *inc, f"-DMDLTS_DEGREE={p}", "-c", os.path.join(CSRC, "variants.hip"),
+                     "-o", o])
+    _run_all(cmds)
     tmp = LIB + ".tmp"
-    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", dev_o, host_o, "-o", tmp])
+    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", dev_o, *var_o, host_o, "-o", tmp])
     os.replace(tmp, LIB)
     return LIB
 

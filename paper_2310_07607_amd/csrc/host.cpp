@@ -47,6 +47,14 @@ bool make_ref_tables(int p, RefTables &T)
         const double r = std::sqrt(0.6);
         T.xi[0] = -r; T.xi[1] = 0.0; T.xi[2] = r;
         T.w[0] = 5.0 / 9.0; T.w[1] = 8.0 / 9.0; T.w[2] = 5.0 / 9.0;
+    } else if (p == 3) {
+        // roots of P_4: x^2 = 3/7 -+ (2/7) sqrt(6/5); weights (18 +- sqrt(30))/36
+        T.m = 4;
+        const double a = std::sqrt(3.0 / 7.0 - 2.0 / 7.0 * std::sqrt(1.2));
+        const double b = std::sqrt(3.0 / 7.0 + 2.0 / 7.0 * std::sqrt(1.2));
+        T.xi[0] = -b; T.xi[1] = -a; T.xi[2] = a; T.xi[3] = b;
+        const double wa = (18.0 + std::sqrt(30.0)) / 36.0, wb = (18.0 - std::sqrt(30.0)) / 36.0;
+        T.w[0] = wb; T.w[1] = wa; T.w[2] = wa; T.w[3] = wb;
     } else {
         return false;
     }

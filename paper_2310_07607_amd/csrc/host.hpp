@@ -8,7 +8,7 @@
 
 namespace mdlts {
 
-constexpr int kMaxM = 3;  // nodes per direction (order <= 2)
+constexpr int kMaxM = 4;  // nodes per direction (order <= 3)
 
 // Face neighbour kinds in the canonical face table (bits 30..31 of an entry).
 enum FaceKind : uint32_t { kBoundary = 0, kSame = 1, kCoarser = 2, kFiner = 3 };

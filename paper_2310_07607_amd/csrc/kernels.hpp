@@ -82,11 +82,19 @@ constexpr RefConst ref_const(int p)
         const double r = 1.0 / csqrt(3.0);
         T.xi[0] = -r; T.xi[1] = r;
         T.w[0] = 1.0; T.w[1] = 1.0;
-    } else {
+    } else if (p == 2) {
         T.m = 3;
         const double r = csqrt(0.6);
         T.xi[0] = -r; T.xi[1] = 0.0; T.xi[2] = r;
         T.w[0] = 5.0 / 9.0; T.w[1] = 8.0 / 9.0; T.w[2] = 5.0 / 9.0;
+    } else {
+        // roots of P_4: x^2 = 3/7 -+ (2/7) sqrt(6/5); weights (18 +- sqrt(30))/36
+        T.m = 4;
+        const double a = csqrt(3.0 / 7.0 - 2.0 / 7.0 * csqrt(1.2));
+        const double b = csqrt(3.0 / 7.0 + 2.0 / 7.0 * csqrt(1.2));
+        T.xi[0] = -b; T.xi[1] = -a; T.xi[2] = a; T.xi[3] = b;
+        const double wa = (18.0 + csqrt(30.0)) / 36.0, wb = (18.0 - csqrt(30.0)) / 36.0;
+        T.w[0] = wb; T.w[1] = wa; T.w[2] = wa; T.w[3] = wb;
     }
     const int m = T.m;
     for (int j = 0; j < m; j++) {
@@ -568,15 +576,17 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
     // interior faces.  Elements too large to prefetch every face keep the
     // neighbours of two faces in flight: face f+2's loads are issued as soon
     // as face f is done (double buffer), so memory overlaps the arithmetic.
-    T nbuf[2][kPrefetch ? 1 : NP];
+    // (Q3 hexahedra, 64 nodes, keep one face in flight)
+    constexpr int NB = kPrefetch ? 1 : (NP <= 27 ? 2 : 1);
+    T nbuf[NB][kPrefetch ? 1 : NP];
     auto issue = [&](int f, T *dst) {
         const uint32_t kind = ent[f] >> 30;
         const bool one = kind == kSame || kind == kCoarser;
         neighbour_slot0<T, NP>(L, ru, one ? ent[f] : self_ent, dst);
     };
     if constexpr (!kPrefetch) {
-        issue(0, nbuf[0]);
-        issue(1, nbuf[1]);
+#pragma unroll
+        for (int f = 0; f < NB; f++) issue(f, nbuf[f]);
     }
 #pragma unroll
     for (int k = 0; k < DIM; k++) {
@@ -641,8 +651,8 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
                         nq[g] = sq;
                     }
                 } else {
-                    neighbour_interp<T, NP>(L, ru, ent[f], nbuf[s]);
-                    trace_from(nbuf[s]);
+                    neighbour_interp<T, NP>(L, ru, ent[f], nbuf[f % NB]);
+                    trace_from(nbuf[f % NB]);
                 }
                 const bool co = kind == kCoarser;  // h_nbr = 2h
                 if (kind == kCoarser) {
@@ -761,7 +771,7 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
                     r[fnode<DIM, M>(k, g, b)] += Fl[g] * (T)(R.winv[b] * R.B[s][b]) + Hl[g] * (T)(R.winv[b] * R.G[s][b]);
             }
             if constexpr (!kPrefetch)
-                if (f + 2 < NFACE) issue(f + 2, nbuf[s]);
+                if (f + NB < NFACE) issue(f + NB, nbuf[f % NB]);
         }
     }
 

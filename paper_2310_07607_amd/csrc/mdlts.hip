@@ -13,6 +13,7 @@
 #include "amr.hpp"
 #include "host.hpp"
 #include "kernels.hpp"
+#include "variants.hpp"
 #include "mdlts.h"
 
 using namespace mdlts;
@@ -570,7 +571,7 @@ struct mdlts_ctx {
     BatchPlan *batch = nullptr;
     int use_graphs = 1;
     // launch shape chosen by the autotuner, per mix of kernel variants
-    // (bit 8*full + 4*(dim-2) + 2*(order-1) + precision)
+    // (bit 12*full + 6*(dim-2) + 2*(order-1) + precision)
     std::map<int, std::pair<int, int>> tuned;  // mask -> (block, blocks per CU)
 };
 
@@ -709,7 +710,7 @@ bool valid_desc(const mdlts_mesh_desc *d)
 {
     if (!d) return false;
     if (d->dim != 2 && d->dim != 3) return false;
-    if (d->order != 1 && d->order != 2) return false;
+    if (d->order < 1 || d->order > 3) return false;
     if (d->max_depth < 0 || d->max_depth > 8) return false;
     if (d->n_levels < 1 || d->n_levels > kMaxLevels) return false;
     if (d->precision != MDLTS_FP64 && d->precision != MDLTS_FP32) return false;
@@ -921,11 +922,15 @@ mdlts_status set_forest(mdlts_sim *s, Forest &&F)
 }
 
 // ---- substep launch -------------------------------------------------------
-template <int DIM, int P_, typename T>
-void launch_substep(const StepArgs<T> *c, const StepLaunch<T> &L, bool full, hipStream_t st)
+template <typename T>
+mdlts_status launch_substep(const mdlts_sim *s, const StepArgs<T> *c, const StepLaunch<T> &L, hipStream_t st)
 {
-    if (full) k_substep<DIM, P_, T, true><<<nblocks(L.n_act), kBlock, 0, st>>>(c, L);
-    else k_substep<DIM, P_, T, false><<<nblocks(L.n_act), kBlock, 0, st>>>(c, L);
+    void *fn = substep_kernel_of(kFormEager, s->desc.dim, s->desc.order, sizeof(T) == 4, s->dfull);
+    if (!fn) return MDLTS_EINVAL;
+    StepLaunch<T> Lv = L;
+    void *args[] = {&c, &Lv};
+    HIP_TRY(hipLaunchKernel(fn, dim3(nblocks(L.n_act)), dim3(kBlock), args, 0, st));
+    return MDLTS_OK;
 }
 
 mdlts_status drain_events(mdlts_sim *s)
@@ -1008,7 +1013,6 @@ mdlts_status run_barriers(mdlts_sim *s, int n_barriers)
     const long long maxS = 1ll << s->lmax;
     const double h_tick = s->dt_bar / (double)maxS;
     hipStream_t st = s->ctx->stream;
-    const int key = s->desc.dim * 10 + s->desc.order;
     for (int nb = 0; nb < n_barriers; nb++) {
         const double t_n = s->t_start + (double)s->n_bar * s->dt_bar;
         L.parity = (int)(s->n_since_assign & 1);
@@ -1029,13 +1033,7 @@ mdlts_status run_barriers(mdlts_sim *s, int n_barriers)
                 }
                 HIP_TRY(hipEventRecord(s->ev[2 * s->ev_used], st));
             }
-            switch (key) {
-            case 21: launch_substep<2, 1, T>(cst, L, s->dfull, st); break;
-            case 22: launch_substep<2, 2, T>(cst, L, s->dfull, st); break;
-            case 31: launch_substep<3, 1, T>(cst, L, s->dfull, st); break;
-            case 32: launch_substep<3, 2, T>(cst, L, s->dfull, st); break;
-            default: return MDLTS_EINVAL;
-            }
+            MD_TRY(launch_substep<T>(s, cst, L, st));
             s->dof_updates += (uint64_t)L.n_act * (uint64_t)s->np;
             if (s->prof) {
                 HIP_TRY(hipEventRecord(s->ev[2 * s->ev_used + 1], st));
@@ -1082,6 +1080,8 @@ mdlts_status run_indicator(mdlts_sim *s, unsigned long long *max_bits, int *nonf
     case 22: launch_indicator<2, 2, T>(a, E, st); break;
     case 31: launch_indicator<3, 1, T>(a, E, st); break;
     case 32: launch_indicator<3, 2, T>(a, E, st); break;
+    case 23: launch_indicator<2, 3, T>(a, E, st); break;
+    case 33: launch_indicator<3, 3, T>(a, E, st); break;
     default: return MDLTS_EINVAL;
     }
     HIP_TRY(hipGetLastError());
@@ -1115,6 +1115,8 @@ mdlts_status run_transfer(mdlts_sim *s, int E_old, int E_new)
     case 22: k_transfer<2, 2, T><<<nblocks(E_new), kBlock, 0, st>>>(a); break;
     case 31: k_transfer<3, 1, T><<<nblocks(E_new), kBlock, 0, st>>>(a); break;
     case 32: k_transfer<3, 2, T><<<nblocks(E_new), kBlock, 0, st>>>(a); break;
+    case 23: k_transfer<2, 3, T><<<nblocks(E_new), kBlock, 0, st>>>(a); break;
+    case 33: k_transfer<3, 3, T><<<nblocks(E_new), kBlock, 0, st>>>(a); break;
     default: return MDLTS_EINVAL;
     }
     HIP_TRY(hipGetLastError());
@@ -1272,25 +1274,9 @@ void free_plan(mdlts_ctx *c, BatchPlan *&slot)
     slot = nullptr;
 }
 
-template <bool FULL>
-void *batch_kernel_of(int dim, int order, int prec)
-{
-    switch (dim * 100 + order * 10 + prec) {
-    case 210: return reinterpret_cast<void *>(&k_substep_batch<2, 1, double, FULL>);
-    case 220: return reinterpret_cast<void *>(&k_substep_batch<2, 2, double, FULL>);
-    case 310: return reinterpret_cast<void *>(&k_substep_batch<3, 1, double, FULL>);
-    case 320: return reinterpret_cast<void *>(&k_substep_batch<3, 2, double, FULL>);
-    case 211: return reinterpret_cast<void *>(&k_substep_batch<2, 1, float, FULL>);
-    case 221: return reinterpret_cast<void *>(&k_substep_batch<2, 2, float, FULL>);
-    case 311: return reinterpret_cast<void *>(&k_substep_batch<3, 1, float, FULL>);
-    case 321: return reinterpret_cast<void *>(&k_substep_batch<3, 2, float, FULL>);
-    }
-    return nullptr;
-}
-
 void *batch_kernel(int dim, int order, int prec, bool full)
 {
-    return full ? batch_kernel_of<true>(dim, order, prec) : batch_kernel_of<false>(dim, order, prec);
+    return substep_kernel_of(kFormBatch, dim, order, prec == MDLTS_FP32, full);
 }
 
 // both clock copies from the host's barrier counts (the next barrier reads
@@ -1613,7 +1599,7 @@ mdlts_status prepare_plan(mdlts_ctx *c, BatchPlan *&slot, mdlts_sim *const *sims
     }
     for (int q = 0; q < n; q++) P->versions.push_back(sims[q]->version);
     for (const BatchGroup &g : P->groups)
-        P->variant_mask |= 1 << (8 * (g.full ? 1 : 0) + 4 * (g.dim - 2) + 2 * (g.order - 1) + (g.prec == MDLTS_FP32 ? 1 : 0));
+        P->variant_mask |= 1 << (12 * (g.full ? 1 : 0) + 6 * (g.dim - 2) + 2 * (g.order - 1) + (g.prec == MDLTS_FP32 ? 1 : 0));
     // a mix of variants tuned before keeps its launch shape
     const auto tk = c->tuned.find(P->variant_mask);
     if (tk != c->tuned.end()) {
@@ -1703,6 +1689,8 @@ mdlts_status mdlts_sim_create(mdlts_ctx *ctx, const mdlts_mesh_desc *desc, mdlts
     s->tsize = desc->precision == MDLTS_FP64 ? 8 : 4;
     for (int k = 0; k < 3; k++) s->h0[k] = s->desc.len[k] / (double)s->desc.n[k];
     make_ref_tables(desc->order, s->ref);
+    // default penalty per degree (coercive: Q2 needs gamma > 2, Q3 > 5)
+    s->gamma = desc->order == 1 ? 2.0 : desc->order == 2 ? 4.0 : 8.0;
     mdlts_status st = compute_G(s);
     Forest F;
     forest_from_desc(&s->desc, F);
@@ -2098,6 +2086,10 @@ mdlts_status mdlts_rvt_indicator(mdlts_sim *s, double *eta_t, size_t n_leaves, d
     case 221: k_rvt<2, 2, float><<<nb, kBlock, 0, st>>>(a); break;
     case 311: k_rvt<3, 1, float><<<nb, kBlock, 0, st>>>(a); break;
     case 321: k_rvt<3, 2, float><<<nb, kBlock, 0, st>>>(a); break;
+    case 230: k_rvt<2, 3, double><<<nb, kBlock, 0, st>>>(a); break;
+    case 330: k_rvt<3, 3, double><<<nb, kBlock, 0, st>>>(a); break;
+    case 231: k_rvt<2, 3, float><<<nb, kBlock, 0, st>>>(a); break;
+    case 331: k_rvt<3, 3, float><<<nb, kBlock, 0, st>>>(a); break;
     default: return MDLTS_EINVAL;
     }
     HIP_TRY(hipGetLastError());

@@ -19,6 +19,9 @@ CASES = [
     (2, 2, (6, 5), (0.06, 0.05), 1, ((1.3e-3, 0.4e-3), (0.4e-3, 0.8e-3)), 4.0, (12,), 3, "f32"),
     (3, 1, (5, 4, 3), (0.05, 0.04, 0.03), 1,
      ((1.3e-3, 0.3e-3, 0.1e-3), (0.3e-3, 0.8e-3, 0.2e-3), (0.1e-3, 0.2e-3, 0.6e-3)), 2.0, (13,), 3, "f32"),
+    # degree 3
+    (2, 3, (5, 4), (0.05, 0.04), 1, (1.2e-3, 0.5e-3), 8.0, (14,), 3, "f32"),
+    (3, 3, (3, 2, 2), (0.03, 0.02, 0.02), 1, (1e-3, 0.7e-3, 0.5e-3), 8.0, (15,), 2, "f32"),
     (2, 1, (13, 9), (0.13, 0.09), 2, (1e-3, 1e-3), 2.0, (8, 9), 3, "f64"),
 ]
 

@@ -27,6 +27,9 @@ MESHES = {
     "q2_2d_full": (2, 2, (6, 5), (0.3, 0.25), 2, FULL_2D, 4.0, (9,)),
     "q1_3d_full": (3, 1, (5, 4, 3), (0.25, 0.2, 0.15), 2, FULL_3D, 2.0, (10,)),
     "q2_3d_full": (3, 2, (4, 3, 3), (0.2, 0.15, 0.15), 1, FULL_3D, 4.0, (11,)),
+    # degree 3 (gamma 8: coercive from about 6)
+    "q3_2d": (2, 3, (5, 4), (0.25, 0.2), 2, (1.2e-3, 0.5e-3), 8.0, (14, 15)),
+    "q3_3d_full": (3, 3, (3, 2, 2), (0.15, 0.1, 0.1), 1, FULL_3D, 8.0, (16,)),
 }
 
 

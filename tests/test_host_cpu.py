@@ -69,6 +69,8 @@ CASES = [
     (2, 2, (4, 6), (0.4, 0.6), 2, FULL_2D, 4.0),
     (3, 1, (3, 3, 2), (0.3, 0.3, 0.2), 2, FULL_3D, 2.0),
     (3, 2, (3, 2, 2), (0.3, 0.2, 0.2), 2, FULL_3D, 4.0),
+    (2, 3, (4, 3), (0.4, 0.3), 2, (1.1e-3, 0.6e-3), 8.0),
+    (3, 3, (2, 2, 2), (0.2, 0.2, 0.2), 1, FULL_3D, 8.0),
 ]
 
 
@@ -106,7 +108,7 @@ def test_plan_levels_matches_oracle_bitwise(dim, p, n, length, depth, D, gamma):
     assert st == mdlts.EUNSTABLE
 
 
-@pytest.mark.parametrize("dim,p,gamma", [(2, 1, 2.0), (2, 2, 4.0), (3, 1, 2.0), (3, 2, 4.0)])
+@pytest.mark.parametrize("dim,p,gamma", [(2, 1, 2.0), (2, 2, 4.0), (3, 1, 2.0), (3, 2, 4.0), (2, 3, 8.0), (3, 3, 8.0)])
 @pytest.mark.parametrize("full", [False, True])
 def test_cfl_bound_is_the_worst_leaf(dim, p, gamma, full):
     n = (4, 4, 3)[:dim]

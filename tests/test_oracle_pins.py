@@ -80,7 +80,7 @@ def test_mass_is_diagonal_with_gl_weights(dim, p):
 # --------------------------------------------------------------------------
 # SIPG operator (Sec. 2.1)
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("dim,p,gamma", [(2, 1, 2.0), (2, 2, 4.0), (3, 1, 2.0), (3, 2, 4.0)])
+@pytest.mark.parametrize("dim,p,gamma", [(2, 1, 2.0), (2, 2, 4.0), (3, 1, 2.0), (3, 2, 4.0), (2, 3, 8.0)])
 def test_operator_symmetric_zero_on_constants_negative_semidefinite(dim, p, gamma):
     n = [3, 2, 2][:dim]
     o = make(dim, p, n, [0.3, 0.2, 0.2][:dim], depth=2, gamma=gamma)
@@ -93,10 +93,12 @@ def test_operator_symmetric_zero_on_constants_negative_semidefinite(dim, p, gamm
     assert ev.min() >= -1e-12 * scale                      # coercive for this gamma
 
 
-def test_q2_penalty_two_is_not_coercive_three_is():
-    # Appendix-A style check of the penalty threshold for degree 2
-    for gamma, coercive in ((2.0, False), (3.0, True)):
-        o = make(2, 2, [4, 4], [1.0, 1.0], gamma=gamma)
+@pytest.mark.parametrize("p,below,above", [(2, 2.0, 3.0), (3, 5.0, 6.0)])
+def test_penalty_threshold_of_coercivity(p, below, above):
+    # Appendix-A style check of the penalty threshold: degree 2 needs gamma
+    # between 2 and 3, degree 3 between 5 and 6
+    for gamma, coercive in ((below, False), (above, True)):
+        o = make(2, p, [4, 4], [1.0, 1.0], gamma=gamma)
         K, _ = o.dense_operators()
         ev = np.linalg.eigvalsh(-K)
         if coercive:
@@ -154,7 +156,7 @@ def test_kronecker_sum_structure_uniform_2d():
     np.testing.assert_allclose(K2, Kk, rtol=0, atol=1e-14 * np.abs(K2).max())
 
 
-@pytest.mark.parametrize("dim,p", [(2, 1), (2, 2), (3, 1), (3, 2)])
+@pytest.mark.parametrize("dim,p", [(2, 1), (2, 2), (3, 1), (3, 2), (2, 3), (3, 3)])
 def test_linear_fields_are_stationary_away_from_the_boundary(dim, p):
     # SIPG consistency: a linear u has zero flux jumps, so (K u)_i = 0 on every
     # element without a boundary face -- also across non-conforming faces and
@@ -181,7 +183,7 @@ FULL_D = {2: np.array([[1.3e-3, 0.4e-3, 0.0], [0.4e-3, 0.8e-3, 0.0], [0.0, 0.0, 
           3: np.array([[1.3e-3, 0.3e-3, 0.1e-3], [0.3e-3, 0.8e-3, 0.2e-3], [0.1e-3, 0.2e-3, 0.6e-3]])}
 
 
-@pytest.mark.parametrize("dim,p,gamma", [(2, 1, 2.0), (2, 2, 4.0), (3, 1, 2.0), (3, 2, 4.0)])
+@pytest.mark.parametrize("dim,p,gamma", [(2, 1, 2.0), (2, 2, 4.0), (3, 1, 2.0), (3, 2, 4.0), (2, 3, 8.0)])
 def test_full_tensor_operator_symmetric_zero_on_constants_negative_semidefinite(dim, p, gamma):
     o = make(dim, p, [3, 2, 2][:dim], [0.3, 0.2, 0.2][:dim], depth=2, D=FULL_D[dim], gamma=gamma)
     refine_some(o, rounds=1 if dim == 3 else 2)
@@ -192,7 +194,7 @@ def test_full_tensor_operator_symmetric_zero_on_constants_negative_semidefinite(
     assert np.linalg.eigvalsh(-0.5 * (K + K.T)).min() >= -1e-12 * scale
 
 
-@pytest.mark.parametrize("dim,p", [(2, 1), (2, 2), (3, 1), (3, 2)])
+@pytest.mark.parametrize("dim,p", [(2, 1), (2, 2), (3, 1), (3, 2), (2, 3), (3, 3)])
 def test_bilinear_field_gives_the_mixed_second_derivatives(dim, p):
     # u = xy (2-D) or xy + 2yz - xz (3-D) lies in Q1: its Hessian has only
     # mixed entries, so div(D grad u) = 2 Dxy (+ 4 Dyz - 2 Dxz) is a constant
@@ -213,9 +215,15 @@ def test_bilinear_field_gives_the_mixed_second_derivatives(dim, p):
     else:
         u = X[:, 0] * X[:, 1] + 2 * X[:, 1] * X[:, 2] - X[:, 0] * X[:, 2]
         c = 2 * D[0, 1] + 4 * D[1, 2] - 2 * D[0, 2]
-    _, M = o.dense_operators()
-    Lu = (o.apply_K(u) / np.diag(M)).reshape(o.n_leaves, -1)
+    # diagonal GL mass w_i |J| (pinned in test_mass_is_diagonal_with_gl_weights)
     depth, coords = o.leaf_info()
+    w = np.array(GL[p][1])
+    wn = w
+    for k in range(1, dim):
+        wn = np.outer(w, wn).ravel()  # node index x fastest
+    h = np.array([0.4 / n[0], 0.4 / n[1], 0.3 / n[-1]])[:dim]
+    Mdiag = np.concatenate([wn * np.prod(h * 0.5 ** depth[e] / 2) for e in range(o.n_leaves)])
+    Lu = (o.apply_K(u) / Mdiag).reshape(o.n_leaves, -1)
     n_int = 0
     for e in range(o.n_leaves):
         if all(0 < coords[e, k] < n[k] * 2 ** depth[e] - 1 for k in range(dim)):
