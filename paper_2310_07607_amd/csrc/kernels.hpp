@@ -462,10 +462,14 @@ __device__ __forceinline__ void neighbour_interp(const StepLaunch<T> &L, __amdgp
 // forward Euler for u and an exponential step for v.  Reads the current
 // slot, writes the other one; v is updated in place.
 //
-// Memory schedule: the element's own nodes, its face entries and (for
-// same-size or coarser faces) one neighbour per face are loaded before any
-// arithmetic, so a wave waits for memory twice; faces with finer neighbours
-// (rare, at refinement interfaces) load their 2^(d-1) neighbours on demand.
+// Memory schedule: Q1 quadrilaterals load their own nodes, face entries
+// and (for same-size or coarser faces) one neighbour per face before any
+// arithmetic, so a wave waits for memory twice: their launches are short and
+// latency-bound.  Larger elements keep one face's neighbour in flight while
+// the previous face is computed, which leaves registers for more waves per
+// SIMD (measured: Q2 hexahedra 244 VGPRs and 2 waves instead of 1, Q1
+// hexahedra 125 and 4 instead of 2).  Faces with finer neighbours (rare, at
+// refinement interfaces) load their 2^(d-1) neighbours on demand.
 // Large FP32 elements stage the gate v through LDS: its loads go straight
 // to LDS at the start (no registers held) and are read at the update.
 template <int DIM, int P, typename T>
@@ -482,8 +486,8 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
     using S = Shape<DIM, P>;
     constexpr int M = S::M, NP = S::NP, NF = S::NF, NS = S::NS;
     constexpr int NFACE = 2 * DIM;
-    // prefetch every face's neighbour unless it costs too many registers
-    constexpr bool kPrefetch = NFACE * NP <= 64;
+    // prefetch every face's neighbour: Q1 quadrilaterals only
+    constexpr bool kPrefetch = NFACE * NP <= 16;
 
     constexpr RefConst R = ref_const(P);
     const int sh = L.lmax - lv;
@@ -573,11 +577,12 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
             }
     }
 
-    // interior faces.  Elements too large to prefetch every face keep the
-    // neighbours of two faces in flight: face f+2's loads are issued as soon
-    // as face f is done (double buffer), so memory overlaps the arithmetic.
-    // (Q3 hexahedra, 64 nodes, keep one face in flight)
-    constexpr int NB = kPrefetch ? 1 : (NP <= 27 ? 2 : 1);
+    // interior faces.  Elements that do not prefetch every face keep NB
+    // faces' neighbours in flight: face f+NB's loads are issued as soon as
+    // face f is done, so memory overlaps the arithmetic.  NB = 1: a second
+    // buffer costs NP registers, and waves per SIMD hide more latency than
+    // a deeper pipeline within one wave (measured on all larger elements).
+    constexpr int NB = 1;
     T nbuf[NB][kPrefetch ? 1 : NP];
     auto issue = [&](int f, T *dst) {
         const uint32_t kind = ent[f] >> 30;

@@ -572,7 +572,11 @@ struct mdlts_ctx {
     int use_graphs = 1;
     // launch shape chosen by the autotuner, per mix of kernel variants
     // (bit 12*full + 6*(dim-2) + 2*(order-1) + precision)
-    std::map<int, std::pair<int, int>> tuned;  // mask -> (block, blocks per CU)
+    struct Tuned {
+        int block, per_cu;
+        double dof;  // DoF-updates per barrier of the plan it was tuned on
+    };
+    std::map<int, Tuned> tuned;  // mask -> launch shape
 };
 
 // Host-visible staging of a simulation's small readbacks (pinned memory, so
@@ -1497,48 +1501,54 @@ mdlts_status run_batch_barriers(mdlts_ctx *c, BatchPlan &P, int nb)
 }
 
 // Autotuner: the first barriers of a new plan are run with each candidate
-// launch shape (block size, one block per tile or persistent blocks) and
-// timed with events; the fastest shape is kept.  Per-element arithmetic
-// does not depend on the shape, so results are unchanged.
+// launch shape (block size, one block per tile or persistent blocks), in
+// rounds over the candidates, and timed with events (one warm and one timed
+// barrier per candidate and round); the shape with the smallest time over
+// the rounds is kept.  Per-element arithmetic does not depend on the shape,
+// so results are unchanged.
 mdlts_status autotune(mdlts_ctx *c, BatchPlan &P, int *remaining)
 {
     struct Cand { int block, per_cu; };
     const Cand cands[] = {{256, 0}, {128, 0}, {64, 0}, {256, 8}, {128, 16}};
-    const int reps = 2;
-    if (*remaining < (int)(sizeof(cands) / sizeof(cands[0])) * reps) return MDLTS_OK;
+    constexpr int n_cand = (int)(sizeof(cands) / sizeof(cands[0]));
+    constexpr int rounds = 2;
+    if (*remaining < n_cand * rounds * 2) return MDLTS_OK;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    float best = 1e30f;
-    Cand pick = cands[0];
+    float best[n_cand];
+    for (int k = 0; k < n_cand; k++) best[k] = 1e30f;
     const bool saved_prof = P.prof;
     P.prof = false;
-    for (const Cand &cd : cands) {
-        P.block = cd.block;
-        P.per_cu = cd.per_cu;
-        MD_TRY(build_plan_data(c, P));
-        MD_TRY(emit_barrier(c, P, P.phase, nullptr));  // warm
-        account_barriers(P, 1);
-        HIP_TRY(hipEventRecord(e0, c->stream));
-        MD_TRY(emit_barrier(c, P, P.phase, nullptr));
-        account_barriers(P, 1);
-        HIP_TRY(hipEventRecord(e1, c->stream));
-        HIP_TRY(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best) {
-            best = ms;
-            pick = cd;
+    for (int rd = 0; rd < rounds; rd++)
+        for (int k = 0; k < n_cand; k++) {
+            P.block = cands[k].block;
+            P.per_cu = cands[k].per_cu;
+            MD_TRY(build_plan_data(c, P));
+            MD_TRY(emit_barrier(c, P, P.phase, nullptr));  // warm
+            account_barriers(P, 1);
+            HIP_TRY(hipEventRecord(e0, c->stream));
+            MD_TRY(emit_barrier(c, P, P.phase, nullptr));
+            account_barriers(P, 1);
+            HIP_TRY(hipEventRecord(e1, c->stream));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            best[k] = std::min(best[k], ms);
+            *remaining -= 2;
         }
-        *remaining -= reps;
-    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    int pick = 0;
+    for (int k = 1; k < n_cand; k++)
+        if (best[k] < best[pick]) pick = k;
     P.prof = saved_prof;
-    P.block = pick.block;
-    P.per_cu = pick.per_cu;
+    P.block = cands[pick].block;
+    P.per_cu = cands[pick].per_cu;
     P.tuned = true;
-    c->tuned[P.variant_mask] = {pick.block, pick.per_cu};
+    double dof = 0.0;
+    for (uint64_t d : P.dof_per_barrier) dof += (double)d;
+    c->tuned[P.variant_mask] = {P.block, P.per_cu, dof};
     return build_plan_data(c, P);
 }
 
@@ -1600,11 +1610,15 @@ mdlts_status prepare_plan(mdlts_ctx *c, BatchPlan *&slot, mdlts_sim *const *sims
     for (int q = 0; q < n; q++) P->versions.push_back(sims[q]->version);
     for (const BatchGroup &g : P->groups)
         P->variant_mask |= 1 << (12 * (g.full ? 1 : 0) + 6 * (g.dim - 2) + 2 * (g.order - 1) + (g.prec == MDLTS_FP32 ? 1 : 0));
-    // a mix of variants tuned before keeps its launch shape
+    // a mix of variants tuned before keeps its launch shape while the work
+    // per barrier stays within 25 % of what it was tuned on (the best shape
+    // moves as meshes refine)
     const auto tk = c->tuned.find(P->variant_mask);
-    if (tk != c->tuned.end()) {
-        P->block = tk->second.first;
-        P->per_cu = tk->second.second;
+    double dof = 0.0;
+    for (uint64_t d : P->dof_per_barrier) dof += (double)d;
+    if (tk != c->tuned.end() && std::fabs(dof - tk->second.dof) <= 0.25 * tk->second.dof) {
+        P->block = tk->second.block;
+        P->per_cu = tk->second.per_cu;
         P->tuned = true;
     }
     *fresh = true;

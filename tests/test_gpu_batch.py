@@ -55,7 +55,7 @@ def test_batch_equals_alone_bitwise(ctx, graphs):
     alone, mixed = [], []
     for k, case in enumerate(CASES):
         o, g, dt, L, u, v = _make(ctx, case, 10 + k)
-        g.step(13)
+        g.step(23)
         alone.append(g.get_state())
         g.close()
     sims, dts = [], []
@@ -63,7 +63,7 @@ def test_batch_equals_alone_bitwise(ctx, graphs):
         o, g, dt, L, u, v = _make(ctx, case, 10 + k)
         sims.append(g)
         dts.append(dt)
-    ctx.batch_step(sims, 13)          # the autotuner uses the first 10 barriers
+    ctx.batch_step(sims, 23)          # the autotuner uses the first 20 barriers
     for k, g in enumerate(sims):
         mixed.append(g.get_state())
         assert np.array_equal(mixed[k][0], alone[k][0]), k
@@ -72,7 +72,7 @@ def test_batch_equals_alone_bitwise(ctx, graphs):
     ctx.batch_step(sims, 2)
     for g, dt in zip(sims, dts):
         n, t = g.counters()
-        assert t == 0.125 + 15 * dt
+        assert t == 0.125 + 25 * dt
     for g in sims:
         g.close()
     ctx.set_graphs(True)
