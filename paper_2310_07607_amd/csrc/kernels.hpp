@@ -701,48 +701,56 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
             } else {
                 const T sigma = (T)1.5 * pen;           // h_nbr = h/2
                 const T qn = ns * Dkk * (T)2 * c2;
-                T Jl[NF];  // full tensors: jumps lifted from the sub-faces
+                // Own-side terms are taken on the whole face: restricting the
+                // own trace to the sub-faces (Isub) and lifting back (Lsub)
+                // gives it unchanged, since the half-interval GL rules
+                // integrate l_a l_b exactly (sum over sub-faces of Lsub Isub
+                // = I).  Only the neighbours' traces go through the sub-faces.
 #pragma unroll
-                for (int g = 0; g < NF; g++) { Fl[g] = 0; Hl[g] = 0; Jl[g] = 0; }
+                for (int g = 0; g < NF; g++) {
+                    Fl[g] = (T)0.5 * qs * tq[g] - sigma * tu[g];
+                    Hl[g] = (T)0.5 * tu[g];
+                }
+                if constexpr (FULL) {
+                    // own tangential derivatives (in face coordinates)
+                    T t0[NF];
+#pragma unroll
+                    for (int tau = 0; tau < DIM - 1; tau++) {
+                        const int t = tang_dir(k, tau);
+                        const T co = ns * a.Dx[off_slot(k, t)] * ih[t];
+                        face_line<T, DIM, M>(R.D1, tau, tu, t0);
+#pragma unroll
+                        for (int g = 0; g < NF; g++) Fl[g] += co * t0[g];
+                    }
+                }
                 auto sub_face = [&](int sub) {
                     const int p0 = sub & 1, p1 = sub >> 1;
-                    T ou[NF], oq[NF], nu[NF], nq[NF], F[NF], H[NF], lf[NF], lh[NF];
-                    tang_apply<T, DIM, M>(R.Isub, p0, p1, tu, ou);
-                    tang_apply<T, DIM, M>(R.Isub, p0, p1, tq, oq);
+                    T nu[NF], nq[NF], G[NF], lg[NF];
                     const uint32_t fe = buf_ld<uint32_t>(buf_of(L.fine, (uint32_t)NFACE * (uint32_t)L.cap * NS * 4u),
                                                          (uint32_t)(j * NS + sub) * 4u,
                                                          (uint32_t)f * (uint32_t)L.cap * NS * 4u);
                     neighbour_trace<T, DIM, P>(a, L, ru, fe, k, 1 - s, nu, nq);
 #pragma unroll
-                    for (int g = 0; g < NF; g++) {
-                        const T jmp = ou[g] - nu[g];
-                        F[g] = (T)0.5 * (qs * oq[g] + qn * nq[g]) - sigma * jmp;
-                        H[g] = (T)0.5 * jmp;
-                    }
+                    for (int g = 0; g < NF; g++) G[g] = (T)0.5 * qn * nq[g] + sigma * nu[g];
                     if constexpr (FULL) {
-                        // tangential derivatives on the sub-face (h_t / 2):
-                        // the mean of both sides into F; the jump is lifted
-                        // to the face and differentiated there (below)
-                        T sm[NF], t0[NF];
-#pragma unroll
-                        for (int g = 0; g < NF; g++) sm[g] = ou[g] + nu[g];
+                        // the neighbour's tangential derivatives on the
+                        // sub-face (extent h_t / 2)
+                        T t0[NF];
 #pragma unroll
                         for (int tau = 0; tau < DIM - 1; tau++) {
                             const int t = tang_dir(k, tau);
                             const T cf = (T)2 * ns * a.Dx[off_slot(k, t)] * ih[t];
-                            face_line<T, DIM, M>(R.D1, tau, sm, t0);
+                            face_line<T, DIM, M>(R.D1, tau, nu, t0);
 #pragma unroll
-                            for (int g = 0; g < NF; g++) F[g] += cf * t0[g];
+                            for (int g = 0; g < NF; g++) G[g] += cf * t0[g];
                         }
-                        T lj[NF];
-                        tang_apply<T, DIM, M>(R.Lsub, p0, p1, H, lj);
-#pragma unroll
-                        for (int g = 0; g < NF; g++) Jl[g] += lj[g];
                     }
-                    tang_apply<T, DIM, M>(R.Lsub, p0, p1, F, lf);
-                    tang_apply<T, DIM, M>(R.Lsub, p0, p1, H, lh);
+                    tang_apply<T, DIM, M>(R.Lsub, p0, p1, G, lg);
 #pragma unroll
-                    for (int g = 0; g < NF; g++) { Fl[g] += lf[g]; Hl[g] += lh[g]; }
+                    for (int g = 0; g < NF; g++) { Fl[g] += lg[g]; G[g] = (T)-0.5 * nu[g]; }
+                    tang_apply<T, DIM, M>(R.Lsub, p0, p1, G, lg);
+#pragma unroll
+                    for (int g = 0; g < NF; g++) Hl[g] += lg[g];
                 };
                 if constexpr (NP <= 16) {
 #pragma unroll
@@ -752,13 +760,14 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
                     for (int sub = 0; sub < NS; sub++) sub_face(sub);
                 }
                 if constexpr (FULL) {
-                    // n.D grad l_i along the face against the lifted jumps
+                    // n.D grad l_i along the face against the lifted half
+                    // jumps (Hl before its scaling)
                     T t1[NF];
 #pragma unroll
                     for (int tau = 0; tau < DIM - 1; tau++) {
                         const int t = tang_dir(k, tau);
                         const T cj = (T)2 * ns * a.Dx[off_slot(k, t)] * ih[t];
-                        face_line<T, DIM, M>(R.W1, tau, Jl, t1);
+                        face_line<T, DIM, M>(R.W1, tau, Hl, t1);
 #pragma unroll
                         for (int g = 0; g < NF; g++) Fl[g] += cj * t1[g];
                     }
@@ -898,20 +907,24 @@ struct BatchClock {
     long long n_bar;  // barriers since t_start
 };
 
-// Substep i of the barrier interval for every tile of the list.  With a
-// grid smaller than the tile count each block walks the tiles of its XCD's
-// contiguous range (persistent form).
+// Substep i of the barrier interval for every tile of the list, one tile
+// per block.  Blocks are dealt round-robin to the 8 XCDs; block b takes tile
+// b/8 of XCD b%8's contiguous range, so that neighbour gathers stay in one
+// XCD's L2.  (A persistent form, blocks walking several tiles, held about 45
+// more VGPRs live across its loop and was never the fastest shape.)
 template <int DIM, int P, typename T, bool FULL>
 __global__ __launch_bounds__(256) void k_substep_batch(const BatchSim<T> *__restrict__ sims,
                                                        const BatchTile *__restrict__ tiles, int n_tiles, int i,
                                                        char *base, const BatchClock *__restrict__ clk,
                                                        BatchClock *__restrict__ clk_next)
 {
-    const int x = blockIdx.x & 7, per = (int)(gridDim.x >> 3);
+    const int x = blockIdx.x & 7;
     const int q = n_tiles >> 3, r = n_tiles & 7;
     const int t0 = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
     const int t1 = t0 + q + (x < r ? 1 : 0);
-    for (int t = t0 + (int)(blockIdx.x >> 3); t < t1; t += per) {
+    const int t = t0 + (int)(blockIdx.x >> 3);
+    if (t >= t1) return;
+    {
         // everything the first loads need comes with the tile, read as one
         // 64-byte value (a single scalar load)
         typedef int TileWords __attribute__((ext_vector_type(16)));
@@ -923,7 +936,7 @@ __global__ __launch_bounds__(256) void k_substep_batch(const BatchSim<T> *__rest
         const bool advance = i == 0 && tl.start == 0 && threadIdx.x == 0;
         if ((int)threadIdx.x >= tl.count) {
             if (advance) clk_next[tl.sim] = BatchClock{ck.n_bar + 1};
-            continue;
+            return;
         }
         const BatchSim<T> &d = sims[tl.sim];
         StepLaunch<T> L;

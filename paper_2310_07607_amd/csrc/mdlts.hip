@@ -1231,7 +1231,7 @@ struct BatchPlan {
     std::vector<uint64_t> versions;
     int lmax_all = 0;
     int block = 256;
-    int per_cu = 0;  // 0: one block per tile; k: persistent, k blocks per CU
+    int per_cu = 0;  // always 0: one block per tile (reported by the profiling call)
     bool tuned = false;
     std::vector<BatchGroup> groups;
     std::vector<uint64_t> dof_per_barrier;  // per simulation
@@ -1377,11 +1377,12 @@ mdlts_status build_plan_data(mdlts_ctx *c, BatchPlan &P)
     return MDLTS_OK;
 }
 
+// one block per tile: 8 times the largest XCD share (tiles are dealt to the
+// XCDs in contiguous ranges)
 int grid_of(const BatchPlan &P, int n_tiles)
 {
-    int grid = (n_tiles + 7) / 8 * 8;
-    if (P.per_cu > 0) grid = std::min(grid, P.per_cu * P.n_cu);
-    return std::max(grid, 8);
+    (void)P;
+    return std::max((n_tiles + 7) / 8 * 8, 8);
 }
 
 // one barrier interval reading clock copy `phase`: launches on the stream,
@@ -1501,7 +1502,7 @@ mdlts_status run_batch_barriers(mdlts_ctx *c, BatchPlan &P, int nb)
 }
 
 // Autotuner: the first barriers of a new plan are run with each candidate
-// launch shape (block size, one block per tile or persistent blocks), in
+// launch shape (block size; one block per tile), in
 // rounds over the candidates, and timed with events (one warm and one timed
 // barrier per candidate and round); the shape with the smallest time over
 // the rounds is kept.  Per-element arithmetic does not depend on the shape,
@@ -1509,7 +1510,7 @@ mdlts_status run_batch_barriers(mdlts_ctx *c, BatchPlan &P, int nb)
 mdlts_status autotune(mdlts_ctx *c, BatchPlan &P, int *remaining)
 {
     struct Cand { int block, per_cu; };
-    const Cand cands[] = {{256, 0}, {128, 0}, {64, 0}, {256, 8}, {128, 16}};
+    const Cand cands[] = {{256, 0}, {128, 0}, {64, 0}};
     constexpr int n_cand = (int)(sizeof(cands) / sizeof(cands[0]));
     constexpr int rounds = 2;
     if (*remaining < n_cand * rounds * 2) return MDLTS_OK;

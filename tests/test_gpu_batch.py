@@ -63,7 +63,7 @@ def test_batch_equals_alone_bitwise(ctx, graphs):
         o, g, dt, L, u, v = _make(ctx, case, 10 + k)
         sims.append(g)
         dts.append(dt)
-    ctx.batch_step(sims, 23)          # the autotuner uses the first 20 barriers
+    ctx.batch_step(sims, 23)          # the autotuner uses the first 12 barriers
     for k, g in enumerate(sims):
         mixed.append(g.get_state())
         assert np.array_equal(mixed[k][0], alone[k][0]), k
