@@ -575,6 +575,7 @@ struct mdlts_ctx {
     struct Tuned {
         int block, per_cu;
         double dof;  // DoF-updates per barrier of the plan it was tuned on
+        bool single_graph;
     };
     std::map<int, Tuned> tuned;  // mask -> launch shape
 };
@@ -1240,6 +1241,13 @@ struct BatchPlan {
     int phase = 0;                          // clock copy the next barrier reads
     hipGraph_t graph[2] = {nullptr, nullptr};  // one barrier, per phase
     hipGraphExec_t exec[2] = {nullptr, nullptr};
+    // the graphs' kernel nodes in emission order and their keys (substep,
+    // kernel variant); a plan whose launches have the same keys updates the
+    // nodes' parameters instead of building new graphs
+    std::vector<hipGraphNode_t> nodes[2];
+    std::vector<long long> topo;
+    bool graph_valid = false;  // the graphs hold this plan's current launches
+    bool single_graph = false;  // a one-variant plan replays graphs (tuned)
     int n_cu = 256;
     // optional event timing of every batched substep launch
     bool prof = false;
@@ -1251,14 +1259,36 @@ struct BatchPlan {
 
 namespace {
 
-void free_graph(BatchPlan *P)
+void destroy_graph(BatchPlan *P)
 {
     for (int k = 0; k < 2; k++) {
         if (P->exec[k]) (void)hipGraphExecDestroy(P->exec[k]);
         if (P->graph[k]) (void)hipGraphDestroy(P->graph[k]);
         P->exec[k] = nullptr;
         P->graph[k] = nullptr;
+        P->nodes[k].clear();
     }
+    P->topo.clear();
+    P->graph_valid = false;
+}
+
+// the plan's launches changed: its graphs must be updated or rebuilt before
+// the next replay
+void free_graph(BatchPlan *P) { P->graph_valid = false; }
+
+// hands the graphs of `from` (a plan being replaced) to `to`, for reuse
+void adopt_graph(BatchPlan *to, BatchPlan *from)
+{
+    if (!from || !to) return;
+    for (int k = 0; k < 2; k++) {
+        to->graph[k] = from->graph[k];
+        to->exec[k] = from->exec[k];
+        to->nodes[k].swap(from->nodes[k]);
+        from->graph[k] = nullptr;
+        from->exec[k] = nullptr;
+    }
+    to->topo.swap(from->topo);
+    to->graph_valid = false;
 }
 
 // frees a plan (the context's batch plan or a simulation's step plan)
@@ -1267,7 +1297,7 @@ void free_plan(mdlts_ctx *c, BatchPlan *&slot)
     BatchPlan *P = slot;
     if (!P) return;
     (void)hipStreamSynchronize(c->stream);
-    free_graph(P);
+    destroy_graph(P);
     for (auto &g : P->groups) {
         dev_free(c, g.descs);
         dev_free(c, g.tiles);
@@ -1388,22 +1418,34 @@ int grid_of(const BatchPlan &P, int n_tiles)
 // one barrier interval reading clock copy `phase`: launches on the stream,
 // or kernel nodes of a graph (the launches of one substep, one per kernel
 // variant, depend on all launches of the previous substep, not on each other)
-mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, int phase, hipGraph_t graph)
+enum EmitMode { kEmitLaunch, kEmitGraph, kEmitUpdate, kEmitKeys };
+
+mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, int phase, hipGraph_t graph, EmitMode mode = kEmitLaunch,
+                          std::vector<long long> *keys = nullptr)
 {
+    if (graph) mode = kEmitGraph;
     const long long nsub = 1ll << P.lmax_all;
     std::vector<hipGraphNode_t> prev, cur;
-    auto add = [&](void *fn, int grid, int block, void **args) -> mdlts_status {
-        if (graph) {
-            hipKernelNodeParams kp{};
-            kp.func = fn;
-            kp.gridDim = dim3(grid);
-            kp.blockDim = dim3(block);
-            kp.sharedMemBytes = 0;
-            kp.kernelParams = args;
-            kp.extra = nullptr;
+    size_t n_node = 0;
+    auto add = [&](long long key, void *fn, int grid, int block, void **args) -> mdlts_status {
+        hipKernelNodeParams kp{};
+        kp.func = fn;
+        kp.gridDim = dim3(grid);
+        kp.blockDim = dim3(block);
+        kp.sharedMemBytes = 0;
+        kp.kernelParams = args;
+        kp.extra = nullptr;
+        if (mode == kEmitGraph) {
             hipGraphNode_t node;
             HIP_TRY(hipGraphAddKernelNode(&node, graph, prev.empty() ? nullptr : prev.data(), prev.size(), &kp));
             cur.push_back(node);
+            P.nodes[phase].push_back(node);
+            if (keys) keys->push_back(key);
+        } else if (mode == kEmitUpdate) {
+            if (n_node >= P.nodes[phase].size()) return MDLTS_EINVAL;
+            HIP_TRY(hipGraphExecKernelNodeSetParams(P.exec[phase], P.nodes[phase][n_node++], &kp));
+        } else if (mode == kEmitKeys) {
+            keys->push_back(key);
         } else {
             HIP_TRY(hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, c->stream));
         }
@@ -1422,7 +1464,7 @@ mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, int phase, hipGraph_t grap
             const BatchClock *ck = static_cast<const BatchClock *>(G.clocks.p) + (size_t)phase * nm;
             BatchClock *ck_next = static_cast<BatchClock *>(G.clocks.p) + (size_t)(phase ^ 1) * nm;
             void *args[] = {&descs, &tl, &n_t, &ii, &base, &ck, &ck_next};
-            const bool prof = P.prof && !graph;
+            const bool prof = P.prof && mode == kEmitLaunch;
             if (prof) {
                 while (P.ev.size() < 2 * (P.ev_used + 1)) {
                     hipEvent_t e;
@@ -1431,7 +1473,9 @@ mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, int phase, hipGraph_t grap
                 }
                 HIP_TRY(hipEventRecord(P.ev[2 * P.ev_used], c->stream));
             }
-            MD_TRY(add(batch_kernel(G.dim, G.order, G.prec, G.full), grid_of(P, n_t), P.block, args));
+            const long long key = i * 64 + 12 * (G.full ? 1 : 0) + 6 * (G.dim - 2) + 2 * (G.order - 1) +
+                                  (G.prec == MDLTS_FP32 ? 1 : 0);
+            MD_TRY(add(key, batch_kernel(G.dim, G.order, G.prec, G.full), grid_of(P, n_t), P.block, args));
             if (prof) {
                 HIP_TRY(hipEventRecord(P.ev[2 * P.ev_used + 1], c->stream));
                 P.ev_used++;
@@ -1443,14 +1487,31 @@ mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, int phase, hipGraph_t grap
     return MDLTS_OK;
 }
 
+// The graphs of the plan's current launches: the nodes of graphs already
+// built for the same keys get the new parameters (grids, blocks, tile lists,
+// clocks); otherwise the graphs are built anew.
 mdlts_status build_graph(mdlts_ctx *c, BatchPlan &P)
 {
-    free_graph(&P);
+    if (P.exec[0] && P.exec[1]) {
+        std::vector<long long> keys;
+        MD_TRY(emit_barrier(c, P, 0, nullptr, kEmitKeys, &keys));
+        if (keys == P.topo && P.nodes[0].size() == keys.size() && P.nodes[1].size() == keys.size()) {
+            // no replay of these graphs may be in flight while they change
+            HIP_TRY(hipStreamSynchronize(c->stream));
+            for (int k = 0; k < 2; k++) MD_TRY(emit_barrier(c, P, k, nullptr, kEmitUpdate));
+            P.graph_valid = true;
+            return MDLTS_OK;
+        }
+    }
+    destroy_graph(&P);
     for (int k = 0; k < 2; k++) {
         HIP_TRY(hipGraphCreate(&P.graph[k], 0));
-        MD_TRY(emit_barrier(c, P, k, P.graph[k]));
+        std::vector<long long> keys;
+        MD_TRY(emit_barrier(c, P, k, P.graph[k], kEmitGraph, &keys));
         HIP_TRY(hipGraphInstantiate(&P.exec[k], P.graph[k], nullptr, nullptr, 0));
+        if (k == 0) P.topo = keys;
     }
+    P.graph_valid = true;
     return MDLTS_OK;
 }
 
@@ -1490,8 +1551,12 @@ mdlts_status run_batch_barriers(mdlts_ctx *c, BatchPlan &P, int nb)
         if (P.prof) {
             if (P.ev_used + P.groups.size() * (1u << P.lmax_all) > kMaxEventPairs) MD_TRY(drain_batch_events(P));
             MD_TRY(emit_barrier(c, P, P.phase, nullptr));
-        } else if (c->use_graphs) {
-            if (!P.exec[0]) MD_TRY(build_graph(c, P));
+        } else if (c->use_graphs && (P.groups.size() > 1 || P.single_graph)) {
+            // the launches of a substep's kernel variants run concurrently
+            // as independent graph nodes; a plan of one variant (a chain of
+            // dependent launches) replays a graph only if the autotuner
+            // found it faster than direct launches
+            if (!P.graph_valid) MD_TRY(build_graph(c, P));
             HIP_TRY(hipGraphLaunch(P.exec[P.phase], c->stream));
         } else {
             MD_TRY(emit_barrier(c, P, P.phase, nullptr));
@@ -1502,11 +1567,12 @@ mdlts_status run_batch_barriers(mdlts_ctx *c, BatchPlan &P, int nb)
 }
 
 // Autotuner: the first barriers of a new plan are run with each candidate
-// launch shape (block size; one block per tile), in
-// rounds over the candidates, and timed with events (one warm and one timed
-// barrier per candidate and round); the shape with the smallest time over
-// the rounds is kept.  Per-element arithmetic does not depend on the shape,
-// so results are unchanged.
+// launch shape (block size; one block per tile), in rounds over the
+// candidates, and timed with events (one warm and one timed barrier per
+// candidate and round); the shape with the smallest time over the rounds is
+// kept.  A one-variant plan then times graph replay of that shape against
+// its direct launches.  Per-element arithmetic does not depend on the
+// choice, so results are unchanged.
 mdlts_status autotune(mdlts_ctx *c, BatchPlan &P, int *remaining)
 {
     struct Cand { int block, per_cu; };
@@ -1538,18 +1604,41 @@ mdlts_status autotune(mdlts_ctx *c, BatchPlan &P, int *remaining)
             best[k] = std::min(best[k], ms);
             *remaining -= 2;
         }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     int pick = 0;
     for (int k = 1; k < n_cand; k++)
         if (best[k] < best[pick]) pick = k;
-    P.prof = saved_prof;
     P.block = cands[pick].block;
     P.per_cu = cands[pick].per_cu;
+    // one kernel variant: graph replay against direct launches of the
+    // chosen shape (long chains of short launches favour the graph, a few
+    // longer ones the direct launches, which also need no graph update)
+    P.single_graph = false;
+    if (c->use_graphs && P.groups.size() == 1 && *remaining >= 2 * rounds) {
+        MD_TRY(build_plan_data(c, P));
+        MD_TRY(build_graph(c, P));
+        float best_graph = 1e30f;
+        for (int rd = 0; rd < rounds; rd++) {
+            HIP_TRY(hipGraphLaunch(P.exec[P.phase], c->stream));  // warm
+            account_barriers(P, 1);
+            HIP_TRY(hipEventRecord(e0, c->stream));
+            HIP_TRY(hipGraphLaunch(P.exec[P.phase], c->stream));
+            account_barriers(P, 1);
+            HIP_TRY(hipEventRecord(e1, c->stream));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            best_graph = std::min(best_graph, ms);
+            *remaining -= 2;
+        }
+        P.single_graph = best_graph < best[pick];
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    P.prof = saved_prof;
     P.tuned = true;
     double dof = 0.0;
     for (uint64_t d : P.dof_per_barrier) dof += (double)d;
-    c->tuned[P.variant_mask] = {P.block, P.per_cu, dof};
+    c->tuned[P.variant_mask] = {P.block, P.per_cu, dof, P.single_graph};
     return build_plan_data(c, P);
 }
 
@@ -1570,9 +1659,12 @@ mdlts_status prepare_plan(mdlts_ctx *c, BatchPlan *&slot, mdlts_sim *const *sims
         if (moved) MD_TRY(build_plan_data(c, *P));
         return MDLTS_OK;
     }
-    free_plan(c, slot);
+    BatchPlan *old = slot;
     P = new (std::nothrow) BatchPlan;
     if (!P) return MDLTS_ENOMEM;
+    if (old) (void)hipStreamSynchronize(c->stream);
+    adopt_graph(P, old);  // the replaced plan's graphs, for a parameter update
+    free_plan(c, slot);
     slot = P;
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess) {
@@ -1620,6 +1712,7 @@ mdlts_status prepare_plan(mdlts_ctx *c, BatchPlan *&slot, mdlts_sim *const *sims
     if (tk != c->tuned.end() && std::fabs(dof - tk->second.dof) <= 0.25 * tk->second.dof) {
         P->block = tk->second.block;
         P->per_cu = tk->second.per_cu;
+        P->single_graph = tk->second.single_graph;
         P->tuned = true;
     }
     *fresh = true;
@@ -2161,8 +2254,8 @@ mdlts_status mdlts_step(mdlts_sim *s, int n_barriers)
         if (s->desc.precision == MDLTS_FP64) return run_barriers<double>(s, n_barriers);
         return run_barriers<float>(s, n_barriers);
     }
-    // a one-simulation plan: each barrier is one graph launch (or, while
-    // profiling, the same launches on the stream between events)
+    // a one-simulation plan of tile launches (one kernel variant: launched
+    // directly, see run_batch_barriers)
     bool fresh = false;
     MD_TRY(prepare_plan(c, s->solo, &s, 1, &fresh));
     BatchPlan &P = *s->solo;
