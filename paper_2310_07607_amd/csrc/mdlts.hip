@@ -578,6 +578,11 @@ struct mdlts_ctx {
         bool single_graph;
     };
     std::map<int, Tuned> tuned;  // mask -> launch shape
+    // pinned host staging of plan and constant uploads (copies from it are
+    // asynchronous); stage_done follows the last copies out of it
+    void *stage = nullptr;
+    size_t stage_bytes = 0;
+    hipEvent_t stage_done = nullptr;
 };
 
 // Host-visible staging of a simulation's small readbacks (pinned memory, so
@@ -681,6 +686,38 @@ mdlts_status dev_alloc(mdlts_ctx *c, DevBuf &b, size_t bytes)
     if (!p) return MDLTS_ENOMEM;
     b.p = p;
     b.bytes = bytes;
+    return MDLTS_OK;
+}
+
+// The context's pinned staging area, at least `bytes` long, once the copies
+// out of it that were queued before have completed.
+mdlts_status stage_acquire(mdlts_ctx *c, size_t bytes, char **out)
+{
+    if (c->stage_done) {
+        HIP_TRY(hipEventSynchronize(c->stage_done));
+    } else {
+        HIP_TRY(hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming));
+    }
+    if (c->stage_bytes < bytes) {
+        if (c->stage) (void)hipHostFree(c->stage);
+        c->stage = nullptr;
+        c->stage_bytes = 0;
+        const size_t nb = std::max(bytes, (size_t)1 << 20);
+        if (hipHostMalloc(&c->stage, nb, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            c->stage = nullptr;
+            return MDLTS_ENOMEM;
+        }
+        c->stage_bytes = nb;
+    }
+    *out = static_cast<char *>(c->stage);
+    return MDLTS_OK;
+}
+
+// marks the staging area busy until the copies queued so far are done
+mdlts_status stage_release(mdlts_ctx *c)
+{
+    HIP_TRY(hipEventRecord(c->stage_done, c->stream));
     return MDLTS_OK;
 }
 
@@ -994,8 +1031,11 @@ mdlts_status upload_step_args(mdlts_sim *s)
     StepArgs<T> &a = *reinterpret_cast<StepArgs<T> *>(s->step_host.data());
     fill_step_args<T>(s, a);
     MD_TRY(dev_alloc(s->ctx, s->step_dev, sizeof(StepArgs<T>)));
-    HIP_TRY(hipMemcpyAsync(s->step_dev.p, &a, sizeof(StepArgs<T>), hipMemcpyHostToDevice, s->ctx->stream));
-    MD_TRY(sync(s->ctx));  // the host copy may change right after
+    char *st = nullptr;
+    MD_TRY(stage_acquire(s->ctx, sizeof(StepArgs<T>), &st));
+    std::memcpy(st, &a, sizeof(StepArgs<T>));
+    HIP_TRY(hipMemcpyAsync(s->step_dev.p, st, sizeof(StepArgs<T>), hipMemcpyHostToDevice, s->ctx->stream));
+    MD_TRY(stage_release(s->ctx));
     s->step_dirty = false;
     return MDLTS_OK;
 }
@@ -1220,7 +1260,13 @@ struct BatchGroup {
     int dim = 2, order = 1, prec = 0;
     bool full = false;  // off-diagonal diffusion tensors (their own kernels)
     std::vector<int> members;   // indices into BatchPlan::sims
-    DevBuf descs, tiles, clocks;  // clocks: [2][members] BatchClock
+    // one device buffer: descriptors [members] BatchSim, clocks [2][members]
+    // BatchClock, tiles [2 phases][n_tiles] BatchTile (one upload)
+    DevBuf data;
+    size_t off_clocks = 0, off_tiles = 0;
+    void *descs() const { return data.p; }
+    BatchClock *clocks() const { return reinterpret_cast<BatchClock *>(static_cast<char *>(data.p) + off_clocks); }
+    BatchTile *tiles() const { return reinterpret_cast<BatchTile *>(static_cast<char *>(data.p) + off_tiles); }
     std::vector<BatchClock> hclk;  // host source of the clock uploads
     std::vector<int> tile_off;  // [2^lmax_all + 1] offsets into tiles per substep
     int n_tiles = 0;            // tiles per barrier; the device list holds two copies (phases)
@@ -1247,8 +1293,8 @@ struct BatchPlan {
     std::vector<hipGraphNode_t> nodes[2];
     std::vector<long long> topo;
     bool graph_valid = false;  // the graphs hold this plan's current launches
+    bool graph_busy = false;   // a replay may be in flight (not synchronised since)
     bool single_graph = false;  // a one-variant plan replays graphs (tuned)
-    int n_cu = 256;
     // optional event timing of every batched substep launch
     bool prof = false;
     std::vector<hipEvent_t> ev;
@@ -1289,19 +1335,21 @@ void adopt_graph(BatchPlan *to, BatchPlan *from)
     }
     to->topo.swap(from->topo);
     to->graph_valid = false;
+    to->graph_busy = from->graph_busy;
 }
 
 // frees a plan (the context's batch plan or a simulation's step plan)
-void free_plan(mdlts_ctx *c, BatchPlan *&slot)
+// (sync_first = false: the plan's graphs have been handed over and its
+// buffers are freed in stream order: through the allocator, or by hipFree,
+// which waits for the device)
+void free_plan(mdlts_ctx *c, BatchPlan *&slot, bool sync_first = true)
 {
     BatchPlan *P = slot;
     if (!P) return;
-    (void)hipStreamSynchronize(c->stream);
+    if (sync_first) (void)hipStreamSynchronize(c->stream);
     destroy_graph(P);
     for (auto &g : P->groups) {
-        dev_free(c, g.descs);
-        dev_free(c, g.tiles);
-        dev_free(c, g.clocks);
+        dev_free(c, g.data);
     }
     for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
     delete P;
@@ -1313,26 +1361,11 @@ void *batch_kernel(int dim, int order, int prec, bool full)
     return substep_kernel_of(kFormBatch, dim, order, prec == MDLTS_FP32, full);
 }
 
-// both clock copies from the host's barrier counts (the next barrier reads
-// copy 0)
-mdlts_status upload_clocks(mdlts_ctx *c, BatchPlan &P, BatchGroup &G)
-{
-    const size_t nm = G.members.size();
-    G.hclk.resize(2 * nm);
-    for (size_t q = 0; q < nm; q++) {
-        const mdlts_sim *s = P.sims[G.members[q]];
-        G.hclk[q] = G.hclk[nm + q] = BatchClock{s->n_bar};
-    }
-    HIP_TRY(hipMemcpyAsync(G.clocks.p, G.hclk.data(), 2 * nm * sizeof(BatchClock), hipMemcpyHostToDevice, c->stream));
-    return MDLTS_OK;
-}
 
 template <typename T>
 mdlts_status fill_group(mdlts_ctx *c, BatchPlan &P, BatchGroup &G)
 {
     const int nm = (int)G.members.size();
-    MD_TRY(dev_alloc(c, G.descs, (size_t)nm * sizeof(BatchSim<T>)));
-    G.base = static_cast<char *>(G.descs.p);
     std::vector<BatchSim<T>> d(nm);
     for (int q = 0; q < nm; q++) {
         mdlts_sim *s = P.sims[G.members[q]];
@@ -1353,12 +1386,12 @@ mdlts_status fill_group(mdlts_ctx *c, BatchPlan &P, BatchGroup &G)
             int v2 = 0;
             while (i > 0 && ((i >> v2) & 1) == 0) v2++;
             const int lmin = i == 0 ? 0 : s->lmax - v2;
-            BatchTile tt{};
-            tt.off_u = static_cast<char *>(s->u_s.p) - G.base;
-            tt.off_v = static_cast<char *>(s->v_s.p) - G.base;
-            tt.off_key = static_cast<char *>(s->key_s.p) - G.base;
-            tt.off_nbr = static_cast<char *>(s->nbr_s.p) - G.base;
-            tt.off_fine = static_cast<char *>(s->fine_s.p) - G.base;
+            BatchTile tt{};  // array addresses here; offsets from the base below
+            tt.off_u = (long long)(uintptr_t)s->u_s.p;
+            tt.off_v = (long long)(uintptr_t)s->v_s.p;
+            tt.off_key = (long long)(uintptr_t)s->key_s.p;
+            tt.off_nbr = (long long)(uintptr_t)s->nbr_s.p;
+            tt.off_fine = (long long)(uintptr_t)s->fine_s.p;
             tt.sim = q;
             tt.node_bytes = (uint32_t)((size_t)s->cap * sizeof(T));
             tt.slot_bytes = (uint32_t)((size_t)s->np * s->cap * sizeof(T));
@@ -1385,14 +1418,32 @@ mdlts_status fill_group(mdlts_ctx *c, BatchPlan &P, BatchGroup &G)
         tt.packed ^= 1 << 4;
         tiles.push_back(tt);
     }
-    MD_TRY(dev_alloc(c, G.tiles, std::max<size_t>(1, tiles.size()) * sizeof(BatchTile)));
-    HIP_TRY(hipMemcpyAsync(G.descs.p, d.data(), (size_t)nm * sizeof(BatchSim<T>), hipMemcpyHostToDevice, c->stream));
-    MD_TRY(dev_alloc(c, G.clocks, 2 * (size_t)nm * sizeof(BatchClock)));
-    MD_TRY(upload_clocks(c, P, G));
-    if (!tiles.empty())
-        HIP_TRY(hipMemcpyAsync(G.tiles.p, tiles.data(), tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice,
-                               c->stream));
-    return sync(c);  // host vectors die here
+    G.hclk.resize(2 * (size_t)nm);
+    for (int q = 0; q < nm; q++) G.hclk[q] = G.hclk[nm + q] = BatchClock{P.sims[G.members[q]]->n_bar};
+    // descriptors, clocks and tiles in one buffer, uploaded in one copy
+    // through the pinned staging area
+    const size_t b_d = (size_t)nm * sizeof(BatchSim<T>), b_c = 2 * (size_t)nm * sizeof(BatchClock);
+    const size_t b_t = tiles.size() * sizeof(BatchTile);
+    G.off_clocks = (b_d + 255) / 256 * 256;
+    G.off_tiles = G.off_clocks + (b_c + 255) / 256 * 256;
+    const size_t total = G.off_tiles + std::max<size_t>(b_t, sizeof(BatchTile));
+    MD_TRY(dev_alloc(c, G.data, total));
+    G.base = static_cast<char *>(G.data.p);
+    const long long base = (long long)(uintptr_t)G.base;
+    for (BatchTile &tt : tiles) {
+        tt.off_u -= base;
+        tt.off_v -= base;
+        tt.off_key -= base;
+        tt.off_nbr -= base;
+        tt.off_fine -= base;
+    }
+    char *st = nullptr;
+    MD_TRY(stage_acquire(c, total, &st));
+    std::memcpy(st, d.data(), b_d);
+    std::memcpy(st + G.off_clocks, G.hclk.data(), b_c);
+    if (b_t) std::memcpy(st + G.off_tiles, tiles.data(), b_t);
+    HIP_TRY(hipMemcpyAsync(G.data.p, st, G.off_tiles + b_t, hipMemcpyHostToDevice, c->stream));
+    return stage_release(c);
 }
 
 // (re)build descriptors and tile lists for the current launch shape
@@ -1456,13 +1507,13 @@ mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, int phase, hipGraph_t grap
         for (auto &G : P.groups) {
             int n_t = G.tile_off[i + 1] - G.tile_off[i];
             if (n_t == 0) continue;
-            const void *descs = G.descs.p;
-            const BatchTile *tl = static_cast<const BatchTile *>(G.tiles.p) + (size_t)phase * G.n_tiles + G.tile_off[i];
+            const void *descs = G.descs();
+            const BatchTile *tl = G.tiles() + (size_t)phase * G.n_tiles + G.tile_off[i];
             int ii = (int)i;
             char *base = G.base;
             const int nm = (int)G.members.size();
-            const BatchClock *ck = static_cast<const BatchClock *>(G.clocks.p) + (size_t)phase * nm;
-            BatchClock *ck_next = static_cast<BatchClock *>(G.clocks.p) + (size_t)(phase ^ 1) * nm;
+            const BatchClock *ck = G.clocks() + (size_t)phase * nm;
+            BatchClock *ck_next = G.clocks() + (size_t)(phase ^ 1) * nm;
             void *args[] = {&descs, &tl, &n_t, &ii, &base, &ck, &ck_next};
             const bool prof = P.prof && mode == kEmitLaunch;
             if (prof) {
@@ -1497,7 +1548,8 @@ mdlts_status build_graph(mdlts_ctx *c, BatchPlan &P)
         MD_TRY(emit_barrier(c, P, 0, nullptr, kEmitKeys, &keys));
         if (keys == P.topo && P.nodes[0].size() == keys.size() && P.nodes[1].size() == keys.size()) {
             // no replay of these graphs may be in flight while they change
-            HIP_TRY(hipStreamSynchronize(c->stream));
+            if (P.graph_busy) HIP_TRY(hipStreamSynchronize(c->stream));
+            P.graph_busy = false;
             for (int k = 0; k < 2; k++) MD_TRY(emit_barrier(c, P, k, nullptr, kEmitUpdate));
             P.graph_valid = true;
             return MDLTS_OK;
@@ -1558,6 +1610,7 @@ mdlts_status run_batch_barriers(mdlts_ctx *c, BatchPlan &P, int nb)
             // found it faster than direct launches
             if (!P.graph_valid) MD_TRY(build_graph(c, P));
             HIP_TRY(hipGraphLaunch(P.exec[P.phase], c->stream));
+            P.graph_busy = true;
         } else {
             MD_TRY(emit_barrier(c, P, P.phase, nullptr));
         }
@@ -1610,27 +1663,35 @@ mdlts_status autotune(mdlts_ctx *c, BatchPlan &P, int *remaining)
     P.block = cands[pick].block;
     P.per_cu = cands[pick].per_cu;
     // one kernel variant: graph replay against direct launches of the
-    // chosen shape (long chains of short launches favour the graph, a few
-    // longer ones the direct launches, which also need no graph update)
+    // chosen shape, each over a run of barriers (the host runs ahead of the
+    // device in both; long chains of short launches favour the graph, a
+    // few longer ones the direct launches, whose host cost is lower)
     P.single_graph = false;
-    if (c->use_graphs && P.groups.size() == 1 && *remaining >= 2 * rounds) {
+    constexpr int run = 3;
+    if (c->use_graphs && P.groups.size() == 1 && *remaining >= 2 * (run + 1)) {
         MD_TRY(build_plan_data(c, P));
-        MD_TRY(build_graph(c, P));
-        float best_graph = 1e30f;
-        for (int rd = 0; rd < rounds; rd++) {
-            HIP_TRY(hipGraphLaunch(P.exec[P.phase], c->stream));  // warm
-            account_barriers(P, 1);
-            HIP_TRY(hipEventRecord(e0, c->stream));
-            HIP_TRY(hipGraphLaunch(P.exec[P.phase], c->stream));
-            account_barriers(P, 1);
+        float t_direct = 0.f, t_graph = 0.f;
+        for (int mode = 0; mode < 2; mode++) {
+            if (mode == 1) MD_TRY(build_graph(c, P));
+            for (int b = 0; b <= run; b++) {
+                if (b == 1) HIP_TRY(hipEventRecord(e0, c->stream));  // after one warm barrier
+                if (mode == 1) {
+                    HIP_TRY(hipGraphLaunch(P.exec[P.phase], c->stream));
+                    P.graph_busy = true;
+                } else {
+                    MD_TRY(emit_barrier(c, P, P.phase, nullptr));
+                }
+                account_barriers(P, 1);
+            }
             HIP_TRY(hipEventRecord(e1, c->stream));
             HIP_TRY(hipEventSynchronize(e1));
+            P.graph_busy = false;
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-            best_graph = std::min(best_graph, ms);
-            *remaining -= 2;
+            (mode == 1 ? t_graph : t_direct) = ms;
+            *remaining -= run + 1;
         }
-        P.single_graph = best_graph < best[pick];
+        P.single_graph = t_graph < t_direct;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1659,23 +1720,19 @@ mdlts_status prepare_plan(mdlts_ctx *c, BatchPlan *&slot, mdlts_sim *const *sims
         if (moved) MD_TRY(build_plan_data(c, *P));
         return MDLTS_OK;
     }
-    BatchPlan *old = slot;
+    // the replaced plan is freed on every way out, after its graphs and
+    // device buffers have been handed over
+    struct OldPlan {
+        mdlts_ctx *c;
+        BatchPlan *p;
+        ~OldPlan() { free_plan(c, p, false); }
+    } old{c, slot};
     P = new (std::nothrow) BatchPlan;
     if (!P) return MDLTS_ENOMEM;
-    if (old) (void)hipStreamSynchronize(c->stream);
-    adopt_graph(P, old);  // the replaced plan's graphs, for a parameter update
-    free_plan(c, slot);
+    adopt_graph(P, old.p);  // the replaced plan's graphs, for a parameter update
     slot = P;
-    int dev = 0;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        int ncu = 0;
-        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
-            P->n_cu = ncu;
-    }
     for (int q = 0; q < n; q++) {
-        mdlts_sim *s = sims[q];
-        if (s->step_dirty)
-            MD_TRY(s->desc.precision == MDLTS_FP64 ? upload_step_args<double>(s) : upload_step_args<float>(s));
+        mdlts_sim *s = sims[q];  // (its step constants travel in the plan's descriptors)
         P->sims.push_back(s);
         P->lmax_all = std::max(P->lmax_all, s->lmax);
         uint64_t dof = 0;
@@ -1701,6 +1758,15 @@ mdlts_status prepare_plan(mdlts_ctx *c, BatchPlan *&slot, mdlts_sim *const *sims
         P->groups[g].members.push_back(q);
     }
     for (int q = 0; q < n; q++) P->versions.push_back(sims[q]->version);
+    // groups of a kernel variant the replaced plan had take over its device
+    // buffers (descriptors, tiles, clocks): no allocator round trips
+    if (old.p)
+        for (BatchGroup &G : P->groups)
+            for (BatchGroup &O : old.p->groups)
+                if (O.dim == G.dim && O.order == G.order && O.prec == G.prec && O.full == G.full && O.data.p) {
+                    std::swap(G.data, O.data);
+                    break;
+                }
     for (const BatchGroup &g : P->groups)
         P->variant_mask |= 1 << (12 * (g.full ? 1 : 0) + 6 * (g.dim - 2) + 2 * (g.order - 1) + (g.prec == MDLTS_FP32 ? 1 : 0));
     // a mix of variants tuned before keeps its launch shape while the work
@@ -1765,6 +1831,9 @@ mdlts_status mdlts_ctx_destroy(mdlts_ctx *ctx)
     if (!ctx) return MDLTS_EINVAL;
     if (ctx->n_sims > 0) return MDLTS_EBUSY;
     free_plan(ctx, ctx->batch);
+    if (ctx->stage_done) (void)hipEventSynchronize(ctx->stage_done);
+    if (ctx->stage) (void)hipHostFree(ctx->stage);
+    if (ctx->stage_done) (void)hipEventDestroy(ctx->stage_done);
     delete ctx;
     return MDLTS_OK;
 }
