@@ -341,7 +341,7 @@ def batched_leg(ctx, args):
     c1 = [s.counters()[0] for s in sims]
     dof = sum(b - a for a, b in zip(c0, c1))
     bytes_alg = sum((b - a) * bytes_per_dof(w["dim"], w["p"]) for a, b, w in zip(c0, c1, specs))
-    # kernel timing: HIP events around graph-replayed barriers (only substep
+    # kernel timing: HIP events around the batch's barriers (only substep
     # launches run between them); launches per barrier: one per kernel
     # variant and substep of the longest schedule in that variant
     ctx.batch_profile(True)
@@ -374,7 +374,7 @@ def batched_leg(ctx, args):
            "value": dof / wall, "unit": "DoF-updates/s", "barriers": args.batched_barriers,
            "ms_per_barrier": wall / args.batched_barriers * 1e3,
            "with_adaptation": {"value": (a1 - a0) / w_int, "interval_ms": w_int * 1e3, "barriers": every},
-           "launch_shape": {"block": blk, "persistent_blocks_per_cu": pcu},
+           "launch_shape": {"block": blk, "blocks": "one per tile"},
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                         "traffic_unit": "HBM bytes per launch",

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "host.hpp"
 
@@ -467,15 +468,26 @@ __device__ __forceinline__ void neighbour_interp(const StepLaunch<T> &L, __amdgp
 // arithmetic, so a wave waits for memory twice: their launches are short and
 // latency-bound.  Larger elements keep one face's neighbour in flight while
 // the previous face is computed, which leaves registers for more waves per
-// SIMD (measured: Q2 hexahedra 244 VGPRs and 2 waves instead of 1, Q1
-// hexahedra 125 and 4 instead of 2).  Faces with finer neighbours (rare, at
-// refinement interfaces) load their 2^(d-1) neighbours on demand.
+// SIMD (with the other register savings below: Q2 hexahedra 156 VGPRs and 3
+// waves per SIMD, against 258 and 1 with two faces in flight; Q1 hexahedra
+// 99 and 4).  Faces with finer neighbours (rare, at refinement interfaces)
+// load their 2^(d-1) neighbours on demand.
 // Large FP32 elements stage the gate v through LDS: its loads go straight
 // to LDS at the start (no registers held) and are read at the update.
 template <int DIM, int P, typename T>
 constexpr bool kGateInLds = Shape<DIM, P>::NP > 16 && sizeof(T) == 4;
-template <int DIM, int P, typename T>
-constexpr int kGateLdsWords = kGateInLds<DIM, P, T> ? 4 * Shape<DIM, P>::NP * 64 : 1;  // 4 waves per block
+
+// Dynamic LDS of a launch: the gate staging area of its waves (launches of
+// fewer than 4 waves per block take less, so more blocks fit on a CU).
+// Same condition as kGateInLds.
+inline size_t gate_lds_bytes(int dim, int p, bool fp32, int block)
+{
+    const int np = dim == 2 ? (p + 1) * (p + 1) : (p + 1) * (p + 1) * (p + 1);
+    return fp32 && np > 16 ? (size_t)(block / 64) * (size_t)np * 64 * sizeof(float) : 0;
+}
+
+// the dynamic LDS of every substep kernel (only the gate staging uses it)
+extern __shared__ float gate_dyn[];
 
 // FULL: the diffusion tensor has off-diagonal entries (separate kernels, so
 // that the diagonal case keeps its register budget)
@@ -593,8 +605,13 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
 #pragma unroll
         for (int f = 0; f < NB; f++) issue(f, nbuf[f]);
     }
-#pragma unroll
-    for (int k = 0; k < DIM; k++) {
+    // one call per face direction and side.  Degree 3 passes both as
+    // compile-time constants: its loop is too large to unroll, and run-time
+    // face indices would put the element arrays in scratch memory.  Lower
+    // degrees unroll a plain loop (measured a few per cent faster there).
+    auto face = [&](auto kc, auto sc) {
+        const int k = kc;
+        const int s = sc;
         const T c2 = (T)2 * ih[k];
         const T Dkk = a.Dk[k];
         const T pen = a.gamma * Dkk * ih[k];  // gamma D / h
@@ -608,8 +625,7 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
                 t++;
             }
         }
-#pragma unroll
-        for (int s = 0; s < 2; s++) {
+        {
             const int f = 2 * k + s;
             const uint32_t kind = ent[f] >> 30;
             if (kind != kBoundary) {
@@ -787,6 +803,24 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
             if constexpr (!kPrefetch)
                 if (f + NB < NFACE) issue(f + NB, nbuf[f % NB]);
         }
+    };
+    if constexpr (P >= 3) {
+        using I0 = std::integral_constant<int, 0>;
+        using I1 = std::integral_constant<int, 1>;
+        using I2 = std::integral_constant<int, 2>;
+        face(I0{}, I0{});
+        face(I0{}, I1{});
+        face(I1{}, I0{});
+        face(I1{}, I1{});
+        if constexpr (DIM == 3) {
+            face(I2{}, I0{});
+            face(I2{}, I1{});
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < DIM; k++)
+#pragma unroll
+            for (int s = 0; s < 2; s++) face(k, s);
     }
 
     // pointwise reaction, stimulus and update; the parameters are read
@@ -861,9 +895,15 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
     }
 }
 
+// FP32 Q2 hexahedra sit at the 168-VGPR limit of 3 waves per SIMD: hold
+// the compiler to it
+template <int DIM, int P, typename T, bool FULL>
+constexpr int kMinWaves = DIM == 3 && P == 2 && sizeof(T) == 4 && !FULL ? 3 : 1;
+
 // one simulation: element j of the active prefix [0, n_act)
 template <int DIM, int P, typename T, bool FULL>
-__global__ __launch_bounds__(256) void k_substep(const StepArgs<T> *__restrict__ cst, const StepLaunch<T> L)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<DIM, P, T, FULL>)))
+void k_substep(const StepArgs<T> *__restrict__ cst, const StepLaunch<T> L)
 {
     const int j = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (j >= L.n_act) return;
@@ -871,8 +911,7 @@ __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> *__restrict__
     int lv = 0;  // elements are grouped finest level first
 #pragma unroll
     for (int l = 1; l < kMaxLevels; l++) lv += (j < a.cnt_ge[l]) ? 1 : 0;
-    __shared__ float gate[kGateLdsWords<DIM, P, T>];
-    substep_element<DIM, P, T, FULL>(a, L, j, lv, gate);
+    substep_element<DIM, P, T, FULL>(a, L, j, lv, gate_dyn);
 }
 
 // ---- many simulations in one launch ------------------------------------------
@@ -913,7 +952,8 @@ struct BatchClock {
 // XCD's L2.  (A persistent form, blocks walking several tiles, held about 45
 // more VGPRs live across its loop and was never the fastest shape.)
 template <int DIM, int P, typename T, bool FULL>
-__global__ __launch_bounds__(256) void k_substep_batch(const BatchSim<T> *__restrict__ sims,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<DIM, P, T, FULL>)))
+void k_substep_batch(const BatchSim<T> *__restrict__ sims,
                                                        const BatchTile *__restrict__ tiles, int n_tiles, int i,
                                                        char *base, const BatchClock *__restrict__ clk,
                                                        BatchClock *__restrict__ clk_next)
@@ -954,8 +994,7 @@ __global__ __launch_bounds__(256) void k_substep_batch(const BatchSim<T> *__rest
         L.parity = (tl.packed >> 4) & 1;
         // t = t_start + n dt + i h, rounded like the host (no contraction)
         L.t_i = __dadd_rn(__dadd_rn(d.t_start, __dmul_rn((double)ck.n_bar, d.a.dt_bar)), __dmul_rn((double)i, d.h_tick));
-        __shared__ float gate[kGateLdsWords<DIM, P, T>];
-        substep_element<DIM, P, T, FULL>(d.a, L, tl.start + (int)threadIdx.x, tl.packed & 15, gate);
+        substep_element<DIM, P, T, FULL>(d.a, L, tl.start + (int)threadIdx.x, tl.packed & 15, gate_dyn);
         if (advance) clk_next[tl.sim] = BatchClock{ck.n_bar + 1};
     }
 }

@@ -635,6 +635,9 @@ struct mdlts_sim {
     int cap = 0;
     bool state_grouped = false;  // else canonical
     bool levels_valid = false;
+    // the current levels are the CFL levels of dt_bar (no forced level, no
+    // cell criterion); the value is set when an assignment completes
+    bool levels_plain = false, levels_plain_pending = false;
     std::vector<int32_t> cnt_ge;  // [n_levels]
     int lmax = 0;
     double dt_bar = 0.0;
@@ -971,7 +974,8 @@ mdlts_status launch_substep(const mdlts_sim *s, const StepArgs<T> *c, const Step
     if (!fn) return MDLTS_EINVAL;
     StepLaunch<T> Lv = L;
     void *args[] = {&c, &Lv};
-    HIP_TRY(hipLaunchKernel(fn, dim3(nblocks(L.n_act)), dim3(kBlock), args, 0, st));
+    const size_t lds = gate_lds_bytes(s->desc.dim, s->desc.order, sizeof(T) == 4, kBlock);
+    HIP_TRY(hipLaunchKernel(fn, dim3(nblocks(L.n_act)), dim3(kBlock), args, lds, st));
     return MDLTS_OK;
 }
 
@@ -1478,12 +1482,12 @@ mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, int phase, hipGraph_t grap
     const long long nsub = 1ll << P.lmax_all;
     std::vector<hipGraphNode_t> prev, cur;
     size_t n_node = 0;
-    auto add = [&](long long key, void *fn, int grid, int block, void **args) -> mdlts_status {
+    auto add = [&](long long key, void *fn, int grid, int block, size_t lds, void **args) -> mdlts_status {
         hipKernelNodeParams kp{};
         kp.func = fn;
         kp.gridDim = dim3(grid);
         kp.blockDim = dim3(block);
-        kp.sharedMemBytes = 0;
+        kp.sharedMemBytes = (unsigned int)lds;
         kp.kernelParams = args;
         kp.extra = nullptr;
         if (mode == kEmitGraph) {
@@ -1498,7 +1502,7 @@ mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, int phase, hipGraph_t grap
         } else if (mode == kEmitKeys) {
             keys->push_back(key);
         } else {
-            HIP_TRY(hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, c->stream));
+            HIP_TRY(hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, c->stream));
         }
         return MDLTS_OK;
     };
@@ -1526,7 +1530,8 @@ mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, int phase, hipGraph_t grap
             }
             const long long key = i * 64 + 12 * (G.full ? 1 : 0) + 6 * (G.dim - 2) + 2 * (G.order - 1) +
                                   (G.prec == MDLTS_FP32 ? 1 : 0);
-            MD_TRY(add(key, batch_kernel(G.dim, G.order, G.prec, G.full), grid_of(P, n_t), P.block, args));
+            MD_TRY(add(key, batch_kernel(G.dim, G.order, G.prec, G.full), grid_of(P, n_t), P.block,
+                       gate_lds_bytes(G.dim, G.order, G.prec == MDLTS_FP32, P.block), args));
             if (prof) {
                 HIP_TRY(hipEventRecord(P.ev[2 * P.ev_used + 1], c->stream));
                 P.ev_used++;
@@ -2073,6 +2078,7 @@ static mdlts_status levels_enqueue(mdlts_sim *s, double dt_barrier, int force_le
     if ((uint64_t)2 * s->np * (uint64_t)s->E * s->tsize > 0xffffffffull) return MDLTS_ENOMEM;
     s->version++;
     s->levels_valid = false;
+    s->levels_plain_pending = force_level < 0 && !eta_t;
     mdlts_ctx *c = s->ctx;
     const int E = (int)s->E;
     const int L = s->desc.n_levels;
@@ -2166,6 +2172,7 @@ static mdlts_status levels_finish(mdlts_sim *s, double dt_barrier, int32_t *leve
         s->dt_bar = dt_barrier;
     }
     s->levels_valid = true;
+    s->levels_plain = s->levels_plain_pending;
     s->step_dirty = true;
     return MDLTS_OK;
 }
@@ -2472,19 +2479,33 @@ mdlts_status mdlts_batch_adapt(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sim
             if (sims[r] == sims[q]) return MDLTS_EINVAL;
         if (!(dt_barrier[q] > 0.0) || !std::isfinite(dt_barrier[q])) return MDLTS_EINVAL;
     }
+    // A simulation whose leaves do not change keeps its levels when they are
+    // the CFL levels of the same barrier step: no transfer, faces, levels or
+    // regrouping; its grouped state (which the indicator only reads from a
+    // canonical copy) stays in place, and its step plans stay valid.  The
+    // results are bitwise those of the full sequence.
+    std::vector<char> keep(n_sims);
+    for (int q = 0; q < n_sims; q++)
+        keep[q] = sims[q]->levels_valid && sims[q]->state_grouped && sims[q]->levels_plain &&
+                  dt_barrier[q] == sims[q]->dt_bar;
     // indicator and the counting half of the adaptation, all simulations
     for (int q = 0; q < n_sims; q++) {
         mdlts_sim *s = sims[q];
-        s->version++;
         MD_TRY(indicator_enqueue(s));
         MD_TRY(to_canonical(s));
         if (s->desc.dim == 2) MD_TRY(adapt_count<2>(s, tau_refine, tau_coarsen));
         else MD_TRY(adapt_count<3>(s, tau_refine, tau_coarsen));
     }
     MD_TRY(sync(ctx));
-    // new leaves, transfer, faces and levels, all simulations
+    // new leaves, transfer, faces and levels, all simulations that change
     for (int q = 0; q < n_sims; q++) {
         mdlts_sim *s = sims[q];
+        keep[q] = keep[q] && s->pin->tallies[0] == 0 && s->pin->tallies[1] == 0 && s->pin->total == (int)s->E;
+        if (keep[q]) {
+            s->state_grouped = true;
+            continue;
+        }
+        s->version++;
         if (s->desc.dim == 2) MD_TRY(adapt_emit<2>(s));
         else MD_TRY(adapt_emit<3>(s));
         MD_TRY(levels_enqueue(s, dt_barrier[q], -1));
@@ -2493,6 +2514,10 @@ mdlts_status mdlts_batch_adapt(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sim
     mdlts_status first = MDLTS_OK;
     for (int q = 0; q < n_sims; q++) {
         mdlts_sim *s = sims[q];
+        if (keep[q]) {
+            if (first == MDLTS_OK && s->pin->eta_nonfinite) first = MDLTS_EUNSTABLE;
+            continue;
+        }
         mdlts_status st = s->pin->face_bad ? MDLTS_EINVAL : levels_finish(s, dt_barrier[q], nullptr);
         if (st == MDLTS_OK && s->pin->eta_nonfinite) st = MDLTS_EUNSTABLE;
         if (first == MDLTS_OK) first = st;

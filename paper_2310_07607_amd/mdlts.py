@@ -225,7 +225,7 @@ class Context:
         _chk(lib().mdlts_batch_profile(self.h, 1 if enable else 0), "mdlts_batch_profile")
 
     def batch_profile_read(self):
-        """(kernel ms, launches, DoF-updates, threads per block, persistent blocks per CU)."""
+        """(kernel ms, launches, DoF-updates, threads per block, 0 (one block per tile))."""
         ms = ctypes.c_double()
         nl, nd = ctypes.c_uint64(), ctypes.c_uint64()
         blk, pcu = ctypes.c_int(), ctypes.c_int()

@@ -99,10 +99,14 @@ def test_batch_against_oracle(ctx):
     g2.close()
 
 
-def test_batch_adapt_equals_per_simulation_calls(ctx):
+@pytest.mark.parametrize("thresholds", [(2e-9, 1e-10), (1e300, -1.0)])
+def test_batch_adapt_equals_per_simulation_calls(ctx, thresholds):
     """mdlts_batch_adapt = indicator, adapt and assign_levels per simulation,
-    bitwise (trees, levels, states, and the steps that follow)."""
+    bitwise (trees, levels, states, and the steps that follow); with
+    thresholds that change no leaf, batch_adapt keeps levels and grouped
+    states in place instead of rebuilding them."""
     from paper_2310_07607_amd import mdlts
+    tau_r, tau_c = thresholds
 
     def build():
         out = []
@@ -121,13 +125,16 @@ def test_batch_adapt_equals_per_simulation_calls(ctx):
     for g, dt in a:
         g.step(3)
         g.indicator(download=False)
-        g.adapt(2e-9, 1e-10)
+        g.adapt(tau_r, tau_c)
         g.assign_levels(dt)
         g.step(2)
     b = build()
     for g, dt in b:
         g.step(3)
-    ctx.batch_adapt([g for g, _ in b], 2e-9, 1e-10, [dt for _, dt in b])
+    leaves = [g.n_leaves for g, _ in b]
+    ctx.batch_adapt([g for g, _ in b], tau_r, tau_c, [dt for _, dt in b])
+    if tau_r > 1e299:
+        assert [g.n_leaves for g, _ in b] == leaves
     for g, dt in b:
         g.step(2)
     for (ga, _), (gb, _) in zip(a, b):
