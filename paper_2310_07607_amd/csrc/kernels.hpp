@@ -312,6 +312,29 @@ __device__ __forceinline__ void tang_apply(const double (&I)[2][kMaxM][kMaxM], i
     }
 }
 
+// point g of tang_apply(I, pos0, pos1, in), in the same order of operations
+template <typename T, int DIM, int M>
+__device__ __forceinline__ T tang_point(const double (&I)[2][kMaxM][kMaxM], int pos0, int pos1, const T *in, int g)
+{
+    if constexpr (DIM == 2) {
+        T s = 0;
+#pragma unroll
+        for (int q = 0; q < M; q++) s += (pos0 ? (T)I[1][g][q] : (T)I[0][g][q]) * in[q];
+        return s;
+    } else {
+        const int g0 = g % M, g1 = g / M;
+        T s = 0;
+#pragma unroll
+        for (int q1 = 0; q1 < M; q1++) {
+            T t = 0;
+#pragma unroll
+            for (int q = 0; q < M; q++) t += (pos0 ? (T)I[1][g0][q] : (T)I[0][g0][q]) * in[q + M * q1];
+            s += (pos1 ? (T)I[1][g1][q1] : (T)I[0][g1][q1]) * t;
+        }
+        return s;
+    }
+}
+
 // out = Op applied along direction k of an element array (lines of M nodes)
 template <typename T, int DIM, int M>
 __device__ __forceinline__ void line_apply(const double (&Op)[kMaxM][kMaxM], int k, const T *in, T *out)
@@ -468,9 +491,9 @@ __device__ __forceinline__ void neighbour_interp(const StepLaunch<T> &L, __amdgp
 // arithmetic, so a wave waits for memory twice: their launches are short and
 // latency-bound.  Larger elements keep one face's neighbour in flight while
 // the previous face is computed, which leaves registers for more waves per
-// SIMD (with the other register savings below: Q2 hexahedra 156 VGPRs and 3
+// SIMD (with the other register savings below: Q2 hexahedra 220 VGPRs and 2
 // waves per SIMD, against 258 and 1 with two faces in flight; Q1 hexahedra
-// 99 and 4).  Faces with finer neighbours (rare, at refinement interfaces)
+// 114 and 4).  Faces with finer neighbours (rare, at refinement interfaces)
 // load their 2^(d-1) neighbours on demand.
 // Large FP32 elements stage the gate v through LDS: its loads go straight
 // to LDS at the start (no registers held) and are read at the update.
@@ -717,63 +740,121 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
             } else {
                 const T sigma = (T)1.5 * pen;           // h_nbr = h/2
                 const T qn = ns * Dkk * (T)2 * c2;
-                // Own-side terms are taken on the whole face: restricting the
-                // own trace to the sub-faces (Isub) and lifting back (Lsub)
-                // gives it unchanged, since the half-interval GL rules
-                // integrate l_a l_b exactly (sum over sub-faces of Lsub Isub
-                // = I).  Only the neighbours' traces go through the sub-faces.
-#pragma unroll
-                for (int g = 0; g < NF; g++) {
-                    Fl[g] = (T)0.5 * qs * tq[g] - sigma * tu[g];
-                    Hl[g] = (T)0.5 * tu[g];
-                }
-                if constexpr (FULL) {
-                    // own tangential derivatives (in face coordinates)
-                    T t0[NF];
-#pragma unroll
-                    for (int tau = 0; tau < DIM - 1; tau++) {
-                        const int t = tang_dir(k, tau);
-                        const T co = ns * a.Dx[off_slot(k, t)] * ih[t];
-                        face_line<T, DIM, M>(R.D1, tau, tu, t0);
-#pragma unroll
-                        for (int g = 0; g < NF; g++) Fl[g] += co * t0[g];
+                if constexpr (P >= 3) {
+                    // degree 3: the own-side terms on the whole face (the
+                    // sub-face restrictions of the own trace, lifted back,
+                    // give it unchanged: sum over sub-faces of Lsub Isub = I)
+                    // keep the reference tables out of scratch memory
+                    // Own-side terms are taken on the whole face: restricting the
+                    // own trace to the sub-faces (Isub) and lifting back (Lsub)
+                    // gives it unchanged, since the half-interval GL rules
+                    // integrate l_a l_b exactly (sum over sub-faces of Lsub Isub
+                    // = I).  Only the neighbours' traces go through the sub-faces.
+    #pragma unroll
+                    for (int g = 0; g < NF; g++) {
+                        Fl[g] = (T)0.5 * qs * tq[g] - sigma * tu[g];
+                        Hl[g] = (T)0.5 * tu[g];
                     }
-                }
-                auto sub_face = [&](int sub) {
-                    const int p0 = sub & 1, p1 = sub >> 1;
-                    T nu[NF], nq[NF], G[NF], lg[NF];
-                    const uint32_t fe = buf_ld<uint32_t>(buf_of(L.fine, (uint32_t)NFACE * (uint32_t)L.cap * NS * 4u),
-                                                         (uint32_t)(j * NS + sub) * 4u,
-                                                         (uint32_t)f * (uint32_t)L.cap * NS * 4u);
-                    neighbour_trace<T, DIM, P>(a, L, ru, fe, k, 1 - s, nu, nq);
-#pragma unroll
-                    for (int g = 0; g < NF; g++) G[g] = (T)0.5 * qn * nq[g] + sigma * nu[g];
                     if constexpr (FULL) {
-                        // the neighbour's tangential derivatives on the
-                        // sub-face (extent h_t / 2)
+                        // own tangential derivatives (in face coordinates)
                         T t0[NF];
-#pragma unroll
+    #pragma unroll
                         for (int tau = 0; tau < DIM - 1; tau++) {
                             const int t = tang_dir(k, tau);
-                            const T cf = (T)2 * ns * a.Dx[off_slot(k, t)] * ih[t];
-                            face_line<T, DIM, M>(R.D1, tau, nu, t0);
-#pragma unroll
-                            for (int g = 0; g < NF; g++) G[g] += cf * t0[g];
+                            const T co = ns * a.Dx[off_slot(k, t)] * ih[t];
+                            face_line<T, DIM, M>(R.D1, tau, tu, t0);
+    #pragma unroll
+                            for (int g = 0; g < NF; g++) Fl[g] += co * t0[g];
                         }
                     }
-                    tang_apply<T, DIM, M>(R.Lsub, p0, p1, G, lg);
-#pragma unroll
-                    for (int g = 0; g < NF; g++) { Fl[g] += lg[g]; G[g] = (T)-0.5 * nu[g]; }
-                    tang_apply<T, DIM, M>(R.Lsub, p0, p1, G, lg);
-#pragma unroll
-                    for (int g = 0; g < NF; g++) Hl[g] += lg[g];
-                };
-                if constexpr (NP <= 16) {
-#pragma unroll
-                    for (int sub = 0; sub < NS; sub++) sub_face(sub);
+                    auto sub_face = [&](int sub) {
+                        const int p0 = sub & 1, p1 = sub >> 1;
+                        T nu[NF], nq[NF], G[NF], lg[NF];
+                        const uint32_t fe = buf_ld<uint32_t>(buf_of(L.fine, (uint32_t)NFACE * (uint32_t)L.cap * NS * 4u),
+                                                             (uint32_t)(j * NS + sub) * 4u,
+                                                             (uint32_t)f * (uint32_t)L.cap * NS * 4u);
+                        neighbour_trace<T, DIM, P>(a, L, ru, fe, k, 1 - s, nu, nq);
+    #pragma unroll
+                        for (int g = 0; g < NF; g++) G[g] = (T)0.5 * qn * nq[g] + sigma * nu[g];
+                        if constexpr (FULL) {
+                            // the neighbour's tangential derivatives on the
+                            // sub-face (extent h_t / 2)
+                            T t0[NF];
+    #pragma unroll
+                            for (int tau = 0; tau < DIM - 1; tau++) {
+                                const int t = tang_dir(k, tau);
+                                const T cf = (T)2 * ns * a.Dx[off_slot(k, t)] * ih[t];
+                                face_line<T, DIM, M>(R.D1, tau, nu, t0);
+    #pragma unroll
+                                for (int g = 0; g < NF; g++) G[g] += cf * t0[g];
+                            }
+                        }
+                        tang_apply<T, DIM, M>(R.Lsub, p0, p1, G, lg);
+    #pragma unroll
+                        for (int g = 0; g < NF; g++) { Fl[g] += lg[g]; G[g] = (T)-0.5 * nu[g]; }
+                        tang_apply<T, DIM, M>(R.Lsub, p0, p1, G, lg);
+    #pragma unroll
+                        for (int g = 0; g < NF; g++) Hl[g] += lg[g];
+                    };
+                    if constexpr (NP <= 16) {
+    #pragma unroll
+                        for (int sub = 0; sub < NS; sub++) sub_face(sub);
+                    } else {
+    #pragma unroll 1
+                        for (int sub = 0; sub < NS; sub++) sub_face(sub);
+                    }
                 } else {
-#pragma unroll 1
-                    for (int sub = 0; sub < NS; sub++) sub_face(sub);
+    #pragma unroll
+                    for (int g = 0; g < NF; g++) { Fl[g] = 0; Hl[g] = 0; }
+                    // Per sub-face: the own trace restricted to its points (Isub),
+                    // formed point by point (no arrays held), and the jump taken
+                    // before any scaling, so that in FP32 the penalty multiplies a
+                    // small difference; then both lifted back to the face (Lsub).
+                    auto sub_face = [&](int sub) {
+                        const int p0 = sub & 1, p1 = sub >> 1;
+                        T nu[NF], nq[NF], G[NF], J[NF], lg[NF];
+                        const uint32_t fe = buf_ld<uint32_t>(buf_of(L.fine, (uint32_t)NFACE * (uint32_t)L.cap * NS * 4u),
+                                                             (uint32_t)(j * NS + sub) * 4u,
+                                                             (uint32_t)f * (uint32_t)L.cap * NS * 4u);
+                        neighbour_trace<T, DIM, P>(a, L, ru, fe, k, 1 - s, nu, nq);
+    #pragma unroll
+                        for (int g = 0; g < NF; g++) {
+                            const T ou = tang_point<T, DIM, M>(R.Isub, p0, p1, tu, g);
+                            const T oq = tang_point<T, DIM, M>(R.Isub, p0, p1, tq, g);
+                            const T jmp = ou - nu[g];
+                            G[g] = (T)0.5 * (qs * oq + qn * nq[g]) - sigma * jmp;
+                            J[g] = (T)0.5 * jmp;
+                        }
+                        if constexpr (FULL) {
+                            // tangential derivatives of both sides on the
+                            // sub-face (extent h_t / 2)
+                            T sm[NF], t0[NF];
+                            tang_apply<T, DIM, M>(R.Isub, p0, p1, tu, sm);
+    #pragma unroll
+                            for (int g = 0; g < NF; g++) sm[g] += nu[g];
+    #pragma unroll
+                            for (int tau = 0; tau < DIM - 1; tau++) {
+                                const int t = tang_dir(k, tau);
+                                const T cf = (T)2 * ns * a.Dx[off_slot(k, t)] * ih[t];
+                                face_line<T, DIM, M>(R.D1, tau, sm, t0);
+    #pragma unroll
+                                for (int g = 0; g < NF; g++) G[g] += cf * t0[g];
+                            }
+                        }
+                        tang_apply<T, DIM, M>(R.Lsub, p0, p1, G, lg);
+    #pragma unroll
+                        for (int g = 0; g < NF; g++) Fl[g] += lg[g];
+                        tang_apply<T, DIM, M>(R.Lsub, p0, p1, J, lg);
+    #pragma unroll
+                        for (int g = 0; g < NF; g++) Hl[g] += lg[g];
+                    };
+                    if constexpr (NP <= 16) {
+    #pragma unroll
+                        for (int sub = 0; sub < NS; sub++) sub_face(sub);
+                    } else {
+    #pragma unroll 1
+                        for (int sub = 0; sub < NS; sub++) sub_face(sub);
+                    }
                 }
                 if constexpr (FULL) {
                     // n.D grad l_i along the face against the lifted half
@@ -895,15 +976,9 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
     }
 }
 
-// FP32 Q2 hexahedra sit at the 168-VGPR limit of 3 waves per SIMD: hold
-// the compiler to it
-template <int DIM, int P, typename T, bool FULL>
-constexpr int kMinWaves = DIM == 3 && P == 2 && sizeof(T) == 4 && !FULL ? 3 : 1;
-
 // one simulation: element j of the active prefix [0, n_act)
 template <int DIM, int P, typename T, bool FULL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<DIM, P, T, FULL>)))
-void k_substep(const StepArgs<T> *__restrict__ cst, const StepLaunch<T> L)
+__global__ __launch_bounds__(256) void k_substep(const StepArgs<T> *__restrict__ cst, const StepLaunch<T> L)
 {
     const int j = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (j >= L.n_act) return;
@@ -952,8 +1027,7 @@ struct BatchClock {
 // XCD's L2.  (A persistent form, blocks walking several tiles, held about 45
 // more VGPRs live across its loop and was never the fastest shape.)
 template <int DIM, int P, typename T, bool FULL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<DIM, P, T, FULL>)))
-void k_substep_batch(const BatchSim<T> *__restrict__ sims,
+__global__ __launch_bounds__(256) void k_substep_batch(const BatchSim<T> *__restrict__ sims,
                                                        const BatchTile *__restrict__ tiles, int n_tiles, int i,
                                                        char *base, const BatchClock *__restrict__ clk,
                                                        BatchClock *__restrict__ clk_next)
