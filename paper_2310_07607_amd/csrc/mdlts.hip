@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <map>
 #include <new>
@@ -143,7 +144,7 @@ __global__ __launch_bounds__(kBlock) void k_level_scan(int *hist, int nb, int n_
             const int tot = base[l];
             base[l] = run;  // leaves of finer levels come first
             run += tot;
-            if (l < n_levels) cnt_ge[l] = run;
+            cnt_ge[l] = l < n_levels ? run : 0;  // every entry written
         }
     }
     __syncthreads();
@@ -583,6 +584,9 @@ struct mdlts_ctx {
     void *stage = nullptr;
     size_t stage_bytes = 0;
     hipEvent_t stage_done = nullptr;
+    // completed synchronisations of the stream: work enqueued before the
+    // last one has finished
+    uint64_t sync_epoch = 0;
 };
 
 // Host-visible staging of a simulation's small readbacks (pinned memory, so
@@ -692,6 +696,36 @@ mdlts_status dev_alloc(mdlts_ctx *c, DevBuf &b, size_t bytes)
     return MDLTS_OK;
 }
 
+// A simulation's device flags block holds the small readbacks at the
+// offsets they have in PinnedReadback (cnt_ge excepted), so that each phase
+// writes its own fields and one copy brings back what several phases wrote.
+constexpr size_t kFlagBytes = 128;
+constexpr size_t kFlagHead = offsetof(PinnedReadback, cnt_ge);
+static_assert(sizeof(PinnedReadback) <= kFlagBytes, "flags block holds the readback fields");
+
+template <typename F>
+F *flag_at(mdlts_sim *s, size_t off)
+{
+    return reinterpret_cast<F *>(static_cast<char *>(s->flags.p) + off);
+}
+#define MD_FLAG(s, F, field) flag_at<F>(s, offsetof(PinnedReadback, field))
+
+// zero the whole flags block (every phase's fields)
+mdlts_status flags_clear(mdlts_sim *s)
+{
+    MD_TRY(dev_alloc(s->ctx, s->flags, kFlagBytes));
+    HIP_TRY(hipMemsetAsync(s->flags.p, 0, kFlagBytes, s->ctx->stream));
+    return MDLTS_OK;
+}
+
+// every field of the flags block (but cnt_ge) into the pinned readback; it
+// arrives after the next synchronisation
+mdlts_status flags_readback(mdlts_sim *s)
+{
+    HIP_TRY(hipMemcpyAsync(s->pin, s->flags.p, kFlagHead, hipMemcpyDeviceToHost, s->ctx->stream));
+    return MDLTS_OK;
+}
+
 // The context's pinned staging area, at least `bytes` long, once the copies
 // out of it that were queued before have completed.
 mdlts_status stage_acquire(mdlts_ctx *c, size_t bytes, char **out)
@@ -779,6 +813,7 @@ void forest_from_desc(const mdlts_mesh_desc *d, Forest &F)
 mdlts_status sync(mdlts_ctx *c)
 {
     if (hipStreamSynchronize(c->stream) != hipSuccess) return MDLTS_EDEVICE;
+    c->sync_epoch++;
     if (hipGetLastError() != hipSuccess) return MDLTS_EDEVICE;
     return MDLTS_OK;
 }
@@ -803,7 +838,7 @@ int n_sub(const mdlts_sim *s) { return s->desc.dim == 2 ? 2 : 4; }
 
 // face tables of the canonical leaves in key_c, built on the device; the
 // consistency flag arrives in pin->face_bad after the next synchronisation
-mdlts_status device_faces(mdlts_sim *s)
+mdlts_status device_faces(mdlts_sim *s, bool own_flags = true)
 {
     mdlts_ctx *c = s->ctx;
     const int E = (int)s->E;
@@ -813,24 +848,24 @@ mdlts_status device_faces(mdlts_sim *s)
     MD_TRY(dev_alloc(c, s->mkey, (size_t)E * sizeof(uint32_t)));
     MD_TRY(dev_alloc(c, s->face_c, (size_t)2 * dim * E * sizeof(uint32_t)));
     MD_TRY(dev_alloc(c, s->fine_c, (size_t)2 * dim * E * n_sub(s) * sizeof(uint32_t)));
-    MD_TRY(dev_alloc(c, s->flags, 64));
-    HIP_TRY(hipMemsetAsync(s->flags.p, 0, 64, c->stream));
+    if (own_flags) MD_TRY(flags_clear(s));
+    int *bad = MD_FLAG(s, int, face_bad);
     const MeshGeo g = geo_of(s);
     if (dim == 2) {
         k_mesh_index<2><<<nblocks(E), kBlock, 0, c->stream>>>(E, n_roots, g, P<uint32_t>(s->key_c),
                                                                P<int>(s->root_start), P<uint32_t>(s->mkey));
         k_mesh_faces<2><<<nblocks(E), kBlock, 0, c->stream>>>(E, g, P<uint32_t>(s->key_c), P<int>(s->root_start),
                                                                P<uint32_t>(s->mkey), P<uint32_t>(s->face_c),
-                                                               P<uint32_t>(s->fine_c), P<int>(s->flags));
+                                                               P<uint32_t>(s->fine_c), bad);
     } else {
         k_mesh_index<3><<<nblocks(E), kBlock, 0, c->stream>>>(E, n_roots, g, P<uint64_t>(s->key_c),
                                                                P<int>(s->root_start), P<uint32_t>(s->mkey));
         k_mesh_faces<3><<<nblocks(E), kBlock, 0, c->stream>>>(E, g, P<uint64_t>(s->key_c), P<int>(s->root_start),
                                                                P<uint32_t>(s->mkey), P<uint32_t>(s->face_c),
-                                                               P<uint32_t>(s->fine_c), P<int>(s->flags));
+                                                               P<uint32_t>(s->fine_c), bad);
     }
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(&s->pin->face_bad, s->flags.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    if (own_flags) HIP_TRY(hipMemcpyAsync(&s->pin->face_bad, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     return MDLTS_OK;
 }
 
@@ -1180,7 +1215,7 @@ mdlts_status run_transfer(mdlts_sim *s, int E_old, int E_new)
 // coarsenable sibling groups, count and scan the new leaves; the counts
 // arrive in pin->tallies / pin->total after the next synchronisation.
 template <int DIM>
-mdlts_status adapt_count(mdlts_sim *s, double tau_refine, double tau_coarsen)
+mdlts_status adapt_count(mdlts_sim *s, double tau_refine, double tau_coarsen, bool own_flags = true)
 {
     using KT = typename KeyOf<DIM>::type;
     mdlts_ctx *c = s->ctx;
@@ -1193,10 +1228,9 @@ mdlts_status adapt_count(mdlts_sim *s, double tau_refine, double tau_coarsen)
     MD_TRY(dev_alloc(c, s->cnt, (size_t)E * sizeof(int)));
     MD_TRY(dev_alloc(c, s->off, (size_t)E * sizeof(int)));
     MD_TRY(dev_alloc(c, s->bsums, (size_t)(nb4 + 1) * sizeof(int)));
-    MD_TRY(dev_alloc(c, s->flags, 64));
-    HIP_TRY(hipMemsetAsync(s->flags.p, 0, 64, st));
-    unsigned long long *tallies = reinterpret_cast<unsigned long long *>(static_cast<char *>(s->flags.p) + 8);
-    int *total = reinterpret_cast<int *>(static_cast<char *>(s->flags.p) + 32);
+    if (own_flags) MD_TRY(flags_clear(s));
+    unsigned long long *tallies = MD_FLAG(s, unsigned long long, tallies);
+    int *total = MD_FLAG(s, int, total);
     const MeshGeo g = geo_of(s);
     const KT *key = P<KT>(s->key_c);
     k_amr_mark<DIM><<<nb, kBlock, 0, st>>>(E, g, key, P<double>(s->eta_c), tau_refine, P<uint8_t>(s->refine));
@@ -1210,8 +1244,11 @@ mdlts_status adapt_count(mdlts_sim *s, double tau_refine, double tau_coarsen)
     k_scan_sums<<<1, kBlock, 0, st>>>(nb4, P<int>(s->bsums), total);
     k_scan_add<<<nb4, kBlock, 0, st>>>(E, P<int>(s->off), P<int>(s->bsums));
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(s->pin->tallies, tallies, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(&s->pin->total, total, sizeof(int), hipMemcpyDeviceToHost, st));
+    // tallies and total are adjacent: one copy
+    static_assert(offsetof(PinnedReadback, total) == 3 * sizeof(unsigned long long), "readback layout");
+    if (own_flags)
+        HIP_TRY(hipMemcpyAsync(s->pin->tallies, tallies, offsetof(PinnedReadback, total) + sizeof(int),
+                               hipMemcpyDeviceToHost, st));
     return MDLTS_OK;
 }
 
@@ -1219,7 +1256,7 @@ mdlts_status adapt_count(mdlts_sim *s, double tau_refine, double tau_coarsen)
 // map, transfer u and v, rebuild the face tables (their consistency flag
 // arrives in pin->face_bad after the next synchronisation).
 template <int DIM>
-mdlts_status adapt_emit(mdlts_sim *s)
+mdlts_status adapt_emit(mdlts_sim *s, bool own_flags = true)
 {
     using KT = typename KeyOf<DIM>::type;
     mdlts_ctx *c = s->ctx;
@@ -1244,7 +1281,7 @@ mdlts_status adapt_emit(mdlts_sim *s)
     s->host_forest_valid = false;
     s->levels_valid = false;
     s->eta_valid = false;
-    return device_faces(s);
+    return device_faces(s, own_flags);
 }
 
 mdlts_status compute_G(mdlts_sim *s)
@@ -1297,7 +1334,8 @@ struct BatchPlan {
     std::vector<hipGraphNode_t> nodes[2];
     std::vector<long long> topo;
     bool graph_valid = false;  // the graphs hold this plan's current launches
-    bool graph_busy = false;   // a replay may be in flight (not synchronised since)
+    bool graph_busy = false;   // a replay was launched in sync epoch busy_epoch
+    uint64_t busy_epoch = 0;
     bool single_graph = false;  // a one-variant plan replays graphs (tuned)
     // optional event timing of every batched substep launch
     bool prof = false;
@@ -1340,6 +1378,7 @@ void adopt_graph(BatchPlan *to, BatchPlan *from)
     to->topo.swap(from->topo);
     to->graph_valid = false;
     to->graph_busy = from->graph_busy;
+    to->busy_epoch = from->busy_epoch;
 }
 
 // frees a plan (the context's batch plan or a simulation's step plan)
@@ -1553,7 +1592,8 @@ mdlts_status build_graph(mdlts_ctx *c, BatchPlan &P)
         MD_TRY(emit_barrier(c, P, 0, nullptr, kEmitKeys, &keys));
         if (keys == P.topo && P.nodes[0].size() == keys.size() && P.nodes[1].size() == keys.size()) {
             // no replay of these graphs may be in flight while they change
-            if (P.graph_busy) HIP_TRY(hipStreamSynchronize(c->stream));
+            // (a stream synchronisation since the last replay suffices)
+            if (P.graph_busy && P.busy_epoch == c->sync_epoch) MD_TRY(sync(c));
             P.graph_busy = false;
             for (int k = 0; k < 2; k++) MD_TRY(emit_barrier(c, P, k, nullptr, kEmitUpdate));
             P.graph_valid = true;
@@ -1616,6 +1656,7 @@ mdlts_status run_batch_barriers(mdlts_ctx *c, BatchPlan &P, int nb)
             if (!P.graph_valid) MD_TRY(build_graph(c, P));
             HIP_TRY(hipGraphLaunch(P.exec[P.phase], c->stream));
             P.graph_busy = true;
+            P.busy_epoch = c->sync_epoch;
         } else {
             MD_TRY(emit_barrier(c, P, P.phase, nullptr));
         }
@@ -1683,6 +1724,7 @@ mdlts_status autotune(mdlts_ctx *c, BatchPlan &P, int *remaining)
                 if (mode == 1) {
                     HIP_TRY(hipGraphLaunch(P.exec[P.phase], c->stream));
                     P.graph_busy = true;
+                    P.busy_epoch = c->sync_epoch;
                 } else {
                     MD_TRY(emit_barrier(c, P, P.phase, nullptr));
                 }
@@ -2071,7 +2113,7 @@ mdlts_status mdlts_assign_uniform(mdlts_sim *s, double dt_barrier, int level, in
 // permutation are enqueued; the level counts and the stability flag arrive
 // in pin->cnt_ge / pin->level_bad after the next synchronisation.
 static mdlts_status levels_enqueue(mdlts_sim *s, double dt_barrier, int force_level, const double *eta_t = nullptr,
-                                   double tau_cell = 0.0, int b_cell = 0)
+                                   double tau_cell = 0.0, int b_cell = 0, bool own_flags = true)
 {
     if (!(dt_barrier > 0.0) || !std::isfinite(dt_barrier)) return MDLTS_EINVAL;
     // the substep kernels address both u slots with 32-bit byte offsets
@@ -2088,11 +2130,9 @@ static mdlts_status levels_enqueue(mdlts_sim *s, double dt_barrier, int force_le
     MD_TRY(dev_alloc(c, s->cfl_c, (size_t)E * sizeof(double)));
     MD_TRY(dev_alloc(c, s->hist, (size_t)nb * kMaxLevels * sizeof(int)));
     MD_TRY(dev_alloc(c, s->cnt_ge_d, kMaxLevels * sizeof(int)));
-    MD_TRY(dev_alloc(c, s->flags, 64));
     MD_TRY(dev_alloc(c, s->perm, (size_t)E * sizeof(int)));
     MD_TRY(dev_alloc(c, s->inv, (size_t)E * sizeof(int)));
-    HIP_TRY(hipMemsetAsync(s->flags.p, 0, 64, c->stream));
-    HIP_TRY(hipMemsetAsync(s->cnt_ge_d.p, 0, kMaxLevels * sizeof(int), c->stream));
+    if (own_flags) MD_TRY(flags_clear(s));
     LevelArgs la;
     std::memset(&la, 0, sizeof(la));
     la.key = s->key_c.p;
@@ -2119,11 +2159,11 @@ static mdlts_status levels_enqueue(mdlts_sim *s, double dt_barrier, int force_le
     la.level = P<uint8_t>(s->level_c);
     la.cfl = P<double>(s->cfl_c);
     la.hist = P<int>(s->hist);
-    la.bad = P<int>(s->flags);
+    la.bad = MD_FLAG(s, int, level_bad);
     if (s->desc.dim == 2) k_levels<2><<<nb, kBlock, 0, c->stream>>>(la);
     else k_levels<3><<<nb, kBlock, 0, c->stream>>>(la);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(&s->pin->level_bad, s->flags.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    if (own_flags) HIP_TRY(hipMemcpyAsync(&s->pin->level_bad, la.bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     // (levels above the cap are clamped by k_levels, so what follows stays
     // well defined; the flag makes the assignment invalid afterwards)
     k_level_scan<<<1, kBlock, 0, c->stream>>>(P<int>(s->hist), nb, L, P<int>(s->cnt_ge_d));
@@ -2193,7 +2233,7 @@ mdlts_status mdlts_assign_levels_auto(mdlts_sim *s, double *dt_barrier, int32_t 
     // CFL of every leaf (the level pass with every leaf forced to level 0),
     // then its minimum
     MD_TRY(levels_enqueue(s, 1.0, 0));
-    unsigned long long *mb = reinterpret_cast<unsigned long long *>(static_cast<char *>(s->flags.p) + 16);
+    unsigned long long *mb = MD_FLAG(s, unsigned long long, eta_max_bits);
     const unsigned long long init = 0x7fefffffffffffffull;  // largest finite double
     HIP_TRY(hipMemcpyAsync(mb, &init, 8, hipMemcpyHostToDevice, c->stream));
     k_min_positive<<<nblocks(E), kBlock, 0, c->stream>>>(E, P<double>(s->cfl_c), mb);
@@ -2237,8 +2277,7 @@ mdlts_status mdlts_rvt_indicator(mdlts_sim *s, double *eta_t, size_t n_leaves, d
     const bool was_grouped = s->state_grouped;
     MD_TRY(to_canonical(s));
     MD_TRY(dev_alloc(c, s->eta_t_c, E * sizeof(double)));
-    MD_TRY(dev_alloc(c, s->flags, 64));
-    HIP_TRY(hipMemsetAsync(s->flags.p, 0, 64, c->stream));
+    MD_TRY(flags_clear(s));
     RvtArgs a;
     std::memset(&a, 0, sizeof(a));
     a.u_a = s->snap_u.p;
@@ -2258,7 +2297,7 @@ mdlts_status mdlts_rvt_indicator(mdlts_sim *s, double *eta_t, size_t n_leaves, d
         a.stim[b][6] = B.t_on; a.stim[b][7] = B.t_off; a.stim[b][8] = B.amp;
     }
     a.eta = P<double>(s->eta_t_c);
-    a.eta_max_bits = reinterpret_cast<unsigned long long *>(static_cast<char *>(s->flags.p) + 8);
+    a.eta_max_bits = MD_FLAG(s, unsigned long long, eta_max_bits);
     const int nb = nblocks((int)E);
     hipStream_t st = c->stream;
     switch (s->desc.dim * 100 + s->desc.order * 10 + (s->desc.precision == MDLTS_FP32 ? 1 : 0)) {
@@ -2346,21 +2385,24 @@ mdlts_status mdlts_step(mdlts_sim *s, int n_barriers)
 
 // the indicator on the device (canonical state, FP64 eta in eta_c); its
 // maximum and non-finite flag arrive in pin after the next synchronisation
-static mdlts_status indicator_enqueue(mdlts_sim *s)
+static mdlts_status indicator_enqueue(mdlts_sim *s, bool own_flags = true)
 {
     mdlts_ctx *c = s->ctx;
     const size_t E = s->E;
     const bool was_grouped = s->state_grouped;
     MD_TRY(to_canonical(s));
     MD_TRY(dev_alloc(c, s->eta_c, E * sizeof(double)));
-    MD_TRY(dev_alloc(c, s->flags, 64));
-    HIP_TRY(hipMemsetAsync(s->flags.p, 0, 64, c->stream));
-    unsigned long long *maxb = reinterpret_cast<unsigned long long *>(static_cast<char *>(s->flags.p) + 8);
-    int *nonf = reinterpret_cast<int *>(static_cast<char *>(s->flags.p) + 16);
+    if (own_flags) MD_TRY(flags_clear(s));
+    unsigned long long *maxb = MD_FLAG(s, unsigned long long, eta_max_bits);
+    int *nonf = MD_FLAG(s, int, eta_nonfinite);
     if (s->desc.precision == MDLTS_FP64) MD_TRY(run_indicator<double>(s, maxb, nonf));
     else MD_TRY(run_indicator<float>(s, maxb, nonf));
-    HIP_TRY(hipMemcpyAsync(&s->pin->eta_max_bits, maxb, 8, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipMemcpyAsync(&s->pin->eta_nonfinite, nonf, 4, hipMemcpyDeviceToHost, c->stream));
+    // the non-finite flag and the maximum are adjacent: one copy
+    static_assert(offsetof(PinnedReadback, eta_max_bits) == offsetof(PinnedReadback, eta_nonfinite) + sizeof(int),
+                  "readback layout");
+    if (own_flags)
+        HIP_TRY(hipMemcpyAsync(&s->pin->eta_nonfinite, nonf, sizeof(int) + sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, c->stream));
     // the grouped copy of the state is untouched
     if (was_grouped) s->state_grouped = true;
     s->eta_valid = true;
@@ -2488,13 +2530,17 @@ mdlts_status mdlts_batch_adapt(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sim
     for (int q = 0; q < n_sims; q++)
         keep[q] = sims[q]->levels_valid && sims[q]->state_grouped && sims[q]->levels_plain &&
                   dt_barrier[q] == sims[q]->dt_bar;
-    // indicator and the counting half of the adaptation, all simulations
+    // indicator and the counting half of the adaptation, all simulations.
+    // Every phase writes its own fields of the flags block, cleared once
+    // here and read back in one copy per synchronisation.
     for (int q = 0; q < n_sims; q++) {
         mdlts_sim *s = sims[q];
-        MD_TRY(indicator_enqueue(s));
+        MD_TRY(flags_clear(s));
+        MD_TRY(indicator_enqueue(s, false));
         MD_TRY(to_canonical(s));
-        if (s->desc.dim == 2) MD_TRY(adapt_count<2>(s, tau_refine, tau_coarsen));
-        else MD_TRY(adapt_count<3>(s, tau_refine, tau_coarsen));
+        if (s->desc.dim == 2) MD_TRY(adapt_count<2>(s, tau_refine, tau_coarsen, false));
+        else MD_TRY(adapt_count<3>(s, tau_refine, tau_coarsen, false));
+        MD_TRY(flags_readback(s));
     }
     MD_TRY(sync(ctx));
     // new leaves, transfer, faces and levels, all simulations that change
@@ -2506,9 +2552,10 @@ mdlts_status mdlts_batch_adapt(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sim
             continue;
         }
         s->version++;
-        if (s->desc.dim == 2) MD_TRY(adapt_emit<2>(s));
-        else MD_TRY(adapt_emit<3>(s));
-        MD_TRY(levels_enqueue(s, dt_barrier[q], -1));
+        if (s->desc.dim == 2) MD_TRY(adapt_emit<2>(s, false));
+        else MD_TRY(adapt_emit<3>(s, false));
+        MD_TRY(levels_enqueue(s, dt_barrier[q], -1, nullptr, 0.0, 0, false));
+        MD_TRY(flags_readback(s));
     }
     MD_TRY(sync(ctx));
     mdlts_status first = MDLTS_OK;
