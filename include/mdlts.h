@@ -216,9 +216,10 @@ mdlts_status mdlts_batch_adapt(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sim
                                double tau_coarsen, const double *dt_barrier);
 /* enable = 1 (default): batches whose substeps launch more than one kernel
  * variant replay one graph per barrier (the variants' launches run
- * concurrently); single-variant plans (mdlts_step) launch their tile kernels
- * directly.  enable = 0: every launch goes directly to the stream, and
- * mdlts_step uses the per-element kernel without tile lists. */
+ * concurrently); single-variant plans (mdlts_step, or a batch of one
+ * variant) launch their tile kernels directly or replay a graph, whichever
+ * the autotuner timed faster.  enable = 0: every launch goes directly to the
+ * stream, and mdlts_step uses the per-element kernel without tile lists. */
 mdlts_status mdlts_set_graphs(mdlts_ctx *ctx, int enable);
 /* Event timing of the batched substep launches (launched directly while
  * enabled); read returns kernel ms, launches, DoF-updates since the last
