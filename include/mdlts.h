@@ -281,7 +281,8 @@ mdlts_status mdlts_plan_levels(const mdlts_mesh_desc *desc, const uint8_t *bits,
 /* Upper bound, in bytes, of the device memory one simulation of this shape
  * holds while it never has more than max_leaves leaves: both state layouts,
  * the transfer and staging buffers, face, level and adaptation tables, and its
- * share of a batch plan.  A request loop that admits solves by device memory
+ * share of a batch plan, each with the 1/8 headroom a growing buffer is given
+ * so that small changes of the leaf count do not reallocate.  A request loop that admits solves by device memory
  * (continuous batching of many simulations, as in the batched form of the
  * LTS step) reserves this for the worst-case leaf count of a request, i.e.
  * every root refined to max_depth.  Host only; no device call.

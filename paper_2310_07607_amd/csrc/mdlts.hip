@@ -683,6 +683,10 @@ mdlts_status dev_alloc(mdlts_ctx *c, DevBuf &b, size_t bytes)
     if (b.p && b.bytes >= bytes) return MDLTS_OK;
     MD_TRY(dev_free(c, b));
     if (bytes == 0) bytes = 256;
+    // a buffer that grows gets 1/8 more than asked, so that leaf counts that
+    // move by a few per cent between adaptations do not go back to the
+    // allocator every time (the memory bound includes this headroom)
+    bytes += bytes / 8;
     void *p = nullptr;
     if (c->has_alloc) {
         p = c->alloc.alloc(bytes, c->stream, c->alloc.user);
@@ -2704,7 +2708,8 @@ mdlts_status mdlts_memory_bound(const mdlts_mesh_desc *desc, int64_t max_leaves,
                            + 4 * 4096       // flags, step constants, batch descriptor, small scans
                            + 8 * 4096       // own-block bounds of a full diffusion tensor
                            + nsub * 16 * 2; // tile list heads
-    *bytes = per_leaf * (uint64_t)max_leaves + fixed;
+    // every buffer may hold 1/8 growth headroom (dev_alloc)
+    *bytes = (per_leaf + (per_leaf + 7) / 8) * (uint64_t)max_leaves + fixed + fixed / 8;
     return MDLTS_OK;
 }
 
