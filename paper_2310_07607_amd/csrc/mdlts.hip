@@ -743,7 +743,7 @@ mdlts_status stage_acquire(mdlts_ctx *c, size_t bytes, char **out)
         if (c->stage) (void)hipHostFree(c->stage);
         c->stage = nullptr;
         c->stage_bytes = 0;
-        const size_t nb = std::max(bytes, (size_t)1 << 20);
+        const size_t nb = std::max(bytes + bytes / 4, (size_t)1 << 20);  // headroom for growth
         if (hipHostMalloc(&c->stage, nb, hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
             c->stage = nullptr;
@@ -1413,82 +1413,93 @@ template <typename T>
 mdlts_status fill_group(mdlts_ctx *c, BatchPlan &P, BatchGroup &G)
 {
     const int nm = (int)G.members.size();
-    std::vector<BatchSim<T>> d(nm);
-    for (int q = 0; q < nm; q++) {
-        mdlts_sim *s = P.sims[G.members[q]];
-        fill_step_args<T>(s, d[q].a);
-        d[q].t_start = s->t_start;
-        d[q].h_tick = s->dt_bar / (double)(1ll << s->lmax);
-    }
     // tile lists: substep i of the barrier interval (each simulation runs
-    // its own 2^lmax substeps; shorter schedules idle at the end)
+    // its own 2^lmax substeps; shorter schedules idle at the end).  Active
+    // levels lmax..lmin of a simulation occupy [0, cnt_ge[lmin]), finest
+    // first, and tiles do not straddle levels.  The tiles are counted first
+    // and then written straight into the pinned staging area.
     const long long nsub = 1ll << P.lmax_all;
-    std::vector<BatchTile> tiles;
+    auto lmin_of = [](long long i, int lmax) {
+        int v2 = 0;
+        while (i > 0 && ((i >> v2) & 1) == 0) v2++;
+        return i == 0 ? 0 : lmax - v2;
+    };
+    auto level_range = [](const mdlts_sim *s, int l, int &lo, int &hi) {
+        lo = l == s->lmax ? 0 : s->cnt_ge[l + 1];
+        hi = s->cnt_ge[l];
+    };
     G.tile_off.assign(nsub + 1, 0);
+    size_t nt = 0;
     for (long long i = 0; i < nsub; i++) {
-        G.tile_off[i] = (int)tiles.size();
+        G.tile_off[i] = (int)nt;
         for (int q = 0; q < nm; q++) {
-            mdlts_sim *s = P.sims[G.members[q]];
+            const mdlts_sim *s = P.sims[G.members[q]];
             if (i >= (1ll << s->lmax)) continue;
-            int v2 = 0;
-            while (i > 0 && ((i >> v2) & 1) == 0) v2++;
-            const int lmin = i == 0 ? 0 : s->lmax - v2;
-            BatchTile tt{};  // array addresses here; offsets from the base below
-            tt.off_u = (long long)(uintptr_t)s->u_s.p;
-            tt.off_v = (long long)(uintptr_t)s->v_s.p;
-            tt.off_key = (long long)(uintptr_t)s->key_s.p;
-            tt.off_nbr = (long long)(uintptr_t)s->nbr_s.p;
-            tt.off_fine = (long long)(uintptr_t)s->fine_s.p;
-            tt.sim = q;
-            tt.node_bytes = (uint32_t)((size_t)s->cap * sizeof(T));
-            tt.slot_bytes = (uint32_t)((size_t)s->np * s->cap * sizeof(T));
-            const int parity = (int)(s->n_since_assign & 1);
-            // active levels lmax..lmin occupy [0, cnt_ge[lmin]), finest first;
-            // tiles do not straddle levels
-            for (int l = s->lmax; l >= lmin; l--) {
-                const int lo = l == s->lmax ? 0 : s->cnt_ge[l + 1], hi = s->cnt_ge[l];
-                for (int st = lo; st < hi; st += P.block) {
-                    tt.start = st;
-                    tt.count = std::min(P.block, hi - st);
-                    tt.packed = l | parity << 4 | s->lmax << 8;
-                    tiles.push_back(tt);
-                }
+            for (int l = s->lmax; l >= lmin_of(i, s->lmax); l--) {
+                int lo, hi;
+                level_range(s, l, lo, hi);
+                if (hi > lo) nt += (size_t)((hi - lo + P.block - 1) / P.block);
             }
         }
     }
-    G.tile_off[nsub] = (int)tiles.size();
-    // the tile list of the barrier after: same tiles, the other parity
-    const size_t nt = tiles.size();
+    G.tile_off[nsub] = (int)nt;
     G.n_tiles = (int)nt;
-    for (size_t k = 0; k < nt; k++) {
-        BatchTile tt = tiles[k];
-        tt.packed ^= 1 << 4;
-        tiles.push_back(tt);
-    }
-    G.hclk.resize(2 * (size_t)nm);
-    for (int q = 0; q < nm; q++) G.hclk[q] = G.hclk[nm + q] = BatchClock{P.sims[G.members[q]]->n_bar};
-    // descriptors, clocks and tiles in one buffer, uploaded in one copy
-    // through the pinned staging area
+    // descriptors, clocks and both tile lists (this barrier's parity and the
+    // next one's) in one buffer, uploaded in one copy
     const size_t b_d = (size_t)nm * sizeof(BatchSim<T>), b_c = 2 * (size_t)nm * sizeof(BatchClock);
-    const size_t b_t = tiles.size() * sizeof(BatchTile);
+    const size_t b_t = 2 * nt * sizeof(BatchTile);
     G.off_clocks = (b_d + 255) / 256 * 256;
     G.off_tiles = G.off_clocks + (b_c + 255) / 256 * 256;
     const size_t total = G.off_tiles + std::max<size_t>(b_t, sizeof(BatchTile));
     MD_TRY(dev_alloc(c, G.data, total));
     G.base = static_cast<char *>(G.data.p);
     const long long base = (long long)(uintptr_t)G.base;
-    for (BatchTile &tt : tiles) {
-        tt.off_u -= base;
-        tt.off_v -= base;
-        tt.off_key -= base;
-        tt.off_nbr -= base;
-        tt.off_fine -= base;
-    }
     char *st = nullptr;
     MD_TRY(stage_acquire(c, total, &st));
-    std::memcpy(st, d.data(), b_d);
+    for (int q = 0; q < nm; q++) {
+        mdlts_sim *s = P.sims[G.members[q]];
+        BatchSim<T> d;
+        std::memset(&d, 0, sizeof(d));
+        fill_step_args<T>(s, d.a);
+        d.t_start = s->t_start;
+        d.h_tick = s->dt_bar / (double)(1ll << s->lmax);
+        std::memcpy(st + (size_t)q * sizeof(BatchSim<T>), &d, sizeof(d));
+    }
+    G.hclk.resize(2 * (size_t)nm);
+    for (int q = 0; q < nm; q++) G.hclk[q] = G.hclk[nm + q] = BatchClock{P.sims[G.members[q]]->n_bar};
     std::memcpy(st + G.off_clocks, G.hclk.data(), b_c);
-    if (b_t) std::memcpy(st + G.off_tiles, tiles.data(), b_t);
+    char *t0 = st + G.off_tiles;                      // this barrier's parity
+    char *t1 = t0 + nt * sizeof(BatchTile);           // the barrier after: the other parity
+    size_t k = 0;
+    for (long long i = 0; i < nsub; i++)
+        for (int q = 0; q < nm; q++) {
+            const mdlts_sim *s = P.sims[G.members[q]];
+            if (i >= (1ll << s->lmax)) continue;
+            BatchTile tt{};  // array locations as offsets from the buffer's base
+            tt.off_u = (long long)(uintptr_t)s->u_s.p - base;
+            tt.off_v = (long long)(uintptr_t)s->v_s.p - base;
+            tt.off_key = (long long)(uintptr_t)s->key_s.p - base;
+            tt.off_nbr = (long long)(uintptr_t)s->nbr_s.p - base;
+            tt.off_fine = (long long)(uintptr_t)s->fine_s.p - base;
+            tt.sim = q;
+            tt.node_bytes = (uint32_t)((size_t)s->cap * sizeof(T));
+            tt.slot_bytes = (uint32_t)((size_t)s->np * s->cap * sizeof(T));
+            const int parity = (int)(s->n_since_assign & 1);
+            for (int l = s->lmax; l >= lmin_of(i, s->lmax); l--) {
+                int lo, hi;
+                level_range(s, l, lo, hi);
+                for (int sa = lo; sa < hi; sa += P.block) {
+                    tt.start = sa;
+                    tt.count = std::min(P.block, hi - sa);
+                    tt.packed = l | parity << 4 | s->lmax << 8;
+                    std::memcpy(t0 + k * sizeof(BatchTile), &tt, sizeof(tt));
+                    tt.packed ^= 1 << 4;
+                    std::memcpy(t1 + k * sizeof(BatchTile), &tt, sizeof(tt));
+                    k++;
+                }
+            }
+        }
+    if (k != nt) return MDLTS_EINVAL;  // the two passes disagree (cannot happen)
     HIP_TRY(hipMemcpyAsync(G.data.p, st, G.off_tiles + b_t, hipMemcpyHostToDevice, c->stream));
     return stage_release(c);
 }
