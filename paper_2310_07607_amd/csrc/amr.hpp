@@ -111,49 +111,53 @@ __global__ __launch_bounds__(256) void k_mesh_faces(int E, const MeshGeo g, cons
                                                     uint32_t *fine, int *bad)
 {
     constexpr int NS = DIM == 2 ? 2 : 4;
-    const int e = blockIdx.x * 256 + threadIdx.x;
-    if (e >= E) return;
+    // one thread per (face, element): face f = 2k + s of element e, elements
+    // fastest, so that the key loads and the table stores are coalesced and
+    // the faces' neighbour searches run side by side
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= 2ll * DIM * E) return;
+    const int f = (int)(i / E);
+    const int e = (int)(i - (long long)f * E);
     int d;
     uint32_t c[3] = {0, 0, 0};
     unpack_key<DIM>(key[e], d, c);
-    for (int k = 0; k < DIM; k++)
-        for (int s = 0; s < 2; s++) {
-            const int f = 2 * k + s;
-            uint32_t t[3] = {c[0], c[1], c[2]};
-            uint32_t entry = kBoundary << 30;
-            const bool inside = s ? (c[k] + 1 < ((uint32_t)g.n[k] << d)) : (c[k] > 0);
-            if (inside) {
-                t[k] = s ? c[k] + 1 : c[k] - 1;
-                const int id = find_containing<DIM>(g, root_start, mkey, d, t);
-                int dn;
-                uint32_t cn[3] = {0, 0, 0};
-                unpack_key<DIM>(key[id], dn, cn);
-                if (dn == d) {
-                    entry = (kSame << 30) | (uint32_t)id;
-                } else if (dn + 1 == d) {
-                    entry = (kCoarser << 30) | (uint32_t)id;
-                } else if (dn > d) {
-                    const int want = s ? 0 : 1;
-                    int q = 0;
-                    for (int ci = 0; ci < (1 << DIM); ci++) {
-                        if (((ci >> k) & 1) != want) continue;
-                        uint32_t cc[3] = {0, 0, 0};
-                        for (int p = 0; p < DIM; p++) cc[p] = 2 * t[p] + ((ci >> p) & 1);
-                        const int fid = find_containing<DIM>(g, root_start, mkey, d + 1, cc);
-                        int df;
-                        uint32_t cf[3];
-                        unpack_key<DIM>(key[fid], df, cf);
-                        if (df != d + 1) atomicOr(bad, 1);
-                        fine[((long long)f * E + e) * NS + q] = (uint32_t)fid;
-                        q++;
-                    }
-                    entry = kFiner << 30;
-                } else {
-                    atomicOr(bad, 1);
+    {
+        const int k = f >> 1, s = f & 1;
+        uint32_t t[3] = {c[0], c[1], c[2]};
+        uint32_t entry = kBoundary << 30;
+        const bool inside = s ? (c[k] + 1 < ((uint32_t)g.n[k] << d)) : (c[k] > 0);
+        if (inside) {
+            t[k] = s ? c[k] + 1 : c[k] - 1;
+            const int id = find_containing<DIM>(g, root_start, mkey, d, t);
+            int dn;
+            uint32_t cn[3] = {0, 0, 0};
+            unpack_key<DIM>(key[id], dn, cn);
+            if (dn == d) {
+                entry = (kSame << 30) | (uint32_t)id;
+            } else if (dn + 1 == d) {
+                entry = (kCoarser << 30) | (uint32_t)id;
+            } else if (dn > d) {
+                const int want = s ? 0 : 1;
+                int q = 0;
+                for (int ci = 0; ci < (1 << DIM); ci++) {
+                    if (((ci >> k) & 1) != want) continue;
+                    uint32_t cc[3] = {0, 0, 0};
+                    for (int p = 0; p < DIM; p++) cc[p] = 2 * t[p] + ((ci >> p) & 1);
+                    const int fid = find_containing<DIM>(g, root_start, mkey, d + 1, cc);
+                    int df;
+                    uint32_t cf[3];
+                    unpack_key<DIM>(key[fid], df, cf);
+                    if (df != d + 1) atomicOr(bad, 1);
+                    fine[((long long)f * E + e) * NS + q] = (uint32_t)fid;
+                    q++;
                 }
+                entry = kFiner << 30;
+            } else {
+                atomicOr(bad, 1);
             }
-            face[(long long)f * E + e] = entry;
         }
+        face[(long long)f * E + e] = entry;
+    }
 }
 
 // ---- adaptation ------------------------------------------------------------

@@ -117,39 +117,46 @@ __global__ __launch_bounds__(kBlock) void k_min_positive(int n, const double *x,
 // exclusive offsets of every (block, level) in the finest-first order
 __global__ __launch_bounds__(kBlock) void k_level_scan(int *hist, int nb, int n_levels, int *cnt_ge)
 {
-    __shared__ int part[kBlock][kMaxLevels];
+    __shared__ int wtot[kBlock / 64][kMaxLevels];
     __shared__ int base[kMaxLevels];
     const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
     const int chunk = (nb + kBlock - 1) / kBlock;
     const int b0 = t * chunk, b1 = min(nb, b0 + chunk);
+    // this thread's rows, summed per level, then scanned over the block's
+    // threads: wavefront inclusive scans by shuffles, then the waves' totals
+    int excl[kMaxLevels];
+#pragma unroll
     for (int l = 0; l < kMaxLevels; l++) {
-        int s = 0;
-        for (int b = b0; b < b1; b++) s += hist[b * kMaxLevels + l];
-        part[t][l] = s;
-    }
-    __syncthreads();
-    if (t < kMaxLevels) {
-        int run = 0;
-        for (int q = 0; q < kBlock; q++) {
-            const int v = part[q][t];
-            part[q][t] = run;
-            run += v;
+        int v = 0;
+        for (int b = b0; b < b1; b++) v += hist[b * kMaxLevels + l];
+        int x = v;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
         }
-        base[t] = run;  // total per level for now
+        if (lane == 63) wtot[wave][l] = x;
+        excl[l] = x - v;
     }
     __syncthreads();
+#pragma unroll
+    for (int l = 0; l < kMaxLevels; l++)
+        for (int w = 0; w < wave; w++) excl[l] += wtot[w][l];
     if (t == 0) {
         int run = 0;
         for (int l = kMaxLevels - 1; l >= 0; l--) {
-            const int tot = base[l];
+            int tot = 0;  // leaves of level l
+            for (int w = 0; w < kBlock / 64; w++) tot += wtot[w][l];
             base[l] = run;  // leaves of finer levels come first
             run += tot;
             cnt_ge[l] = l < n_levels ? run : 0;  // every entry written
         }
     }
     __syncthreads();
+#pragma unroll
     for (int l = 0; l < kMaxLevels; l++) {
-        int run = base[l] + part[t][l];
+        int run = base[l] + excl[l];
         for (int b = b0; b < b1; b++) {
             const int v = hist[b * kMaxLevels + l];
             hist[b * kMaxLevels + l] = run;
@@ -858,13 +865,13 @@ mdlts_status device_faces(mdlts_sim *s, bool own_flags = true)
     if (dim == 2) {
         k_mesh_index<2><<<nblocks(E), kBlock, 0, c->stream>>>(E, n_roots, g, P<uint32_t>(s->key_c),
                                                                P<int>(s->root_start), P<uint32_t>(s->mkey));
-        k_mesh_faces<2><<<nblocks(E), kBlock, 0, c->stream>>>(E, g, P<uint32_t>(s->key_c), P<int>(s->root_start),
+        k_mesh_faces<2><<<nblocks(2ll * 2 * E), kBlock, 0, c->stream>>>(E, g, P<uint32_t>(s->key_c), P<int>(s->root_start),
                                                                P<uint32_t>(s->mkey), P<uint32_t>(s->face_c),
                                                                P<uint32_t>(s->fine_c), bad);
     } else {
         k_mesh_index<3><<<nblocks(E), kBlock, 0, c->stream>>>(E, n_roots, g, P<uint64_t>(s->key_c),
                                                                P<int>(s->root_start), P<uint32_t>(s->mkey));
-        k_mesh_faces<3><<<nblocks(E), kBlock, 0, c->stream>>>(E, g, P<uint64_t>(s->key_c), P<int>(s->root_start),
+        k_mesh_faces<3><<<nblocks(2ll * 3 * E), kBlock, 0, c->stream>>>(E, g, P<uint64_t>(s->key_c), P<int>(s->root_start),
                                                                P<uint32_t>(s->mkey), P<uint32_t>(s->face_c),
                                                                P<uint32_t>(s->fine_c), bad);
     }
