@@ -1320,8 +1320,10 @@ struct BatchGroup {
     BatchClock *clocks() const { return reinterpret_cast<BatchClock *>(static_cast<char *>(data.p) + off_clocks); }
     BatchTile *tiles() const { return reinterpret_cast<BatchTile *>(static_cast<char *>(data.p) + off_tiles); }
     std::vector<BatchClock> hclk;  // host source of the clock uploads
-    std::vector<int> tile_off;  // [2^lmax_all + 1] offsets into tiles per substep
-    int n_tiles = 0;            // tiles per barrier; the device list holds two copies (phases)
+    // substep i launches tile_count[i] tiles from tile_start[i]; substeps
+    // whose active sets are the same share one list
+    std::vector<int> tile_start, tile_count;
+    int n_tiles = 0;  // tiles in the distinct lists; the device holds two copies (phases)
     char *base = nullptr;
 };
 
@@ -1435,21 +1437,41 @@ mdlts_status fill_group(mdlts_ctx *c, BatchPlan &P, BatchGroup &G)
         lo = l == s->lmax ? 0 : s->cnt_ge[l + 1];
         hi = s->cnt_ge[l];
     };
-    G.tile_off.assign(nsub + 1, 0);
+    // a substep's list is fixed by each member's lowest active level (-1:
+    // past the member's schedule); the distinct lists are kept once each
+    std::map<std::vector<int>, int> seen;  // active levels -> list
+    std::vector<long long> first;          // first substep of each list
+    G.tile_start.assign(nsub, 0);
+    G.tile_count.assign(nsub, 0);
     size_t nt = 0;
+    std::vector<int> sig(nm);
     for (long long i = 0; i < nsub; i++) {
-        G.tile_off[i] = (int)nt;
         for (int q = 0; q < nm; q++) {
             const mdlts_sim *s = P.sims[G.members[q]];
-            if (i >= (1ll << s->lmax)) continue;
-            for (int l = s->lmax; l >= lmin_of(i, s->lmax); l--) {
+            sig[q] = i < (1ll << s->lmax) ? lmin_of(i, s->lmax) : -1;
+        }
+        auto it = seen.find(sig);
+        if (it != seen.end()) {
+            G.tile_start[i] = G.tile_start[first[it->second]];
+            G.tile_count[i] = G.tile_count[first[it->second]];
+            continue;
+        }
+        seen.emplace(sig, (int)first.size());
+        first.push_back(i);
+        size_t n_i = 0;
+        for (int q = 0; q < nm; q++) {
+            if (sig[q] < 0) continue;
+            const mdlts_sim *s = P.sims[G.members[q]];
+            for (int l = s->lmax; l >= sig[q]; l--) {
                 int lo, hi;
                 level_range(s, l, lo, hi);
-                if (hi > lo) nt += (size_t)((hi - lo + P.block - 1) / P.block);
+                if (hi > lo) n_i += (size_t)((hi - lo + P.block - 1) / P.block);
             }
         }
+        G.tile_start[i] = (int)nt;
+        G.tile_count[i] = (int)n_i;
+        nt += n_i;
     }
-    G.tile_off[nsub] = (int)nt;
     G.n_tiles = (int)nt;
     // descriptors, clocks and both tile lists (this barrier's parity and the
     // next one's) in one buffer, uploaded in one copy
@@ -1478,7 +1500,7 @@ mdlts_status fill_group(mdlts_ctx *c, BatchPlan &P, BatchGroup &G)
     char *t0 = st + G.off_tiles;                      // this barrier's parity
     char *t1 = t0 + nt * sizeof(BatchTile);           // the barrier after: the other parity
     size_t k = 0;
-    for (long long i = 0; i < nsub; i++)
+    for (const long long i : first)
         for (int q = 0; q < nm; q++) {
             const mdlts_sim *s = P.sims[G.members[q]];
             if (i >= (1ll << s->lmax)) continue;
@@ -1570,10 +1592,10 @@ mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, int phase, hipGraph_t grap
     for (long long i = 0; i < nsub; i++) {
         cur.clear();
         for (auto &G : P.groups) {
-            int n_t = G.tile_off[i + 1] - G.tile_off[i];
+            int n_t = G.tile_count[i];
             if (n_t == 0) continue;
             const void *descs = G.descs();
-            const BatchTile *tl = G.tiles() + (size_t)phase * G.n_tiles + G.tile_off[i];
+            const BatchTile *tl = G.tiles() + (size_t)phase * G.n_tiles + G.tile_start[i];
             int ii = (int)i;
             char *base = G.base;
             const int nm = (int)G.members.size();
