@@ -200,7 +200,8 @@ mdlts_status mdlts_step(mdlts_sim *sim, int n_barriers);
  * until a simulation of the list changes and, when it holds more than one
  * kernel variant, replayed as a HIP graph; the first barriers of a new
  * list time the candidate launch shapes (threads per block, one block per
- * tile) and keep the fastest.  Asynchronous on the context stream.  EINVAL for a
+ * tile) and keep the fastest for each kernel variant.  Asynchronous on the
+ * context stream.  EINVAL for a
  * repeated or foreign simulation, ESTATE if levels are not assigned. */
 mdlts_status mdlts_batch_step(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sims, int n_barriers);
 /* Error indicator, adaptation and level assignment of several simulations
@@ -223,8 +224,9 @@ mdlts_status mdlts_batch_adapt(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sim
 mdlts_status mdlts_set_graphs(mdlts_ctx *ctx, int enable);
 /* Event timing of the batched substep launches (launched directly while
  * enabled); read returns kernel ms, launches, DoF-updates since the last
- * read, and the launch shape in use (threads per block; per_cu is always 0:
- * one block per tile).  ESTATE before the first mdlts_batch_step. */
+ * read, and the launch shape in use (threads per block of the kernel variant
+ * with the most device time; per_cu is always 0: one block per tile).
+ * ESTATE before the first mdlts_batch_step. */
 mdlts_status mdlts_batch_profile(mdlts_ctx *ctx, int enable);
 mdlts_status mdlts_batch_profile_read(mdlts_ctx *ctx, double *substep_ms, uint64_t *n_launches,
                                       uint64_t *dof_updates, int *block, int *per_cu);

@@ -578,10 +578,11 @@ struct mdlts_ctx {
     int n_sims = 0;  // live simulations; the context outlives them
     BatchPlan *batch = nullptr;
     int use_graphs = 1;
-    // launch shape chosen by the autotuner, per mix of kernel variants
+    // launch shapes chosen by the autotuner, per mix of kernel variants
     // (bit 12*full + 6*(dim-2) + 2*(order-1) + precision)
     struct Tuned {
-        int block, per_cu;
+        std::map<int, int> blocks;  // variant bit -> threads per block
+        int block;                  // that of the variant with the most device time
         double dof;  // DoF-updates per barrier of the plan it was tuned on
         bool single_graph;
     };
@@ -1311,6 +1312,8 @@ mdlts_status compute_G(mdlts_sim *s)
 struct BatchGroup {
     int dim = 2, order = 1, prec = 0;
     bool full = false;  // off-diagonal diffusion tensors (their own kernels)
+    int block = 256;    // threads per block (= elements per tile), tuned per variant
+    int variant_bit() const { return 12 * (full ? 1 : 0) + 6 * (dim - 2) + 2 * (order - 1) + (prec == MDLTS_FP32 ? 1 : 0); }
     std::vector<int> members;   // indices into BatchPlan::sims
     // one device buffer: descriptors [members] BatchSim, clocks [2][members]
     // BatchClock, tiles [2 phases][n_tiles] BatchTile (one upload)
@@ -1465,7 +1468,7 @@ mdlts_status fill_group(mdlts_ctx *c, BatchPlan &P, BatchGroup &G)
             for (int l = s->lmax; l >= sig[q]; l--) {
                 int lo, hi;
                 level_range(s, l, lo, hi);
-                if (hi > lo) n_i += (size_t)((hi - lo + P.block - 1) / P.block);
+                if (hi > lo) n_i += (size_t)((hi - lo + G.block - 1) / G.block);
             }
         }
         G.tile_start[i] = (int)nt;
@@ -1517,9 +1520,9 @@ mdlts_status fill_group(mdlts_ctx *c, BatchPlan &P, BatchGroup &G)
             for (int l = s->lmax; l >= lmin_of(i, s->lmax); l--) {
                 int lo, hi;
                 level_range(s, l, lo, hi);
-                for (int sa = lo; sa < hi; sa += P.block) {
+                for (int sa = lo; sa < hi; sa += G.block) {
                     tt.start = sa;
-                    tt.count = std::min(P.block, hi - sa);
+                    tt.count = std::min(G.block, hi - sa);
                     tt.packed = l | parity << 4 | s->lmax << 8;
                     std::memcpy(t0 + k * sizeof(BatchTile), &tt, sizeof(tt));
                     tt.packed ^= 1 << 4;
@@ -1559,9 +1562,14 @@ int grid_of(const BatchPlan &P, int n_tiles)
 enum EmitMode { kEmitLaunch, kEmitGraph, kEmitUpdate, kEmitKeys };
 
 mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, int phase, hipGraph_t graph, EmitMode mode = kEmitLaunch,
-                          std::vector<long long> *keys = nullptr)
+                          std::vector<long long> *keys = nullptr, std::vector<hipEvent_t> *timed = nullptr,
+                          std::vector<int> *timed_group = nullptr)
 {
+    // timed (direct launches only): an event pair around every launch, and
+    // the index of the launch's group in timed_group
     if (graph) mode = kEmitGraph;
+    if (mode != kEmitLaunch) timed = nullptr;
+    size_t n_timed = 0;
     const long long nsub = 1ll << P.lmax_all;
     std::vector<hipGraphNode_t> prev, cur;
     size_t n_node = 0;
@@ -1613,8 +1621,21 @@ mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, int phase, hipGraph_t grap
             }
             const long long key = i * 64 + 12 * (G.full ? 1 : 0) + 6 * (G.dim - 2) + 2 * (G.order - 1) +
                                   (G.prec == MDLTS_FP32 ? 1 : 0);
-            MD_TRY(add(key, batch_kernel(G.dim, G.order, G.prec, G.full), grid_of(P, n_t), P.block,
-                       gate_lds_bytes(G.dim, G.order, G.prec == MDLTS_FP32, P.block), args));
+            if (timed) {
+                while (timed->size() < 2 * (n_timed + 1)) {
+                    hipEvent_t e;
+                    HIP_TRY(hipEventCreate(&e));
+                    timed->push_back(e);
+                }
+                HIP_TRY(hipEventRecord((*timed)[2 * n_timed], c->stream));
+            }
+            MD_TRY(add(key, batch_kernel(G.dim, G.order, G.prec, G.full), grid_of(P, n_t), G.block,
+                       gate_lds_bytes(G.dim, G.order, G.prec == MDLTS_FP32, G.block), args));
+            if (timed) {
+                HIP_TRY(hipEventRecord((*timed)[2 * n_timed + 1], c->stream));
+                if (timed_group) timed_group->push_back((int)(&G - P.groups.data()));
+                n_timed++;
+            }
             if (prof) {
                 HIP_TRY(hipEventRecord(P.ev[2 * P.ev_used + 1], c->stream));
                 P.ev_used++;
@@ -1709,49 +1730,82 @@ mdlts_status run_batch_barriers(mdlts_ctx *c, BatchPlan &P, int nb)
     return MDLTS_OK;
 }
 
+// the tuned launch shapes of a plan's mix of kernel variants
+void ctx_tuned_store(mdlts_ctx *c, const BatchPlan &P, double dof)
+{
+    mdlts_ctx::Tuned t;
+    for (const BatchGroup &G : P.groups) t.blocks[G.variant_bit()] = G.block;
+    t.block = P.block;
+    t.dof = dof;
+    t.single_graph = P.single_graph;
+    c->tuned[P.variant_mask] = t;
+}
+
 // Autotuner: the first barriers of a new plan are run with each candidate
-// launch shape (block size; one block per tile), in rounds over the
-// candidates, and timed with events (one warm and one timed barrier per
-// candidate and round); the shape with the smallest time over the rounds is
-// kept.  A one-variant plan then times graph replay of that shape against
+// block size (threads per block = elements per tile; one block per tile),
+// the same for every kernel variant, in rounds over the candidates, with an
+// event pair around every launch (one warm and one timed barrier per
+// candidate and round).  Each variant keeps the candidate with its smallest
+// launch time summed over the barrier, taking the best round: the variants
+// differ (small elements favour small blocks, 27-node hexahedra large
+// ones).  A one-variant plan then times graph replay of its shape against
 // its direct launches.  Per-element arithmetic does not depend on the
 // choice, so results are unchanged.
 mdlts_status autotune(mdlts_ctx *c, BatchPlan &P, int *remaining)
 {
-    struct Cand { int block, per_cu; };
-    const Cand cands[] = {{256, 0}, {128, 0}, {64, 0}};
+    const int cands[] = {256, 128, 64};
     constexpr int n_cand = (int)(sizeof(cands) / sizeof(cands[0]));
     constexpr int rounds = 2;
     if (*remaining < n_cand * rounds * 2) return MDLTS_OK;
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    float best[n_cand];
-    for (int k = 0; k < n_cand; k++) best[k] = 1e30f;
+    struct Events {  // destroyed on every return
+        std::vector<hipEvent_t> v;
+        ~Events()
+        {
+            for (hipEvent_t e : v) (void)hipEventDestroy(e);
+        }
+    } tev, pair;
+    pair.v.resize(2, nullptr);
+    HIP_TRY(hipEventCreate(&pair.v[0]));
+    HIP_TRY(hipEventCreate(&pair.v[1]));
+    hipEvent_t e0 = pair.v[0], e1 = pair.v[1];
+    const size_t ng = P.groups.size();
+    std::vector<double> best(ng * n_cand, 1e300);
+    std::vector<int> tgrp;
     const bool saved_prof = P.prof;
     P.prof = false;
     for (int rd = 0; rd < rounds; rd++)
         for (int k = 0; k < n_cand; k++) {
-            P.block = cands[k].block;
-            P.per_cu = cands[k].per_cu;
+            for (BatchGroup &G : P.groups) G.block = cands[k];
             MD_TRY(build_plan_data(c, P));
             MD_TRY(emit_barrier(c, P, P.phase, nullptr));  // warm
             account_barriers(P, 1);
-            HIP_TRY(hipEventRecord(e0, c->stream));
-            MD_TRY(emit_barrier(c, P, P.phase, nullptr));
+            tgrp.clear();
+            MD_TRY(emit_barrier(c, P, P.phase, nullptr, kEmitLaunch, nullptr, &tev.v, &tgrp));
             account_barriers(P, 1);
-            HIP_TRY(hipEventRecord(e1, c->stream));
-            HIP_TRY(hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-            best[k] = std::min(best[k], ms);
             *remaining -= 2;
+            if (tgrp.empty()) continue;
+            HIP_TRY(hipEventSynchronize(tev.v[2 * tgrp.size() - 1]));
+            std::vector<double> sum(ng, 0.0);
+            for (size_t n = 0; n < tgrp.size(); n++) {
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, tev.v[2 * n], tev.v[2 * n + 1]));
+                sum[tgrp[n]] += ms;
+            }
+            for (size_t g = 0; g < ng; g++) best[g * n_cand + k] = std::min(best[g * n_cand + k], sum[g]);
         }
-    int pick = 0;
-    for (int k = 1; k < n_cand; k++)
-        if (best[k] < best[pick]) pick = k;
-    P.block = cands[pick].block;
-    P.per_cu = cands[pick].per_cu;
+    // each variant its fastest candidate; the plan reports the block size
+    // of the variant with the most device time
+    double top = -1.0;
+    for (size_t g = 0; g < ng; g++) {
+        int pick = 0;
+        for (int k = 1; k < n_cand; k++)
+            if (best[g * n_cand + k] < best[g * n_cand + pick]) pick = k;
+        P.groups[g].block = cands[pick];
+        if (best[g * n_cand + pick] > top) {
+            top = best[g * n_cand + pick];
+            P.block = cands[pick];
+        }
+    }
     // one kernel variant: graph replay against direct launches of the
     // chosen shape, each over a run of barriers (the host runs ahead of the
     // device in both; long chains of short launches favour the graph, a
@@ -1784,13 +1838,11 @@ mdlts_status autotune(mdlts_ctx *c, BatchPlan &P, int *remaining)
         }
         P.single_graph = t_graph < t_direct;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     P.prof = saved_prof;
     P.tuned = true;
     double dof = 0.0;
     for (uint64_t d : P.dof_per_barrier) dof += (double)d;
-    c->tuned[P.variant_mask] = {P.block, P.per_cu, dof, P.single_graph};
+    ctx_tuned_store(c, P, dof);
     return build_plan_data(c, P);
 }
 
@@ -1858,8 +1910,7 @@ mdlts_status prepare_plan(mdlts_ctx *c, BatchPlan *&slot, mdlts_sim *const *sims
                     std::swap(G.data, O.data);
                     break;
                 }
-    for (const BatchGroup &g : P->groups)
-        P->variant_mask |= 1 << (12 * (g.full ? 1 : 0) + 6 * (g.dim - 2) + 2 * (g.order - 1) + (g.prec == MDLTS_FP32 ? 1 : 0));
+    for (const BatchGroup &g : P->groups) P->variant_mask |= 1 << g.variant_bit();
     // a mix of variants tuned before keeps its launch shape while the work
     // per barrier stays within 25 % of what it was tuned on (the best shape
     // moves as meshes refine)
@@ -1867,8 +1918,11 @@ mdlts_status prepare_plan(mdlts_ctx *c, BatchPlan *&slot, mdlts_sim *const *sims
     double dof = 0.0;
     for (uint64_t d : P->dof_per_barrier) dof += (double)d;
     if (tk != c->tuned.end() && std::fabs(dof - tk->second.dof) <= 0.25 * tk->second.dof) {
+        for (BatchGroup &G : P->groups) {
+            const auto b = tk->second.blocks.find(G.variant_bit());
+            G.block = b != tk->second.blocks.end() ? b->second : tk->second.block;
+        }
         P->block = tk->second.block;
-        P->per_cu = tk->second.per_cu;
         P->single_graph = tk->second.single_graph;
         P->tuned = true;
     }
