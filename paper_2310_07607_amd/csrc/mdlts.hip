@@ -1557,8 +1557,10 @@ int grid_of(const BatchPlan &P, int n_tiles)
 }
 
 // one barrier interval reading clock copy `phase`: launches on the stream,
-// or kernel nodes of a graph (the launches of one substep, one per kernel
-// variant, depend on all launches of the previous substep, not on each other)
+// or kernel nodes of a graph.  In a graph each kernel variant's launches
+// form a chain of their own (substep after substep): the variants hold
+// disjoint simulations, so one variant's later substeps overlap another's
+// longer launches.
 enum EmitMode { kEmitLaunch, kEmitGraph, kEmitUpdate, kEmitKeys };
 
 mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, int phase, hipGraph_t graph, EmitMode mode = kEmitLaunch,
@@ -1571,9 +1573,9 @@ mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, int phase, hipGraph_t grap
     if (mode != kEmitLaunch) timed = nullptr;
     size_t n_timed = 0;
     const long long nsub = 1ll << P.lmax_all;
-    std::vector<hipGraphNode_t> prev, cur;
+    std::vector<hipGraphNode_t> last(P.groups.size(), nullptr);  // per group: its previous node
     size_t n_node = 0;
-    auto add = [&](long long key, void *fn, int grid, int block, size_t lds, void **args) -> mdlts_status {
+    auto add = [&](long long key, size_t g, void *fn, int grid, int block, size_t lds, void **args) -> mdlts_status {
         hipKernelNodeParams kp{};
         kp.func = fn;
         kp.gridDim = dim3(grid);
@@ -1583,8 +1585,8 @@ mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, int phase, hipGraph_t grap
         kp.extra = nullptr;
         if (mode == kEmitGraph) {
             hipGraphNode_t node;
-            HIP_TRY(hipGraphAddKernelNode(&node, graph, prev.empty() ? nullptr : prev.data(), prev.size(), &kp));
-            cur.push_back(node);
+            HIP_TRY(hipGraphAddKernelNode(&node, graph, last[g] ? &last[g] : nullptr, last[g] ? 1 : 0, &kp));
+            last[g] = node;
             P.nodes[phase].push_back(node);
             if (keys) keys->push_back(key);
         } else if (mode == kEmitUpdate) {
@@ -1598,7 +1600,6 @@ mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, int phase, hipGraph_t grap
         return MDLTS_OK;
     };
     for (long long i = 0; i < nsub; i++) {
-        cur.clear();
         for (auto &G : P.groups) {
             int n_t = G.tile_count[i];
             if (n_t == 0) continue;
@@ -1629,11 +1630,12 @@ mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, int phase, hipGraph_t grap
                 }
                 HIP_TRY(hipEventRecord((*timed)[2 * n_timed], c->stream));
             }
-            MD_TRY(add(key, batch_kernel(G.dim, G.order, G.prec, G.full), grid_of(P, n_t), G.block,
+            const size_t g = (size_t)(&G - P.groups.data());
+            MD_TRY(add(key, g, batch_kernel(G.dim, G.order, G.prec, G.full), grid_of(P, n_t), G.block,
                        gate_lds_bytes(G.dim, G.order, G.prec == MDLTS_FP32, G.block), args));
             if (timed) {
                 HIP_TRY(hipEventRecord((*timed)[2 * n_timed + 1], c->stream));
-                if (timed_group) timed_group->push_back((int)(&G - P.groups.data()));
+                if (timed_group) timed_group->push_back((int)g);
                 n_timed++;
             }
             if (prof) {
@@ -1642,7 +1644,6 @@ mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, int phase, hipGraph_t grap
                 P.prof_launches++;
             }
         }
-        if (!cur.empty()) prev.swap(cur);
     }
     return MDLTS_OK;
 }
