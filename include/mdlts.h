@@ -216,8 +216,8 @@ mdlts_status mdlts_batch_step(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sims
 mdlts_status mdlts_batch_adapt(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sims, double tau_refine,
                                double tau_coarsen, const double *dt_barrier);
 /* enable = 1 (default): batches whose substeps launch more than one kernel
- * variant replay one graph per barrier (the variants' launches run
- * concurrently); single-variant plans (mdlts_step, or a batch of one
+ * variant replay one graph per barrier (each variant's launches form a
+ * chain of their own, and the chains run concurrently); single-variant plans (mdlts_step, or a batch of one
  * variant) launch their tile kernels directly or replay a graph, whichever
  * the autotuner timed faster.  enable = 0: every launch goes directly to the
  * stream, and mdlts_step uses the per-element kernel without tile lists. */

@@ -1715,10 +1715,10 @@ mdlts_status run_batch_barriers(mdlts_ctx *c, BatchPlan &P, int nb)
             if (P.ev_used + P.groups.size() * (1u << P.lmax_all) > kMaxEventPairs) MD_TRY(drain_batch_events(P));
             MD_TRY(emit_barrier(c, P, P.phase, nullptr));
         } else if (c->use_graphs && (P.groups.size() > 1 || P.single_graph)) {
-            // the launches of a substep's kernel variants run concurrently
-            // as independent graph nodes; a plan of one variant (a chain of
-            // dependent launches) replays a graph only if the autotuner
-            // found it faster than direct launches
+            // each kernel variant's launches are a chain of their own in
+            // the graph, and the chains run concurrently; a plan of one
+            // variant (a single chain) replays a graph only if the
+            // autotuner found it faster than direct launches
             if (!P.graph_valid) MD_TRY(build_graph(c, P));
             HIP_TRY(hipGraphLaunch(P.exec[P.phase], c->stream));
             P.graph_busy = true;
