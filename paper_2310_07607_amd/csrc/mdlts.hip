@@ -592,6 +592,11 @@ struct mdlts_ctx {
     void *stage = nullptr;
     size_t stage_bytes = 0;
     hipEvent_t stage_done = nullptr;
+    // auxiliary streams of the adaptation of several simulations, and the
+    // events that fork them from the context stream and join them back
+    std::vector<hipStream_t> aux;
+    hipEvent_t fork_ev = nullptr;
+    std::vector<hipEvent_t> join_ev;
     // completed synchronisations of the stream: work enqueued before the
     // last one has finished
     uint64_t sync_epoch = 0;
@@ -1931,6 +1936,60 @@ mdlts_status prepare_plan(mdlts_ctx *c, BatchPlan *&slot, mdlts_sim *const *sims
     return build_plan_data(c, *P);
 }
 
+// The adaptation work of several simulations side by side: simulation q's
+// work of a phase goes to auxiliary stream q mod kAuxStreams, which starts
+// after everything enqueued on the context stream before the phase (an
+// event) and which the context stream waits for at the phase's end.  Within
+// a phase the streams share no buffer: every buffer a phase frees (when it
+// grows) was last used before the phase began, and what it allocates
+// belongs to one simulation.
+constexpr int kAuxStreams = 4;
+
+struct AuxStreams {
+    mdlts_ctx *c;
+    hipStream_t main;
+    int n = 0;            // streams in use (0: the phase runs on the context stream)
+    bool forked = false;  // an error return still joins the streams
+    AuxStreams(mdlts_ctx *c_, int n_sims)
+        : c(c_), main(c_->stream), n(n_sims > 1 ? std::min(n_sims, kAuxStreams) : 0)
+    {
+    }
+    ~AuxStreams()
+    {
+        if (forked) (void)join();
+        c->stream = main;
+    }
+    mdlts_status fork()
+    {
+        if (n == 0) return MDLTS_OK;
+        while ((int)c->aux.size() < n) {
+            hipStream_t st;
+            HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+            c->aux.push_back(st);
+            hipEvent_t e;
+            HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            c->join_ev.push_back(e);
+        }
+        if (!c->fork_ev) HIP_TRY(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+        HIP_TRY(hipEventRecord(c->fork_ev, main));
+        for (int k = 0; k < n; k++) HIP_TRY(hipStreamWaitEvent(c->aux[k], c->fork_ev, 0));
+        forked = true;
+        return MDLTS_OK;
+    }
+    void use(int q) { c->stream = n ? c->aux[q % n] : main; }
+    mdlts_status join()
+    {
+        c->stream = main;
+        if (!forked) return MDLTS_OK;
+        forked = false;
+        for (int k = 0; k < n; k++) {
+            HIP_TRY(hipEventRecord(c->join_ev[k], c->aux[k]));
+            HIP_TRY(hipStreamWaitEvent(main, c->join_ev[k], 0));
+        }
+        return MDLTS_OK;
+    }
+};
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1977,6 +2036,12 @@ mdlts_status mdlts_ctx_destroy(mdlts_ctx *ctx)
     if (!ctx) return MDLTS_EINVAL;
     if (ctx->n_sims > 0) return MDLTS_EBUSY;
     free_plan(ctx, ctx->batch);
+    for (hipStream_t st : ctx->aux) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
+    for (hipEvent_t e : ctx->join_ev) (void)hipEventDestroy(e);
+    if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
     if (ctx->stage_done) (void)hipEventSynchronize(ctx->stage_done);
     if (ctx->stage) (void)hipHostFree(ctx->stage);
     if (ctx->stage_done) (void)hipEventDestroy(ctx->stage_done);
@@ -2632,8 +2697,11 @@ mdlts_status mdlts_batch_adapt(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sim
     // indicator and the counting half of the adaptation, all simulations.
     // Every phase writes its own fields of the flags block, cleared once
     // here and read back in one copy per synchronisation.
+    AuxStreams aux(ctx, n_sims);
+    MD_TRY(aux.fork());
     for (int q = 0; q < n_sims; q++) {
         mdlts_sim *s = sims[q];
+        aux.use(q);
         MD_TRY(flags_clear(s));
         MD_TRY(indicator_enqueue(s, false));
         MD_TRY(to_canonical(s));
@@ -2641,10 +2709,13 @@ mdlts_status mdlts_batch_adapt(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sim
         else MD_TRY(adapt_count<3>(s, tau_refine, tau_coarsen, false));
         MD_TRY(flags_readback(s));
     }
+    MD_TRY(aux.join());
     MD_TRY(sync(ctx));
     // new leaves, transfer, faces and levels, all simulations that change
+    MD_TRY(aux.fork());
     for (int q = 0; q < n_sims; q++) {
         mdlts_sim *s = sims[q];
+        aux.use(q);
         keep[q] = keep[q] && s->pin->tallies[0] == 0 && s->pin->tallies[1] == 0 && s->pin->total == (int)s->E;
         if (keep[q]) {
             s->state_grouped = true;
@@ -2656,6 +2727,7 @@ mdlts_status mdlts_batch_adapt(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sim
         MD_TRY(levels_enqueue(s, dt_barrier[q], -1, nullptr, 0.0, 0, false));
         MD_TRY(flags_readback(s));
     }
+    MD_TRY(aux.join());
     MD_TRY(sync(ctx));
     mdlts_status first = MDLTS_OK;
     for (int q = 0; q < n_sims; q++) {
