@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kBlock) void k_min_positive(int n, const double *x,
 }
 
 // exclusive offsets of every (block, level) in the finest-first order
-__global__ __launch_bounds__(kBlock) void k_level_scan(int *hist, int nb, int n_levels, int *cnt_ge)
+__global__ __launch_bounds__(kBlock) void k_level_scan(int *hist, int nb, int n_levels, int *cnt_ge, int *cnt_ge2)
 {
     __shared__ int wtot[kBlock / 64][kMaxLevels];
     __shared__ int base[kMaxLevels];
@@ -151,6 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_level_scan(int *hist, int nb, int n_
             base[l] = run;  // leaves of finer levels come first
             run += tot;
             cnt_ge[l] = l < n_levels ? run : 0;  // every entry written
+            if (cnt_ge2) cnt_ge2[l] = cnt_ge[l];  // a second copy (readback block)
         }
     }
     __syncthreads();
@@ -714,8 +715,8 @@ mdlts_status dev_alloc(mdlts_ctx *c, DevBuf &b, size_t bytes)
 }
 
 // A simulation's device flags block holds the small readbacks at the
-// offsets they have in PinnedReadback (cnt_ge excepted), so that each phase
-// writes its own fields and one copy brings back what several phases wrote.
+// offsets they have in PinnedReadback, so that each phase writes its own
+// fields and one copy brings back what several phases wrote.
 constexpr size_t kFlagBytes = 128;
 constexpr size_t kFlagHead = offsetof(PinnedReadback, cnt_ge);
 static_assert(sizeof(PinnedReadback) <= kFlagBytes, "flags block holds the readback fields");
@@ -735,11 +736,13 @@ mdlts_status flags_clear(mdlts_sim *s)
     return MDLTS_OK;
 }
 
-// every field of the flags block (but cnt_ge) into the pinned readback; it
-// arrives after the next synchronisation
-mdlts_status flags_readback(mdlts_sim *s)
+// the fields of the flags block into the pinned readback (the level counts
+// too when `levels`: a level assignment wrote them); they arrive after the
+// next synchronisation
+mdlts_status flags_readback(mdlts_sim *s, bool levels = false)
 {
-    HIP_TRY(hipMemcpyAsync(s->pin, s->flags.p, kFlagHead, hipMemcpyDeviceToHost, s->ctx->stream));
+    HIP_TRY(hipMemcpyAsync(s->pin, s->flags.p, levels ? sizeof(PinnedReadback) : kFlagHead, hipMemcpyDeviceToHost,
+                           s->ctx->stream));
     return MDLTS_OK;
 }
 
@@ -2330,7 +2333,9 @@ static mdlts_status levels_enqueue(mdlts_sim *s, double dt_barrier, int force_le
     if (own_flags) HIP_TRY(hipMemcpyAsync(&s->pin->level_bad, la.bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     // (levels above the cap are clamped by k_levels, so what follows stays
     // well defined; the flag makes the assignment invalid afterwards)
-    k_level_scan<<<1, kBlock, 0, c->stream>>>(P<int>(s->hist), nb, L, P<int>(s->cnt_ge_d));
+    // the counts also go to the flags block, read back with the flags when
+    // the caller collects them
+    k_level_scan<<<1, kBlock, 0, c->stream>>>(P<int>(s->hist), nb, L, P<int>(s->cnt_ge_d), MD_FLAG(s, int, cnt_ge));
     k_level_scatter<<<nb, kBlock, 0, c->stream>>>(P<uint8_t>(s->level_c), E, P<int>(s->hist), P<int>(s->perm),
                                                    P<int>(s->inv));
     // grouped tables
@@ -2355,7 +2360,8 @@ static mdlts_status levels_enqueue(mdlts_sim *s, double dt_barrier, int force_le
     MD_TRY(dev_alloc(c, s->u_s, 2 * sbytes));
     MD_TRY(dev_alloc(c, s->v_s, sbytes));
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(s->pin->cnt_ge, s->cnt_ge_d.p, kMaxLevels * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    if (own_flags)
+        HIP_TRY(hipMemcpyAsync(s->pin->cnt_ge, s->cnt_ge_d.p, kMaxLevels * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     return to_grouped(s);
 }
 
@@ -2725,7 +2731,7 @@ mdlts_status mdlts_batch_adapt(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sim
         if (s->desc.dim == 2) MD_TRY(adapt_emit<2>(s, false));
         else MD_TRY(adapt_emit<3>(s, false));
         MD_TRY(levels_enqueue(s, dt_barrier[q], -1, nullptr, 0.0, 0, false));
-        MD_TRY(flags_readback(s));
+        MD_TRY(flags_readback(s, true));
     }
     MD_TRY(aux.join());
     MD_TRY(sync(ctx));
