@@ -1571,18 +1571,28 @@ int grid_of(const BatchPlan &P, int n_tiles)
 // longer launches.
 enum EmitMode { kEmitLaunch, kEmitGraph, kEmitUpdate, kEmitKeys };
 
-mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, int phase, hipGraph_t graph, EmitMode mode = kEmitLaunch,
+// Where kEmitGraph puts a barrier's nodes and which nodes kEmitUpdate sets:
+// consecutive barriers emitted into one target form one graph, each
+// group's chain continuing from one barrier into the next.
+struct GraphTarget {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<hipGraphNode_t> *nodes = nullptr;  // in emission order
+    std::vector<hipGraphNode_t> last;              // per group: its latest node
+    size_t n_node = 0;                             // next node to update
+};
+
+mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, int phase, GraphTarget *gt, EmitMode mode = kEmitLaunch,
                           std::vector<long long> *keys = nullptr, std::vector<hipEvent_t> *timed = nullptr,
                           std::vector<int> *timed_group = nullptr)
 {
     // timed (direct launches only): an event pair around every launch, and
     // the index of the launch's group in timed_group
-    if (graph) mode = kEmitGraph;
+    if ((mode == kEmitGraph || mode == kEmitUpdate) && (!gt || !gt->nodes)) return MDLTS_EINVAL;
     if (mode != kEmitLaunch) timed = nullptr;
+    if (gt) gt->last.resize(P.groups.size(), nullptr);
     size_t n_timed = 0;
     const long long nsub = 1ll << P.lmax_all;
-    std::vector<hipGraphNode_t> last(P.groups.size(), nullptr);  // per group: its previous node
-    size_t n_node = 0;
     auto add = [&](long long key, size_t g, void *fn, int grid, int block, size_t lds, void **args) -> mdlts_status {
         hipKernelNodeParams kp{};
         kp.func = fn;
@@ -1593,13 +1603,14 @@ mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, int phase, hipGraph_t grap
         kp.extra = nullptr;
         if (mode == kEmitGraph) {
             hipGraphNode_t node;
-            HIP_TRY(hipGraphAddKernelNode(&node, graph, last[g] ? &last[g] : nullptr, last[g] ? 1 : 0, &kp));
-            last[g] = node;
-            P.nodes[phase].push_back(node);
+            hipGraphNode_t *dep = gt->last[g] ? &gt->last[g] : nullptr;
+            HIP_TRY(hipGraphAddKernelNode(&node, gt->graph, dep, dep ? 1 : 0, &kp));
+            gt->last[g] = node;
+            gt->nodes->push_back(node);
             if (keys) keys->push_back(key);
         } else if (mode == kEmitUpdate) {
-            if (n_node >= P.nodes[phase].size()) return MDLTS_EINVAL;
-            HIP_TRY(hipGraphExecKernelNodeSetParams(P.exec[phase], P.nodes[phase][n_node++], &kp));
+            if (gt->n_node >= gt->nodes->size()) return MDLTS_EINVAL;
+            HIP_TRY(hipGraphExecKernelNodeSetParams(gt->exec, (*gt->nodes)[gt->n_node++], &kp));
         } else if (mode == kEmitKeys) {
             keys->push_back(key);
         } else {
@@ -1656,20 +1667,27 @@ mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, int phase, hipGraph_t grap
     return MDLTS_OK;
 }
 
-// The graphs of the plan's current launches: the nodes of graphs already
-// built for the same keys get the new parameters (grids, blocks, tile lists,
-// clocks); otherwise the graphs are built anew.
+// The graphs of the plan's current launches, two barriers each (graph k
+// starts with clock copy k): the nodes of graphs already built for the same
+// keys get the new parameters (grids, blocks, tile lists, clocks);
+// otherwise the graphs are built anew.
 mdlts_status build_graph(mdlts_ctx *c, BatchPlan &P)
 {
     if (P.exec[0] && P.exec[1]) {
         std::vector<long long> keys;
         MD_TRY(emit_barrier(c, P, 0, nullptr, kEmitKeys, &keys));
-        if (keys == P.topo && P.nodes[0].size() == keys.size() && P.nodes[1].size() == keys.size()) {
+        if (keys == P.topo && P.nodes[0].size() == 2 * keys.size() && P.nodes[1].size() == 2 * keys.size()) {
             // no replay of these graphs may be in flight while they change
             // (a stream synchronisation since the last replay suffices)
             if (P.graph_busy && P.busy_epoch == c->sync_epoch) MD_TRY(sync(c));
             P.graph_busy = false;
-            for (int k = 0; k < 2; k++) MD_TRY(emit_barrier(c, P, k, nullptr, kEmitUpdate));
+            for (int k = 0; k < 2; k++) {
+                GraphTarget gt;
+                gt.exec = P.exec[k];
+                gt.nodes = &P.nodes[k];
+                MD_TRY(emit_barrier(c, P, k, &gt, kEmitUpdate));
+                MD_TRY(emit_barrier(c, P, k ^ 1, &gt, kEmitUpdate));
+            }
             P.graph_valid = true;
             return MDLTS_OK;
         }
@@ -1677,8 +1695,12 @@ mdlts_status build_graph(mdlts_ctx *c, BatchPlan &P)
     destroy_graph(&P);
     for (int k = 0; k < 2; k++) {
         HIP_TRY(hipGraphCreate(&P.graph[k], 0));
+        GraphTarget gt;
+        gt.graph = P.graph[k];
+        gt.nodes = &P.nodes[k];
         std::vector<long long> keys;
-        MD_TRY(emit_barrier(c, P, k, P.graph[k], kEmitGraph, &keys));
+        MD_TRY(emit_barrier(c, P, k, &gt, kEmitGraph, &keys));
+        MD_TRY(emit_barrier(c, P, k ^ 1, &gt, kEmitGraph));
         HIP_TRY(hipGraphInstantiate(&P.exec[k], P.graph[k], nullptr, nullptr, 0));
         if (k == 0) P.topo = keys;
     }
@@ -1686,8 +1708,8 @@ mdlts_status build_graph(mdlts_ctx *c, BatchPlan &P)
     return MDLTS_OK;
 }
 
-// host-side bookkeeping of barriers run by the batch (one at a time: the
-// clock copies alternate)
+// host-side bookkeeping of nb barriers run by the batch (the clock copies
+// alternate, so an odd count changes the phase)
 void account_barriers(BatchPlan &P, int nb)
 {
     for (size_t q = 0; q < P.sims.size(); q++) {
@@ -1718,23 +1740,28 @@ mdlts_status drain_batch_events(BatchPlan &P)
 
 mdlts_status run_batch_barriers(mdlts_ctx *c, BatchPlan &P, int nb)
 {
-    for (int b = 0; b < nb; b++) {
-        if (P.prof) {
-            if (P.ev_used + P.groups.size() * (1u << P.lmax_all) > kMaxEventPairs) MD_TRY(drain_batch_events(P));
-            MD_TRY(emit_barrier(c, P, P.phase, nullptr));
-        } else if (c->use_graphs && (P.groups.size() > 1 || P.single_graph)) {
-            // each kernel variant's launches are a chain of their own in
-            // the graph, and the chains run concurrently; a plan of one
-            // variant (a single chain) replays a graph only if the
-            // autotuner found it faster than direct launches
+    const bool graphs = c->use_graphs && (P.groups.size() > 1 || P.single_graph) && !P.prof;
+    int b = 0;
+    while (b < nb) {
+        if (graphs && nb - b >= 2) {
+            // two barriers per graph; each kernel variant's launches are a
+            // chain of their own through both, and the chains run
+            // concurrently.  A plan of one variant (a single chain)
+            // replays graphs only if the autotuner found them faster than
+            // direct launches; an odd last barrier is launched directly.
             if (!P.graph_valid) MD_TRY(build_graph(c, P));
             HIP_TRY(hipGraphLaunch(P.exec[P.phase], c->stream));
             P.graph_busy = true;
             P.busy_epoch = c->sync_epoch;
-        } else {
-            MD_TRY(emit_barrier(c, P, P.phase, nullptr));
+            account_barriers(P, 2);
+            b += 2;
+            continue;
         }
+        if (P.prof && P.ev_used + P.groups.size() * (1u << P.lmax_all) > kMaxEventPairs)
+            MD_TRY(drain_batch_events(P));
+        MD_TRY(emit_barrier(c, P, P.phase, nullptr));
         account_barriers(P, 1);
+        b++;
     }
     return MDLTS_OK;
 }
@@ -1820,22 +1847,25 @@ mdlts_status autotune(mdlts_ctx *c, BatchPlan &P, int *remaining)
     // device in both; long chains of short launches favour the graph, a
     // few longer ones the direct launches, whose host cost is lower)
     P.single_graph = false;
-    constexpr int run = 3;
-    if (c->use_graphs && P.groups.size() == 1 && *remaining >= 2 * (run + 1)) {
+    constexpr int pairs = 2;  // timed pairs of barriers after one warm pair
+    if (c->use_graphs && P.groups.size() == 1 && *remaining >= 2 * 2 * (pairs + 1)) {
         MD_TRY(build_plan_data(c, P));
         float t_direct = 0.f, t_graph = 0.f;
         for (int mode = 0; mode < 2; mode++) {
             if (mode == 1) MD_TRY(build_graph(c, P));
-            for (int b = 0; b <= run; b++) {
-                if (b == 1) HIP_TRY(hipEventRecord(e0, c->stream));  // after one warm barrier
+            for (int b = 0; b <= pairs; b++) {
+                if (b == 1) HIP_TRY(hipEventRecord(e0, c->stream));
                 if (mode == 1) {
                     HIP_TRY(hipGraphLaunch(P.exec[P.phase], c->stream));
                     P.graph_busy = true;
                     P.busy_epoch = c->sync_epoch;
+                    account_barriers(P, 2);
                 } else {
-                    MD_TRY(emit_barrier(c, P, P.phase, nullptr));
+                    for (int h = 0; h < 2; h++) {
+                        MD_TRY(emit_barrier(c, P, P.phase, nullptr));
+                        account_barriers(P, 1);
+                    }
                 }
-                account_barriers(P, 1);
             }
             HIP_TRY(hipEventRecord(e1, c->stream));
             HIP_TRY(hipEventSynchronize(e1));
@@ -1843,7 +1873,7 @@ mdlts_status autotune(mdlts_ctx *c, BatchPlan &P, int *remaining)
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
             (mode == 1 ? t_graph : t_direct) = ms;
-            *remaining -= run + 1;
+            *remaining -= 2 * (pairs + 1);
         }
         P.single_graph = t_graph < t_direct;
     }
