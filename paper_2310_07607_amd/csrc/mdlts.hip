@@ -1667,16 +1667,20 @@ mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, int phase, GraphTarget *gt
     return MDLTS_OK;
 }
 
-// The graphs of the plan's current launches, two barriers each (graph k
-// starts with clock copy k): the nodes of graphs already built for the same
-// keys get the new parameters (grids, blocks, tile lists, clocks);
+// Barriers per graph (even: a graph ends on the clock copy it starts with).
+constexpr int kGraphBarriers = 4;
+
+// The graphs of the plan's current launches, kGraphBarriers barriers each
+// (graph k starts with clock copy k): the nodes of graphs already built for
+// the same keys get the new parameters (grids, blocks, tile lists, clocks);
 // otherwise the graphs are built anew.
 mdlts_status build_graph(mdlts_ctx *c, BatchPlan &P)
 {
     if (P.exec[0] && P.exec[1]) {
         std::vector<long long> keys;
         MD_TRY(emit_barrier(c, P, 0, nullptr, kEmitKeys, &keys));
-        if (keys == P.topo && P.nodes[0].size() == 2 * keys.size() && P.nodes[1].size() == 2 * keys.size()) {
+        const size_t n = kGraphBarriers * keys.size();
+        if (keys == P.topo && P.nodes[0].size() == n && P.nodes[1].size() == n) {
             // no replay of these graphs may be in flight while they change
             // (a stream synchronisation since the last replay suffices)
             if (P.graph_busy && P.busy_epoch == c->sync_epoch) MD_TRY(sync(c));
@@ -1685,8 +1689,7 @@ mdlts_status build_graph(mdlts_ctx *c, BatchPlan &P)
                 GraphTarget gt;
                 gt.exec = P.exec[k];
                 gt.nodes = &P.nodes[k];
-                MD_TRY(emit_barrier(c, P, k, &gt, kEmitUpdate));
-                MD_TRY(emit_barrier(c, P, k ^ 1, &gt, kEmitUpdate));
+                for (int h = 0; h < kGraphBarriers; h++) MD_TRY(emit_barrier(c, P, k ^ (h & 1), &gt, kEmitUpdate));
             }
             P.graph_valid = true;
             return MDLTS_OK;
@@ -1700,7 +1703,7 @@ mdlts_status build_graph(mdlts_ctx *c, BatchPlan &P)
         gt.nodes = &P.nodes[k];
         std::vector<long long> keys;
         MD_TRY(emit_barrier(c, P, k, &gt, kEmitGraph, &keys));
-        MD_TRY(emit_barrier(c, P, k ^ 1, &gt, kEmitGraph));
+        for (int h = 1; h < kGraphBarriers; h++) MD_TRY(emit_barrier(c, P, k ^ (h & 1), &gt, kEmitGraph));
         HIP_TRY(hipGraphInstantiate(&P.exec[k], P.graph[k], nullptr, nullptr, 0));
         if (k == 0) P.topo = keys;
     }
@@ -1743,18 +1746,19 @@ mdlts_status run_batch_barriers(mdlts_ctx *c, BatchPlan &P, int nb)
     const bool graphs = c->use_graphs && (P.groups.size() > 1 || P.single_graph) && !P.prof;
     int b = 0;
     while (b < nb) {
-        if (graphs && nb - b >= 2) {
-            // two barriers per graph; each kernel variant's launches are a
-            // chain of their own through both, and the chains run
-            // concurrently.  A plan of one variant (a single chain)
-            // replays graphs only if the autotuner found them faster than
-            // direct launches; an odd last barrier is launched directly.
+        if (graphs && nb - b >= kGraphBarriers) {
+            // kGraphBarriers barriers per graph; each kernel variant's
+            // launches are a chain of their own through all of them, and
+            // the chains run concurrently.  A plan of one variant (a single
+            // chain) replays graphs only if the autotuner found them faster
+            // than direct launches; the barriers of a call that do not fill
+            // a graph are launched directly.
             if (!P.graph_valid) MD_TRY(build_graph(c, P));
             HIP_TRY(hipGraphLaunch(P.exec[P.phase], c->stream));
             P.graph_busy = true;
             P.busy_epoch = c->sync_epoch;
-            account_barriers(P, 2);
-            b += 2;
+            account_barriers(P, kGraphBarriers);
+            b += kGraphBarriers;
             continue;
         }
         if (P.prof && P.ev_used + P.groups.size() * (1u << P.lmax_all) > kMaxEventPairs)
@@ -1847,21 +1851,21 @@ mdlts_status autotune(mdlts_ctx *c, BatchPlan &P, int *remaining)
     // device in both; long chains of short launches favour the graph, a
     // few longer ones the direct launches, whose host cost is lower)
     P.single_graph = false;
-    constexpr int pairs = 2;  // timed pairs of barriers after one warm pair
-    if (c->use_graphs && P.groups.size() == 1 && *remaining >= 2 * 2 * (pairs + 1)) {
+    constexpr int runs = 1;  // timed graph-sized runs of barriers after one warm run
+    if (c->use_graphs && P.groups.size() == 1 && *remaining >= 2 * kGraphBarriers * (runs + 1)) {
         MD_TRY(build_plan_data(c, P));
         float t_direct = 0.f, t_graph = 0.f;
         for (int mode = 0; mode < 2; mode++) {
             if (mode == 1) MD_TRY(build_graph(c, P));
-            for (int b = 0; b <= pairs; b++) {
+            for (int b = 0; b <= runs; b++) {
                 if (b == 1) HIP_TRY(hipEventRecord(e0, c->stream));
                 if (mode == 1) {
                     HIP_TRY(hipGraphLaunch(P.exec[P.phase], c->stream));
                     P.graph_busy = true;
                     P.busy_epoch = c->sync_epoch;
-                    account_barriers(P, 2);
+                    account_barriers(P, kGraphBarriers);
                 } else {
-                    for (int h = 0; h < 2; h++) {
+                    for (int h = 0; h < kGraphBarriers; h++) {
                         MD_TRY(emit_barrier(c, P, P.phase, nullptr));
                         account_barriers(P, 1);
                     }
@@ -1873,7 +1877,7 @@ mdlts_status autotune(mdlts_ctx *c, BatchPlan &P, int *remaining)
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
             (mode == 1 ? t_graph : t_direct) = ms;
-            *remaining -= 2 * (pairs + 1);
+            *remaining -= kGraphBarriers * (runs + 1);
         }
         P.single_graph = t_graph < t_direct;
     }
