@@ -210,7 +210,7 @@ mdlts_status mdlts_batch_step(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sims
  * device indicator) and mdlts_assign_levels(dt_barrier[q]) in sequence, with
  * two host synchronisations for all simulations together instead of several
  * per simulation; the simulations' device work runs side by side on up to
- * four internal streams, forked from the context stream and joined back to
+ * three internal streams, forked from the context stream and joined back to
  * it before each synchronisation.  sims as for mdlts_batch_step;
  * dt_barrier [n_sims].
  * Returns the first error of any simulation (EUNSTABLE: non-finite

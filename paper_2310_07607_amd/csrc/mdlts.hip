@@ -1980,7 +1980,7 @@ mdlts_status prepare_plan(mdlts_ctx *c, BatchPlan *&slot, mdlts_sim *const *sims
 // a phase the streams share no buffer: every buffer a phase frees (when it
 // grows) was last used before the phase began, and what it allocates
 // belongs to one simulation.
-constexpr int kAuxStreams = 4;
+constexpr int kAuxStreams = 3;  // with the context stream, one per hardware queue HIP gives a process by default (4)
 
 struct AuxStreams {
     mdlts_ctx *c;
