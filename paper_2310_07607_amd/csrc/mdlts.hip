@@ -342,6 +342,22 @@ __global__ __launch_bounds__(kBlock) void k_indicator(const IndArgs a)
         unpack_key<DIM>(static_cast<const typename KeyOf<DIM>::type *>(a.key)[e], depth, c);
         double h[3] = {1, 1, 1};
         for (int k = 0; k < DIM; k++) h[k] = ldexp(a.h0[k], -depth);
+        // face entries first; Q1 quadrilaterals also take every same-size or
+        // coarser neighbour's trace up front (16 doubles), so the faces do not
+        // wait for memory one after another (same arithmetic, same results)
+        uint32_t ents[2 * DIM];
+#pragma unroll
+        for (int f = 0; f < 2 * DIM; f++) ents[f] = a.face[(long long)f * a.E + e];
+        constexpr bool kPre = 2 * DIM * NF * 2 <= 16;
+        double pu[kPre ? 2 * DIM : 1][NF], pq[kPre ? 2 * DIM : 1][NF];
+        if constexpr (kPre) {
+#pragma unroll
+            for (int f = 0; f < 2 * DIM; f++) {
+                const uint32_t kind = ents[f] >> 30;
+                if (kind == kSame || kind == kCoarser)
+                    canon_trace<DIM, P, T>(a, ents[f] & kIdMask30, f >> 1, 1 - (f & 1), pu[f], pq[f]);
+            }
+        }
         double acc = 0.0;
 #pragma unroll
         for (int k = 0; k < DIM; k++) {
@@ -360,7 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_indicator(const IndArgs a)
                 om[g] = DIM == 2 ? 0.5 * a.ref.w[g] : 0.25 * a.ref.w[g % M] * a.ref.w[g / M];
 #pragma unroll
             for (int s = 0; s < 2; s++) {
-                const uint32_t ent = a.face[(long long)(2 * k + s) * a.E + e];
+                const uint32_t ent = ents[2 * k + s];
                 const uint32_t kind = ent >> 30;
                 if (kind == kBoundary) continue;
                 const double ns = s ? 1.0 : -1.0;
@@ -369,7 +385,14 @@ __global__ __launch_bounds__(kBlock) void k_indicator(const IndArgs a)
                 canon_trace<DIM, P, T>(a, (uint32_t)e, k, s, tu, tq);
                 if (kind != kFiner) {
                     double nu[NF], nq[NF];
-                    canon_trace<DIM, P, T>(a, ent & kIdMask30, k, 1 - s, nu, nq);
+                    if constexpr (kPre) {
+                        for (int g = 0; g < NF; g++) {
+                            nu[g] = pu[2 * k + s][g];
+                            nq[g] = pq[2 * k + s][g];
+                        }
+                    } else {
+                        canon_trace<DIM, P, T>(a, ent & kIdMask30, k, 1 - s, nu, nq);
+                    }
                     const double hn = kind == kSame ? h[k] : 2.0 * h[k];
                     if (kind == kCoarser) {
                         double iq[NF], iu[NF];
