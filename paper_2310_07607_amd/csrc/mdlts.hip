@@ -2767,7 +2767,9 @@ mdlts_status mdlts_batch_adapt(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sim
         aux.use(q);
         MD_TRY(flags_clear(s));
         MD_TRY(indicator_enqueue(s, false));
-        MD_TRY(to_canonical(s));
+        // the indicator's gather made the canonical copy current (it keeps
+        // the grouped copy marked valid); the adaptation works on it
+        s->state_grouped = false;
         if (s->desc.dim == 2) MD_TRY(adapt_count<2>(s, tau_refine, tau_coarsen, false));
         else MD_TRY(adapt_count<3>(s, tau_refine, tau_coarsen, false));
         MD_TRY(flags_readback(s));
