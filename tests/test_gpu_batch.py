@@ -147,3 +147,32 @@ def test_batch_adapt_equals_per_simulation_calls(ctx, thresholds):
         assert np.array_equal(ua, ub) and np.array_equal(va, vb)
         ga.close()
         gb.close()
+
+
+def test_graph_and_direct_barriers_mix_bitwise(ctx):
+    """Barrier counts that fill graphs of four barriers, leave a remainder
+    launched directly, or are launched directly alone: the same states,
+    counters and times as all-direct launches (clock copies and tile
+    parities alternate correctly across the mix)."""
+    counts = [13, 4, 5, 1, 8, 3]      # the first 12 barriers of a new plan tune it
+    cases = CASES[:5]
+
+    def run(graphs):
+        ctx.set_graphs(graphs)
+        sims = []
+        for k, case in enumerate(cases):
+            _, g, dt, _, _, _ = _make(ctx, case, 60 + k)
+            sims.append((g, dt))
+        for n in counts:
+            ctx.batch_step([g for g, _ in sims], n)
+        out = [(g.get_state(), g.counters()) for g, _ in sims]
+        for g, dt in sims:
+            assert g.counters()[1] == 0.125 + sum(counts) * dt
+            g.close()
+        return out
+
+    direct = run(False)
+    mixed = run(True)
+    for (sd, cd), (sm, cm) in zip(direct, mixed):
+        assert np.array_equal(sd[0], sm[0]) and np.array_equal(sd[1], sm[1])
+        assert cd == cm
