@@ -198,7 +198,7 @@ mdlts_status mdlts_step(mdlts_sim *sim, int n_barriers);
  * barrier step, parameters and time.  Each result is bitwise the same as
  * running the simulation alone.  The per-barrier launch sequence is cached
  * until a simulation of the list changes and, when it holds more than one
- * kernel variant, replayed as HIP graphs of four barriers; the first
+ * kernel variant, replayed as HIP graphs of eight barriers; the first
  * barriers of a new list time the candidate launch shapes (threads per
  * block, one block per tile) and keep the fastest for each kernel variant.
  * Asynchronous on the context stream.  EINVAL for a repeated or foreign
@@ -219,12 +219,12 @@ mdlts_status mdlts_batch_step(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sims
 mdlts_status mdlts_batch_adapt(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sims, double tau_refine,
                                double tau_coarsen, const double *dt_barrier);
 /* enable = 1 (default): batches whose substeps launch more than one kernel
- * variant replay graphs of four barriers (each variant's launches form a
+ * variant replay graphs of eight barriers (each variant's launches form a
  * chain of their own through them, and the chains run concurrently; the
  * barriers of a call that do not fill a graph are launched directly);
  * single-variant plans (mdlts_step, or a batch of one variant) launch their
- * tile kernels directly or replay such graphs, whichever the autotuner
- * timed faster.  enable = 0: every launch goes directly to the stream, and
+ * tile kernels directly or replay graphs of four barriers, whichever the
+ * autotuner timed faster.  enable = 0: every launch goes directly to the stream, and
  * mdlts_step uses the per-element kernel without tile lists. */
 mdlts_status mdlts_set_graphs(mdlts_ctx *ctx, int enable);
 /* Event timing of the batched substep launches (launched directly while

@@ -1690,10 +1690,12 @@ mdlts_status emit_barrier(mdlts_ctx *c, BatchPlan &P, int phase, GraphTarget *gt
     return MDLTS_OK;
 }
 
-// Barriers per graph (even: a graph ends on the clock copy it starts with).
-constexpr int kGraphBarriers = 4;
+// Barriers per graph (even: a graph ends on the clock copy it starts with):
+// more for plans of several kernel variants, whose chains overlap across
+// the barriers inside a graph; a one-variant plan is a single chain.
+int graph_barriers(const BatchPlan &P) { return P.groups.size() > 1 ? 8 : 4; }
 
-// The graphs of the plan's current launches, kGraphBarriers barriers each
+// The graphs of the plan's current launches, graph_barriers(P) barriers each
 // (graph k starts with clock copy k): the nodes of graphs already built for
 // the same keys get the new parameters (grids, blocks, tile lists, clocks);
 // otherwise the graphs are built anew.
@@ -1702,7 +1704,7 @@ mdlts_status build_graph(mdlts_ctx *c, BatchPlan &P)
     if (P.exec[0] && P.exec[1]) {
         std::vector<long long> keys;
         MD_TRY(emit_barrier(c, P, 0, nullptr, kEmitKeys, &keys));
-        const size_t n = kGraphBarriers * keys.size();
+        const size_t n = (size_t)graph_barriers(P) * keys.size();
         if (keys == P.topo && P.nodes[0].size() == n && P.nodes[1].size() == n) {
             // no replay of these graphs may be in flight while they change
             // (a stream synchronisation since the last replay suffices)
@@ -1712,7 +1714,7 @@ mdlts_status build_graph(mdlts_ctx *c, BatchPlan &P)
                 GraphTarget gt;
                 gt.exec = P.exec[k];
                 gt.nodes = &P.nodes[k];
-                for (int h = 0; h < kGraphBarriers; h++) MD_TRY(emit_barrier(c, P, k ^ (h & 1), &gt, kEmitUpdate));
+                for (int h = 0; h < graph_barriers(P); h++) MD_TRY(emit_barrier(c, P, k ^ (h & 1), &gt, kEmitUpdate));
             }
             P.graph_valid = true;
             return MDLTS_OK;
@@ -1726,7 +1728,7 @@ mdlts_status build_graph(mdlts_ctx *c, BatchPlan &P)
         gt.nodes = &P.nodes[k];
         std::vector<long long> keys;
         MD_TRY(emit_barrier(c, P, k, &gt, kEmitGraph, &keys));
-        for (int h = 1; h < kGraphBarriers; h++) MD_TRY(emit_barrier(c, P, k ^ (h & 1), &gt, kEmitGraph));
+        for (int h = 1; h < graph_barriers(P); h++) MD_TRY(emit_barrier(c, P, k ^ (h & 1), &gt, kEmitGraph));
         HIP_TRY(hipGraphInstantiate(&P.exec[k], P.graph[k], nullptr, nullptr, 0));
         if (k == 0) P.topo = keys;
     }
@@ -1769,8 +1771,9 @@ mdlts_status run_batch_barriers(mdlts_ctx *c, BatchPlan &P, int nb)
     const bool graphs = c->use_graphs && (P.groups.size() > 1 || P.single_graph) && !P.prof;
     int b = 0;
     while (b < nb) {
-        if (graphs && nb - b >= kGraphBarriers) {
-            // kGraphBarriers barriers per graph; each kernel variant's
+        const int gb = graph_barriers(P);
+        if (graphs && nb - b >= gb) {
+            // gb barriers per graph; each kernel variant's
             // launches are a chain of their own through all of them, and
             // the chains run concurrently.  A plan of one variant (a single
             // chain) replays graphs only if the autotuner found them faster
@@ -1780,8 +1783,8 @@ mdlts_status run_batch_barriers(mdlts_ctx *c, BatchPlan &P, int nb)
             HIP_TRY(hipGraphLaunch(P.exec[P.phase], c->stream));
             P.graph_busy = true;
             P.busy_epoch = c->sync_epoch;
-            account_barriers(P, kGraphBarriers);
-            b += kGraphBarriers;
+            account_barriers(P, gb);
+            b += gb;
             continue;
         }
         if (P.prof && P.ev_used + P.groups.size() * (1u << P.lmax_all) > kMaxEventPairs)
@@ -1875,7 +1878,8 @@ mdlts_status autotune(mdlts_ctx *c, BatchPlan &P, int *remaining)
     // few longer ones the direct launches, whose host cost is lower)
     P.single_graph = false;
     constexpr int runs = 1;  // timed graph-sized runs of barriers after one warm run
-    if (c->use_graphs && P.groups.size() == 1 && *remaining >= 2 * kGraphBarriers * (runs + 1)) {
+    const int gb = graph_barriers(P);
+    if (c->use_graphs && P.groups.size() == 1 && *remaining >= 2 * gb * (runs + 1)) {
         MD_TRY(build_plan_data(c, P));
         float t_direct = 0.f, t_graph = 0.f;
         for (int mode = 0; mode < 2; mode++) {
@@ -1886,9 +1890,9 @@ mdlts_status autotune(mdlts_ctx *c, BatchPlan &P, int *remaining)
                     HIP_TRY(hipGraphLaunch(P.exec[P.phase], c->stream));
                     P.graph_busy = true;
                     P.busy_epoch = c->sync_epoch;
-                    account_barriers(P, kGraphBarriers);
+                    account_barriers(P, gb);
                 } else {
-                    for (int h = 0; h < kGraphBarriers; h++) {
+                    for (int h = 0; h < gb; h++) {
                         MD_TRY(emit_barrier(c, P, P.phase, nullptr));
                         account_barriers(P, 1);
                     }
@@ -1900,7 +1904,7 @@ mdlts_status autotune(mdlts_ctx *c, BatchPlan &P, int *remaining)
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
             (mode == 1 ? t_graph : t_direct) = ms;
-            *remaining -= kGraphBarriers * (runs + 1);
+            *remaining -= gb * (runs + 1);
         }
         P.single_graph = t_graph < t_direct;
     }
