@@ -150,11 +150,12 @@ def test_batch_adapt_equals_per_simulation_calls(ctx, thresholds):
 
 
 def test_graph_and_direct_barriers_mix_bitwise(ctx):
-    """Barrier counts that fill graphs of four barriers, leave a remainder
-    launched directly, or are launched directly alone: the same states,
-    counters and times as all-direct launches (clock copies and tile
-    parities alternate correctly across the mix)."""
-    counts = [13, 4, 5, 1, 8, 3]      # the first 12 barriers of a new plan tune it
+    """Barrier counts that fill graphs of several barriers (eight for a mix
+    of kernel variants), leave a remainder launched directly, or are launched
+    directly alone: the same states, counters and times as all-direct
+    launches (clock copies and tile parities alternate correctly across the
+    mix)."""
+    counts = [13, 8, 9, 1, 16, 3, 4]  # the first 12 barriers of a new plan tune it
     cases = CASES[:5]
 
     def run(graphs):
