@@ -235,8 +235,11 @@ __global__ __launch_bounds__(kBlock) void k_permute(int E, int np, int cap, cons
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_gather(int E, int np, int cap, long long slot_stride, const int *perm,
                                                    const int *cnt_ge, int parity, const T *us, const T *vs, T *uc,
-                                                   T *vc)
+                                                   T *vc, int *zero32)
 {
+    // (zero32, if given: 32 ints cleared by the first block, for the
+    // kernels that follow on the stream)
+    if (zero32 && blockIdx.x == 0 && threadIdx.x < 32) zero32[threadIdx.x] = 0;
     const int j = blockIdx.x * kBlock + threadIdx.x;
     if (j >= E) return;
     // level-0 elements sit at the end of the grouped order
@@ -741,6 +744,7 @@ mdlts_status dev_alloc(mdlts_ctx *c, DevBuf &b, size_t bytes)
 // offsets they have in PinnedReadback, so that each phase writes its own
 // fields and one copy brings back what several phases wrote.
 constexpr size_t kFlagBytes = 128;
+static_assert(kFlagBytes == 32 * sizeof(int), "the gather clears the flags block as 32 ints");
 constexpr size_t kFlagHead = offsetof(PinnedReadback, cnt_ge);
 static_assert(sizeof(PinnedReadback) <= kFlagBytes, "flags block holds the readback fields");
 
@@ -995,7 +999,7 @@ mdlts_status zero_canonical_state(mdlts_sim *s)
 }
 
 // grouped -> canonical at a barrier
-mdlts_status to_canonical(mdlts_sim *s)
+mdlts_status to_canonical(mdlts_sim *s, int *zero32 = nullptr)
 {
     if (!s->state_grouped) return MDLTS_OK;
     const int E = (int)s->E;
@@ -1006,12 +1010,12 @@ mdlts_status to_canonical(mdlts_sim *s)
         k_gather<double><<<nblocks(E), kBlock, 0, s->ctx->stream>>>(E, s->np, s->cap, stride, P<int>(s->perm),
                                                                      P<int>(s->cnt_ge_d), parity, P<double>(s->u_s),
                                                                      P<double>(s->v_s), P<double>(s->u_c),
-                                                                     P<double>(s->v_c));
+                                                                     P<double>(s->v_c), zero32);
     else
         k_gather<float><<<nblocks(E), kBlock, 0, s->ctx->stream>>>(E, s->np, s->cap, stride, P<int>(s->perm),
                                                                     P<int>(s->cnt_ge_d), parity, P<float>(s->u_s),
                                                                     P<float>(s->v_s), P<float>(s->u_c),
-                                                                    P<float>(s->v_c));
+                                                                    P<float>(s->v_c), zero32);
     HIP_TRY(hipGetLastError());
     s->state_grouped = false;
     return MDLTS_OK;
@@ -2769,11 +2773,16 @@ mdlts_status mdlts_batch_adapt(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sim
     for (int q = 0; q < n_sims; q++) {
         mdlts_sim *s = sims[q];
         aux.use(q);
-        MD_TRY(flags_clear(s));
+        // the adaptation works on the canonical copy of the state; the
+        // gather that makes it current also clears the flags block (the
+        // grouped copy stays valid for simulations that keep their leaves)
+        if (s->state_grouped) {
+            MD_TRY(dev_alloc(ctx, s->flags, kFlagBytes));
+            MD_TRY(to_canonical(s, flag_at<int>(s, 0)));
+        } else {
+            MD_TRY(flags_clear(s));
+        }
         MD_TRY(indicator_enqueue(s, false));
-        // the indicator's gather made the canonical copy current (it keeps
-        // the grouped copy marked valid); the adaptation works on it
-        s->state_grouped = false;
         if (s->desc.dim == 2) MD_TRY(adapt_count<2>(s, tau_refine, tau_coarsen, false));
         else MD_TRY(adapt_count<3>(s, tau_refine, tau_coarsen, false));
         MD_TRY(flags_readback(s));
