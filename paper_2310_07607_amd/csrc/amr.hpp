@@ -237,24 +237,6 @@ __global__ __launch_bounds__(256) void k_amr_coarsen(int E, const typename KeyOf
     cflag[e] = ok ? 1 : 0;
 }
 
-template <int DIM>
-__global__ __launch_bounds__(256) void k_amr_count(int E, const typename KeyOf<DIM>::type *key, const uint8_t *refine,
-                                                   const uint8_t *cflag, int *cnt, unsigned long long *tallies)
-{
-    const int e = blockIdx.x * 256 + threadIdx.x;
-    if (e >= E) return;
-    int n = 1;
-    if (refine[e]) {
-        n = 1 << DIM;
-        atomicAdd(&tallies[0], 1ull);
-    } else if (cflag[e]) {
-        atomicAdd(&tallies[1], 1ull);
-    } else {
-        const int ci = child_index<DIM>(key[e]);
-        if (ci > 0 && e - ci >= 0 && cflag[e - ci] && sibling_of<DIM>(key[e - ci], key[e])) n = 0;
-    }
-    cnt[e] = n;
-}
 
 template <int DIM>
 __global__ __launch_bounds__(256) void k_amr_emit(int E, const typename KeyOf<DIM>::type *key, const uint8_t *refine,
@@ -324,6 +306,42 @@ __device__ __forceinline__ int block_excl_scan4(int *x4)
     x4[3] = excl + t2;
     __syncthreads();
     return total;
+}
+
+// Leaves after adaptation per current leaf (2^d for a refined leaf, 0 for
+// the later children of a coarsened parent, 1 otherwise), with the
+// refine/coarsen tallies, and their block-local exclusive scan, in one
+// launch: each thread counts four consecutive leaves, then the block scans.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_amr_count_scan(int E, const typename KeyOf<DIM>::type *key,
+                                                        const uint8_t *refine, const uint8_t *cflag, int *cnt,
+                                                        int *off, int *block_sums, unsigned long long *tallies)
+{
+    int x[4];
+    const long long base = (long long)blockIdx.x * 1024 + threadIdx.x * 4;
+    for (int q = 0; q < 4; q++) {
+        const long long el = base + q;
+        int n = 0;
+        if (el < E) {
+            const int e = (int)el;
+            n = 1;
+            if (refine[e]) {
+                n = 1 << DIM;
+                atomicAdd(&tallies[0], 1ull);
+            } else if (cflag[e]) {
+                atomicAdd(&tallies[1], 1ull);
+            } else {
+                const int ci = child_index<DIM>(key[e]);
+                if (ci > 0 && e - ci >= 0 && cflag[e - ci] && sibling_of<DIM>(key[e - ci], key[e])) n = 0;
+            }
+            cnt[e] = n;
+        }
+        x[q] = n;
+    }
+    const int tot = block_excl_scan4(x);
+    for (int q = 0; q < 4; q++)
+        if (base + q < E) off[base + q] = x[q];
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
 }
 
 __global__ __launch_bounds__(256) void k_scan_local(int n, const int *in, int *out, int *block_sums)

@@ -1285,9 +1285,8 @@ mdlts_status adapt_count(mdlts_sim *s, double tau_refine, double tau_coarsen, bo
         k_amr_close<DIM><<<nb, kBlock, 0, st>>>(E, P<uint32_t>(s->face_c), P<uint8_t>(s->refine));
     k_amr_coarsen<DIM><<<nb, kBlock, 0, st>>>(E, key, P<double>(s->eta_c), tau_coarsen, P<uint8_t>(s->refine),
                                                P<uint32_t>(s->face_c), P<uint8_t>(s->cflag));
-    k_amr_count<DIM><<<nb, kBlock, 0, st>>>(E, key, P<uint8_t>(s->refine), P<uint8_t>(s->cflag), P<int>(s->cnt),
-                                             tallies);
-    k_scan_local<<<nb4, kBlock, 0, st>>>(E, P<int>(s->cnt), P<int>(s->off), P<int>(s->bsums));
+    k_amr_count_scan<DIM><<<nb4, kBlock, 0, st>>>(E, key, P<uint8_t>(s->refine), P<uint8_t>(s->cflag), P<int>(s->cnt),
+                                                   P<int>(s->off), P<int>(s->bsums), tallies);
     k_scan_sums<<<1, kBlock, 0, st>>>(nb4, P<int>(s->bsums), total);
     k_scan_add<<<nb4, kBlock, 0, st>>>(E, P<int>(s->off), P<int>(s->bsums));
     HIP_TRY(hipGetLastError());
