@@ -241,15 +241,17 @@ __global__ __launch_bounds__(256) void k_amr_coarsen(int E, const typename KeyOf
 template <int DIM>
 __global__ __launch_bounds__(256) void k_amr_emit(int E, const typename KeyOf<DIM>::type *key, const uint8_t *refine,
                                                   const uint8_t *cflag, const int *cnt, const int *off,
-                                                  typename KeyOf<DIM>::type *key_new, uint8_t *xkind, int32_t *xsrc,
-                                                  uint8_t *xchild)
+                                                  const int *block_off, typename KeyOf<DIM>::type *key_new,
+                                                  uint8_t *xkind, int32_t *xsrc, uint8_t *xchild)
 {
+    // off: exclusive scan of cnt within blocks of 1024 leaves; block_off:
+    // exclusive scan of the blocks' totals
     const int e = blockIdx.x * 256 + threadIdx.x;
     if (e >= E || cnt[e] == 0) return;
     int d;
     uint32_t c[3] = {0, 0, 0};
     unpack_key<DIM>(key[e], d, c);
-    const int o = off[e];
+    const int o = off[e] + block_off[e >> 10];
     if (refine[e]) {
         for (int ci = 0; ci < (1 << DIM); ci++) {
             uint32_t cc[3] = {0, 0, 0};
@@ -344,17 +346,6 @@ __global__ __launch_bounds__(256) void k_amr_count_scan(int E, const typename Ke
     if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(256) void k_scan_local(int n, const int *in, int *out, int *block_sums)
-{
-    int x[4];
-    const long long base = (long long)blockIdx.x * 1024 + threadIdx.x * 4;
-    for (int q = 0; q < 4; q++) x[q] = base + q < n ? in[base + q] : 0;
-    const int tot = block_excl_scan4(x);
-    for (int q = 0; q < 4; q++)
-        if (base + q < n) out[base + q] = x[q];
-    if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
-}
-
 // one block scans the block sums in chunks of 1024; total to *total
 __global__ __launch_bounds__(256) void k_scan_sums(int nb, int *sums, int *total)
 {
@@ -374,14 +365,6 @@ __global__ __launch_bounds__(256) void k_scan_sums(int nb, int *sums, int *total
         __syncthreads();
     }
     if (threadIdx.x == 0) *total = carry;
-}
-
-__global__ __launch_bounds__(256) void k_scan_add(int n, int *out, const int *sums)
-{
-    const long long base = (long long)blockIdx.x * 1024 + threadIdx.x * 4;
-    const int add = sums[blockIdx.x];
-    for (int q = 0; q < 4; q++)
-        if (base + q < n) out[base + q] += add;
 }
 
 }  // namespace mdlts

@@ -1287,8 +1287,9 @@ mdlts_status adapt_count(mdlts_sim *s, double tau_refine, double tau_coarsen, bo
                                                P<uint32_t>(s->face_c), P<uint8_t>(s->cflag));
     k_amr_count_scan<DIM><<<nb4, kBlock, 0, st>>>(E, key, P<uint8_t>(s->refine), P<uint8_t>(s->cflag), P<int>(s->cnt),
                                                    P<int>(s->off), P<int>(s->bsums), tallies);
+    // block sums to block offsets and the total; the emit adds a leaf's
+    // block offset to its block-local one
     k_scan_sums<<<1, kBlock, 0, st>>>(nb4, P<int>(s->bsums), total);
-    k_scan_add<<<nb4, kBlock, 0, st>>>(E, P<int>(s->off), P<int>(s->bsums));
     HIP_TRY(hipGetLastError());
     // tallies and total are adjacent: one copy
     static_assert(offsetof(PinnedReadback, total) == 3 * sizeof(unsigned long long), "readback layout");
@@ -1316,8 +1317,8 @@ mdlts_status adapt_emit(mdlts_sim *s, bool own_flags = true)
     MD_TRY(dev_alloc(c, s->xs, (size_t)E_new * sizeof(int32_t)));
     MD_TRY(dev_alloc(c, s->xc, (size_t)E_new));
     k_amr_emit<DIM><<<nb, kBlock, 0, st>>>(E, P<KT>(s->key_c), P<uint8_t>(s->refine), P<uint8_t>(s->cflag),
-                                            P<int>(s->cnt), P<int>(s->off), P<KT>(s->key_n), P<uint8_t>(s->xk),
-                                            P<int32_t>(s->xs), P<uint8_t>(s->xc));
+                                            P<int>(s->cnt), P<int>(s->off), P<int>(s->bsums), P<KT>(s->key_n),
+                                            P<uint8_t>(s->xk), P<int32_t>(s->xs), P<uint8_t>(s->xc));
     HIP_TRY(hipGetLastError());
     if (s->desc.precision == MDLTS_FP64) MD_TRY(run_transfer<double>(s, E, E_new));
     else MD_TRY(run_transfer<float>(s, E, E_new));
