@@ -12,8 +12,9 @@
  *            (Algorithm 1's inequalities);
  *   Sec. 2.3, forward Euler for phi, exponential (Rush-Larsen type) step for
  *            the gate, Gershgorin CFL per element block, substeps 2^b,
- *            Algorithm 1 (multi-queue synchronous LTS with linear time
- *            interpolation of coarser neighbours).
+ *            synchronous LTS (Algorithm 1: elements of level l updated at
+ *            every 2^(lmax-l)-th substep, linear time interpolation of
+ *            coarser neighbours).
  * Where the paper is silent or garbled, the reading taken is stated next to
  * the code it affects.
  *
@@ -907,53 +908,54 @@ int or_lts_barrier(or_sim *S, double dt_barrier, double t_n, const int8_t *level
     double unew[MAXNP], vnew[MAXNP];
 
     if (mode == 0) {
-        /* the current solution, the most recent (buffered) solution, the
-         * tick each of them belongs to, and one queue per substep */
-        double *ubuf = (double *)malloc(sizeof(double) * (size_t)(E * np + 1));
-        int64_t *tick_cur = (int64_t *)calloc((size_t)E + 1, sizeof(int64_t));
-        int64_t *tick_prev = (int64_t *)calloc((size_t)E + 1, sizeof(int64_t));
-        int64_t *qlen = (int64_t *)calloc((size_t)maxS, sizeof(int64_t));
-        int64_t **queue = (int64_t **)malloc(sizeof(int64_t *) * (size_t)maxS);
-        for (int64_t i = 0; i < maxS; i++) queue[i] = (int64_t *)malloc(sizeof(int64_t) * (size_t)(E + 1));
-        for (int64_t e = 0; e < E; e++) queue[0][qlen[0]++] = e;
+        /* Time-history form, from the definitions of Sec. 2.3: an element
+         * of level l takes S = 2^l steps of dt/S, i.e. it is updated at the
+         * ticks that are multiples of k = maxS/S, and its value is known at
+         * those ticks and at maxS.  hist[e] holds the values of element e at
+         * ticks 0, k_e, 2 k_e, ..., maxS.  At tick i a neighbour's value is
+         * its known value at i if i is one of its ticks; otherwise the
+         * neighbour is coarser and its value at t_i is linear in time
+         * between its known values at the ticks enclosing i (both already
+         * computed: the later one at the earlier tick).  Nothing written at
+         * tick i is read at tick i, so the order inside a tick is free. */
+        int64_t *hoff = (int64_t *)malloc(sizeof(int64_t) * (size_t)(E + 1));
+        hoff[0] = 0;
+        for (int64_t e = 0; e < E; e++) hoff[e + 1] = hoff[e] + (((int64_t)1 << level[e]) + 1) * np;
+        double *hist = (double *)malloc(sizeof(double) * (size_t)(hoff[E] + 1));
+        for (int64_t e = 0; e < E; e++) memcpy(&hist[hoff[e]], &S->u[e * np], sizeof(double) * np);
         for (int64_t i = 0; i < maxS; i++) {
-            for (int64_t a = 0; a < qlen[i]; a++) {
-                int64_t e = queue[i][a];
-                memcpy(&ubuf[e * np], &S->u[e * np], sizeof(double) * np);
-                tick_prev[e] = tick_cur[e];
-            }
-            for (int64_t a = 0; a < qlen[i]; a++) {
-                int64_t e = queue[i][a];
-                /* neighbour values at tick i: the buffered value if it was
-                 * buffered at tick i, otherwise linear in time between the
-                 * buffered and the current solution */
+            for (int64_t e = 0; e < E; e++) {
+                int64_t ke = maxS >> level[e];
+                if (i % ke != 0) continue;
                 for (int64_t q = S->seg_start[e]; q < S->seg_start[e + 1]; q++) {
                     int64_t nb = S->seg[q].nbr;
+                    int64_t kn = maxS >> level[nb];
+                    int64_t m0 = i / kn;
+                    const double *h0 = &hist[hoff[nb] + m0 * np];
                     double *dst = &nbuf[(q - S->seg_start[e]) * MAXNP];
-                    double theta = 0.0;
-                    if (tick_prev[nb] == i) {
-                        memcpy(dst, &ubuf[nb * np], sizeof(double) * np);
+                    double theta = (double)(i - m0 * kn) / (double)kn;
+                    if (i == m0 * kn) {
+                        memcpy(dst, h0, sizeof(double) * np);
                     } else {
-                        theta = (double)(i - tick_prev[nb]) / (double)(tick_cur[nb] - tick_prev[nb]);
-                        for (int j = 0; j < np; j++)
-                            dst[j] = (1.0 - theta) * ubuf[nb * np + j] + theta * S->u[nb * np + j];
+                        const double *h1 = h0 + np;
+                        for (int j = 0; j < np; j++) dst[j] = (1.0 - theta) * h0[j] + theta * h1[j];
                     }
                     un_seg[q - S->seg_start[e]] = dst;
                     trace_row(trace, trace_cap, &tl, (double)i, (double)e, (double)nb, theta);
                 }
                 double dt_e = ldexp(dt_barrier, -level[e]);
                 double t_i = t_n + (double)i * h_tick;
-                element_update(S, e, &ubuf[e * np], &S->v[e * np], un_seg, t_i, dt_e, unew, vnew);
-                memcpy(&S->u[e * np], unew, sizeof(double) * np);
+                double *he = &hist[hoff[e] + (i / ke) * np];
+                element_update(S, e, he, &S->v[e * np], un_seg, t_i, dt_e, unew, vnew);
+                memcpy(he + np, unew, sizeof(double) * np);
                 memcpy(&S->v[e * np], vnew, sizeof(double) * np);
                 nupd++;
-                int64_t j = i + (maxS >> level[e]);
-                tick_cur[e] = j;
-                if (j <= maxS - 1) queue[j][qlen[j]++] = e;
             }
         }
-        for (int64_t i = 0; i < maxS; i++) free(queue[i]);
-        free(queue); free(qlen); free(tick_cur); free(tick_prev); free(ubuf);
+        for (int64_t e = 0; e < E; e++)
+            memcpy(&S->u[e * np], &hist[hoff[e] + ((int64_t)1 << level[e]) * np], sizeof(double) * np);
+        free(hist);
+        free(hoff);
     } else {
         /* two-slot level-bucket form: slot[e] holds the element's value at
          * its last update tick, other[e] its value one step later.  At

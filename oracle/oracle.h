@@ -12,7 +12,9 @@
  * Everything here is deliberately slow and literal: a pointer forest for the
  * mesh, element and face matrices assembled by quadrature in physical
  * coordinates (as the paper's serial implementation pre-assembles K_e and
- * M_e^{-1}, Sec. 2.3), and Algorithm 1 executed with explicit queues.
+ * M_e^{-1}, Sec. 2.3), and the synchronous LTS barrier written from its
+ * definitions in Sec. 2.3 (per-element update ticks, linear-in-time coarser
+ * neighbours), checked bitwise against a level-bucket form.
  *
  * Index conventions (shared with the GPU library's ABI, not with its code):
  *   - root grid n[0] x n[1] (x n[2]); root id = rx + n0*(ry + n1*rz);
@@ -70,7 +72,10 @@ int or_rvt_indicator(or_sim *S, const double *u_a, const double *v_a, double t_a
 int or_levels_cell(or_sim *S, double dt_barrier, int n_levels, const double *eta_t, double tau_cell,
                    double dt_cell, int8_t *level);
 void or_bucket(int64_t E, const int8_t *level, int n_levels, int32_t *perm, int32_t *cnt_ge);
-/* mode 0: Algorithm 1 with explicit queues; mode 1: two-slot level-bucket form.
+/* mode 0: time-history form (an element of level l updates at the ticks that
+ * are multiples of 2^(lmax-l); a coarser neighbour is linear in time between
+ * its values at the ticks enclosing the substep); mode 1: two-slot
+ * level-bucket form.
  * trace (optional, capacity trace_cap rows of 4 doubles): substep, element,
  * neighbour, theta for every neighbour read of every element update. */
 int or_lts_barrier(or_sim *S, double dt_barrier, double t_n, const int8_t *level, int mode,

@@ -334,6 +334,33 @@ def test_cell_threshold_behaviour():
     assert _single_cell(0.01, 10.0, 0.0) == (0.0, 0.0)
 
 
+@pytest.mark.parametrize("u0,v0,dt", [(0.1, 2.0, 3.0), (0.6, 1.5, 10.0), (-0.1, 0.5, 8.0)])
+def test_gate_step_is_exact_for_the_frozen_linear_equation(u0, v0, dt):
+    # Sec. 2.3: the gate takes an exponential (Rush-Larsen type) step, exact
+    # for dv/dt = eps (v_inf - v) with eps and v_inf frozen at the start of
+    # the step.  A constant field has K u = 0, so one global step of the
+    # oracle is one such step per node.  eps dt >= 3 here: forward Euler
+    # would overshoot v_inf, and eps taken at the new state would change
+    # the decay rate; both fail the comparison below.
+    k, a, e0, m1, m2 = inputs.AP_PARAMS
+    eps = e0 + m1 * v0 / (u0 + m2)
+    vinf = k * u0 * (1 + a - u0)
+    assert eps * dt >= 3.0
+    o = make(2, 1, [1, 1], [0.1, 0.1])
+    o.set_state(np.full(4, u0), np.full(4, v0))
+    o.step_global(dt, 0.0, 1)
+    u1, v1 = o.get_state()
+    ref = solve_ivp(lambda t, y: [eps * (vinf - y[0])], (0.0, dt), [v0], method="DOP853",
+                    rtol=1e-12, atol=1e-14).y[0, -1]
+    scale = abs(v0 - vinf)
+    np.testing.assert_allclose(v1, ref, rtol=0, atol=1e-9 * scale)
+    assert np.all((v1 - v0) * (v1 - vinf) < 0)  # strictly between v and v_inf
+    fe = v0 + dt * eps * (vinf - v0)
+    assert abs(fe - ref) > 0.5 * scale
+    # the potential takes one forward-Euler step of the published model
+    np.testing.assert_allclose(u1, u0 + dt * _ap_rhs(0.0, [u0, v0])[0], rtol=1e-14, atol=1e-15)
+
+
 def test_stimulus_acts_only_inside_box_and_window():
     o = make(2, 1, [4, 4], [0.4, 0.4], ap=NO_REACTION)
     o.set_stimulus(inputs.box_array([((0.0, 0.0), (0.1, 0.1), 0.5, 1.0, 2.0)]))
@@ -491,6 +518,50 @@ def test_indicator_closed_form_for_a_kink(p):
     expect = math.sqrt(h / (2 * p) * h ** 2 * h * (2 * D) ** 2)
     np.testing.assert_allclose(eta[:, 1:3], expect, rtol=1e-12)
     assert np.abs(eta[:, [0, 3]]).max() < 1e-15
+
+
+@pytest.mark.parametrize("dim,p", [(2, 1), (2, 2), (3, 1), (3, 2)])
+def test_indicator_closed_form_for_a_kink_on_a_non_conforming_face(dim, p):
+    # u = |x - x0| with x0 on a 2:1 interface: the roots right of x0 are
+    # refined once.  Every element sees u linear, so only the face pieces on
+    # x0 carry a flux jump, 2 Dxx.  A piece F (a sub-face, |F| = (h/2)^(d-1))
+    # contributes h_F/(2p) |F|^2 |F| (2 Dxx)^2 with h_F = |F|^(1/(d-1)), by
+    # its own measure: the coarse element has 2^(d-1) pieces on that face,
+    # each fine element one.  (Taking the coarse face's measure for the
+    # coarse side's pieces would give 2^(d+2) times the value there.)
+    h, x0 = 0.1, 0.2
+    n = [4, 3, 2][:dim]
+    D = np.diag([1.3e-3, 0.4e-3, 0.7e-3])
+    o = make(dim, p, n, [h * q for q in n], depth=1, D=D, gamma=2.0 if p == 1 else 4.0)
+    n_roots = int(np.prod(n))
+    bits = []
+    for r in range(n_roots):
+        rx = r % n[0]
+        bits += [1] + [0] * 2 ** dim if rx >= 2 else [0]
+    o.set_tree(np.array(bits, dtype=np.uint8))
+    X = o.leaf_nodes()
+    u = np.abs(X[:, 0] - x0)
+    o.set_state(u, np.zeros_like(u))
+    eta = o.indicator()
+    depth, coords = o.leaf_info()
+    area = (h / 2) ** (dim - 1)
+    hF = area ** (1.0 / (dim - 1))
+    piece = hF / (2 * p) * area ** 2 * area * (2 * D[0, 0]) ** 2
+    n_coarse = n_fine = 0
+    for e in range(o.n_leaves):
+        he = h / 2 ** depth[e]
+        lo = coords[e, 0] * he
+        if depth[e] == 0 and abs(lo + he - x0) < 1e-12:
+            expect = math.sqrt(2 ** (dim - 1) * piece)
+            n_coarse += 1
+        elif depth[e] == 1 and abs(lo - x0) < 1e-12:
+            expect = math.sqrt(piece)
+            n_fine += 1
+        else:
+            assert abs(eta[e]) < 1e-15, (e, eta[e])
+            continue
+        assert eta[e] == pytest.approx(expect, rel=1e-11), (e, depth[e], eta[e], expect)
+    assert n_coarse == n_roots // n[0] and n_fine == 2 ** (dim - 1) * n_coarse
 
 
 def test_tree_bits_roundtrip_and_validation():
