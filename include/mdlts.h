@@ -13,9 +13,12 @@
  * --------------------------------
  *  - Every function returns an mdlts_status; MDLTS_OK (0) on success.  No
  *    function aborts, prints, or retains a host pointer after it returns.
+ *    No C++ exception leaves the library: a failed host allocation inside a
+ *    call returns MDLTS_ENOMEM, any other host-side exception MDLTS_EDEVICE.
  *  - Host arrays are owned by the caller and copied during the call.
- *  - Device memory comes from the allocator given to mdlts_ctx_create (or
- *    hipMalloc when none is given) and is used on the context's stream.
+ *  - Device memory comes from the allocator given to mdlts_ctx_create and is
+ *    used on the context's stream.  A caller without an allocator (plain C)
+ *    passes NULL, and the library then calls hipMalloc/hipFree itself.
  *  - Mesh: an axis-aligned box [0,len0]x[0,len1](x[0,len2]) split into a root
  *    grid n0 x n1 (x n2) of boxes ("root elements", Sec. 2.2); each root is
  *    the root of a 2^d-tree.  Root id = rx + n0*(ry + n1*rz).  Child index =

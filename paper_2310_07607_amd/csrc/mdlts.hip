@@ -11,6 +11,7 @@
 #include <new>
 #include <vector>
 
+#include "abi_guard.hpp"
 #include "amr.hpp"
 #include "host.hpp"
 #include "kernels.hpp"
@@ -2081,263 +2082,295 @@ const char *mdlts_strerror(mdlts_status s)
 
 mdlts_status mdlts_ctx_create(int device, void *hip_stream, const mdlts_allocator *alloc, mdlts_ctx **out)
 {
-    if (!out) return MDLTS_EINVAL;
-    *out = nullptr;
-    int n = 0;
-    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return MDLTS_EINVAL;
-    if (alloc && (!alloc->alloc || !alloc->free)) return MDLTS_EINVAL;
-    HIP_TRY(hipSetDevice(device));
-    mdlts_ctx *c = new (std::nothrow) mdlts_ctx;
-    if (!c) return MDLTS_ENOMEM;
-    c->device = device;
-    c->stream = static_cast<hipStream_t>(hip_stream);
-    if (alloc) {
-        c->alloc = *alloc;
-        c->has_alloc = true;
-    }
-    *out = c;
-    return MDLTS_OK;
+    return abi_guard([&]() -> mdlts_status {
+        if (!out) return MDLTS_EINVAL;
+        *out = nullptr;
+        int n = 0;
+        if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return MDLTS_EINVAL;
+        if (alloc && (!alloc->alloc || !alloc->free)) return MDLTS_EINVAL;
+        HIP_TRY(hipSetDevice(device));
+        mdlts_ctx *c = new (std::nothrow) mdlts_ctx;
+        if (!c) return MDLTS_ENOMEM;
+        c->device = device;
+        c->stream = static_cast<hipStream_t>(hip_stream);
+        if (alloc) {
+            c->alloc = *alloc;
+            c->has_alloc = true;
+        }
+        *out = c;
+        return MDLTS_OK;
+    });
 }
 
 mdlts_status mdlts_ctx_destroy(mdlts_ctx *ctx)
 {
-    if (!ctx) return MDLTS_EINVAL;
-    if (ctx->n_sims > 0) return MDLTS_EBUSY;
-    free_plan(ctx, ctx->batch);
-    for (hipStream_t st : ctx->aux) {
-        (void)hipStreamSynchronize(st);
-        (void)hipStreamDestroy(st);
-    }
-    for (hipEvent_t e : ctx->join_ev) (void)hipEventDestroy(e);
-    if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
-    if (ctx->stage_done) (void)hipEventSynchronize(ctx->stage_done);
-    if (ctx->stage) (void)hipHostFree(ctx->stage);
-    if (ctx->stage_done) (void)hipEventDestroy(ctx->stage_done);
-    delete ctx;
-    return MDLTS_OK;
+    return abi_guard([&]() -> mdlts_status {
+        if (!ctx) return MDLTS_EINVAL;
+        if (ctx->n_sims > 0) return MDLTS_EBUSY;
+        free_plan(ctx, ctx->batch);
+        for (hipStream_t st : ctx->aux) {
+            (void)hipStreamSynchronize(st);
+            (void)hipStreamDestroy(st);
+        }
+        for (hipEvent_t e : ctx->join_ev) (void)hipEventDestroy(e);
+        if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+        if (ctx->stage_done) (void)hipEventSynchronize(ctx->stage_done);
+        if (ctx->stage) (void)hipHostFree(ctx->stage);
+        if (ctx->stage_done) (void)hipEventDestroy(ctx->stage_done);
+        delete ctx;
+        return MDLTS_OK;
+    });
 }
 
 mdlts_status mdlts_sync(mdlts_ctx *ctx)
 {
-    if (!ctx) return MDLTS_EINVAL;
-    return sync(ctx);
+    return abi_guard([&]() -> mdlts_status {
+        if (!ctx) return MDLTS_EINVAL;
+        return sync(ctx);
+    });
 }
 
 mdlts_status mdlts_sim_create(mdlts_ctx *ctx, const mdlts_mesh_desc *desc, mdlts_sim **out)
 {
-    if (!ctx || !out || !valid_desc(desc)) return MDLTS_EINVAL;
-    *out = nullptr;
-    mdlts_sim *s = new (std::nothrow) mdlts_sim;
-    if (!s) return MDLTS_ENOMEM;
-    s->ctx = ctx;
-    ctx->n_sims++;
-    if (hipHostMalloc(reinterpret_cast<void **>(&s->pin), sizeof(PinnedReadback), hipHostMallocDefault) != hipSuccess) {
-        (void)hipGetLastError();
-        s->pin = nullptr;
-        mdlts_sim_destroy(s);
-        return MDLTS_ENOMEM;
-    }
-    std::memset(s->pin, 0, sizeof(PinnedReadback));
-    s->desc = *desc;
-    if (desc->dim == 2) { s->desc.n[2] = 1; s->desc.len[2] = 1.0; }
-    s->np = 1;
-    for (int k = 0; k < desc->dim; k++) s->np *= desc->order + 1;
-    s->tsize = desc->precision == MDLTS_FP64 ? 8 : 4;
-    for (int k = 0; k < 3; k++) s->h0[k] = s->desc.len[k] / (double)s->desc.n[k];
-    make_ref_tables(desc->order, s->ref);
-    // default penalty per degree (coercive: Q2 needs gamma > 2, Q3 > 5)
-    s->gamma = desc->order == 1 ? 2.0 : desc->order == 2 ? 4.0 : 8.0;
-    mdlts_status st = compute_G(s);
-    Forest F;
-    forest_from_desc(&s->desc, F);
-    F.init_roots();
-    if (st == MDLTS_OK && !F.build_faces()) st = MDLTS_EINVAL;
-    if (st == MDLTS_OK) st = set_forest(s, std::move(F));
-    if (st == MDLTS_OK) st = zero_canonical_state(s);
-    if (st == MDLTS_OK) st = sync(ctx);
-    if (st != MDLTS_OK) {
-        mdlts_sim_destroy(s);
-        return st;
-    }
-    *out = s;
-    return MDLTS_OK;
+    return abi_guard([&]() -> mdlts_status {
+        if (!ctx || !out || !valid_desc(desc)) return MDLTS_EINVAL;
+        *out = nullptr;
+        mdlts_sim *s = new (std::nothrow) mdlts_sim;
+        if (!s) return MDLTS_ENOMEM;
+        s->ctx = ctx;
+        ctx->n_sims++;
+        if (hipHostMalloc(reinterpret_cast<void **>(&s->pin), sizeof(PinnedReadback), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            s->pin = nullptr;
+            mdlts_sim_destroy(s);
+            return MDLTS_ENOMEM;
+        }
+        std::memset(s->pin, 0, sizeof(PinnedReadback));
+        s->desc = *desc;
+        if (desc->dim == 2) { s->desc.n[2] = 1; s->desc.len[2] = 1.0; }
+        s->np = 1;
+        for (int k = 0; k < desc->dim; k++) s->np *= desc->order + 1;
+        s->tsize = desc->precision == MDLTS_FP64 ? 8 : 4;
+        for (int k = 0; k < 3; k++) s->h0[k] = s->desc.len[k] / (double)s->desc.n[k];
+        make_ref_tables(desc->order, s->ref);
+        // default penalty per degree (coercive: Q2 needs gamma > 2, Q3 > 5)
+        s->gamma = desc->order == 1 ? 2.0 : desc->order == 2 ? 4.0 : 8.0;
+        mdlts_status st = compute_G(s);
+        Forest F;
+        forest_from_desc(&s->desc, F);
+        F.init_roots();
+        if (st == MDLTS_OK && !F.build_faces()) st = MDLTS_EINVAL;
+        if (st == MDLTS_OK) st = set_forest(s, std::move(F));
+        if (st == MDLTS_OK) st = zero_canonical_state(s);
+        if (st == MDLTS_OK) st = sync(ctx);
+        if (st != MDLTS_OK) {
+            mdlts_sim_destroy(s);
+            return st;
+        }
+        *out = s;
+        return MDLTS_OK;
+    });
 }
 
 mdlts_status mdlts_sim_destroy(mdlts_sim *s)
 {
-    if (!s) return MDLTS_EINVAL;
-    mdlts_ctx *c = s->ctx;
-    (void)hipStreamSynchronize(c->stream);
-    if (c->batch)
-        for (mdlts_sim *m : c->batch->sims)
-            if (m == s) {
-                free_plan(c, c->batch);
-                break;
-            }
-    free_plan(c, s->solo);
-    DevBuf *bufs[] = {&s->key_c, &s->face_c, &s->fine_c, &s->u_c, &s->v_c, &s->level_c, &s->cfl_c, &s->eta_c,
-                      &s->tmp_u, &s->tmp_v, &s->u_s, &s->v_s, &s->key_s, &s->nbr_s, &s->fine_s, &s->perm,
-                      &s->inv, &s->hist, &s->cnt_ge_d, &s->flags, &s->xk, &s->xs, &s->xc, &s->stage,
-                      &s->root_start, &s->mkey, &s->refine, &s->cflag, &s->cnt, &s->off, &s->bsums, &s->key_n,
-                      &s->step_dev, &s->snap_u, &s->snap_v, &s->eta_t_c, &s->otab_d};
-    mdlts_status st = MDLTS_OK;
-    for (DevBuf *b : bufs)
-        if (dev_free(c, *b) != MDLTS_OK) st = MDLTS_EDEVICE;
-    for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
-    if (s->pin) (void)hipHostFree(s->pin);
-    c->n_sims--;
-    delete s;
-    return st;
+    return abi_guard([&]() -> mdlts_status {
+        if (!s) return MDLTS_EINVAL;
+        mdlts_ctx *c = s->ctx;
+        (void)hipStreamSynchronize(c->stream);
+        if (c->batch)
+            for (mdlts_sim *m : c->batch->sims)
+                if (m == s) {
+                    free_plan(c, c->batch);
+                    break;
+                }
+        free_plan(c, s->solo);
+        DevBuf *bufs[] = {&s->key_c, &s->face_c, &s->fine_c, &s->u_c, &s->v_c, &s->level_c, &s->cfl_c, &s->eta_c,
+                          &s->tmp_u, &s->tmp_v, &s->u_s, &s->v_s, &s->key_s, &s->nbr_s, &s->fine_s, &s->perm,
+                          &s->inv, &s->hist, &s->cnt_ge_d, &s->flags, &s->xk, &s->xs, &s->xc, &s->stage,
+                          &s->root_start, &s->mkey, &s->refine, &s->cflag, &s->cnt, &s->off, &s->bsums, &s->key_n,
+                          &s->step_dev, &s->snap_u, &s->snap_v, &s->eta_t_c, &s->otab_d};
+        mdlts_status st = MDLTS_OK;
+        for (DevBuf *b : bufs)
+            if (dev_free(c, *b) != MDLTS_OK) st = MDLTS_EDEVICE;
+        for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+        if (s->pin) (void)hipHostFree(s->pin);
+        c->n_sims--;
+        delete s;
+        return st;
+    });
 }
 
 mdlts_status mdlts_set_tree(mdlts_sim *s, const uint8_t *bits, size_t n_bits)
 {
-    if (!s || (!bits && n_bits)) return MDLTS_EINVAL;
-    s->version++;
-    Forest F;
-    forest_from_desc(&s->desc, F);
-    if (!F.parse_bits(bits, n_bits)) return MDLTS_EINVAL;
-    if (F.size() >= (1u << 27)) return MDLTS_EINVAL;
-    MD_TRY(set_forest(s, std::move(F)));
-    return zero_canonical_state(s);
+    return abi_guard([&]() -> mdlts_status {
+        if (!s || (!bits && n_bits)) return MDLTS_EINVAL;
+        s->version++;
+        Forest F;
+        forest_from_desc(&s->desc, F);
+        if (!F.parse_bits(bits, n_bits)) return MDLTS_EINVAL;
+        if (F.size() >= (1u << 27)) return MDLTS_EINVAL;
+        MD_TRY(set_forest(s, std::move(F)));
+        return zero_canonical_state(s);
+    });
 }
 
 mdlts_status mdlts_get_tree(mdlts_sim *s, uint8_t *bits, size_t cap, size_t *n_bits)
 {
-    if (!s || !n_bits) return MDLTS_EINVAL;
-    MD_TRY(refresh_host_forest(s));
-    std::vector<uint8_t> out;
-    s->forest.write_bits(out);
-    *n_bits = out.size();
-    if (bits && cap >= out.size()) std::memcpy(bits, out.data(), out.size());
-    return MDLTS_OK;
+    return abi_guard([&]() -> mdlts_status {
+        if (!s || !n_bits) return MDLTS_EINVAL;
+        MD_TRY(refresh_host_forest(s));
+        std::vector<uint8_t> out;
+        s->forest.write_bits(out);
+        *n_bits = out.size();
+        if (bits && cap >= out.size()) std::memcpy(bits, out.data(), out.size());
+        return MDLTS_OK;
+    });
 }
 
 mdlts_status mdlts_n_leaves(mdlts_sim *s, size_t *n)
 {
-    if (!s || !n) return MDLTS_EINVAL;
-    *n = s->E;
-    return MDLTS_OK;
+    return abi_guard([&]() -> mdlts_status {
+        if (!s || !n) return MDLTS_EINVAL;
+        *n = s->E;
+        return MDLTS_OK;
+    });
 }
 
 mdlts_status mdlts_set_conductivity(mdlts_sim *s, const double D_sym[6], double gamma)
 {
-    if (!s || !(gamma > 0.0) || !std::isfinite(gamma)) return MDLTS_EINVAL;
-    s->version++;
-    Conductivity C;
-    if (!parse_conductivity(D_sym, s->desc.dim, C)) return MDLTS_EINVAL;
-    double G[4][4];
-    if (!gershgorin_table(s->ref, gamma, G)) return MDLTS_EINVAL;
-    std::vector<double> otab;
-    if (C.full && !own_block_table(s->ref, s->desc.dim, s->h0, C, gamma, otab)) return MDLTS_EINVAL;
-    for (int k = 0; k < 3; k++) {
-        s->Dk[k] = k < s->desc.dim ? C.Dk[k] : 0.0;
-        s->Dx[k] = C.Dx[k];
-    }
-    s->dfull = C.full;
-    s->otab = std::move(otab);
-    s->otab_dirty = C.full;
-    s->gamma = gamma;
-    s->step_dirty = true;
-    std::memcpy(s->G, G, sizeof(G));
-    s->levels_valid = s->levels_valid && false;
-    return MDLTS_OK;
+    return abi_guard([&]() -> mdlts_status {
+        if (!s || !(gamma > 0.0) || !std::isfinite(gamma)) return MDLTS_EINVAL;
+        s->version++;
+        Conductivity C;
+        if (!parse_conductivity(D_sym, s->desc.dim, C)) return MDLTS_EINVAL;
+        double G[4][4];
+        if (!gershgorin_table(s->ref, gamma, G)) return MDLTS_EINVAL;
+        std::vector<double> otab;
+        if (C.full && !own_block_table(s->ref, s->desc.dim, s->h0, C, gamma, otab)) return MDLTS_EINVAL;
+        for (int k = 0; k < 3; k++) {
+            s->Dk[k] = k < s->desc.dim ? C.Dk[k] : 0.0;
+            s->Dx[k] = C.Dx[k];
+        }
+        s->dfull = C.full;
+        s->otab = std::move(otab);
+        s->otab_dirty = C.full;
+        s->gamma = gamma;
+        s->step_dirty = true;
+        std::memcpy(s->G, G, sizeof(G));
+        s->levels_valid = s->levels_valid && false;
+        return MDLTS_OK;
+    });
 }
 
 mdlts_status mdlts_set_ionic(mdlts_sim *s, const mdlts_ap_params *p)
 {
-    if (!s || !p) return MDLTS_EINVAL;
-    s->version++;
-    s->ap = *p;
-    s->step_dirty = true;
-    return MDLTS_OK;
+    return abi_guard([&]() -> mdlts_status {
+        if (!s || !p) return MDLTS_EINVAL;
+        s->version++;
+        s->ap = *p;
+        s->step_dirty = true;
+        return MDLTS_OK;
+    });
 }
 
 mdlts_status mdlts_set_stimulus(mdlts_sim *s, const mdlts_stim_box *boxes, int n_boxes)
 {
-    if (!s || n_boxes < 0 || n_boxes > kMaxStim || (n_boxes && !boxes)) return MDLTS_EINVAL;
-    s->version++;
-    s->stim.assign(boxes, boxes + n_boxes);
-    s->step_dirty = true;
-    return MDLTS_OK;
+    return abi_guard([&]() -> mdlts_status {
+        if (!s || n_boxes < 0 || n_boxes > kMaxStim || (n_boxes && !boxes)) return MDLTS_EINVAL;
+        s->version++;
+        s->stim.assign(boxes, boxes + n_boxes);
+        s->step_dirty = true;
+        return MDLTS_OK;
+    });
 }
 
 mdlts_status mdlts_set_state(mdlts_sim *s, const double *u, const double *v, size_t n_dof)
 {
-    if (!s) return MDLTS_EINVAL;
-    s->version++;
-    const size_t E = s->E;
-    if (n_dof != E * (size_t)s->np) return MDLTS_EINVAL;
-    mdlts_ctx *c = s->ctx;
-    s->eta_valid = false;
-    MD_TRY(to_canonical(s));
-    MD_TRY(dev_alloc(c, s->stage, n_dof * sizeof(double)));
-    const double *src[2] = {u, v};
-    DevBuf *dst[2] = {&s->u_c, &s->v_c};
-    for (int f = 0; f < 2; f++) {
-        if (!src[f]) continue;
-        HIP_TRY(hipMemcpyAsync(s->stage.p, src[f], n_dof * sizeof(double), hipMemcpyHostToDevice, c->stream));
-        if (s->desc.precision == MDLTS_FP64)
-            k_from_host<double><<<nblocks((long long)n_dof), kBlock, 0, c->stream>>>((int)E, s->np, P<double>(s->stage),
-                                                                                    P<double>(*dst[f]));
-        else
-            k_from_host<float><<<nblocks((long long)n_dof), kBlock, 0, c->stream>>>((int)E, s->np, P<double>(s->stage),
-                                                                                   P<float>(*dst[f]));
-        HIP_TRY(hipGetLastError());
-        MD_TRY(sync(c));  // the staging buffer is reused
-    }
-    if (s->levels_valid) MD_TRY(to_grouped(s));
-    return sync(c);
+    return abi_guard([&]() -> mdlts_status {
+        if (!s) return MDLTS_EINVAL;
+        s->version++;
+        const size_t E = s->E;
+        if (n_dof != E * (size_t)s->np) return MDLTS_EINVAL;
+        mdlts_ctx *c = s->ctx;
+        s->eta_valid = false;
+        MD_TRY(to_canonical(s));
+        MD_TRY(dev_alloc(c, s->stage, n_dof * sizeof(double)));
+        const double *src[2] = {u, v};
+        DevBuf *dst[2] = {&s->u_c, &s->v_c};
+        for (int f = 0; f < 2; f++) {
+            if (!src[f]) continue;
+            HIP_TRY(hipMemcpyAsync(s->stage.p, src[f], n_dof * sizeof(double), hipMemcpyHostToDevice, c->stream));
+            if (s->desc.precision == MDLTS_FP64)
+                k_from_host<double><<<nblocks((long long)n_dof), kBlock, 0, c->stream>>>((int)E, s->np, P<double>(s->stage),
+                                                                                        P<double>(*dst[f]));
+            else
+                k_from_host<float><<<nblocks((long long)n_dof), kBlock, 0, c->stream>>>((int)E, s->np, P<double>(s->stage),
+                                                                                       P<float>(*dst[f]));
+            HIP_TRY(hipGetLastError());
+            MD_TRY(sync(c));  // the staging buffer is reused
+        }
+        if (s->levels_valid) MD_TRY(to_grouped(s));
+        return sync(c);
+    });
 }
 
 mdlts_status mdlts_get_state(mdlts_sim *s, double *u, double *v, size_t n_dof)
 {
-    if (!s) return MDLTS_EINVAL;
-    const size_t E = s->E;
-    if (n_dof != E * (size_t)s->np) return MDLTS_EINVAL;
-    mdlts_ctx *c = s->ctx;
-    const bool was_grouped = s->state_grouped;
-    MD_TRY(to_canonical(s));
-    MD_TRY(dev_alloc(c, s->stage, n_dof * sizeof(double)));
-    double *dst[2] = {u, v};
-    DevBuf *src[2] = {&s->u_c, &s->v_c};
-    for (int f = 0; f < 2; f++) {
-        if (!dst[f]) continue;
-        if (s->desc.precision == MDLTS_FP64)
-            k_to_host<double><<<nblocks((long long)n_dof), kBlock, 0, c->stream>>>((int)E, s->np, P<double>(*src[f]),
-                                                                                  P<double>(s->stage));
-        else
-            k_to_host<float><<<nblocks((long long)n_dof), kBlock, 0, c->stream>>>((int)E, s->np, P<float>(*src[f]),
-                                                                                 P<double>(s->stage));
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(dst[f], s->stage.p, n_dof * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        MD_TRY(sync(c));
-    }
-    // the grouped copy is still current: keep stepping from it
-    if (was_grouped) s->state_grouped = true;
-    return MDLTS_OK;
+    return abi_guard([&]() -> mdlts_status {
+        if (!s) return MDLTS_EINVAL;
+        const size_t E = s->E;
+        if (n_dof != E * (size_t)s->np) return MDLTS_EINVAL;
+        mdlts_ctx *c = s->ctx;
+        const bool was_grouped = s->state_grouped;
+        MD_TRY(to_canonical(s));
+        MD_TRY(dev_alloc(c, s->stage, n_dof * sizeof(double)));
+        double *dst[2] = {u, v};
+        DevBuf *src[2] = {&s->u_c, &s->v_c};
+        for (int f = 0; f < 2; f++) {
+            if (!dst[f]) continue;
+            if (s->desc.precision == MDLTS_FP64)
+                k_to_host<double><<<nblocks((long long)n_dof), kBlock, 0, c->stream>>>((int)E, s->np, P<double>(*src[f]),
+                                                                                      P<double>(s->stage));
+            else
+                k_to_host<float><<<nblocks((long long)n_dof), kBlock, 0, c->stream>>>((int)E, s->np, P<float>(*src[f]),
+                                                                                     P<double>(s->stage));
+            HIP_TRY(hipGetLastError());
+            HIP_TRY(hipMemcpyAsync(dst[f], s->stage.p, n_dof * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            MD_TRY(sync(c));
+        }
+        // the grouped copy is still current: keep stepping from it
+        if (was_grouped) s->state_grouped = true;
+        return MDLTS_OK;
+    });
 }
 
 mdlts_status mdlts_set_time(mdlts_sim *s, double t)
 {
-    if (!s || !std::isfinite(t)) return MDLTS_EINVAL;
-    s->version++;
-    s->t_start = t;
-    s->n_bar = 0;
-    return MDLTS_OK;
+    return abi_guard([&]() -> mdlts_status {
+        if (!s || !std::isfinite(t)) return MDLTS_EINVAL;
+        s->version++;
+        s->t_start = t;
+        s->n_bar = 0;
+        return MDLTS_OK;
+    });
 }
 
 static mdlts_status assign_levels_impl(mdlts_sim *s, double dt_barrier, int force_level, int32_t *level_hist);
 
 mdlts_status mdlts_assign_levels(mdlts_sim *s, double dt_barrier, int32_t *level_hist)
 {
-    return assign_levels_impl(s, dt_barrier, -1, level_hist);
+    return abi_guard([&]() -> mdlts_status {
+        return assign_levels_impl(s, dt_barrier, -1, level_hist);
+    });
 }
 
 mdlts_status mdlts_assign_uniform(mdlts_sim *s, double dt_barrier, int level, int32_t *level_hist)
 {
-    if (!s || level < 0 || level >= s->desc.n_levels) return MDLTS_EINVAL;
-    return assign_levels_impl(s, dt_barrier, level, level_hist);
+    return abi_guard([&]() -> mdlts_status {
+        if (!s || level < 0 || level >= s->desc.n_levels) return MDLTS_EINVAL;
+        return assign_levels_impl(s, dt_barrier, level, level_hist);
+    });
 }
 
 // Level assignment in two halves (so that several simulations can share the
@@ -2462,160 +2495,174 @@ static mdlts_status assign_levels_impl(mdlts_sim *s, double dt_barrier, int forc
 
 mdlts_status mdlts_assign_levels_auto(mdlts_sim *s, double *dt_barrier, int32_t *level_hist)
 {
-    if (!s || !dt_barrier) return MDLTS_EINVAL;
-    mdlts_ctx *c = s->ctx;
-    const int E = (int)s->E;
-    // CFL of every leaf (the level pass with every leaf forced to level 0),
-    // then its minimum
-    MD_TRY(levels_enqueue(s, 1.0, 0));
-    unsigned long long *mb = MD_FLAG(s, unsigned long long, eta_max_bits);
-    const unsigned long long init = 0x7fefffffffffffffull;  // largest finite double
-    HIP_TRY(hipMemcpyAsync(mb, &init, 8, hipMemcpyHostToDevice, c->stream));
-    k_min_positive<<<nblocks(E), kBlock, 0, c->stream>>>(E, P<double>(s->cfl_c), mb);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(&s->pin->eta_max_bits, mb, 8, hipMemcpyDeviceToHost, c->stream));
-    MD_TRY(sync(c));
-    double cfl_min;
-    std::memcpy(&cfl_min, &s->pin->eta_max_bits, 8);
-    if (!(cfl_min > 0.0) || !std::isfinite(cfl_min)) return MDLTS_EUNSTABLE;
-    // every leaf within the configured levels, off the power-of-two ties
-    const double dt = std::ldexp(cfl_min, s->desc.n_levels - 1) * (1.0 - std::ldexp(1.0, -20));
-    *dt_barrier = dt;
-    return assign_levels_impl(s, dt, -1, level_hist);
+    return abi_guard([&]() -> mdlts_status {
+        if (!s || !dt_barrier) return MDLTS_EINVAL;
+        mdlts_ctx *c = s->ctx;
+        const int E = (int)s->E;
+        // CFL of every leaf (the level pass with every leaf forced to level 0),
+        // then its minimum
+        MD_TRY(levels_enqueue(s, 1.0, 0));
+        unsigned long long *mb = MD_FLAG(s, unsigned long long, eta_max_bits);
+        const unsigned long long init = 0x7fefffffffffffffull;  // largest finite double
+        HIP_TRY(hipMemcpyAsync(mb, &init, 8, hipMemcpyHostToDevice, c->stream));
+        k_min_positive<<<nblocks(E), kBlock, 0, c->stream>>>(E, P<double>(s->cfl_c), mb);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(&s->pin->eta_max_bits, mb, 8, hipMemcpyDeviceToHost, c->stream));
+        MD_TRY(sync(c));
+        double cfl_min;
+        std::memcpy(&cfl_min, &s->pin->eta_max_bits, 8);
+        if (!(cfl_min > 0.0) || !std::isfinite(cfl_min)) return MDLTS_EUNSTABLE;
+        // every leaf within the configured levels, off the power-of-two ties
+        const double dt = std::ldexp(cfl_min, s->desc.n_levels - 1) * (1.0 - std::ldexp(1.0, -20));
+        *dt_barrier = dt;
+        return assign_levels_impl(s, dt, -1, level_hist);
+    });
 }
 
 mdlts_status mdlts_rvt_snapshot(mdlts_sim *s)
 {
-    if (!s) return MDLTS_EINVAL;
-    mdlts_ctx *c = s->ctx;
-    const bool was_grouped = s->state_grouped;
-    MD_TRY(to_canonical(s));
-    const size_t bytes = s->E * s->np * s->tsize;
-    MD_TRY(dev_alloc(c, s->snap_u, bytes));
-    MD_TRY(dev_alloc(c, s->snap_v, bytes));
-    HIP_TRY(hipMemcpyAsync(s->snap_u.p, s->u_c.p, bytes, hipMemcpyDeviceToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(s->snap_v.p, s->v_c.p, bytes, hipMemcpyDeviceToDevice, c->stream));
-    if (was_grouped) s->state_grouped = true;  // the grouped copy is untouched
-    s->snap_t = s->t_start + (double)s->n_bar * s->dt_bar;
-    s->snap_rev = s->tree_rev;
-    return MDLTS_OK;
+    return abi_guard([&]() -> mdlts_status {
+        if (!s) return MDLTS_EINVAL;
+        mdlts_ctx *c = s->ctx;
+        const bool was_grouped = s->state_grouped;
+        MD_TRY(to_canonical(s));
+        const size_t bytes = s->E * s->np * s->tsize;
+        MD_TRY(dev_alloc(c, s->snap_u, bytes));
+        MD_TRY(dev_alloc(c, s->snap_v, bytes));
+        HIP_TRY(hipMemcpyAsync(s->snap_u.p, s->u_c.p, bytes, hipMemcpyDeviceToDevice, c->stream));
+        HIP_TRY(hipMemcpyAsync(s->snap_v.p, s->v_c.p, bytes, hipMemcpyDeviceToDevice, c->stream));
+        if (was_grouped) s->state_grouped = true;  // the grouped copy is untouched
+        s->snap_t = s->t_start + (double)s->n_bar * s->dt_bar;
+        s->snap_rev = s->tree_rev;
+        return MDLTS_OK;
+    });
 }
 
 mdlts_status mdlts_rvt_indicator(mdlts_sim *s, double *eta_t, size_t n_leaves, double *eta_t_max)
 {
-    if (!s) return MDLTS_EINVAL;
-    const size_t E = s->E;
-    if (eta_t && n_leaves != E) return MDLTS_EINVAL;
-    const double t_b = s->t_start + (double)s->n_bar * s->dt_bar;
-    if (s->snap_rev != s->tree_rev || !(t_b > s->snap_t)) return MDLTS_ESTATE;
-    mdlts_ctx *c = s->ctx;
-    const bool was_grouped = s->state_grouped;
-    MD_TRY(to_canonical(s));
-    MD_TRY(dev_alloc(c, s->eta_t_c, E * sizeof(double)));
-    MD_TRY(flags_clear(s));
-    RvtArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.u_a = s->snap_u.p;
-    a.v_a = s->snap_v.p;
-    a.u_b = s->u_c.p;
-    a.v_b = s->v_c.p;
-    a.key = s->key_c.p;
-    a.E = (int)E;
-    for (int k = 0; k < 3; k++) a.h0[k] = s->h0[k];
-    a.apk = s->ap.k; a.apa = s->ap.a; a.eps0 = s->ap.eps0; a.mu1 = s->ap.mu1; a.mu2 = s->ap.mu2;
-    a.t_a = s->snap_t;
-    a.t_b = t_b;
-    a.n_stim = (int)s->stim.size();
-    for (int b = 0; b < a.n_stim; b++) {
-        const mdlts_stim_box &B = s->stim[b];
-        for (int k = 0; k < 3; k++) { a.stim[b][k] = B.lo[k]; a.stim[b][3 + k] = B.hi[k]; }
-        a.stim[b][6] = B.t_on; a.stim[b][7] = B.t_off; a.stim[b][8] = B.amp;
-    }
-    a.eta = P<double>(s->eta_t_c);
-    a.eta_max_bits = MD_FLAG(s, unsigned long long, eta_max_bits);
-    const int nb = nblocks((int)E);
-    hipStream_t st = c->stream;
-    switch (s->desc.dim * 100 + s->desc.order * 10 + (s->desc.precision == MDLTS_FP32 ? 1 : 0)) {
-    case 210: k_rvt<2, 1, double><<<nb, kBlock, 0, st>>>(a); break;
-    case 220: k_rvt<2, 2, double><<<nb, kBlock, 0, st>>>(a); break;
-    case 310: k_rvt<3, 1, double><<<nb, kBlock, 0, st>>>(a); break;
-    case 320: k_rvt<3, 2, double><<<nb, kBlock, 0, st>>>(a); break;
-    case 211: k_rvt<2, 1, float><<<nb, kBlock, 0, st>>>(a); break;
-    case 221: k_rvt<2, 2, float><<<nb, kBlock, 0, st>>>(a); break;
-    case 311: k_rvt<3, 1, float><<<nb, kBlock, 0, st>>>(a); break;
-    case 321: k_rvt<3, 2, float><<<nb, kBlock, 0, st>>>(a); break;
-    case 230: k_rvt<2, 3, double><<<nb, kBlock, 0, st>>>(a); break;
-    case 330: k_rvt<3, 3, double><<<nb, kBlock, 0, st>>>(a); break;
-    case 231: k_rvt<2, 3, float><<<nb, kBlock, 0, st>>>(a); break;
-    case 331: k_rvt<3, 3, float><<<nb, kBlock, 0, st>>>(a); break;
-    default: return MDLTS_EINVAL;
-    }
-    HIP_TRY(hipGetLastError());
-    if (eta_t) HIP_TRY(hipMemcpyAsync(eta_t, s->eta_t_c.p, E * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(&s->pin->eta_max_bits, a.eta_max_bits, 8, hipMemcpyDeviceToHost, st));
-    MD_TRY(sync(c));
-    if (was_grouped) s->state_grouped = true;
-    if (eta_t_max) std::memcpy(eta_t_max, &s->pin->eta_max_bits, 8);
-    s->eta_t_rev = s->tree_rev;
-    return MDLTS_OK;
+    return abi_guard([&]() -> mdlts_status {
+        if (!s) return MDLTS_EINVAL;
+        const size_t E = s->E;
+        if (eta_t && n_leaves != E) return MDLTS_EINVAL;
+        const double t_b = s->t_start + (double)s->n_bar * s->dt_bar;
+        if (s->snap_rev != s->tree_rev || !(t_b > s->snap_t)) return MDLTS_ESTATE;
+        mdlts_ctx *c = s->ctx;
+        const bool was_grouped = s->state_grouped;
+        MD_TRY(to_canonical(s));
+        MD_TRY(dev_alloc(c, s->eta_t_c, E * sizeof(double)));
+        MD_TRY(flags_clear(s));
+        RvtArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.u_a = s->snap_u.p;
+        a.v_a = s->snap_v.p;
+        a.u_b = s->u_c.p;
+        a.v_b = s->v_c.p;
+        a.key = s->key_c.p;
+        a.E = (int)E;
+        for (int k = 0; k < 3; k++) a.h0[k] = s->h0[k];
+        a.apk = s->ap.k; a.apa = s->ap.a; a.eps0 = s->ap.eps0; a.mu1 = s->ap.mu1; a.mu2 = s->ap.mu2;
+        a.t_a = s->snap_t;
+        a.t_b = t_b;
+        a.n_stim = (int)s->stim.size();
+        for (int b = 0; b < a.n_stim; b++) {
+            const mdlts_stim_box &B = s->stim[b];
+            for (int k = 0; k < 3; k++) { a.stim[b][k] = B.lo[k]; a.stim[b][3 + k] = B.hi[k]; }
+            a.stim[b][6] = B.t_on; a.stim[b][7] = B.t_off; a.stim[b][8] = B.amp;
+        }
+        a.eta = P<double>(s->eta_t_c);
+        a.eta_max_bits = MD_FLAG(s, unsigned long long, eta_max_bits);
+        const int nb = nblocks((int)E);
+        hipStream_t st = c->stream;
+        switch (s->desc.dim * 100 + s->desc.order * 10 + (s->desc.precision == MDLTS_FP32 ? 1 : 0)) {
+        case 210: k_rvt<2, 1, double><<<nb, kBlock, 0, st>>>(a); break;
+        case 220: k_rvt<2, 2, double><<<nb, kBlock, 0, st>>>(a); break;
+        case 310: k_rvt<3, 1, double><<<nb, kBlock, 0, st>>>(a); break;
+        case 320: k_rvt<3, 2, double><<<nb, kBlock, 0, st>>>(a); break;
+        case 211: k_rvt<2, 1, float><<<nb, kBlock, 0, st>>>(a); break;
+        case 221: k_rvt<2, 2, float><<<nb, kBlock, 0, st>>>(a); break;
+        case 311: k_rvt<3, 1, float><<<nb, kBlock, 0, st>>>(a); break;
+        case 321: k_rvt<3, 2, float><<<nb, kBlock, 0, st>>>(a); break;
+        case 230: k_rvt<2, 3, double><<<nb, kBlock, 0, st>>>(a); break;
+        case 330: k_rvt<3, 3, double><<<nb, kBlock, 0, st>>>(a); break;
+        case 231: k_rvt<2, 3, float><<<nb, kBlock, 0, st>>>(a); break;
+        case 331: k_rvt<3, 3, float><<<nb, kBlock, 0, st>>>(a); break;
+        default: return MDLTS_EINVAL;
+        }
+        HIP_TRY(hipGetLastError());
+        if (eta_t) HIP_TRY(hipMemcpyAsync(eta_t, s->eta_t_c.p, E * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(&s->pin->eta_max_bits, a.eta_max_bits, 8, hipMemcpyDeviceToHost, st));
+        MD_TRY(sync(c));
+        if (was_grouped) s->state_grouped = true;
+        if (eta_t_max) std::memcpy(eta_t_max, &s->pin->eta_max_bits, 8);
+        s->eta_t_rev = s->tree_rev;
+        return MDLTS_OK;
+    });
 }
 
 mdlts_status mdlts_assign_levels_cell(mdlts_sim *s, double dt_barrier, double tau_cell, double dt_cell,
                                       int32_t *level_hist)
 {
-    if (!s || !(dt_cell > 0.0) || !std::isfinite(dt_cell) || !(dt_barrier > 0.0)) return MDLTS_EINVAL;
-    if (s->eta_t_rev != s->tree_rev) return MDLTS_ESTATE;
-    int b_cell = 0;  // ceil(log2(dt_barrier / dt_cell)) by exact scaling
-    while (b_cell < 64 && std::ldexp(dt_barrier, -b_cell) > dt_cell) b_cell++;
-    MD_TRY(levels_enqueue(s, dt_barrier, -1, P<double>(s->eta_t_c), tau_cell, b_cell));
-    MD_TRY(sync(s->ctx));
-    return levels_finish(s, dt_barrier, level_hist);
+    return abi_guard([&]() -> mdlts_status {
+        if (!s || !(dt_cell > 0.0) || !std::isfinite(dt_cell) || !(dt_barrier > 0.0)) return MDLTS_EINVAL;
+        if (s->eta_t_rev != s->tree_rev) return MDLTS_ESTATE;
+        int b_cell = 0;  // ceil(log2(dt_barrier / dt_cell)) by exact scaling
+        while (b_cell < 64 && std::ldexp(dt_barrier, -b_cell) > dt_cell) b_cell++;
+        MD_TRY(levels_enqueue(s, dt_barrier, -1, P<double>(s->eta_t_c), tau_cell, b_cell));
+        MD_TRY(sync(s->ctx));
+        return levels_finish(s, dt_barrier, level_hist);
+    });
 }
 
 mdlts_status mdlts_get_levels(mdlts_sim *s, int8_t *level, int32_t *perm, int32_t *cnt_ge, size_t n_leaves)
 {
-    if (!s) return MDLTS_EINVAL;
-    if (!s->levels_valid) return MDLTS_ESTATE;
-    if (n_leaves != s->E) return MDLTS_EINVAL;
-    mdlts_ctx *c = s->ctx;
-    if (level) HIP_TRY(hipMemcpyAsync(level, s->level_c.p, n_leaves, hipMemcpyDeviceToHost, c->stream));
-    if (perm) HIP_TRY(hipMemcpyAsync(perm, s->perm.p, n_leaves * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-    if (cnt_ge)
-        for (size_t l = 0; l < s->cnt_ge.size(); l++) cnt_ge[l] = s->cnt_ge[l];
-    return sync(c);
+    return abi_guard([&]() -> mdlts_status {
+        if (!s) return MDLTS_EINVAL;
+        if (!s->levels_valid) return MDLTS_ESTATE;
+        if (n_leaves != s->E) return MDLTS_EINVAL;
+        mdlts_ctx *c = s->ctx;
+        if (level) HIP_TRY(hipMemcpyAsync(level, s->level_c.p, n_leaves, hipMemcpyDeviceToHost, c->stream));
+        if (perm) HIP_TRY(hipMemcpyAsync(perm, s->perm.p, n_leaves * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+        if (cnt_ge)
+            for (size_t l = 0; l < s->cnt_ge.size(); l++) cnt_ge[l] = s->cnt_ge[l];
+        return sync(c);
+    });
 }
 
 mdlts_status mdlts_get_cfl(mdlts_sim *s, double *cfl, size_t n_leaves)
 {
-    if (!s || !cfl) return MDLTS_EINVAL;
-    if (!s->levels_valid) return MDLTS_ESTATE;
-    if (n_leaves != s->E) return MDLTS_EINVAL;
-    HIP_TRY(hipMemcpyAsync(cfl, s->cfl_c.p, n_leaves * sizeof(double), hipMemcpyDeviceToHost, s->ctx->stream));
-    return sync(s->ctx);
+    return abi_guard([&]() -> mdlts_status {
+        if (!s || !cfl) return MDLTS_EINVAL;
+        if (!s->levels_valid) return MDLTS_ESTATE;
+        if (n_leaves != s->E) return MDLTS_EINVAL;
+        HIP_TRY(hipMemcpyAsync(cfl, s->cfl_c.p, n_leaves * sizeof(double), hipMemcpyDeviceToHost, s->ctx->stream));
+        return sync(s->ctx);
+    });
 }
 
 mdlts_status mdlts_step(mdlts_sim *s, int n_barriers)
 {
-    if (!s || n_barriers < 0) return MDLTS_EINVAL;
-    if (!s->levels_valid || !s->state_grouped) return MDLTS_ESTATE;
-    s->eta_valid = false;
-    mdlts_ctx *c = s->ctx;
-    if (!c->use_graphs) {
-        if (s->desc.precision == MDLTS_FP64) return run_barriers<double>(s, n_barriers);
-        return run_barriers<float>(s, n_barriers);
-    }
-    // a one-simulation plan of tile launches (one kernel variant: launched
-    // directly, see run_batch_barriers)
-    bool fresh = false;
-    MD_TRY(prepare_plan(c, s->solo, &s, 1, &fresh));
-    BatchPlan &P = *s->solo;
-    if (P.prof != s->prof) {
-        MD_TRY(drain_batch_events(P));
-        P.prof = s->prof;
-    }
-    int remaining = n_barriers;
-    if (!P.tuned) MD_TRY(autotune(c, P, &remaining));
-    return run_batch_barriers(c, P, remaining);
+    return abi_guard([&]() -> mdlts_status {
+        if (!s || n_barriers < 0) return MDLTS_EINVAL;
+        if (!s->levels_valid || !s->state_grouped) return MDLTS_ESTATE;
+        s->eta_valid = false;
+        mdlts_ctx *c = s->ctx;
+        if (!c->use_graphs) {
+            if (s->desc.precision == MDLTS_FP64) return run_barriers<double>(s, n_barriers);
+            return run_barriers<float>(s, n_barriers);
+        }
+        // a one-simulation plan of tile launches (one kernel variant: launched
+        // directly, see run_batch_barriers)
+        bool fresh = false;
+        MD_TRY(prepare_plan(c, s->solo, &s, 1, &fresh));
+        BatchPlan &P = *s->solo;
+        if (P.prof != s->prof) {
+            MD_TRY(drain_batch_events(P));
+            P.prof = s->prof;
+        }
+        int remaining = n_barriers;
+        if (!P.tuned) MD_TRY(autotune(c, P, &remaining));
+        return run_batch_barriers(c, P, remaining);
+    });
 }
 
 // the indicator on the device (canonical state, FP64 eta in eta_c); its
@@ -2646,48 +2693,54 @@ static mdlts_status indicator_enqueue(mdlts_sim *s, bool own_flags = true)
 
 mdlts_status mdlts_indicator(mdlts_sim *s, double *eta, size_t n_leaves, double *eta_max)
 {
-    if (!s) return MDLTS_EINVAL;
-    const size_t E = s->E;
-    if (eta && n_leaves != E) return MDLTS_EINVAL;
-    mdlts_ctx *c = s->ctx;
-    MD_TRY(indicator_enqueue(s));
-    if (eta) HIP_TRY(hipMemcpyAsync(eta, s->eta_c.p, E * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    MD_TRY(sync(c));
-    if (eta_max) std::memcpy(eta_max, &s->pin->eta_max_bits, 8);
-    return s->pin->eta_nonfinite ? MDLTS_EUNSTABLE : MDLTS_OK;
+    return abi_guard([&]() -> mdlts_status {
+        if (!s) return MDLTS_EINVAL;
+        const size_t E = s->E;
+        if (eta && n_leaves != E) return MDLTS_EINVAL;
+        mdlts_ctx *c = s->ctx;
+        MD_TRY(indicator_enqueue(s));
+        if (eta) HIP_TRY(hipMemcpyAsync(eta, s->eta_c.p, E * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        MD_TRY(sync(c));
+        if (eta_max) std::memcpy(eta_max, &s->pin->eta_max_bits, 8);
+        return s->pin->eta_nonfinite ? MDLTS_EUNSTABLE : MDLTS_OK;
+    });
 }
 
 mdlts_status mdlts_adapt(mdlts_sim *s, const double *eta, size_t n_leaves, double tau_refine, double tau_coarsen,
                          int64_t *n_refined, int64_t *n_coarsened)
 {
-    if (!s) return MDLTS_EINVAL;
-    const size_t E = s->E;
-    if (eta && n_leaves != E) return MDLTS_EINVAL;
-    if (!eta && !s->eta_valid) return MDLTS_ESTATE;
-    s->version++;
-    mdlts_ctx *c = s->ctx;
-    if (eta) {
-        MD_TRY(copy_h2d(c, s->eta_c, eta, E));
+    return abi_guard([&]() -> mdlts_status {
+        if (!s) return MDLTS_EINVAL;
+        const size_t E = s->E;
+        if (eta && n_leaves != E) return MDLTS_EINVAL;
+        if (!eta && !s->eta_valid) return MDLTS_ESTATE;
+        s->version++;
+        mdlts_ctx *c = s->ctx;
+        if (eta) {
+            MD_TRY(copy_h2d(c, s->eta_c, eta, E));
+            MD_TRY(sync(c));
+        }
+        MD_TRY(to_canonical(s));
+        if (s->desc.dim == 2) MD_TRY(adapt_count<2>(s, tau_refine, tau_coarsen));
+        else MD_TRY(adapt_count<3>(s, tau_refine, tau_coarsen));
         MD_TRY(sync(c));
-    }
-    MD_TRY(to_canonical(s));
-    if (s->desc.dim == 2) MD_TRY(adapt_count<2>(s, tau_refine, tau_coarsen));
-    else MD_TRY(adapt_count<3>(s, tau_refine, tau_coarsen));
-    MD_TRY(sync(c));
-    if (n_refined) *n_refined = (int64_t)s->pin->tallies[0];
-    if (n_coarsened) *n_coarsened = (int64_t)s->pin->tallies[1];
-    if (s->desc.dim == 2) MD_TRY(adapt_emit<2>(s));
-    else MD_TRY(adapt_emit<3>(s));
-    MD_TRY(sync(c));
-    return s->pin->face_bad ? MDLTS_EINVAL : MDLTS_OK;
+        if (n_refined) *n_refined = (int64_t)s->pin->tallies[0];
+        if (n_coarsened) *n_coarsened = (int64_t)s->pin->tallies[1];
+        if (s->desc.dim == 2) MD_TRY(adapt_emit<2>(s));
+        else MD_TRY(adapt_emit<3>(s));
+        MD_TRY(sync(c));
+        return s->pin->face_bad ? MDLTS_EINVAL : MDLTS_OK;
+    });
 }
 
 mdlts_status mdlts_counters(mdlts_sim *s, uint64_t *dof_updates, double *t_sim)
 {
-    if (!s) return MDLTS_EINVAL;
-    if (dof_updates) *dof_updates = s->dof_updates;
-    if (t_sim) *t_sim = s->t_start + (double)s->n_bar * s->dt_bar;
-    return MDLTS_OK;
+    return abi_guard([&]() -> mdlts_status {
+        if (!s) return MDLTS_EINVAL;
+        if (dof_updates) *dof_updates = s->dof_updates;
+        if (t_sim) *t_sim = s->t_start + (double)s->n_bar * s->dt_bar;
+        return MDLTS_OK;
+    });
 }
 
 // event times of the step plan's launches, added to the simulation's
@@ -2706,304 +2759,326 @@ static mdlts_status drain_solo(mdlts_sim *s)
 
 mdlts_status mdlts_profile(mdlts_sim *s, int enable)
 {
-    if (!s) return MDLTS_EINVAL;
-    MD_TRY(drain_events(s));
-    MD_TRY(drain_solo(s));
-    s->prof = enable != 0;
-    s->prof_ms = 0.0;
-    s->prof_launches = s->prof_dof = 0;
-    return MDLTS_OK;
+    return abi_guard([&]() -> mdlts_status {
+        if (!s) return MDLTS_EINVAL;
+        MD_TRY(drain_events(s));
+        MD_TRY(drain_solo(s));
+        s->prof = enable != 0;
+        s->prof_ms = 0.0;
+        s->prof_launches = s->prof_dof = 0;
+        return MDLTS_OK;
+    });
 }
 
 mdlts_status mdlts_profile_read(mdlts_sim *s, double *substep_ms, uint64_t *n_launches, uint64_t *dof_updates)
 {
-    if (!s) return MDLTS_EINVAL;
-    MD_TRY(drain_events(s));
-    MD_TRY(drain_solo(s));
-    if (substep_ms) *substep_ms = s->prof_ms;
-    if (n_launches) *n_launches = s->prof_launches;
-    if (dof_updates) *dof_updates = s->prof_dof;
-    s->prof_ms = 0.0;
-    s->prof_launches = s->prof_dof = 0;
-    return MDLTS_OK;
+    return abi_guard([&]() -> mdlts_status {
+        if (!s) return MDLTS_EINVAL;
+        MD_TRY(drain_events(s));
+        MD_TRY(drain_solo(s));
+        if (substep_ms) *substep_ms = s->prof_ms;
+        if (n_launches) *n_launches = s->prof_launches;
+        if (dof_updates) *dof_updates = s->prof_dof;
+        s->prof_ms = 0.0;
+        s->prof_launches = s->prof_dof = 0;
+        return MDLTS_OK;
+    });
 }
 
 mdlts_status mdlts_batch_step(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sims, int n_barriers)
 {
-    if (!ctx || !sims || n_sims < 1 || n_barriers < 0) return MDLTS_EINVAL;
-    for (int q = 0; q < n_sims; q++) {
-        if (!sims[q] || sims[q]->ctx != ctx) return MDLTS_EINVAL;
-        for (int r = 0; r < q; r++)
-            if (sims[r] == sims[q]) return MDLTS_EINVAL;
-        if (!sims[q]->levels_valid || !sims[q]->state_grouped) return MDLTS_ESTATE;
-    }
-    bool fresh = false;
-    MD_TRY(prepare_plan(ctx, ctx->batch, sims, n_sims, &fresh));
-    BatchPlan &P = *ctx->batch;
-    int remaining = n_barriers;
-    if (!P.tuned) MD_TRY(autotune(ctx, P, &remaining));
-    MD_TRY(run_batch_barriers(ctx, P, remaining));
-    return MDLTS_OK;
+    return abi_guard([&]() -> mdlts_status {
+        if (!ctx || !sims || n_sims < 1 || n_barriers < 0) return MDLTS_EINVAL;
+        for (int q = 0; q < n_sims; q++) {
+            if (!sims[q] || sims[q]->ctx != ctx) return MDLTS_EINVAL;
+            for (int r = 0; r < q; r++)
+                if (sims[r] == sims[q]) return MDLTS_EINVAL;
+            if (!sims[q]->levels_valid || !sims[q]->state_grouped) return MDLTS_ESTATE;
+        }
+        bool fresh = false;
+        MD_TRY(prepare_plan(ctx, ctx->batch, sims, n_sims, &fresh));
+        BatchPlan &P = *ctx->batch;
+        int remaining = n_barriers;
+        if (!P.tuned) MD_TRY(autotune(ctx, P, &remaining));
+        MD_TRY(run_batch_barriers(ctx, P, remaining));
+        return MDLTS_OK;
+    });
 }
 
 mdlts_status mdlts_batch_adapt(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sims, double tau_refine,
                                double tau_coarsen, const double *dt_barrier)
 {
-    if (!ctx || !sims || n_sims < 1 || !dt_barrier) return MDLTS_EINVAL;
-    for (int q = 0; q < n_sims; q++) {
-        if (!sims[q] || sims[q]->ctx != ctx) return MDLTS_EINVAL;
-        for (int r = 0; r < q; r++)
-            if (sims[r] == sims[q]) return MDLTS_EINVAL;
-        if (!(dt_barrier[q] > 0.0) || !std::isfinite(dt_barrier[q])) return MDLTS_EINVAL;
-    }
-    // A simulation whose leaves do not change keeps its levels when they are
-    // the CFL levels of the same barrier step: no transfer, faces, levels or
-    // regrouping; its grouped state (which the indicator only reads from a
-    // canonical copy) stays in place, and its step plans stay valid.  The
-    // results are bitwise those of the full sequence.
-    std::vector<char> keep(n_sims);
-    for (int q = 0; q < n_sims; q++)
-        keep[q] = sims[q]->levels_valid && sims[q]->state_grouped && sims[q]->levels_plain &&
-                  dt_barrier[q] == sims[q]->dt_bar;
-    // indicator and the counting half of the adaptation, all simulations.
-    // Every phase writes its own fields of the flags block, cleared once
-    // here and read back in one copy per synchronisation.
-    AuxStreams aux(ctx, n_sims);
-    MD_TRY(aux.fork());
-    for (int q = 0; q < n_sims; q++) {
-        mdlts_sim *s = sims[q];
-        aux.use(q);
-        // the adaptation works on the canonical copy of the state; the
-        // gather that makes it current also clears the flags block (the
-        // grouped copy stays valid for simulations that keep their leaves)
-        if (s->state_grouped) {
-            MD_TRY(dev_alloc(ctx, s->flags, kFlagBytes));
-            MD_TRY(to_canonical(s, flag_at<int>(s, 0)));
-        } else {
-            MD_TRY(flags_clear(s));
+    return abi_guard([&]() -> mdlts_status {
+        if (!ctx || !sims || n_sims < 1 || !dt_barrier) return MDLTS_EINVAL;
+        for (int q = 0; q < n_sims; q++) {
+            if (!sims[q] || sims[q]->ctx != ctx) return MDLTS_EINVAL;
+            for (int r = 0; r < q; r++)
+                if (sims[r] == sims[q]) return MDLTS_EINVAL;
+            if (!(dt_barrier[q] > 0.0) || !std::isfinite(dt_barrier[q])) return MDLTS_EINVAL;
         }
-        MD_TRY(indicator_enqueue(s, false));
-        if (s->desc.dim == 2) MD_TRY(adapt_count<2>(s, tau_refine, tau_coarsen, false));
-        else MD_TRY(adapt_count<3>(s, tau_refine, tau_coarsen, false));
-        MD_TRY(flags_readback(s));
-    }
-    MD_TRY(aux.join());
-    MD_TRY(sync(ctx));
-    // new leaves, transfer, faces and levels, all simulations that change
-    MD_TRY(aux.fork());
-    for (int q = 0; q < n_sims; q++) {
-        mdlts_sim *s = sims[q];
-        aux.use(q);
-        keep[q] = keep[q] && s->pin->tallies[0] == 0 && s->pin->tallies[1] == 0 && s->pin->total == (int)s->E;
-        if (keep[q]) {
-            s->state_grouped = true;
-            continue;
+        // A simulation whose leaves do not change keeps its levels when they are
+        // the CFL levels of the same barrier step: no transfer, faces, levels or
+        // regrouping; its grouped state (which the indicator only reads from a
+        // canonical copy) stays in place, and its step plans stay valid.  The
+        // results are bitwise those of the full sequence.
+        std::vector<char> keep(n_sims);
+        for (int q = 0; q < n_sims; q++)
+            keep[q] = sims[q]->levels_valid && sims[q]->state_grouped && sims[q]->levels_plain &&
+                      dt_barrier[q] == sims[q]->dt_bar;
+        // indicator and the counting half of the adaptation, all simulations.
+        // Every phase writes its own fields of the flags block, cleared once
+        // here and read back in one copy per synchronisation.
+        AuxStreams aux(ctx, n_sims);
+        MD_TRY(aux.fork());
+        for (int q = 0; q < n_sims; q++) {
+            mdlts_sim *s = sims[q];
+            aux.use(q);
+            // the adaptation works on the canonical copy of the state; the
+            // gather that makes it current also clears the flags block (the
+            // grouped copy stays valid for simulations that keep their leaves)
+            if (s->state_grouped) {
+                MD_TRY(dev_alloc(ctx, s->flags, kFlagBytes));
+                MD_TRY(to_canonical(s, flag_at<int>(s, 0)));
+            } else {
+                MD_TRY(flags_clear(s));
+            }
+            MD_TRY(indicator_enqueue(s, false));
+            if (s->desc.dim == 2) MD_TRY(adapt_count<2>(s, tau_refine, tau_coarsen, false));
+            else MD_TRY(adapt_count<3>(s, tau_refine, tau_coarsen, false));
+            MD_TRY(flags_readback(s));
         }
-        s->version++;
-        if (s->desc.dim == 2) MD_TRY(adapt_emit<2>(s, false));
-        else MD_TRY(adapt_emit<3>(s, false));
-        MD_TRY(levels_enqueue(s, dt_barrier[q], -1, nullptr, 0.0, 0, false));
-        MD_TRY(flags_readback(s, true));
-    }
-    MD_TRY(aux.join());
-    MD_TRY(sync(ctx));
-    mdlts_status first = MDLTS_OK;
-    for (int q = 0; q < n_sims; q++) {
-        mdlts_sim *s = sims[q];
-        if (keep[q]) {
-            if (first == MDLTS_OK && s->pin->eta_nonfinite) first = MDLTS_EUNSTABLE;
-            continue;
+        MD_TRY(aux.join());
+        MD_TRY(sync(ctx));
+        // new leaves, transfer, faces and levels, all simulations that change
+        MD_TRY(aux.fork());
+        for (int q = 0; q < n_sims; q++) {
+            mdlts_sim *s = sims[q];
+            aux.use(q);
+            keep[q] = keep[q] && s->pin->tallies[0] == 0 && s->pin->tallies[1] == 0 && s->pin->total == (int)s->E;
+            if (keep[q]) {
+                s->state_grouped = true;
+                continue;
+            }
+            s->version++;
+            if (s->desc.dim == 2) MD_TRY(adapt_emit<2>(s, false));
+            else MD_TRY(adapt_emit<3>(s, false));
+            MD_TRY(levels_enqueue(s, dt_barrier[q], -1, nullptr, 0.0, 0, false));
+            MD_TRY(flags_readback(s, true));
         }
-        mdlts_status st = s->pin->face_bad ? MDLTS_EINVAL : levels_finish(s, dt_barrier[q], nullptr);
-        if (st == MDLTS_OK && s->pin->eta_nonfinite) st = MDLTS_EUNSTABLE;
-        if (first == MDLTS_OK) first = st;
-    }
-    return first;
+        MD_TRY(aux.join());
+        MD_TRY(sync(ctx));
+        mdlts_status first = MDLTS_OK;
+        for (int q = 0; q < n_sims; q++) {
+            mdlts_sim *s = sims[q];
+            if (keep[q]) {
+                if (first == MDLTS_OK && s->pin->eta_nonfinite) first = MDLTS_EUNSTABLE;
+                continue;
+            }
+            mdlts_status st = s->pin->face_bad ? MDLTS_EINVAL : levels_finish(s, dt_barrier[q], nullptr);
+            if (st == MDLTS_OK && s->pin->eta_nonfinite) st = MDLTS_EUNSTABLE;
+            if (first == MDLTS_OK) first = st;
+        }
+        return first;
+    });
 }
 
 mdlts_status mdlts_set_graphs(mdlts_ctx *ctx, int enable)
 {
-    if (!ctx) return MDLTS_EINVAL;
-    ctx->use_graphs = enable != 0;
-    return MDLTS_OK;
+    return abi_guard([&]() -> mdlts_status {
+        if (!ctx) return MDLTS_EINVAL;
+        ctx->use_graphs = enable != 0;
+        return MDLTS_OK;
+    });
 }
 
 mdlts_status mdlts_batch_profile(mdlts_ctx *ctx, int enable)
 {
-    if (!ctx || !ctx->batch) return MDLTS_ESTATE;
-    BatchPlan &P = *ctx->batch;
-    MD_TRY(drain_batch_events(P));
-    P.prof = enable != 0;
-    P.prof_ms = 0.0;
-    P.prof_launches = P.prof_dof = 0;
-    return MDLTS_OK;
+    return abi_guard([&]() -> mdlts_status {
+        if (!ctx || !ctx->batch) return MDLTS_ESTATE;
+        BatchPlan &P = *ctx->batch;
+        MD_TRY(drain_batch_events(P));
+        P.prof = enable != 0;
+        P.prof_ms = 0.0;
+        P.prof_launches = P.prof_dof = 0;
+        return MDLTS_OK;
+    });
 }
 
 mdlts_status mdlts_batch_profile_read(mdlts_ctx *ctx, double *substep_ms, uint64_t *n_launches,
                                       uint64_t *dof_updates, int *block, int *per_cu)
 {
-    if (!ctx || !ctx->batch) return MDLTS_ESTATE;
-    BatchPlan &P = *ctx->batch;
-    MD_TRY(drain_batch_events(P));
-    if (substep_ms) *substep_ms = P.prof_ms;
-    if (n_launches) *n_launches = P.prof_launches;
-    if (dof_updates) *dof_updates = P.prof_dof;
-    if (block) *block = P.block;
-    if (per_cu) *per_cu = P.per_cu;
-    P.prof_ms = 0.0;
-    P.prof_launches = P.prof_dof = 0;
-    return MDLTS_OK;
+    return abi_guard([&]() -> mdlts_status {
+        if (!ctx || !ctx->batch) return MDLTS_ESTATE;
+        BatchPlan &P = *ctx->batch;
+        MD_TRY(drain_batch_events(P));
+        if (substep_ms) *substep_ms = P.prof_ms;
+        if (n_launches) *n_launches = P.prof_launches;
+        if (dof_updates) *dof_updates = P.prof_dof;
+        if (block) *block = P.block;
+        if (per_cu) *per_cu = P.per_cu;
+        P.prof_ms = 0.0;
+        P.prof_launches = P.prof_dof = 0;
+        return MDLTS_OK;
+    });
 }
 
 mdlts_status mdlts_cfl_bound(const mdlts_mesh_desc *desc, const double D_sym[6], double gamma, int depth,
                              double *cfl_min)
 {
-    if (!valid_desc(desc) || !cfl_min || depth < 0 || depth > desc->max_depth || !(gamma > 0.0)) return MDLTS_EINVAL;
-    Conductivity C;
-    if (!parse_conductivity(D_sym, desc->dim, C)) return MDLTS_EINVAL;
-    RefTables R;
-    make_ref_tables(desc->order, R);
-    double G[4][4];
-    if (!gershgorin_table(R, gamma, G)) return MDLTS_EINVAL;
-    // Face kinds a leaf of this depth can have in direction k: no finer
-    // neighbour at the depth cap, no coarser one at depth 0, both faces on
-    // the boundary only for a single root across the box, and below the
-    // roots one face always sees the sibling cell (same size or finer).
-    double s = 0.0;
-    for (int k = 0; k < desc->dim; k++) {
-        double worst = 0.0;
-        for (int lo = 0; lo < 4; lo++)
-            for (int hi = 0; hi < 4; hi++) {
-                bool ok = true;
-                if ((lo == kFiner || hi == kFiner) && depth == desc->max_depth) ok = false;
-                if ((lo == kCoarser || hi == kCoarser) && depth == 0) ok = false;
-                if (lo == kBoundary && hi == kBoundary && !(depth == 0 && desc->n[k] == 1)) ok = false;
-                const bool sib_lo = lo == kSame || lo == kFiner, sib_hi = hi == kSame || hi == kFiner;
-                if (depth > 0 && !sib_lo && !sib_hi) ok = false;
-                if (ok) worst = std::max(worst, G[lo][hi]);
-            }
-        const double h = std::ldexp(desc->len[k] / (double)desc->n[k], -depth);
-        s += C.Dk[k] / (h * h) * worst;
-    }
-    if (C.full) {
-        // the worst admissible combination of the kinds of all faces
-        double h0[3];
-        for (int k = 0; k < 3; k++) h0[k] = k < desc->dim ? desc->len[k] / (double)desc->n[k] : 1.0;
-        std::vector<double> tab;
-        if (!own_block_table(R, desc->dim, h0, C, gamma, tab)) return MDLTS_EINVAL;
-        double worst = 0.0;
-        for (size_t idx = 0; idx < tab.size(); idx++) {
-            bool ok = true;
-            for (int k = 0; k < desc->dim && ok; k++) {
-                const uint32_t lo = (uint32_t)(idx >> (4 * k)) & 3, hi = (uint32_t)(idx >> (4 * k + 2)) & 3;
-                if ((lo == kFiner || hi == kFiner) && depth == desc->max_depth) ok = false;
-                if ((lo == kCoarser || hi == kCoarser) && depth == 0) ok = false;
-                if (lo == kBoundary && hi == kBoundary && !(depth == 0 && desc->n[k] == 1)) ok = false;
-                const bool sib_lo = lo == kSame || lo == kFiner, sib_hi = hi == kSame || hi == kFiner;
-                if (depth > 0 && !sib_lo && !sib_hi) ok = false;
-            }
-            if (ok) worst = std::max(worst, tab[idx]);
+    return abi_guard([&]() -> mdlts_status {
+        if (!valid_desc(desc) || !cfl_min || depth < 0 || depth > desc->max_depth || !(gamma > 0.0)) return MDLTS_EINVAL;
+        Conductivity C;
+        if (!parse_conductivity(D_sym, desc->dim, C)) return MDLTS_EINVAL;
+        RefTables R;
+        make_ref_tables(desc->order, R);
+        double G[4][4];
+        if (!gershgorin_table(R, gamma, G)) return MDLTS_EINVAL;
+        // Face kinds a leaf of this depth can have in direction k: no finer
+        // neighbour at the depth cap, no coarser one at depth 0, both faces on
+        // the boundary only for a single root across the box, and below the
+        // roots one face always sees the sibling cell (same size or finer).
+        double s = 0.0;
+        for (int k = 0; k < desc->dim; k++) {
+            double worst = 0.0;
+            for (int lo = 0; lo < 4; lo++)
+                for (int hi = 0; hi < 4; hi++) {
+                    bool ok = true;
+                    if ((lo == kFiner || hi == kFiner) && depth == desc->max_depth) ok = false;
+                    if ((lo == kCoarser || hi == kCoarser) && depth == 0) ok = false;
+                    if (lo == kBoundary && hi == kBoundary && !(depth == 0 && desc->n[k] == 1)) ok = false;
+                    const bool sib_lo = lo == kSame || lo == kFiner, sib_hi = hi == kSame || hi == kFiner;
+                    if (depth > 0 && !sib_lo && !sib_hi) ok = false;
+                    if (ok) worst = std::max(worst, G[lo][hi]);
+                }
+            const double h = std::ldexp(desc->len[k] / (double)desc->n[k], -depth);
+            s += C.Dk[k] / (h * h) * worst;
         }
-        s = worst * std::ldexp(1.0, 2 * depth);
-    }
-    *cfl_min = 1.0 / s;
-    return MDLTS_OK;
+        if (C.full) {
+            // the worst admissible combination of the kinds of all faces
+            double h0[3];
+            for (int k = 0; k < 3; k++) h0[k] = k < desc->dim ? desc->len[k] / (double)desc->n[k] : 1.0;
+            std::vector<double> tab;
+            if (!own_block_table(R, desc->dim, h0, C, gamma, tab)) return MDLTS_EINVAL;
+            double worst = 0.0;
+            for (size_t idx = 0; idx < tab.size(); idx++) {
+                bool ok = true;
+                for (int k = 0; k < desc->dim && ok; k++) {
+                    const uint32_t lo = (uint32_t)(idx >> (4 * k)) & 3, hi = (uint32_t)(idx >> (4 * k + 2)) & 3;
+                    if ((lo == kFiner || hi == kFiner) && depth == desc->max_depth) ok = false;
+                    if ((lo == kCoarser || hi == kCoarser) && depth == 0) ok = false;
+                    if (lo == kBoundary && hi == kBoundary && !(depth == 0 && desc->n[k] == 1)) ok = false;
+                    const bool sib_lo = lo == kSame || lo == kFiner, sib_hi = hi == kSame || hi == kFiner;
+                    if (depth > 0 && !sib_lo && !sib_hi) ok = false;
+                }
+                if (ok) worst = std::max(worst, tab[idx]);
+            }
+            s = worst * std::ldexp(1.0, 2 * depth);
+        }
+        *cfl_min = 1.0 / s;
+        return MDLTS_OK;
+    });
 }
 
 mdlts_status mdlts_plan_adapt(const mdlts_mesh_desc *desc, const uint8_t *bits, size_t n_bits, const double *eta,
                               size_t n_leaves, double tau_refine, double tau_coarsen, uint8_t *out_bits, size_t cap,
                               size_t *n_out)
 {
-    if (!valid_desc(desc) || !eta || !n_out) return MDLTS_EINVAL;
-    Forest F;
-    forest_from_desc(desc, F);
-    if (!F.parse_bits(bits, n_bits)) return MDLTS_EINVAL;
-    if (F.size() != n_leaves) return MDLTS_EINVAL;
-    AdaptPlan plan;
-    if (!plan_adapt(F, eta, tau_refine, tau_coarsen, plan)) return MDLTS_EINVAL;
-    std::vector<uint8_t> out;
-    plan.next.write_bits(out);
-    *n_out = out.size();
-    if (out_bits && cap >= out.size()) std::memcpy(out_bits, out.data(), out.size());
-    return MDLTS_OK;
+    return abi_guard([&]() -> mdlts_status {
+        if (!valid_desc(desc) || !eta || !n_out) return MDLTS_EINVAL;
+        Forest F;
+        forest_from_desc(desc, F);
+        if (!F.parse_bits(bits, n_bits)) return MDLTS_EINVAL;
+        if (F.size() != n_leaves) return MDLTS_EINVAL;
+        AdaptPlan plan;
+        if (!plan_adapt(F, eta, tau_refine, tau_coarsen, plan)) return MDLTS_EINVAL;
+        std::vector<uint8_t> out;
+        plan.next.write_bits(out);
+        *n_out = out.size();
+        if (out_bits && cap >= out.size()) std::memcpy(out_bits, out.data(), out.size());
+        return MDLTS_OK;
+    });
 }
 
 mdlts_status mdlts_memory_bound(const mdlts_mesh_desc *desc, int64_t max_leaves, uint64_t *bytes)
 {
-    if (!valid_desc(desc) || max_leaves < 1 || max_leaves >= (1 << 27) || !bytes) return MDLTS_EINVAL;
-    const uint64_t d = (uint64_t)desc->dim;
-    const uint64_t np = desc->dim == 2 ? (uint64_t)(desc->order + 1) * (desc->order + 1)
-                                       : (uint64_t)(desc->order + 1) * (desc->order + 1) * (desc->order + 1);
-    const uint64_t T = desc->precision == MDLTS_FP64 ? 8 : 4;
-    const uint64_t ksz = desc->dim == 2 ? 4 : 8;
-    const uint64_t ns = desc->dim == 2 ? 2 : 4;
-    const uint64_t nsub = 1ull << (desc->n_levels - 1);
-    // every buffer a simulation holds is sized by its largest leaf count
-    const uint64_t per_leaf =
-        9 * np * T                  // u and v canonical, transfer copies, two u slots and v grouped, RV-T snapshot
-        + 8 * np                    // FP64 staging of uploads and readbacks
-        + 3 * ksz + 4               // canonical, new and grouped keys; Morton keys
-        + 2 * (2 * d * 4)           // face tables, canonical and grouped
-        + 2 * (2 * d * ns * 4)      // sub-face tables, canonical and grouped
-        + 1 + 1 + 4 + 4 + 4 + 1     // refine and coarsen flags, counts, offsets, root offsets, scan sums
-        + 1 + 4 + 1                 // transfer kind, source and child
-        + 1 + 8 + 4 + 4 + 8 + 8 + 1 // level, CFL, permutation both ways, indicators, histogram share
-        + (nsub * 16 + 31) / 32;    // batch tiles: per substep one per 64 leaves (blocks of >= 64 threads)
-    const uint64_t fixed = 64 * 512         // allocator rounding of every buffer
-                           + 4 * 4096       // flags, step constants, batch descriptor, small scans
-                           + 8 * 4096       // own-block bounds of a full diffusion tensor
-                           + nsub * 16 * 2; // tile list heads
-    // every buffer may hold 1/8 growth headroom (dev_alloc)
-    *bytes = (per_leaf + (per_leaf + 7) / 8) * (uint64_t)max_leaves + fixed + fixed / 8;
-    return MDLTS_OK;
+    return abi_guard([&]() -> mdlts_status {
+        if (!valid_desc(desc) || max_leaves < 1 || max_leaves >= (1 << 27) || !bytes) return MDLTS_EINVAL;
+        const uint64_t d = (uint64_t)desc->dim;
+        const uint64_t np = desc->dim == 2 ? (uint64_t)(desc->order + 1) * (desc->order + 1)
+                                           : (uint64_t)(desc->order + 1) * (desc->order + 1) * (desc->order + 1);
+        const uint64_t T = desc->precision == MDLTS_FP64 ? 8 : 4;
+        const uint64_t ksz = desc->dim == 2 ? 4 : 8;
+        const uint64_t ns = desc->dim == 2 ? 2 : 4;
+        const uint64_t nsub = 1ull << (desc->n_levels - 1);
+        // every buffer a simulation holds is sized by its largest leaf count
+        const uint64_t per_leaf =
+            9 * np * T                  // u and v canonical, transfer copies, two u slots and v grouped, RV-T snapshot
+            + 8 * np                    // FP64 staging of uploads and readbacks
+            + 3 * ksz + 4               // canonical, new and grouped keys; Morton keys
+            + 2 * (2 * d * 4)           // face tables, canonical and grouped
+            + 2 * (2 * d * ns * 4)      // sub-face tables, canonical and grouped
+            + 1 + 1 + 4 + 4 + 4 + 1     // refine and coarsen flags, counts, offsets, root offsets, scan sums
+            + 1 + 4 + 1                 // transfer kind, source and child
+            + 1 + 8 + 4 + 4 + 8 + 8 + 1 // level, CFL, permutation both ways, indicators, histogram share
+            + (nsub * 16 + 31) / 32;    // batch tiles: per substep one per 64 leaves (blocks of >= 64 threads)
+        const uint64_t fixed = 64 * 512         // allocator rounding of every buffer
+                               + 4 * 4096       // flags, step constants, batch descriptor, small scans
+                               + 8 * 4096       // own-block bounds of a full diffusion tensor
+                               + nsub * 16 * 2; // tile list heads
+        // every buffer may hold 1/8 growth headroom (dev_alloc)
+        *bytes = (per_leaf + (per_leaf + 7) / 8) * (uint64_t)max_leaves + fixed + fixed / 8;
+        return MDLTS_OK;
+    });
 }
 
 mdlts_status mdlts_plan_levels(const mdlts_mesh_desc *desc, const uint8_t *bits, size_t n_bits, const double D_sym[6],
                                double gamma, double dt_barrier, int8_t *level, int32_t *perm, int32_t *cnt_ge,
                                double *cfl, size_t n_leaves)
 {
-    if (!valid_desc(desc) || !(dt_barrier > 0.0) || !(gamma > 0.0)) return MDLTS_EINVAL;
-    Conductivity C;
-    if (!parse_conductivity(D_sym, desc->dim, C)) return MDLTS_EINVAL;
-    Forest F;
-    forest_from_desc(desc, F);
-    if (!F.parse_bits(bits, n_bits)) return MDLTS_EINVAL;
-    if (F.size() != n_leaves) return MDLTS_EINVAL;
-    RefTables R;
-    make_ref_tables(desc->order, R);
-    double G[4][4];
-    if (!gershgorin_table(R, gamma, G)) return MDLTS_EINVAL;
-    double h0[3];
-    for (int k = 0; k < 3; k++) h0[k] = k < desc->dim ? desc->len[k] / (double)desc->n[k] : 1.0;
-    std::vector<double> c(n_leaves);
-    if (C.full) {
-        std::vector<double> tab;
-        if (!own_block_table(R, desc->dim, h0, C, gamma, tab)) return MDLTS_EINVAL;
-        host_cfl_full(F, tab, c.data());
-    } else {
-        host_cfl(F, h0, C.Dk, G, c.data());
-    }
-    std::vector<int> lv(n_leaves);
-    mdlts_status st = MDLTS_OK;
-    for (size_t e = 0; e < n_leaves; e++) {
-        lv[e] = level_of(dt_barrier, c[e]);
-        if (lv[e] > desc->n_levels - 1) st = MDLTS_EUNSTABLE;
-    }
-    if (cfl) std::memcpy(cfl, c.data(), n_leaves * sizeof(double));
-    if (level)
-        for (size_t e = 0; e < n_leaves; e++) level[e] = (int8_t)std::min(lv[e], 127);
-    if (perm || cnt_ge) {
-        size_t pos = 0;
-        for (int l = desc->n_levels - 1; l >= 0; l--) {
-            for (size_t e = 0; e < n_leaves; e++)
-                if (lv[e] == l) {
-                    if (perm) perm[pos] = (int32_t)e;
-                    pos++;
-                }
-            if (cnt_ge) cnt_ge[l] = (int32_t)pos;
+    return abi_guard([&]() -> mdlts_status {
+        if (!valid_desc(desc) || !(dt_barrier > 0.0) || !(gamma > 0.0)) return MDLTS_EINVAL;
+        Conductivity C;
+        if (!parse_conductivity(D_sym, desc->dim, C)) return MDLTS_EINVAL;
+        Forest F;
+        forest_from_desc(desc, F);
+        if (!F.parse_bits(bits, n_bits)) return MDLTS_EINVAL;
+        if (F.size() != n_leaves) return MDLTS_EINVAL;
+        RefTables R;
+        make_ref_tables(desc->order, R);
+        double G[4][4];
+        if (!gershgorin_table(R, gamma, G)) return MDLTS_EINVAL;
+        double h0[3];
+        for (int k = 0; k < 3; k++) h0[k] = k < desc->dim ? desc->len[k] / (double)desc->n[k] : 1.0;
+        std::vector<double> c(n_leaves);
+        if (C.full) {
+            std::vector<double> tab;
+            if (!own_block_table(R, desc->dim, h0, C, gamma, tab)) return MDLTS_EINVAL;
+            host_cfl_full(F, tab, c.data());
+        } else {
+            host_cfl(F, h0, C.Dk, G, c.data());
         }
-    }
-    return st;
+        std::vector<int> lv(n_leaves);
+        mdlts_status st = MDLTS_OK;
+        for (size_t e = 0; e < n_leaves; e++) {
+            lv[e] = level_of(dt_barrier, c[e]);
+            if (lv[e] > desc->n_levels - 1) st = MDLTS_EUNSTABLE;
+        }
+        if (cfl) std::memcpy(cfl, c.data(), n_leaves * sizeof(double));
+        if (level)
+            for (size_t e = 0; e < n_leaves; e++) level[e] = (int8_t)std::min(lv[e], 127);
+        if (perm || cnt_ge) {
+            size_t pos = 0;
+            for (int l = desc->n_levels - 1; l >= 0; l--) {
+                for (size_t e = 0; e < n_leaves; e++)
+                    if (lv[e] == l) {
+                        if (perm) perm[pos] = (int32_t)e;
+                        pos++;
+                    }
+                if (cnt_ge) cnt_ge[l] = (int32_t)pos;
+            }
+        }
+        return st;
+    });
 }
 
 }  // extern "C"
