@@ -246,6 +246,22 @@ mdlts_status mdlts_batch_profile_read(mdlts_ctx *ctx, double *substep_ms, uint64
  * NULL); eta_max: max over leaves (may be NULL).  Synchronises the stream.
  * EUNSTABLE if the state holds a non-finite value. */
 mdlts_status mdlts_indicator(mdlts_sim *sim, double *eta, size_t n_leaves, double *eta_max);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * indicator of mdlts_indicator with the same arguments, results and errors,
+ * calling no hipMalloc, hipFree or allocator.  Its scratch memory (the
+ * canonical copy of the state, eta on the device, the maximum and the
+ * non-finite flag) is one fixed device array of 64 MiB per GPU, held from
+ * the first context on that GPU until the process ends.  ENOMEM if a call
+ * needs more: 256 + 8 E bytes, plus E (p+1)^d bytes-per-value while the
+ * state is grouped by level (after a level assignment), each part rounded up
+ * to 256 bytes; about 2.8M Q1 quadrilaterals or 0.58M Q2 hexahedra in FP32.
+ * Every call on a GPU shares that GPU's array, which keeps the last call's
+ * contents: calls that overlap on one GPU (several host threads or
+ * contexts) race, and the caller must serialise them.  Unlike
+ * mdlts_indicator, the result is not kept for mdlts_adapt(eta = NULL).
+ * Synchronises. */
+mdlts_status mdlts_indicator_noalloc(mdlts_sim *sim, double *eta, size_t n_leaves, double *eta_max);
 /* Refines leaves with eta >= tau_refine (below max_depth), closes the 2:1
  * balance by refining coarser face neighbours, coarsens parents whose
  * children all have eta <= tau_coarsen (when that keeps 2:1 balance), and

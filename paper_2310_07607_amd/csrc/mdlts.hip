@@ -8,6 +8,7 @@
 #include <cstddef>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -249,8 +250,15 @@ __global__ __launch_bounds__(kBlock) void k_gather(int E, int np, int cap, long 
     const int e = perm[j];
     for (int n = 0; n < np; n++) {
         uc[(long long)n * E + e] = us[(long long)cur * slot_stride + (long long)n * cap + j];
-        vc[(long long)n * E + e] = vs[(long long)n * cap + j];
+        if (vc) vc[(long long)n * E + e] = vs[(long long)n * cap + j];
     }
+}
+
+// clears n 32-bit words (a kernel rather than a memset, so that the
+// clearing is an ordinary kernel node if the caller captures the stream)
+__global__ __launch_bounds__(64) void k_clear_u32(uint32_t *p, int n)
+{
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
 }
 
 // host FP64 [E][np] <-> device T [np][E]
@@ -589,6 +597,40 @@ inline int nblocks(long long n) { return (int)((n + kBlock - 1) / kBlock); }
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// The scratch memory of the allocation-free indicator (mdlts_indicator_noalloc):
+// one fixed device array per GPU, held from the library's load on that GPU to
+// the end of the process.  In host code `scratch` names a host-side stand-in,
+// not device memory: its device address is taken once per device with
+// hipGetSymbolAddress (kept in scratch_dev) and only that address is passed
+// to kernels.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void *scratch_dev[kMaxDevices];  // device address of `scratch` per device, set once
+
+// the device address of `scratch` on the current device (`device`)
+mdlts_status scratch_address(int device, void **out)
+{
+    if (device < 0 || device >= kMaxDevices) return MDLTS_EINVAL;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return MDLTS_EDEVICE;
+        }
+        scratch_dev[device] = p;
+    }
+    *out = scratch_dev[device];
+    return MDLTS_OK;
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // context and simulation objects
 // ---------------------------------------------------------------------------
 struct DevBuf {
@@ -601,6 +643,7 @@ struct BatchPlan;
 struct mdlts_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    void *scratch = nullptr;  // device address of this device's `scratch`
     mdlts_allocator alloc{};
     bool has_alloc = false;
     int n_sims = 0;  // live simulations; the context outlives them
@@ -1188,13 +1231,15 @@ void launch_indicator(const IndArgs &a, int E, hipStream_t st)
     else k_indicator<DIM, P_, T, false><<<nblocks(E), kBlock, 0, st>>>(a);
 }
 
+// the indicator of the canonical state u (bulk precision, [np][E]) into eta
+// [E], its maximum and non-finite flag into max_bits and nonfinite
 template <typename T>
-mdlts_status run_indicator(mdlts_sim *s, unsigned long long *max_bits, int *nonfinite)
+mdlts_status run_indicator(mdlts_sim *s, const void *u, double *eta, unsigned long long *max_bits, int *nonfinite)
 {
     IndArgs a;
     std::memset(&a, 0, sizeof(a));
     const int E = (int)s->E;
-    a.u = s->u_c.p;
+    a.u = u;
     a.key = s->key_c.p;
     a.face = P<uint32_t>(s->face_c);
     a.fine = P<uint32_t>(s->fine_c);
@@ -1203,7 +1248,7 @@ mdlts_status run_indicator(mdlts_sim *s, unsigned long long *max_bits, int *nonf
     for (int k = 0; k < 3; k++) { a.h0[k] = s->h0[k]; a.Dk[k] = s->Dk[k]; a.Dx[k] = s->Dx[k]; }
     a.full = s->dfull ? 1 : 0;
     fill_ref(s->ref, a.ref);
-    a.eta = P<double>(s->eta_c);
+    a.eta = eta;
     a.eta_max_bits = max_bits;
     a.nonfinite = nonfinite;
     hipStream_t st = s->ctx->stream;
@@ -2089,9 +2134,12 @@ mdlts_status mdlts_ctx_create(int device, void *hip_stream, const mdlts_allocato
         if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return MDLTS_EINVAL;
         if (alloc && (!alloc->alloc || !alloc->free)) return MDLTS_EINVAL;
         HIP_TRY(hipSetDevice(device));
+        void *scr = nullptr;
+        MD_TRY(scratch_address(device, &scr));
         mdlts_ctx *c = new (std::nothrow) mdlts_ctx;
         if (!c) return MDLTS_ENOMEM;
         c->device = device;
+        c->scratch = scr;
         c->stream = static_cast<hipStream_t>(hip_stream);
         if (alloc) {
             c->alloc = *alloc;
@@ -2677,8 +2725,8 @@ static mdlts_status indicator_enqueue(mdlts_sim *s, bool own_flags = true)
     if (own_flags) MD_TRY(flags_clear(s));
     unsigned long long *maxb = MD_FLAG(s, unsigned long long, eta_max_bits);
     int *nonf = MD_FLAG(s, int, eta_nonfinite);
-    if (s->desc.precision == MDLTS_FP64) MD_TRY(run_indicator<double>(s, maxb, nonf));
-    else MD_TRY(run_indicator<float>(s, maxb, nonf));
+    if (s->desc.precision == MDLTS_FP64) MD_TRY(run_indicator<double>(s, s->u_c.p, P<double>(s->eta_c), maxb, nonf));
+    else MD_TRY(run_indicator<float>(s, s->u_c.p, P<double>(s->eta_c), maxb, nonf));
     // the non-finite flag and the maximum are adjacent: one copy
     static_assert(offsetof(PinnedReadback, eta_max_bits) == offsetof(PinnedReadback, eta_nonfinite) + sizeof(int),
                   "readback layout");
@@ -2700,6 +2748,59 @@ mdlts_status mdlts_indicator(mdlts_sim *s, double *eta, size_t n_leaves, double 
         mdlts_ctx *c = s->ctx;
         MD_TRY(indicator_enqueue(s));
         if (eta) HIP_TRY(hipMemcpyAsync(eta, s->eta_c.p, E * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        MD_TRY(sync(c));
+        if (eta_max) std::memcpy(eta_max, &s->pin->eta_max_bits, 8);
+        return s->pin->eta_nonfinite ? MDLTS_EUNSTABLE : MDLTS_OK;
+    });
+}
+
+mdlts_status mdlts_indicator_noalloc(mdlts_sim *s, double *eta, size_t n_leaves, double *eta_max)
+{
+    return abi_guard([&]() -> mdlts_status {
+        if (!s) return MDLTS_EINVAL;
+        const size_t E = s->E;
+        if (eta && n_leaves != E) return MDLTS_EINVAL;
+        mdlts_ctx *c = s->ctx;
+        if (!c->scratch) return MDLTS_EDEVICE;
+        // scratch layout: [flags 256 B | eta E doubles | canonical u, if the
+        // state is grouped], each part 256-byte aligned
+        const auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+        const size_t eta_off = 256;
+        const size_t u_off = eta_off + up(E * sizeof(double));
+        const size_t need = u_off + (s->state_grouped ? up(E * (size_t)s->np * s->tsize) : 0);
+        if (need > kScratchBytes) return MDLTS_ENOMEM;
+        char *base = static_cast<char *>(c->scratch);
+        unsigned long long *maxb = reinterpret_cast<unsigned long long *>(base);
+        int *nonf = reinterpret_cast<int *>(base + 8);
+        double *eta_d = reinterpret_cast<double *>(base + eta_off);
+        hipStream_t st = c->stream;
+        // the maximum (as bits of a non-negative double) and the flag start at 0
+        k_clear_u32<<<1, 64, 0, st>>>(reinterpret_cast<uint32_t *>(base), 4);
+        HIP_TRY(hipGetLastError());
+        const void *u = s->u_c.p;
+        if (s->state_grouped) {
+            // the current slot in canonical order; the grouped state stays as is
+            const int Ei = (int)E;
+            const long long stride = (long long)s->np * s->cap;
+            const int parity = (int)(s->n_since_assign & 1);
+            void *uc = base + u_off;
+            if (s->desc.precision == MDLTS_FP64)
+                k_gather<double><<<nblocks(Ei), kBlock, 0, st>>>(Ei, s->np, s->cap, stride, P<int>(s->perm),
+                                                                  P<int>(s->cnt_ge_d), parity, P<double>(s->u_s),
+                                                                  nullptr, static_cast<double *>(uc), nullptr, nullptr);
+            else
+                k_gather<float><<<nblocks(Ei), kBlock, 0, st>>>(Ei, s->np, s->cap, stride, P<int>(s->perm),
+                                                                 P<int>(s->cnt_ge_d), parity, P<float>(s->u_s),
+                                                                 nullptr, static_cast<float *>(uc), nullptr, nullptr);
+            HIP_TRY(hipGetLastError());
+            u = uc;
+        }
+        if (s->desc.precision == MDLTS_FP64) MD_TRY(run_indicator<double>(s, u, eta_d, maxb, nonf));
+        else MD_TRY(run_indicator<float>(s, u, eta_d, maxb, nonf));
+        if (eta) HIP_TRY(hipMemcpyAsync(eta, eta_d, E * sizeof(double), hipMemcpyDeviceToHost, st));
+        // the flag and the maximum into the simulation's pinned readback block
+        HIP_TRY(hipMemcpyAsync(&s->pin->eta_nonfinite, nonf, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(&s->pin->eta_max_bits, maxb, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
         MD_TRY(sync(c));
         if (eta_max) std::memcpy(eta_max, &s->pin->eta_max_bits, 8);
         return s->pin->eta_nonfinite ? MDLTS_EUNSTABLE : MDLTS_OK;

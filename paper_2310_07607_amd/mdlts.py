@@ -86,6 +86,7 @@ def lib():
         "mdlts_get_cfl": (I, [P, P, S]),
         "mdlts_step": (I, [P, I]),
         "mdlts_indicator": (I, [P, P, S, P]),
+        "mdlts_indicator_noalloc": (I, [P, P, S, P]),
         "mdlts_adapt": (I, [P, P, S, D, D, P, P]),
         "mdlts_counters": (I, [P, P, P]),
         "mdlts_profile": (I, [P, I]),
@@ -398,6 +399,17 @@ class Simulation:
             return None, m.value
         eta = np.zeros(self.n_leaves)
         _chk(lib().mdlts_indicator(self.h, _p(eta), eta.size, ctypes.byref(m)), "mdlts_indicator")
+        return eta, m.value
+
+    def indicator_noalloc(self, download=True):
+        """(eta per leaf or None, max eta) through the allocation-free entry
+        point (fixed per-device scratch; nothing kept for adapt())."""
+        m = ctypes.c_double()
+        if not download:
+            _chk(lib().mdlts_indicator_noalloc(self.h, None, 0, ctypes.byref(m)), "mdlts_indicator_noalloc")
+            return None, m.value
+        eta = np.zeros(self.n_leaves)
+        _chk(lib().mdlts_indicator_noalloc(self.h, _p(eta), eta.size, ctypes.byref(m)), "mdlts_indicator_noalloc")
         return eta, m.value
 
     def adapt(self, tau_refine, tau_coarsen, eta=None):
