@@ -1,19 +1,22 @@
-"""Calibrate the refine/coarsen thresholds of the 2-D Aliev-Panfilov workload
+"""Calibrate the refine/coarsen thresholds of the Aliev-Panfilov workloads
 on the CPU oracle (test infrastructure; its output is frozen into
-paper_2310_07607_amd/inputs.py).
+paper_2310_07607_amd/inputs.py): the 2-D Q1 square (default) and, with
+`--slab`, the 3-D Q2 slab (front along the fibres, x).
 
 The paper tunes tau_refine for its own ionic model and units (Sec. 3) and
 uses tau_coarsen = tau_refine / 3.  For the Aliev-Panfilov workload the
 rule used here is: a plane front resolved on a uniform mesh of depth
 max_depth-1 must be refined (its largest indicator exceeds tau_refine by a
-factor 2).  The indicator of a front falls by about 8x per refinement
-depth, so children of a just-refined leaf sit near tau_refine/8; with
+factor 2).  The indicator of a front falls by a factor `ratio` per
+refinement depth (about 8 for the 2-D Q1 square, about 94 for the 3-D Q2
+slab, whose face weights scale with the face area squared), so children of
+a just-refined leaf sit near tau_refine/ratio; with the paper's
 tau_coarsen = tau_refine/3 they would be coarsened again at once.  Hence
-tau_coarsen = tau_refine/16 here.  The script also measures the front speed
+tau_coarsen = tau_refine/(2 ratio) here (tau_refine/16 in 2-D).  The script also measures the front speed
 from two snapshots, which sets how many barriers may pass between two
 adaptations (the front may cross at most one finest element per interval).
 
-Usage: python oracle/calibrate_thresholds.py
+Usage: python oracle/calibrate_thresholds.py [--slab]
 """
 import math
 import os
@@ -39,6 +42,19 @@ def strip(depth, n_roots=64, h0=2.0 / 256, D=1e-3, gamma=2.0):
     return o
 
 
+def strip_slab(depth, n_roots=24):
+    """A row of slab roots along x (h = 2.0/128 x 0.7/48 x 0.3/24 cm, Q2,
+    D = diag(1.3e-3, 0.33e-3, 0.33e-3), gamma 4), uniformly refined to
+    `depth`, stimulated at x < 0.1 cm for 1 ms: a plane front along x."""
+    h = (2.0 / 128, 0.7 / 48, 0.3 / 24)
+    o = Oracle(3, 2, [n_roots, 1, 1], [n_roots * h[0], h[1], h[2]], depth)
+    o.set_params(np.diag([1.3e-3, 0.33e-3, 0.33e-3]), 4.0, AP)
+    for _ in range(depth):
+        o.adapt(np.ones(o.n_leaves), 0.5, -1.0)
+    o.set_stimulus(np.array([[0, 0, 0, 0.1, h[1], h[2], 0.0, 1.0, 1.0]]))
+    return o
+
+
 def front_position(o):
     X = o.leaf_nodes()
     u, _ = o.get_state()
@@ -46,13 +62,13 @@ def front_position(o):
     return ahead.max() if ahead.size else 0.0
 
 
-def run(depth, t_end=5.0):
-    o = strip(depth)
+def run(depth, t_end=5.0, slab=False):
+    o = strip_slab(depth) if slab else strip(depth)
     dt = 0.9 * o.cfl().min()
     n = int(math.ceil(t_end / dt))
     dt = t_end / n
     snaps = {}
-    t_marks = {3.0: None, t_end: None}
+    t_marks = {t_end - 2.0: None, t_end: None}
     t = 0.0
     step = 0
     for tm in sorted(t_marks):
@@ -65,17 +81,25 @@ def run(depth, t_end=5.0):
 
 
 def main():
+    slab = "--slab" in sys.argv
+    t_end = 3.0 if slab else 5.0
     out = {}
     for depth in (0, 1, 2):
-        o, snaps = run(depth)
+        o, snaps = run(depth, t_end, slab)
         eta = o.indicator()
-        c = (snaps[5.0] - snaps[3.0]) / 2.0
+        c = (snaps[t_end] - snaps[t_end - 2.0]) / 2.0
         out[depth] = (eta.max(), c)
         print(f"depth {depth}: max eta {eta.max():.4e}, front speed {c:.4f} cm/ms", flush=True)
-    tau_r = 0.5 * out[2][0]
     ratio = out[1][0] / out[2][0]
     print(f"indicator ratio per depth {ratio:.2f}")
-    print(f"tau_refine = {tau_r:.3e}, tau_coarsen = {tau_r / 16:.3e}")
+    # a front on depth d must be refined: tau_refine = half its largest
+    # indicator, for a depth cap of d + 1; children of a just-refined leaf
+    # sit near tau_refine / ratio, so tau_coarsen = tau_refine / (2 ratio)
+    # keeps them from being coarsened at the next adaptation (ratio 8 in 2-D
+    # gives the factor 16)
+    for d in (1, 2):
+        tau_r = 0.5 * out[d][0]
+        print(f"depth cap {d + 1}: tau_refine = {tau_r:.3e}, tau_coarsen = {tau_r / (2 * ratio):.3e}")
 
 
 if __name__ == "__main__":

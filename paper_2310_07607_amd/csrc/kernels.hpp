@@ -976,22 +976,314 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
     }
 }
 
+// ---- Q1 quadrilaterals: four lanes per element -------------------------------
+// Threads per element of a kernel variant: Q1 quadrilaterals with a diagonal
+// diffusion tensor spread an element over the four lanes of a quad (lane q
+// owns node q for the volume term, the reaction and the stores, and face q,
+// direction q >> 1 and side q & 1, for the neighbour gather and the flux);
+// every other variant maps one element to one thread.
+__host__ __device__ constexpr int lanes_per_element(int dim, int p, bool full)
+{
+    return dim == 2 && p == 1 && !full ? 4 : 1;
+}
+
+// quad_perm data movement inside each quad of lanes (DPP, no LDS): lane l
+// receives the value of lane (PERM >> 2l) & 3 of its quad
+template <int PERM>
+__device__ __forceinline__ float quad_move(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), PERM, 0xf, 0xf, false));
+}
+template <int PERM>
+__device__ __forceinline__ double quad_move(double x)
+{
+    const HIP_vector_base<int, 2>::Native_vec_ w = __builtin_bit_cast(HIP_vector_base<int, 2>::Native_vec_, x);
+    HIP_vector_base<int, 2>::Native_vec_ r;
+    r[0] = __builtin_amdgcn_update_dpp(0, w[0], PERM, 0xf, 0xf, false);
+    r[1] = __builtin_amdgcn_update_dpp(0, w[1], PERM, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, r);
+}
+constexpr int kQuadBcast0 = 0x00, kQuadBcast1 = 0x55, kQuadBcast2 = 0xaa, kQuadBcast3 = 0xff;
+constexpr int kQuadXor1 = 0xb1;  // lanes 1 0 3 2
+constexpr int kQuadXor2 = 0x4e;  // lanes 2 3 0 1
+
+// x[i] = the value of lane i of the quad, in every lane
+template <typename T>
+__device__ __forceinline__ void quad_gather(T v, T *x)
+{
+    x[0] = quad_move<kQuadBcast0>(v);
+    x[1] = quad_move<kQuadBcast1>(v);
+    x[2] = quad_move<kQuadBcast2>(v);
+    x[3] = quad_move<kQuadBcast3>(v);
+}
+
+// the sum over the quad's lanes of c[q], returned to lane q (a two-step
+// butterfly: pairs of nodes by bit 0 of the lane, then single nodes by bit 1)
+template <typename T>
+__device__ __forceinline__ T quad_reduce_scatter(const T *c, int q)
+{
+    const bool b0 = q & 1, b1 = q & 2;
+    T keep0 = b0 ? c[1] : c[0], keep1 = b0 ? c[3] : c[2];
+    const T send0 = b0 ? c[0] : c[1], send1 = b0 ? c[2] : c[3];
+    keep0 += quad_move<kQuadXor1>(send0);
+    keep1 += quad_move<kQuadXor1>(send1);
+    T keep = b1 ? keep1 : keep0;
+    const T send = b1 ? keep0 : keep1;
+    keep += quad_move<kQuadXor2>(send);
+    return keep;
+}
+
+// The four nodes of a Q1 quadrilateral at the substep time (packed entry:
+// level | id), read with per-lane byte offsets: a neighbour updated at this
+// substep from its current slot, a coarser one not updated linear in time
+// between its two slots (the second read from the first's address when not
+// needed, so that the loads issue without branches).
+template <typename T>
+__device__ __forceinline__ void quad_neighbour(const StepLaunch<T> &L, __amdgpu_buffer_rsrc_t ru, uint32_t ent,
+                                               T *val)
+{
+    const uint32_t id = ent & kIdMask27;
+    const int ln = (int)((ent >> 27) & 7);
+    const int sh = L.lmax - ln;
+    const int cur = (ln == 0 ? L.parity : 0) ^ ((L.i >> sh) & 1);
+    const int rem = L.i & ((1 << sh) - 1);
+    const T th = ldexp((T)rem, -sh);
+    const uint32_t o0 = (uint32_t)cur * L.slot_bytes + id * (uint32_t)sizeof(T);
+    const uint32_t o1 = rem ? (uint32_t)(cur ^ 1) * L.slot_bytes + id * (uint32_t)sizeof(T) : o0;
+    // the second slot only where some lane of the wave interpolates (a
+    // wave-uniform branch; x0 + 0 (x1 - x0) = x0 for the others)
+    if (__builtin_amdgcn_ballot_w64(rem != 0) != 0) {
+        T x0[4], x1[4];
+#pragma unroll
+        for (int n = 0; n < 4; n++) {
+            x0[n] = buf_ld<T>(ru, o0 + (uint32_t)n * L.node_bytes, 0);
+            x1[n] = buf_ld<T>(ru, o1 + (uint32_t)n * L.node_bytes, 0);
+        }
+#pragma unroll
+        for (int n = 0; n < 4; n++) val[n] = x0[n] + th * (x1[n] - x0[n]);
+    } else {
+#pragma unroll
+        for (int n = 0; n < 4; n++) val[n] = buf_ld<T>(ru, o0 + (uint32_t)n * L.node_bytes, 0);
+    }
+}
+
+// One substep of Q1 quadrilateral j (diagonal D) on lane q of its quad: the
+// same operator as substep_element (Sec. 2.1 volume and SIPG faces, inverse
+// diagonal mass; Sec. 2.3 reaction, forward Euler for u, exponential step
+// for the gate).  A face is handled in its own frame: the element's nodes
+// are relabelled so that the face's normal line is the second index (a swap
+// of nodes 1 and 2 for faces normal to y), which keeps every lane on the
+// same instructions whatever its face.
+template <typename T>
+__device__ __forceinline__ void substep_quad(const StepArgs<T> &a, const StepLaunch<T> &L, const int j, const int lv,
+                                             const int q)
+{
+    constexpr RefConst R = ref_const(1);
+    const int k = q >> 1, s = q & 1;  // this lane's face: direction and side
+    const int sh = L.lmax - lv;
+    const int cur = (lv == 0 ? L.parity : 0) ^ ((L.i >> sh) & 1);
+    const T dt = (T)ldexp(a.dt_bar, -lv);
+
+    // ---- loads: own node q (u, v), face entry q, key; then face q's neighbour
+    const uint32_t ojt = (uint32_t)j * (uint32_t)sizeof(T);
+    const __amdgpu_buffer_rsrc_t ru = buf_of(L.u, 2u * L.slot_bytes);
+    const __amdgpu_buffer_rsrc_t rv = buf_of(L.v, L.slot_bytes);
+    const __amdgpu_buffer_rsrc_t rn = buf_of(L.nbr, 4u * (uint32_t)L.cap * 4u);
+    const uint32_t ent = buf_ld<uint32_t>(rn, (uint32_t)j * 4u + (uint32_t)q * (uint32_t)L.cap * 4u, 0);
+    const uint32_t kraw = buf_ld<uint32_t>(buf_of(L.key, (uint32_t)L.cap * 4u), (uint32_t)j * 4u, 0);
+    const uint32_t ou = (uint32_t)cur * L.slot_bytes + ojt;
+    const T uq = buf_ld<T>(ru, ou + (uint32_t)q * L.node_bytes, 0);
+    const T vq = buf_ld<T>(rv, ojt + (uint32_t)q * L.node_bytes, 0);
+    const uint32_t kind = ent >> 30;
+    const bool one = kind == kSame || kind == kCoarser;
+    T nv[4];
+    quad_neighbour<T>(L, ru, one ? ent : (((uint32_t)lv << 27) | (uint32_t)j), nv);
+
+    int depth;
+    uint32_t c[3] = {0, 0, 0};
+    unpack_key<2>(kraw, depth, c);
+    const T ih0 = ldexp(a.inv_h0[0], depth), ih1 = ldexp(a.inv_h0[1], depth);
+
+    T u[4];
+    quad_gather<T>(uq, u);
+
+    // ---- volume term of node q: -(4 D_kk / h_k^2) A along both directions;
+    // the line partner of node q is node q^1 along x and q^2 along y, and A
+    // of the two symmetric Gauss nodes has equal diagonal (and off-diagonal)
+    // entries
+    static_assert(R.A[0][0] == R.A[1][1] && R.A[0][1] == R.A[1][0], "Q1 line operator");
+    T rq;
+    {
+        const T c0 = (T)4 * a.Dk[0] * ih0 * ih0, c1 = (T)4 * a.Dk[1] * ih1 * ih1;
+        const T ux = quad_move<kQuadXor1>(uq), uy = quad_move<kQuadXor2>(uq);
+        const T sx = (T)R.A[0][0] * uq + (T)R.A[0][1] * ux;
+        const T sy = (T)R.A[0][0] * uq + (T)R.A[0][1] * uy;
+        rq = -(c0 * sx) - c1 * sy;
+    }
+
+    // ---- face q in its own frame: w[g][b] = node (tangential g, normal b)
+    T cf[4] = {0, 0, 0, 0};  // this face's lift to nodes 0..3
+    if (kind != kBoundary) {
+        const T ihk = k ? ih1 : ih0;
+        const T Dkk = k ? a.Dk[1] : a.Dk[0];
+        const T c2 = (T)2 * ihk;
+        const T pen = a.gamma * Dkk * ihk;
+        const T ns = s ? (T)1 : (T)-1;
+        const T qs = ns * Dkk * c2;
+        const int pos0 = (int)(k ? c[0] : c[1]) & 1;  // own half of a coarser neighbour's face
+        // own nodes in the face frame: swap nodes 1 and 2 for faces normal to y
+        const T w00 = u[0], w01 = k ? u[2] : u[1], w10 = k ? u[1] : u[2], w11 = u[3];
+        const T Bs0 = s ? (T)R.B[1][0] : (T)R.B[0][0], Bs1 = s ? (T)R.B[1][1] : (T)R.B[0][1];
+        const T Gs0 = s ? (T)R.G[1][0] : (T)R.G[0][0], Gs1 = s ? (T)R.G[1][1] : (T)R.G[0][1];
+        const T Bn0 = s ? (T)R.B[0][0] : (T)R.B[1][0], Bn1 = s ? (T)R.B[0][1] : (T)R.B[1][1];
+        const T Gn0 = s ? (T)R.G[0][0] : (T)R.G[1][0], Gn1 = s ? (T)R.G[0][1] : (T)R.G[1][1];
+        T tu[2], tq[2];
+        tu[0] = Bs0 * w00 + Bs1 * w01;
+        tu[1] = Bs0 * w10 + Bs1 * w11;
+        tq[0] = Gs0 * w00 + Gs1 * w01;
+        tq[1] = Gs0 * w10 + Gs1 * w11;
+        T Fl[2], Hl[2];
+        if (kind != kFiner) {
+            const T n00 = nv[0], n01 = k ? nv[2] : nv[1], n10 = k ? nv[1] : nv[2], n11 = nv[3];
+            T nu[2], nq[2];
+            nu[0] = Bn0 * n00 + Bn1 * n01;
+            nu[1] = Bn0 * n10 + Bn1 * n11;
+            nq[0] = Gn0 * n00 + Gn1 * n01;
+            nq[1] = Gn0 * n10 + Gn1 * n11;
+            const bool co = kind == kCoarser;  // h_nbr = 2h: its trace at the own sub-face points
+            if (co) {
+                const T i00 = pos0 ? (T)R.Isub[1][0][0] : (T)R.Isub[0][0][0];
+                const T i01 = pos0 ? (T)R.Isub[1][0][1] : (T)R.Isub[0][0][1];
+                const T i10 = pos0 ? (T)R.Isub[1][1][0] : (T)R.Isub[0][1][0];
+                const T i11 = pos0 ? (T)R.Isub[1][1][1] : (T)R.Isub[0][1][1];
+                const T a0 = i00 * nu[0] + i01 * nu[1], a1 = i10 * nu[0] + i11 * nu[1];
+                const T b0 = i00 * nq[0] + i01 * nq[1], b1 = i10 * nq[0] + i11 * nq[1];
+                nu[0] = a0; nu[1] = a1; nq[0] = b0; nq[1] = b1;
+            }
+            // F = 1/2 (qs tq + qn nq) - sigma [u], H = 1/2 [u], pre-scaled for the lift
+            const T sigma = co ? (T)0.75 * pen : pen;
+            const T qn = ns * Dkk * (co ? ihk : c2);
+            const T cf_q = (T)0.5 * c2 * qs, cf_n = (T)0.5 * c2 * qn, cf_j = c2 * sigma;
+            const T ch = (T)0.5 * c2 * qs;
+#pragma unroll
+            for (int g = 0; g < 2; g++) {
+                const T jmp = tu[g] - nu[g];
+                Fl[g] = cf_q * tq[g] + cf_n * nq[g] - cf_j * jmp;
+                Hl[g] = ch * jmp;
+            }
+        } else {
+            // two finer neighbours, one per half of the face: the own trace
+            // restricted to each half's points, the jump formed there, both
+            // lifted back to the face
+            const T sigma = (T)1.5 * pen;  // h_nbr = h/2
+            const T qn = ns * Dkk * (T)2 * c2;
+            Fl[0] = Fl[1] = Hl[0] = Hl[1] = 0;
+            const __amdgpu_buffer_rsrc_t rf = buf_of(L.fine, 4u * (uint32_t)L.cap * 2u * 4u);
+#pragma unroll 1
+            for (int sub = 0; sub < 2; sub++) {
+                const uint32_t fe = buf_ld<uint32_t>(rf, ((uint32_t)q * (uint32_t)L.cap * 2u + (uint32_t)j * 2u +
+                                                          (uint32_t)sub) * 4u, 0);
+                T fv[4];
+                quad_neighbour<T>(L, ru, fe, fv);
+                const T f00 = fv[0], f01 = k ? fv[2] : fv[1], f10 = k ? fv[1] : fv[2], f11 = fv[3];
+                T nu[2], nq[2], G[2], J[2];
+                nu[0] = Bn0 * f00 + Bn1 * f01;
+                nu[1] = Bn0 * f10 + Bn1 * f11;
+                nq[0] = Gn0 * f00 + Gn1 * f01;
+                nq[1] = Gn0 * f10 + Gn1 * f11;
+#pragma unroll
+                for (int g = 0; g < 2; g++) {
+                    const T i0 = sub ? (T)R.Isub[1][g][0] : (T)R.Isub[0][g][0];
+                    const T i1 = sub ? (T)R.Isub[1][g][1] : (T)R.Isub[0][g][1];
+                    const T ou_ = i0 * tu[0] + i1 * tu[1];
+                    const T oq_ = i0 * tq[0] + i1 * tq[1];
+                    const T jmp = ou_ - nu[g];
+                    G[g] = (T)0.5 * (qs * oq_ + qn * nq[g]) - sigma * jmp;
+                    J[g] = (T)0.5 * jmp;
+                }
+#pragma unroll
+                for (int g = 0; g < 2; g++) {
+                    const T l0 = sub ? (T)R.Lsub[1][g][0] : (T)R.Lsub[0][g][0];
+                    const T l1 = sub ? (T)R.Lsub[1][g][1] : (T)R.Lsub[0][g][1];
+                    Fl[g] += l0 * G[0] + l1 * G[1];
+                    Hl[g] += l0 * J[0] + l1 * J[1];
+                }
+            }
+            const T chq = c2 * qs;
+#pragma unroll
+            for (int g = 0; g < 2; g++) { Fl[g] *= c2; Hl[g] *= chq; }
+        }
+        // lift to the face-frame nodes (already times the inverse mass), then
+        // back to node numbers
+        const T e0 = (T)(R.winv[0] * R.B[0][0]), e1 = (T)(R.winv[1] * R.B[0][1]);
+        const T d0 = (T)(R.winv[0] * R.G[0][0]), d1 = (T)(R.winv[1] * R.G[0][1]);
+        const T E0 = (T)(R.winv[0] * R.B[1][0]), E1 = (T)(R.winv[1] * R.B[1][1]);
+        const T D0 = (T)(R.winv[0] * R.G[1][0]), D1 = (T)(R.winv[1] * R.G[1][1]);
+        const T lb0 = s ? E0 : e0, lb1 = s ? E1 : e1, lg0 = s ? D0 : d0, lg1 = s ? D1 : d1;
+        const T z00 = Fl[0] * lb0 + Hl[0] * lg0, z01 = Fl[0] * lb1 + Hl[0] * lg1;
+        const T z10 = Fl[1] * lb0 + Hl[1] * lg0, z11 = Fl[1] * lb1 + Hl[1] * lg1;
+        cf[0] = z00;
+        cf[1] = k ? z10 : z01;
+        cf[2] = k ? z01 : z10;
+        cf[3] = z11;
+    }
+    rq += quad_reduce_scatter<T>(cf, q);
+
+    // ---- node q: reaction, stimulus, update
+    const uint32_t ouo = (uint32_t)(cur ^ 1) * L.slot_bytes + ojt + (uint32_t)q * L.node_bytes;
+    const T apk = a.apk, apa = a.apa, eps0 = a.eps0, mu1 = a.mu1, mu2 = a.mu2;
+    T stim = 0;
+    bool on = false;  // some stimulus box is on at t_i (the same for every lane)
+    for (int b = 0; b < a.n_stim; b++) on = on || (L.t_i >= a.stim[b][6] && L.t_i < a.stim[b][7]);
+    if (on) {
+        double X[2];
+#pragma unroll
+        for (int d = 0; d < 2; d++) {
+            const double hk = ldexp(a.h0[d], -depth);
+            const double xi = ((d ? q >> 1 : q & 1) ? R.xi[1] : R.xi[0]);
+            X[d] = (double)c[d] * hk + 0.5 * (xi + 1.0) * hk;
+        }
+        for (int b = 0; b < a.n_stim; b++) {
+            const bool in = L.t_i >= a.stim[b][6] && L.t_i < a.stim[b][7] && X[0] >= a.stim[b][0] &&
+                            X[0] <= a.stim[b][3] && X[1] >= a.stim[b][1] && X[1] <= a.stim[b][4];
+            if (in) stim += (T)a.stim[b][8];
+        }
+    }
+    const T f = -apk * uq * (uq - apa) * (uq - (T)1) - uq * vq;
+    T den = uq + mu2;
+    den = den < (T)1e-6 ? (T)1e-6 : den;
+    const T vinf = apk * uq * ((T)1 + apa - uq);
+    T decay;
+    if constexpr (sizeof(T) == 4) {
+        const T eps = eps0 + mu1 * (vq * __builtin_amdgcn_rcpf(den));
+        decay = __expf(-eps * dt);
+    } else {
+        const T eps = eps0 + mu1 * vq / den;
+        decay = exp(-eps * dt);
+    }
+    buf_st<T>(ru, ouo, 0, uq + dt * (rq + f + stim));
+    buf_st<T>(rv, ojt + (uint32_t)q * L.node_bytes, 0, vinf + (vq - vinf) * decay);
+}
+
 // one simulation: element j of the active prefix [0, n_act)
 template <int DIM, int P, typename T, bool FULL>
 __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> *__restrict__ cst, const StepLaunch<T> L)
 {
-    const int j = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    constexpr int LPE = lanes_per_element(DIM, P, FULL);
+    const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int j = t / LPE;
     if (j >= L.n_act) return;
     const StepArgs<T> &a = *cst;
     int lv = 0;  // elements are grouped finest level first
 #pragma unroll
     for (int l = 1; l < kMaxLevels; l++) lv += (j < a.cnt_ge[l]) ? 1 : 0;
-    substep_element<DIM, P, T, FULL>(a, L, j, lv, gate_dyn);
+    if constexpr (LPE == 4) substep_quad<T>(a, L, j, lv, t & 3);
+    else substep_element<DIM, P, T, FULL>(a, L, j, lv, gate_dyn);
 }
 
 // ---- many simulations in one launch ------------------------------------------
-// A tile is up to blockDim.x consecutive active elements of one simulation,
-// all of one level.
+// A tile is up to blockDim.x / lanes_per_element consecutive active elements
+// of one simulation, all of one level.
 struct BatchTile {
     // the simulation's arrays as byte offsets from the kernel's base pointer
     long long off_u, off_v, off_key, off_nbr, off_fine;
@@ -1047,8 +1339,9 @@ __global__ __launch_bounds__(256) void k_substep_batch(const BatchSim<T> *__rest
         // every simulation has a tile at start 0 in substep 0: it advances
         // the simulation's clock for the next barrier (after its own work,
         // so that the element loads do not wait for the clock)
+        constexpr int LPE = lanes_per_element(DIM, P, FULL);
         const bool advance = i == 0 && tl.start == 0 && threadIdx.x == 0;
-        if ((int)threadIdx.x >= tl.count) {
+        if ((int)threadIdx.x / LPE >= tl.count) {
             if (advance) clk_next[tl.sim] = BatchClock{ck.n_bar + 1};
             return;
         }
@@ -1068,7 +1361,10 @@ __global__ __launch_bounds__(256) void k_substep_batch(const BatchSim<T> *__rest
         L.parity = (tl.packed >> 4) & 1;
         // t = t_start + n dt + i h, rounded like the host (no contraction)
         L.t_i = __dadd_rn(__dadd_rn(d.t_start, __dmul_rn((double)ck.n_bar, d.a.dt_bar)), __dmul_rn((double)i, d.h_tick));
-        substep_element<DIM, P, T, FULL>(d.a, L, tl.start + (int)threadIdx.x, tl.packed & 15, gate_dyn);
+        if constexpr (LPE == 4)
+            substep_quad<T>(d.a, L, tl.start + (int)(threadIdx.x >> 2), tl.packed & 15, (int)(threadIdx.x & 3));
+        else
+            substep_element<DIM, P, T, FULL>(d.a, L, tl.start + (int)threadIdx.x, tl.packed & 15, gate_dyn);
         if (advance) clk_next[tl.sim] = BatchClock{ck.n_bar + 1};
     }
 }

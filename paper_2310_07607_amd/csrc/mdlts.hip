@@ -1101,7 +1101,8 @@ mdlts_status launch_substep(const mdlts_sim *s, const StepArgs<T> *c, const Step
     StepLaunch<T> Lv = L;
     void *args[] = {&c, &Lv};
     const size_t lds = gate_lds_bytes(s->desc.dim, s->desc.order, sizeof(T) == 4, kBlock);
-    HIP_TRY(hipLaunchKernel(fn, dim3(nblocks(L.n_act)), dim3(kBlock), args, lds, st));
+    const long long threads = (long long)L.n_act * lanes_per_element(s->desc.dim, s->desc.order, s->dfull);
+    HIP_TRY(hipLaunchKernel(fn, dim3(nblocks(threads)), dim3(kBlock), args, lds, st));
     return MDLTS_OK;
 }
 
@@ -1506,6 +1507,7 @@ template <typename T>
 mdlts_status fill_group(mdlts_ctx *c, BatchPlan &P, BatchGroup &G)
 {
     const int nm = (int)G.members.size();
+    const int per_tile = G.block / lanes_per_element(G.dim, G.order, G.full);  // elements per tile
     // tile lists: substep i of the barrier interval (each simulation runs
     // its own 2^lmax substeps; shorter schedules idle at the end).  Active
     // levels lmax..lmin of a simulation occupy [0, cnt_ge[lmin]), finest
@@ -1549,7 +1551,7 @@ mdlts_status fill_group(mdlts_ctx *c, BatchPlan &P, BatchGroup &G)
             for (int l = s->lmax; l >= sig[q]; l--) {
                 int lo, hi;
                 level_range(s, l, lo, hi);
-                if (hi > lo) n_i += (size_t)((hi - lo + G.block - 1) / G.block);
+                if (hi > lo) n_i += (size_t)((hi - lo + per_tile - 1) / per_tile);
             }
         }
         G.tile_start[i] = (int)nt;
@@ -1601,9 +1603,9 @@ mdlts_status fill_group(mdlts_ctx *c, BatchPlan &P, BatchGroup &G)
             for (int l = s->lmax; l >= lmin_of(i, s->lmax); l--) {
                 int lo, hi;
                 level_range(s, l, lo, hi);
-                for (int sa = lo; sa < hi; sa += G.block) {
+                for (int sa = lo; sa < hi; sa += per_tile) {
                     tt.start = sa;
-                    tt.count = std::min(G.block, hi - sa);
+                    tt.count = std::min(per_tile, hi - sa);
                     tt.packed = l | parity << 4 | s->lmax << 8;
                     std::memcpy(t0 + k * sizeof(BatchTile), &tt, sizeof(tt));
                     tt.packed ^= 1 << 4;
@@ -3121,7 +3123,8 @@ mdlts_status mdlts_memory_bound(const mdlts_mesh_desc *desc, int64_t max_leaves,
             + 1 + 1 + 4 + 4 + 4 + 1     // refine and coarsen flags, counts, offsets, root offsets, scan sums
             + 1 + 4 + 1                 // transfer kind, source and child
             + 1 + 8 + 4 + 4 + 8 + 8 + 1 // level, CFL, permutation both ways, indicators, histogram share
-            + (nsub * 16 + 31) / 32;    // batch tiles: per substep one per 64 leaves (blocks of >= 64 threads)
+            + lanes_per_element(desc->dim, desc->order, false) * ((nsub * 16 + 31) / 32);
+                                    // batch tiles: per substep one per 64 threads (blocks of >= 64)
         const uint64_t fixed = 64 * 512         // allocator rounding of every buffer
                                + 4 * 4096       // flags, step constants, batch descriptor, small scans
                                + 8 * 4096       // own-block bounds of a full diffusion tensor

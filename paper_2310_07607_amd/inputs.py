@@ -33,9 +33,21 @@ WORKLOADS = {
     "amr_2d": dict(dim=2, p=1, n=(256, 256, 1), length=(2.0, 2.0, 1.0), max_depth=3, n_levels=4,
                    D=(1e-3, 1e-3, 1e-3), gamma=2.0, t_end=50.0, stim_size=0.1, stim_dur=1.0,
                    tau_refine=1.42e-9, tau_coarsen=1.42e-9 / 16, amr_every=32, fp="f32"),
+    # thresholds from `oracle/calibrate_thresholds.py --slab` (plane front
+    # along x on depth 2 for the depth cap 3; indicator ratio 94 per depth,
+    # tau_coarsen = tau_refine / (2 * 94)); the front (0.05 cm/ms along x)
+    # crosses about 0.3 finest elements per 32 barriers
     "amr_3d": dict(dim=3, p=2, n=(128, 48, 24), length=(2.0, 0.7, 0.3), max_depth=3, n_levels=4,
                    D=(1.3e-3, 0.33e-3, 0.33e-3), gamma=4.0, t_end=40.0,
-                   stim=[((0.0, 0.0, 0.0), (0.1, 0.1, 0.1), 0.0, 1.0, 1.0)], fp="f32"),
+                   stim=[((0.0, 0.0, 0.0), (0.1, 0.1, 0.1), 0.0, 1.0, 1.0)],
+                   tau_refine=8.2e-16, tau_coarsen=8.2e-16 / 188, amr_every=32, fp="f32"),
+    # the slab at half the root resolution with depth cap 2 (the activation-
+    # time parity case): thresholds from the depth-1 front of the same
+    # calibration
+    "slab_small": dict(dim=3, p=2, n=(64, 24, 12), length=(2.0, 0.7, 0.3), max_depth=2, n_levels=4,
+                       D=(1.3e-3, 0.33e-3, 0.33e-3), gamma=4.0, t_end=5.0,
+                       stim=[((0.0, 0.0, 0.0), (0.1, 0.1, 0.1), 0.0, 1.0, 1.0)],
+                       tau_refine=7.7e-14, tau_coarsen=7.7e-14 / 188, amr_every=16, fp="f32"),
 }
 
 
@@ -83,7 +95,8 @@ def serving_requests(seed, n_requests, rate, t_scale=1.0, large_frac=0.05, large
             w = dict(WORKLOADS["amr_3d"])
             w.update(large_overrides or {})
             spec = dict(dim=3, p=w["p"], n=tuple(w["n"]), length=tuple(w["length"]), max_depth=w["max_depth"],
-                        n_levels=w["n_levels"], D=tuple(w["D"]), gamma=w["gamma"], stim=list(w["stim"]), fp="f32")
+                        n_levels=w["n_levels"], D=tuple(w["D"]), gamma=w["gamma"], stim=list(w["stim"]), fp="f32",
+                        tau_refine=w["tau_refine"], tau_coarsen=w["tau_coarsen"])
         else:
             spec = small[q]
         out.append((spec, r.uniform(20.0, 100.0) * t_scale, float(arrivals[q])))
@@ -122,6 +135,20 @@ def random_state(seed, n_dof, u_range=(-0.05, 1.0), v_range=(0.0, 1.5)):
     r = rng(seed)
     u = r.uniform(u_range[0], u_range[1], n_dof)
     v = r.uniform(v_range[0], v_range[1], n_dof)
+    return u, v
+
+
+def front_state(X, center, radius, width=0.015, scale=(1.0, 1.0, 1.0)):
+    """A synthetic excitation front at nodes X [n, 3]: u goes smoothly from 1
+    inside the ellipsoid |(x - center) / scale| < radius to 0 outside over
+    `width` cm (a logistic profile, the shape of an upstroke), and the gate
+    v rises from 0 at the front to 0.8 about four widths behind it."""
+    X = np.asarray(X, dtype=np.float64)
+    d = len(center)
+    r = np.sqrt(sum(((X[:, k] - center[k]) / scale[k]) ** 2 for k in range(d)))
+    z = np.clip((r - radius) / width, -60.0, 60.0)
+    u = 1.0 / (1.0 + np.exp(z))
+    v = 0.8 * u * np.clip((radius - r) / (4.0 * width), 0.0, 1.0)
     return u, v
 
 

@@ -86,12 +86,18 @@ class MdltsBackend:
         s.set_stimulus(inputs.box_array(spec["stim"]))
         s.set_time(0.0)
         s._dt_barrier = self.dt_barrier(spec)
+        s._taus = (float(spec.get("tau_refine", self.tau_refine)), float(spec.get("tau_coarsen", self.tau_coarsen)))
         return s
 
     def adapt(self, sims):
         """Indicator, adaptation and levels of every resident solve, with two
-        host synchronisations in all."""
-        self.ctx.batch_adapt(sims, self.tau_refine, self.tau_coarsen, [s._dt_barrier for s in sims])
+        host synchronisations per group of solves that share thresholds (a
+        request may carry its own tau_refine / tau_coarsen)."""
+        groups = {}
+        for s in sims:
+            groups.setdefault(s._taus, []).append(s)
+        for (tr, tc), g in groups.items():
+            self.ctx.batch_adapt(g, tr, tc, [s._dt_barrier for s in g])
 
     def advance(self, sims):
         import torch

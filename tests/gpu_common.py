@@ -24,6 +24,23 @@ def oracle_mesh(dim, p, n, length, depth, D, gamma, seeds=(), frac=0.25):
     return o
 
 
+def oracle_front(dim, p, n, length, depth, D, gamma, taus, center, radius, width=0.015, scale=None, rounds=None):
+    """An oracle mesh refined around a synthetic front (inputs.front_state) by
+    the oracle's own indicator and adaptation, the state set from the closed
+    form on the final leaves: an established-front input built without the
+    device.  Returns (oracle, u, v)."""
+    o = Oracle(dim, p, n, length, depth)
+    o.set_params(diag3(D), gamma, inputs.AP_PARAMS)
+    scale = scale or (1.0,) * dim
+    for _ in range(depth + 1 if rounds is None else rounds):
+        u, v = inputs.front_state(o.leaf_nodes(), center, radius, width, scale)
+        o.set_state(u, v)
+        o.adapt(o.indicator(), taus[0], taus[1])
+    u, v = inputs.front_state(o.leaf_nodes(), center, radius, width, scale)
+    o.set_state(u, v)
+    return o, u, v
+
+
 def gpu_sim(ctx, o, dim, p, n, length, depth, D, gamma, n_levels, precision, stim=None):
     from paper_2310_07607_amd import mdlts
     g = mdlts.Simulation(ctx, dim, p, n, length, depth, n_levels, precision)

@@ -1,20 +1,25 @@
 """Parity at the benchmark's full sizes, in the launch configuration bench.py
-times (graph-replayed steps of one simulation; one batched step of all 64
-simulations), on sampled element updates the oracle computes one by one;
-and, for the 3-D slab whose full-size operator is too large for the oracle,
-FP32 against FP64 on the device.
+times (tile launches of one simulation, direct or graph-replayed as the
+autotuner chose; one batched step of all 64 simulations), from established-
+front inputs built without the device: a closed-form front
+(inputs.front_state) on a mesh refined around it by the oracle's own
+indicator and adaptation.
 
-A level-0 element is updated once per barrier, at the first substep, from
-the barrier's start state of itself and all its neighbours: one call of the
-oracle's element update with the full start state.  A uniform level makes
-every element such an element, whatever its faces (conforming, coarser,
-finer)."""
+* amr_2d (256x256 Q1 roots, depth 3, 4 levels): whole LTS barriers, every
+  element against the oracle's barrier (FP32 and FP64);
+* the 3-D slab at half resolution (64x24x12 Q2 roots, depth 2, 4 levels,
+  anisotropic D): whole barriers, every element;
+* the batched workload: sampled level-0 element updates (one barrier) of one
+  simulation per kernel variant, all 64 simulations in the launch;
+* the full 3-D slab (128x48x24 Q2, depth 3), too large for the oracle's
+  assembly: FP32 against FP64 on the device.
+"""
 import numpy as np
 import pytest
 
 from oracle.oracle import Oracle
 from paper_2310_07607_amd import inputs
-from tests.gpu_common import rel_l2
+from tests.gpu_common import oracle_front, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -35,15 +40,6 @@ def dt_barrier(desc_args, D, gamma, depth, L):
     return 2 ** (L - 1) * mdlts.cfl_bound(d, D, gamma, depth) * (1 - 2 ** -20)
 
 
-def oracle_for(dim, p, n, length, depth, D, gamma, stim, bits, u, v):
-    o = Oracle(dim, p, n, length, depth)
-    o.set_params(np.diag(list(D) + [0.0] * (3 - len(D))), gamma, inputs.AP_PARAMS)
-    o.set_stimulus(stim)
-    o.set_tree(bits)
-    o.set_state(u, v)
-    return o
-
-
 def check_sampled(o, elems, u_n, t, dt, u_gpu, v_gpu, np_):
     """Oracle element updates of `elems` against the device's new state."""
     eu, ev, gu, gv = [], [], [], []
@@ -62,99 +58,143 @@ def check_sampled(o, elems, u_n, t, dt, u_gpu, v_gpu, np_):
     assert np.max(np.abs(gv - ev)) <= 1e-5 * max(1.0, np.max(np.abs(ev))), np.max(np.abs(gv - ev))
 
 
-def test_amr_2d_full_size_sampled_elements(ctx):
-    """256x256 Q1 roots, depth <= 3, 4 levels, FP32: the benchmark workload
-    after its front has formed."""
+def _whole_barriers(ctx, o, u, v, dim, p, n, length, depth, D, gamma, L, stim, t0, checks):
+    """Both precisions on the device against the oracle over whole barriers
+    from the same input; `checks`: {precision: (barriers, rel L2 bound)}."""
     from paper_2310_07607_amd import mdlts
+    dt = 2 ** (L - 1) * o.cfl().min() * (1 - 2 ** -20)
+    lv, rc = o.levels(dt, L)
+    assert rc == 0
+    hist = np.bincount(lv, minlength=L)
+    assert (hist > 0).sum() >= 3, hist
+    bits = o.tree_bits()
+    for prec, (nb, tol) in checks.items():
+        g = mdlts.Simulation(ctx, dim, p, n, length, depth, L, prec)
+        g.set_conductivity(D, gamma)
+        g.set_ionic(*inputs.AP_PARAMS)
+        g.set_stimulus(stim)
+        g.set_tree(bits)
+        # launch-shape tuning on this mesh first, so that the compared
+        # barriers run in the tuned (benchmark) launch configuration
+        g.set_state(u, v)
+        g.assign_levels(dt)
+        g.set_time(t0)
+        g.step(16)
+        g.set_state(u, v)
+        g.assign_levels(dt)
+        g.set_time(t0)
+        assert np.array_equal(g.get_levels()[0], lv)
+        g.step(nb)
+        o.set_state(u, v)
+        for b in range(nb):
+            o.lts_barrier(dt, t0 + b * dt, lv)
+        gu, gv = g.get_state()
+        ou, ov = o.get_state()
+        err = rel_l2(gu, ou)
+        per_level = {}
+        for l in range(L):
+            m = np.repeat(lv == l, o.np_)
+            if m.any():
+                per_level[l] = rel_l2(gu[m], ou[m])
+        print(f"{prec}: {o.n_leaves} leaves, levels {hist.tolist()}, {nb} barriers, rel L2 {err:.2e}, "
+              f"per level {per_level}", flush=True)
+        assert np.all(np.isfinite(gu))
+        assert err <= tol, err
+        assert max(per_level.values()) <= 10 * tol, per_level
+        assert np.max(np.abs(gu - ou)) <= (1e-10 if prec == "f64" else 1e-5), np.max(np.abs(gu - ou))
+        assert np.max(np.abs(gv - ov)) <= (1e-10 if prec == "f64" else 1e-5) * max(1.0, np.abs(ov).max())
+        assert rel_l2(gu, u) > 10 * tol  # the state moved
+        g.close()
+
+
+def test_amr_2d_full_size_whole_barriers(ctx):
+    """256x256 Q1 roots, depth <= 3, 4 levels: an established front."""
     W = inputs.WORKLOADS["amr_2d"]
     n, length, D = W["n"][:2], W["length"][:2], W["D"][:2]
-    dt = dt_barrier((2, 1, n, length, W["max_depth"], W["n_levels"]), D, W["gamma"], W["max_depth"], W["n_levels"])
     box = inputs.stimulus_site(0, length, W["stim_size"], 0.1, 0.0, W["stim_dur"], 1.0)
-    stim = inputs.box_array([box])
-    g = mdlts.Simulation(ctx, 2, 1, n, length, W["max_depth"], W["n_levels"], "f32")
-    g.set_conductivity(D, W["gamma"])
-    g.set_ionic(*inputs.AP_PARAMS)
-    g.set_stimulus(stim)
-    g.set_time(0.0)
-    for _ in range(40):  # the front forms and the mesh refines around it
-        g.indicator(download=False)
-        g.adapt(W["tau_refine"], W["tau_coarsen"])
-        g.assign_levels(dt)
-        g.step(W["amr_every"])
-    _, t_n = g.counters()
-    bits = g.get_tree()
-    u_n, v_n = g.get_state()
-    assert g.n_leaves > 256 * 256
-    g.assign_levels(dt)
-    level, _, cnt = g.get_levels()
-    assert cnt[-1] > 0  # every level is present
-    g.step(1)
-    u1, v1 = g.get_state()
-    o = oracle_for(2, 1, n, length, W["max_depth"], D, W["gamma"], stim, bits, u_n, v_n)
-    rng = np.random.default_rng(7)
-    lvl0 = np.flatnonzero(level == 0)
-    check_sampled(o, rng.choice(lvl0, N_SAMPLES, replace=False), u_n, t_n, dt, u1, v1, 4)
+    centre = [0.5 * (box[0][k] + box[1][k]) for k in range(2)]
+    o, u, v = oracle_front(2, 1, n, length, W["max_depth"], D, W["gamma"], (W["tau_refine"], W["tau_coarsen"]),
+                           centre, 0.45, width=0.01)
+    assert o.n_leaves > 2 * 256 * 256
+    _whole_barriers(ctx, o, u, v, 2, 1, n, length, W["max_depth"], D, W["gamma"], W["n_levels"],
+                    inputs.box_array([box]), 5.0, {"f32": (4, 1e-4), "f64": (2, 1e-12)})
 
-    # every element at one level: one global step of the finest substep
-    dt_f = dt / 2 ** (W["n_levels"] - 1)
-    g.set_state(u_n, v_n)
-    g.set_time(t_n)
-    g.assign_uniform(dt_f, 0)
-    g.step(1)
-    u2, v2 = g.get_state()
-    depth, _ = o.leaf_info()
-    deep = np.flatnonzero(depth == W["max_depth"])
-    assert len(deep) > 0
-    pick = np.concatenate([rng.choice(g.n_leaves, N_SAMPLES, replace=False),
-                           rng.choice(deep, min(len(deep), 500), replace=False)])
-    check_sampled(o, pick, u_n, t_n, dt_f, u2, v2, 4)
-    g.close()
+
+def test_slab_half_resolution_whole_barriers(ctx):
+    """64x24x12 Q2 roots of the 2.0x0.7x0.3 cm slab, depth <= 2, 4 levels,
+    anisotropic D: a front around the stimulated corner."""
+    W = inputs.WORKLOADS["slab_small"]
+    n, length, D = W["n"], W["length"], W["D"]
+    scale = tuple(np.sqrt(np.array(D) / D[0]))
+    o, u, v = oracle_front(3, 2, n, length, W["max_depth"], D, W["gamma"], (W["tau_refine"], W["tau_coarsen"]),
+                           (0.0, 0.0, 0.0), 0.16, width=0.02, scale=scale, rounds=2)
+    assert o.n_leaves > 64 * 24 * 12
+    _whole_barriers(ctx, o, u, v, 3, 2, n, length, W["max_depth"], D, W["gamma"], W["n_levels"],
+                    inputs.box_array(W["stim"]), 2.0, {"f32": (2, 1e-4), "f64": (1, 1e-12)})
 
 
 def test_batched_full_size_sampled_elements(ctx):
-    """All 64 simulations of the batched workload in one batched step; sampled
-    elements of the simulations small enough for the oracle's assembly."""
+    """All 64 simulations of the batched workload in one batched step; for the
+    smallest simulation of each kernel variant, an oracle-built front input
+    and sampled level-0 element updates against the oracle's."""
     from paper_2310_07607_amd import mdlts
     specs = inputs.batched_workload(0, 64)
     tau_r, tau_c = inputs.WORKLOADS["amr_2d"]["tau_refine"], inputs.WORKLOADS["amr_2d"]["tau_coarsen"]
+    chosen = {}
+    for q, w in enumerate(specs):
+        key = (w["dim"], w["p"])
+        if key not in chosen or np.prod(w["n"]) < np.prod(specs[chosen[key]]["n"]):
+            chosen[key] = q
+    assert len(chosen) == 4
+    fronts = {}
+    for key, q in chosen.items():
+        w = specs[q]
+        centre = [0.5 * (w["stim"][0][0][k] + w["stim"][0][1][k]) for k in range(w["dim"])]
+        # a front small enough for the oracle's assembly, refined to the
+        # depth cap by the oracle's indicator (thresholds relative to its
+        # largest value on the root mesh)
+        o = Oracle(w["dim"], w["p"], w["n"], w["length"], w["max_depth"])
+        o.set_params(np.diag(list(w["D"]) + [0.0] * (3 - w["dim"])), w["gamma"], inputs.AP_PARAMS)
+        o.set_stimulus(inputs.box_array(w["stim"]))
+        radius = 0.25 * min(w["length"])
+        u, v = inputs.front_state(o.leaf_nodes(), centre, radius, 0.02)
+        o.set_state(u, v)
+        eta = o.indicator()
+        o.adapt(eta, 0.05 * eta.max(), -1.0)
+        u, v = inputs.front_state(o.leaf_nodes(), centre, radius, 0.02)
+        o.set_state(u, v)
+        fronts[q] = o, u, v
     sims, dts = [], []
-    for w in specs:
+    for q, w in enumerate(specs):
         s = mdlts.Simulation(ctx, w["dim"], w["p"], w["n"], w["length"], w["max_depth"], w["n_levels"], "f32")
         s.set_conductivity(w["D"], w["gamma"])
         s.set_ionic(*inputs.AP_PARAMS)
         s.set_stimulus(inputs.box_array(w["stim"]))
         dts.append(dt_barrier((w["dim"], w["p"], w["n"], w["length"], w["max_depth"], w["n_levels"]),
                               w["D"], w["gamma"], w["max_depth"], w["n_levels"]))
+        if q in fronts:
+            o, u, v = fronts[q]
+            s.set_tree(o.tree_bits())
+            s.set_state(u, v)
         s.assign_levels(dts[-1])
-        s.set_time(0.0)
+        s.set_time(0.5)
         sims.append(s)
-    for _ in range(6):
-        for s, dt in zip(sims, dts):
-            s.indicator(download=False)
-            s.adapt(tau_r, tau_c)
-            s.assign_levels(dt)
-        ctx.batch_step(sims, 32)
-    # one simulation of each kernel variant, the smallest of its kind
-    chosen = {}
-    for q, w in enumerate(specs):
-        key = (w["dim"], w["p"])
-        if key not in chosen or sims[q].n_leaves < sims[chosen[key]].n_leaves:
-            chosen[key] = q
-    assert len(chosen) == 4
-    start = {q: (sims[q].counters()[1], sims[q].get_tree(), *sims[q].get_state()) for q in chosen.values()}
-    levels = {q: sims[q].get_levels()[0] for q in chosen.values()}
+    ctx.batch_step(sims, 12)  # launch-shape tuning of the plan
+    for q, (o, u, v) in fronts.items():
+        sims[q].set_state(u, v)
+        sims[q].assign_levels(dts[q])
+        sims[q].set_time(0.5)
+    levels = {q: sims[q].get_levels()[0] for q in fronts}
     ctx.batch_step(sims, 1)
     rng = np.random.default_rng(11)
     for key, q in sorted(chosen.items()):
         w = specs[q]
-        t_n, bits, u_n, v_n = start[q]
+        o, u_n, v_n = fronts[q]
         u1, v1 = sims[q].get_state()
-        o = oracle_for(w["dim"], w["p"], w["n"], w["length"], w["max_depth"], w["D"], w["gamma"],
-                       inputs.box_array(w["stim"]), bits, u_n, v_n)
         lvl0 = np.flatnonzero(levels[q] == 0)
         pick = rng.choice(lvl0, min(len(lvl0), 800), replace=False)
         print(f"batched sim {q} dim={w['dim']} p={w['p']} leaves={sims[q].n_leaves} samples={len(pick)}", flush=True)
-        check_sampled(o, pick, u_n, t_n, dts[q], u1, v1, (w["p"] + 1) ** w["dim"])
+        check_sampled(o, pick, u_n, 0.5, dts[q], u1, v1, (w["p"] + 1) ** w["dim"])
     for s in sims:
         s.close()
 

@@ -1,12 +1,15 @@
 """RV-T temporal indicator and the cell criterion on the device against the
-oracle: the indicator over barriers of LTS stepping (FP64 and FP32 states,
-refined trees, a stimulus switching off inside the interval), levels with
-both criteria bit-exact, the state errors, and the benchmark-size mesh."""
+oracle.  Both sides take the same seeded end states of the interval (state
+A at t_a, snapshot; state B at t_b; rounded to FP32 first for the FP32
+cases, so that both hold the same values): the indicator on refined trees
+with a stimulus switching off inside the interval (FP64 and FP32), levels
+with both criteria bit-exact (thresholds in gaps of the oracle's
+indicator), the state errors, and the benchmark-size mesh."""
 import numpy as np
 import pytest
 
 from paper_2310_07607_amd import inputs
-from tests.gpu_common import gpu_sim, oracle_mesh
+from tests.gpu_common import gpu_sim, oracle_front, oracle_mesh
 
 pytestmark = pytest.mark.gpu
 
@@ -27,14 +30,30 @@ def ctx():
     c.close()
 
 
-def smooth_state(o, seed):
-    """A front-like state: u a tanh ramp in x with seeded jitter, v small."""
+def smooth_state(o, seed, shift=0.0):
+    """A front-like state: u a tanh ramp in x (moved by `shift` cm) with
+    seeded jitter, v small."""
     X = o.leaf_nodes()
     r = np.random.default_rng(seed)
-    x0 = r.uniform(0.3, 0.7) * X[:, 0].max()
+    x0 = r.uniform(0.3, 0.7) * X[:, 0].max() + shift
     u = 0.5 * (1 - np.tanh((X[:, 0] - x0) / 0.01)) + 0.01 * r.standard_normal(len(X))
     v = 0.05 * r.random(len(X))
     return u, v
+
+
+def as_stored(x, prec):
+    """The values a simulation of this precision holds for x."""
+    return x.astype(np.float32).astype(np.float64) if prec == "f32" else x
+
+
+def gap_threshold(eta, q):
+    """A threshold near the q-quantile of eta in the widest gap between
+    neighbouring values there (no decision sits near a tie)."""
+    e = np.sort(eta)
+    i0 = int(q * (len(e) - 1))
+    lo, hi = max(1, i0 - 50), min(len(e) - 1, i0 + 50)
+    k = lo + int(np.argmax(e[lo:hi] - e[lo - 1:hi - 1]))
+    return 0.5 * (e[k - 1] + e[k])
 
 
 def make(ctx, case, seed, t0):
@@ -45,24 +64,41 @@ def make(ctx, case, seed, t0):
     o.set_stimulus(stim)
     g = gpu_sim(ctx, o, dim, p, n, length, depth, D, gamma, L, prec, stim)
     u, v = smooth_state(o, seed)
-    g.set_state(u, v)
+    g.set_state(as_stored(u, prec), as_stored(v, prec))
     dt = 2 ** (L - 1) * o.cfl().min() * (1 - 2 ** -20)
     g.assign_levels(dt)
     g.set_time(t0)
     return o, g, dt, L
 
 
+def interval_states(o, seed, prec, dt_frac=0.002):
+    """Seeded end states A and B of an interval (the front moved slightly)."""
+    ua, va = smooth_state(o, seed)
+    ub, vb = smooth_state(o, seed, shift=dt_frac)
+    vb = vb + 0.01
+    return tuple(as_stored(x, prec) for x in (ua, va, ub, vb))
+
+
+def rvt_both(g, o, A, B, t_a, t_b):
+    """The indicator over [t_a, t_b] on the device (snapshot of A, then B)
+    and in the oracle, from the same states."""
+    g.set_state(*A)
+    g.set_time(t_a)
+    g.rvt_snapshot()
+    g.set_state(*B)
+    g.set_time(t_b)
+    eta_g, m = g.rvt_indicator()
+    o.set_state(*B)
+    eta_o = o.rvt_indicator(A[0], A[1], t_a, t_b)
+    return eta_g, m, eta_o
+
+
 @pytest.mark.parametrize("case", range(len(CASES)))
 def test_rvt_indicator_matches_oracle(ctx, case):
     t0 = 0.25
     o, g, dt, L = make(ctx, CASES[case], 30 + case, t0)
-    u_a, v_a = g.get_state()  # the device's own start state (FP32-rounded for f32)
-    g.rvt_snapshot()
-    g.step(2)
-    u_b, v_b = g.get_state()
-    eta_g, m = g.rvt_indicator()
-    o.set_state(u_b, v_b)
-    eta_o = o.rvt_indicator(u_a, v_a, t0, t0 + 2 * dt)
+    ua, va, ub, vb = interval_states(o, 30 + case, CASES[case][-1])
+    eta_g, m, eta_o = rvt_both(g, o, (ua, va), (ub, vb), t0, t0 + 2 * dt)
     assert eta_o.max() > 0
     assert np.max(np.abs(eta_g - eta_o)) <= 1e-12 * eta_o.max(), np.max(np.abs(eta_g - eta_o)) / eta_o.max()
     assert m == pytest.approx(eta_o.max(), rel=1e-12)
@@ -74,12 +110,11 @@ def test_levels_with_cell_criterion_bitwise(ctx, case):
     from oracle.oracle import Oracle
     t0 = 0.25
     o, g, dt, L = make(ctx, CASES[case], 50 + case, t0)
-    g.rvt_snapshot()
-    g.step(1)
-    eta, m = g.rvt_indicator()
-    tau = float(np.quantile(eta, 0.7))  # about 30 % of the leaves above
+    ua, va, ub, vb = interval_states(o, 50 + case, CASES[case][-1])
+    eta, m, eta_o = rvt_both(g, o, (ua, va), (ub, vb), t0, t0 + dt)
+    tau = gap_threshold(eta_o, 0.7)     # about 30 % of the leaves above
     dt_cell = dt / 2.5                  # b^cell = 2
-    lv_o, rc = o.levels_cell(dt, L, eta, tau, dt_cell)
+    lv_o, rc = o.levels_cell(dt, L, eta_o, tau, dt_cell)
     assert rc == 0
     hist = g.assign_levels_cell(dt, tau, dt_cell)
     level, perm, cnt = g.get_levels()
@@ -114,40 +149,33 @@ def test_rvt_state_errors(ctx):
 
 
 def test_rvt_full_size_amr_2d(ctx):
-    """256x256 Q1 roots, depth <= 3, FP32, after the front has formed: the
-    indicator over one barrier for every leaf, and the levels with both
-    criteria."""
-    from oracle.oracle import Oracle
+    """256x256 Q1 roots, depth <= 3, FP32, an established front built by the
+    oracle: the indicator over one barrier for every leaf, and the levels
+    with both criteria."""
     from paper_2310_07607_amd import mdlts
     W = inputs.WORKLOADS["amr_2d"]
     n, length, D = W["n"][:2], W["length"][:2], W["D"][:2]
-    desc = mdlts.make_desc(2, 1, n, length, W["max_depth"], W["n_levels"])
-    dt = 2 ** (W["n_levels"] - 1) * mdlts.cfl_bound(desc, D, W["gamma"], W["max_depth"]) * (1 - 2 ** -20)
     box = inputs.stimulus_site(0, length, W["stim_size"], 0.1, 0.0, W["stim_dur"], 1.0)
     stim = inputs.box_array([box])
+    centre = [0.5 * (box[0][k] + box[1][k]) for k in range(2)]
+    o, u, v = oracle_front(2, 1, n, length, W["max_depth"], D, W["gamma"], (W["tau_refine"], W["tau_coarsen"]),
+                           centre, 0.45, width=0.01)
+    o.set_stimulus(stim)
+    dt = 2 ** (W["n_levels"] - 1) * o.cfl().min() * (1 - 2 ** -20)
+    ub, vb = inputs.front_state(o.leaf_nodes(), centre, 0.45 + 0.044 * dt, 0.01)
+    A = (as_stored(u, "f32"), as_stored(v, "f32"))
+    B = (as_stored(ub, "f32"), as_stored(vb + 1e-3, "f32"))
     g = mdlts.Simulation(ctx, 2, 1, n, length, W["max_depth"], W["n_levels"], "f32")
     g.set_conductivity(D, W["gamma"])
     g.set_ionic(*inputs.AP_PARAMS)
     g.set_stimulus(stim)
-    g.set_time(0.0)
-    for _ in range(40):
-        ctx.batch_adapt([g], W["tau_refine"], W["tau_coarsen"], [dt])
-        g.step(W["amr_every"])
-    t_a = g.counters()[1]
-    u_a, v_a = g.get_state()
-    g.rvt_snapshot()
-    g.step(1)
-    u_b, v_b = g.get_state()
-    eta, m = g.rvt_indicator()
-    o = Oracle(2, 1, n, length, W["max_depth"])
-    o.set_params(np.diag(list(D) + [0.0]), W["gamma"], inputs.AP_PARAMS)
-    o.set_stimulus(stim)
-    o.set_tree(g.get_tree())
-    o.set_state(u_b, v_b)
-    eta_o = o.rvt_indicator(u_a, v_a, t_a, t_a + dt)
+    g.set_tree(o.tree_bits())
+    t_a = 0.6  # the stimulus is on
+    eta, m, eta_o = rvt_both(g, o, A, B, t_a, t_a + dt)
+    assert eta_o.max() > 0
     assert np.max(np.abs(eta - eta_o)) <= 1e-12 * eta_o.max()
-    tau = float(np.quantile(eta, 0.95))
-    lv_o, rc = o.levels_cell(dt, W["n_levels"], eta, tau, dt / 8)
+    tau = gap_threshold(eta_o, 0.95)
+    lv_o, rc = o.levels_cell(dt, W["n_levels"], eta_o, tau, dt / 8)
     assert rc == 0
     g.assign_levels_cell(dt, tau, dt / 8)
     level, _, _ = g.get_levels()
