@@ -500,12 +500,27 @@ __device__ __forceinline__ void neighbour_interp(const StepLaunch<T> &L, __amdgp
 template <int DIM, int P, typename T>
 constexpr bool kGateInLds = Shape<DIM, P>::NP > 16 && sizeof(T) == 4;
 
-// Dynamic LDS of a launch: the gate staging area of its waves (launches of
-// fewer than 4 waves per block take less, so more blocks fit on a CU).
-// Same condition as kGateInLds.
+// ---- layouts of an element over the lanes ------------------------------------
+// Q1 quadrilaterals with a diagonal tensor: four lanes per element (one node
+// and one face each, substep_quad); every other element: one thread
+// (substep_element).
+__host__ __device__ constexpr bool uses_quad(int dim, int p, bool full) { return dim == 2 && p == 1 && !full; }
+__host__ __device__ constexpr int node_count(int dim, int p)
+{
+    return dim == 2 ? (p + 1) * (p + 1) : (p + 1) * (p + 1) * (p + 1);
+}
+// elements per block of `block` threads (a multiple of 64)
+__host__ __device__ constexpr int elements_per_block(int dim, int p, bool full, int block)
+{
+    return uses_quad(dim, p, full) ? block / 4 : block;
+}
+
+// Dynamic LDS of a launch: the gate staging area of per-thread elements above
+// 16 nodes in FP32 (launches of fewer than 4 waves per block take less, so
+// more blocks fit on a CU).  Same condition as kGateInLds.
 inline size_t gate_lds_bytes(int dim, int p, bool fp32, int block)
 {
-    const int np = dim == 2 ? (p + 1) * (p + 1) : (p + 1) * (p + 1) * (p + 1);
+    const int np = node_count(dim, p);
     return fp32 && np > 16 ? (size_t)(block / 64) * (size_t)np * 64 * sizeof(float) : 0;
 }
 
@@ -984,7 +999,7 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
 // every other variant maps one element to one thread.
 __host__ __device__ constexpr int lanes_per_element(int dim, int p, bool full)
 {
-    return dim == 2 && p == 1 && !full ? 4 : 1;
+    return uses_quad(dim, p, full) ? 4 : 1;
 }
 
 // quad_perm data movement inside each quad of lanes (DPP, no LDS): lane l
@@ -1269,21 +1284,24 @@ __device__ __forceinline__ void substep_quad(const StepArgs<T> &a, const StepLau
 template <int DIM, int P, typename T, bool FULL>
 __global__ __launch_bounds__(256) void k_substep(const StepArgs<T> *__restrict__ cst, const StepLaunch<T> L)
 {
-    constexpr int LPE = lanes_per_element(DIM, P, FULL);
-    const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    const int j = t / LPE;
-    if (j >= L.n_act) return;
     const StepArgs<T> &a = *cst;
-    int lv = 0;  // elements are grouped finest level first
+    // elements are grouped finest level first
+    auto lv_of = [&](int j) {
+        int lv = 0;
 #pragma unroll
-    for (int l = 1; l < kMaxLevels; l++) lv += (j < a.cnt_ge[l]) ? 1 : 0;
-    if constexpr (LPE == 4) substep_quad<T>(a, L, j, lv, t & 3);
-    else substep_element<DIM, P, T, FULL>(a, L, j, lv, gate_dyn);
+        for (int l = 1; l < kMaxLevels; l++) lv += (j < a.cnt_ge[l]) ? 1 : 0;
+        return lv;
+    };
+    const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int j = t / lanes_per_element(DIM, P, FULL);
+    if (j >= L.n_act) return;
+    if constexpr (uses_quad(DIM, P, FULL)) substep_quad<T>(a, L, j, lv_of(j), t & 3);
+    else substep_element<DIM, P, T, FULL>(a, L, j, lv_of(j), gate_dyn);
 }
 
 // ---- many simulations in one launch ------------------------------------------
-// A tile is up to blockDim.x / lanes_per_element consecutive active elements
-// of one simulation, all of one level.
+// A tile is up to elements_per_block consecutive active elements of one
+// simulation, all of one level.
 struct BatchTile {
     // the simulation's arrays as byte offsets from the kernel's base pointer
     long long off_u, off_v, off_key, off_nbr, off_fine;
@@ -1339,9 +1357,11 @@ __global__ __launch_bounds__(256) void k_substep_batch(const BatchSim<T> *__rest
         // every simulation has a tile at start 0 in substep 0: it advances
         // the simulation's clock for the next barrier (after its own work,
         // so that the element loads do not wait for the clock)
-        constexpr int LPE = lanes_per_element(DIM, P, FULL);
+        // this thread's element of the tile and its part of it
+        const int slot = (int)threadIdx.x / lanes_per_element(DIM, P, FULL);
+        const int part = (int)threadIdx.x & 3;
         const bool advance = i == 0 && tl.start == 0 && threadIdx.x == 0;
-        if ((int)threadIdx.x / LPE >= tl.count) {
+        if (slot >= tl.count) {
             if (advance) clk_next[tl.sim] = BatchClock{ck.n_bar + 1};
             return;
         }
@@ -1361,10 +1381,11 @@ __global__ __launch_bounds__(256) void k_substep_batch(const BatchSim<T> *__rest
         L.parity = (tl.packed >> 4) & 1;
         // t = t_start + n dt + i h, rounded like the host (no contraction)
         L.t_i = __dadd_rn(__dadd_rn(d.t_start, __dmul_rn((double)ck.n_bar, d.a.dt_bar)), __dmul_rn((double)i, d.h_tick));
-        if constexpr (LPE == 4)
-            substep_quad<T>(d.a, L, tl.start + (int)(threadIdx.x >> 2), tl.packed & 15, (int)(threadIdx.x & 3));
-        else
-            substep_element<DIM, P, T, FULL>(d.a, L, tl.start + (int)threadIdx.x, tl.packed & 15, gate_dyn);
+        if constexpr (uses_quad(DIM, P, FULL)) {
+            substep_quad<T>(d.a, L, tl.start + slot, tl.packed & 15, part);
+        } else {
+            substep_element<DIM, P, T, FULL>(d.a, L, tl.start + slot, tl.packed & 15, gate_dyn);
+        }
         if (advance) clk_next[tl.sim] = BatchClock{ck.n_bar + 1};
     }
 }

@@ -1507,7 +1507,7 @@ template <typename T>
 mdlts_status fill_group(mdlts_ctx *c, BatchPlan &P, BatchGroup &G)
 {
     const int nm = (int)G.members.size();
-    const int per_tile = G.block / lanes_per_element(G.dim, G.order, G.full);  // elements per tile
+    const int per_tile = elements_per_block(G.dim, G.order, G.full, G.block);  // elements per tile
     // tile lists: substep i of the barrier interval (each simulation runs
     // its own 2^lmax substeps; shorter schedules idle at the end).  Active
     // levels lmax..lmin of a simulation occupy [0, cnt_ge[lmin]), finest

@@ -145,3 +145,23 @@ def test_memory_bound_is_affine_in_leaves_and_covers_the_state(dim, p):
     assert mdlts.memory_bound(d64, E) > b1
     with pytest.raises(mdlts.MdltsError):
         mdlts.memory_bound(d32, 0)
+
+
+@pytest.mark.parametrize("name", ["amr2d", "slab"])
+def test_lat_golden_barrier_step_fits_the_library_levels(name):
+    # the activation-time goldens take their barrier step from the oracle
+    # (2^(L-1) times the smallest CFL of a uniform mesh at the depth cap);
+    # the library's bound for the same mesh must agree, so that both sides
+    # assign every leaf within the configured levels
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", f"lat_{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not written yet (tests/golden/make_lat_golden.py {name})")
+    with open(path) as f:
+        G = json.load(f)
+    c = G["case"]
+    desc = mdlts.make_desc(c["dim"], c["p"], c["n"], c["length"], c["depth"], c["levels"])
+    lib_dt = 2 ** (c["levels"] - 1) * mdlts.cfl_bound(desc, c["D"], c["gamma"], c["depth"]) * (1 - 2 ** -20)
+    assert G["dt_barrier"] == pytest.approx(lib_dt, rel=1e-12)
+    assert G["dt_barrier"] <= lib_dt
