@@ -725,6 +725,7 @@ def headline(ctx, W, dt, args):
         interval(sim, W, dt)
         n_pre += 1
     ctx.set_graphs(True)
+    n_tiles0 = sim.counters()[0]  # DoF-updates by the tile kernel start here
     for _ in range(args.warmup):
         interval(sim, W, dt)
     torch.cuda.synchronize()
@@ -744,8 +745,10 @@ def headline(ctx, W, dt, args):
     wall = time.perf_counter() - w0
     n1, t_sim1 = sim.counters()
     leaves1 = sim.n_leaves
-    # kernel timing pass: HIP events around the barriers of each interval
-    # after its first (only substep launches run between them)
+    # kernel timing pass: HIP events on the library's stream around the
+    # barriers of each interval after its first (only substep launches run
+    # between them; an event pair around every launch would add its own
+    # gaps, about 2.5 us per launch)
     k_ms, k_launch, k_dof = 0.0, 0, 0
     for _ in range(args.profile_steps):
         sim.ctx.batch_adapt([sim], W["tau_refine"], W["tau_coarsen"], [dt])
@@ -754,6 +757,7 @@ def headline(ctx, W, dt, args):
         k_ms += ms
         k_dof += nd
         k_launch += launches_per_barrier(sim) * nb_k
+    n_tiles1 = sim.counters()[0]
     progress(f"amr_2d window done: {args.steps} intervals in {wall:.2f} s, t = {t_sim1:.3f} ms")
     achieved = BYTES_PER_DOF_Q1_2D_F32 * k_dof / (k_ms * 1e-3) / 1e9 if k_ms > 0 else 0.0
     alg_per_launch = BYTES_PER_DOF_Q1_2D_F32 * k_dof / max(k_launch, 1)
@@ -762,7 +766,10 @@ def headline(ctx, W, dt, args):
         "window": {"preamble_ms": args.preamble_ms, "preamble_intervals": n_pre, "warmup_intervals": args.warmup,
                    "t_sim_ms": [t_sim0, t_sim1], "leaves": [leaves0, leaves1], "level_hist_at_start": hist0},
         "kernel_only": {"value": k_dof / (k_ms * 1e-3) if k_ms > 0 else None, "unit": "DoF-updates/s",
-                        "substep_ms": k_ms, "launches": k_launch, "profile_steps": args.profile_steps},
+                        "substep_ms": k_ms, "launches": k_launch, "profile_steps": args.profile_steps,
+                        "timing": "HIP events around the barriers of the profile pass (launches and the gaps "
+                                  "between them)",
+                        "tile_kernel_dof_updates": n_tiles1 - n_tiles0},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic_per_launch("k_substep_batch<2,1,float,false>", alg_per_launch),
