@@ -57,16 +57,18 @@ BYTES_PER_DOF_Q1_2D_F32 = bytes_per_dof(2, 1)  # 21 B
 # FETCH_SIZE and WRITE_SIZE summed over every dispatch of a kernel in a run of
 # this script, each counter scaled by what it reads for a plain device copy of
 # known size (`--copy-probe`), divided by the algorithmic bytes of the same
-# dispatches (the "dispatch_totals" this script prints).  An entry is used only
-# while the kernel source still has the digest it was measured with.
+# dispatches (amr_2d: the window's tile-kernel DoF-updates, which
+# `--headline-only` prints; batched: the "dispatch_totals").  An entry is used
+# only while the kernel source still has the digest it was measured with.
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2310_07607_amd", "csrc", "kernels.hpp")
 FETCH_SCALE = 2.0   # copy of 256 MiB: FETCH_SIZE reads 128.0 MiB
 WRITE_SCALE = 1.0   # copy of 256 MiB: WRITE_SIZE reads 256.0 MiB
 MEASURED_TRAFFIC = {
-    # amr_2d workload, all dispatches of the kernel in a 100 + 20 + 5 interval run
-    "k_substep_batch<2,1,float,false>": {"digest": "ee226e95625cea2a", "hbm_over_algorithmic": 1.291},
-    # batched workload, the four FP32 variants weighted by algorithmic bytes
-    "k_substep_batch": {"digest": "ee226e95625cea2a", "hbm_over_algorithmic": 1.121},
+    # amr_2d window (`bench.py --headline-only`), every dispatch of the kernel
+    "k_substep_batch<2,1,float,false>": {"digest": "bcf7545a757e63f2", "hbm_over_algorithmic": 1.244},
+    # batched workload (`bench.py --batched-only --no-cpu-baseline`), the four
+    # FP32 variants weighted by algorithmic bytes
+    "k_substep_batch": {"digest": "bcf7545a757e63f2", "hbm_over_algorithmic": 1.122},
 }
 
 
