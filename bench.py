@@ -611,7 +611,8 @@ def slab_leg(ctx, args):
            "kernel_only": {"value": k_dof / (k_ms * 1e-3), "achieved_GBps": bpd * k_dof / (k_ms * 1e-3) / 1e9,
                            "kernel": "k_substep_batch<3,2,float,false>", "bytes_per_dof_update": bpd},
            "state_bytes_fp32": 12 * sim.n_dof,
-           "note": "working set below the 256 MB Infinity Cache: a cache-resident rate, not an HBM roofline"}
+           "note": "the FP32 state is about the size of the 256 MB Infinity Cache, so part of each substep's "
+                   "reads hit it: a cache-assisted rate, not an HBM roofline"}
     sim.close()
     return out
 
