@@ -212,10 +212,10 @@ mdlts_status mdlts_batch_step(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sims
  * work and results as mdlts_indicator (no readback), mdlts_adapt (with the
  * device indicator) and mdlts_assign_levels(dt_barrier[q]) in sequence, with
  * two host synchronisations for all simulations together instead of several
- * per simulation; the simulations' device work runs side by side on up to
- * three internal streams, forked from the context stream and joined back to
- * it before each synchronisation.  sims as for mdlts_batch_step;
- * dt_barrier [n_sims].
+ * per simulation.  With two or more simulations each step of the sequence
+ * is one launch per kernel variant over all of them (the per-simulation
+ * arguments go to the device as tables, one copy per half), all on the
+ * context stream.  sims as for mdlts_batch_step; dt_barrier [n_sims].
  * Returns the first error of any simulation (EUNSTABLE: non-finite
  * indicator or a leaf beyond the levels; that simulation's levels are then
  * invalid); the others are still processed. */

@@ -15,6 +15,7 @@
 #include <cstdint>
 
 #include "kernels.hpp"
+#include "multi.hpp"
 
 namespace mdlts {
 
@@ -82,11 +83,11 @@ __device__ __forceinline__ int find_containing(const MeshGeo &g, const int *root
 }
 
 template <int DIM>
-__global__ __launch_bounds__(256) void k_mesh_index(int E, int n_roots, const MeshGeo g,
+__device__ __forceinline__ void mesh_index_body(const int blk, int E, int n_roots, const MeshGeo g,
                                                     const typename KeyOf<DIM>::type *key, int *root_start,
                                                     uint32_t *mkey)
 {
-    const int e = blockIdx.x * 256 + threadIdx.x;
+    const int e = blk * 256 + threadIdx.x;
     if (e >= E) return;
     int d;
     uint32_t c[3] = {0, 0, 0};
@@ -104,9 +105,32 @@ __global__ __launch_bounds__(256) void k_mesh_index(int E, int n_roots, const Me
     if (e == E - 1) root_start[n_roots] = E;
 }
 
+template <int DIM>
+__global__ __launch_bounds__(256) void k_mesh_index(int E, int n_roots, const MeshGeo g,
+                                                    const typename KeyOf<DIM>::type *key, int *root_start,
+                                                    uint32_t *mkey)
+{
+    mesh_index_body<DIM>(blockIdx.x, E, n_roots, g, key, root_start, mkey);
+}
+
+// its arguments, for a launch over many simulations (k_multi)
+template <int DIM>
+struct MeshIndexOp {
+    int E;
+    int n_roots;
+    MeshGeo g;
+    const typename KeyOf<DIM>::type *key;
+    int *root_start;
+    uint32_t *mkey;
+    __device__ __forceinline__ void operator()(const int blk) const
+    {
+        mesh_index_body<DIM>(blk, E, n_roots, g, key, root_start, mkey);
+    }
+};
+
 // face table of every leaf; *bad is set if the forest is not 2:1 balanced
 template <int DIM>
-__global__ __launch_bounds__(256) void k_mesh_faces(int E, const MeshGeo g, const typename KeyOf<DIM>::type *key,
+__device__ __forceinline__ void mesh_faces_body(const int blk, int E, const MeshGeo g, const typename KeyOf<DIM>::type *key,
                                                     const int *root_start, const uint32_t *mkey, uint32_t *face,
                                                     uint32_t *fine, int *bad)
 {
@@ -114,7 +138,7 @@ __global__ __launch_bounds__(256) void k_mesh_faces(int E, const MeshGeo g, cons
     // one thread per (face, element): face f = 2k + s of element e, elements
     // fastest, so that the key loads and the table stores are coalesced and
     // the faces' neighbour searches run side by side
-    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long i = (long long)blk * 256 + threadIdx.x;
     if (i >= 2ll * DIM * E) return;
     const int f = (int)(i / E);
     const int e = (int)(i - (long long)f * E);
@@ -160,30 +184,95 @@ __global__ __launch_bounds__(256) void k_mesh_faces(int E, const MeshGeo g, cons
     }
 }
 
+template <int DIM>
+__global__ __launch_bounds__(256) void k_mesh_faces(int E, const MeshGeo g, const typename KeyOf<DIM>::type *key,
+                                                    const int *root_start, const uint32_t *mkey, uint32_t *face,
+                                                    uint32_t *fine, int *bad)
+{
+    mesh_faces_body<DIM>(blockIdx.x, E, g, key, root_start, mkey, face, fine, bad);
+}
+
+// its arguments, for a launch over many simulations (k_multi)
+template <int DIM>
+struct MeshFacesOp {
+    int E;
+    MeshGeo g;
+    const typename KeyOf<DIM>::type *key;
+    const int *root_start;
+    const uint32_t *mkey;
+    uint32_t *face;
+    uint32_t *fine;
+    int *bad;
+    __device__ __forceinline__ void operator()(const int blk) const
+    {
+        mesh_faces_body<DIM>(blk, E, g, key, root_start, mkey, face, fine, bad);
+    }
+};
+
 // ---- adaptation ------------------------------------------------------------
 template <int DIM>
-__global__ __launch_bounds__(256) void k_amr_mark(int E, const MeshGeo g, const typename KeyOf<DIM>::type *key,
+__device__ __forceinline__ void amr_mark_body(const int blk, int E, const MeshGeo g, const typename KeyOf<DIM>::type *key,
                                                   const double *eta, double tau_refine, uint8_t *refine)
 {
-    const int e = blockIdx.x * 256 + threadIdx.x;
+    const int e = blk * 256 + threadIdx.x;
     if (e >= E) return;
     const int d = (int)(key[e] & 15);
     refine[e] = (eta[e] >= tau_refine && d < g.max_depth) ? 1 : 0;
 }
 
+template <int DIM>
+__global__ __launch_bounds__(256) void k_amr_mark(int E, const MeshGeo g, const typename KeyOf<DIM>::type *key,
+                                                  const double *eta, double tau_refine, uint8_t *refine)
+{
+    amr_mark_body<DIM>(blockIdx.x, E, g, key, eta, tau_refine, refine);
+}
+
+// its arguments, for a launch over many simulations (k_multi)
+template <int DIM>
+struct AmrMarkOp {
+    int E;
+    MeshGeo g;
+    const typename KeyOf<DIM>::type *key;
+    const double *eta;
+    double tau_refine;
+    uint8_t *refine;
+    __device__ __forceinline__ void operator()(const int blk) const
+    {
+        amr_mark_body<DIM>(blk, E, g, key, eta, tau_refine, refine);
+    }
+};
+
 // one pass of the 2:1 closure: a leaf being refined marks its coarser face
 // neighbours (every chain of such marks descends one depth per step, so
 // max_depth passes reach the least fixed point)
 template <int DIM>
-__global__ __launch_bounds__(256) void k_amr_close(int E, const uint32_t *face, uint8_t *refine)
+__device__ __forceinline__ void amr_close_body(const int blk, int E, const uint32_t *face, uint8_t *refine)
 {
-    const int e = blockIdx.x * 256 + threadIdx.x;
+    const int e = blk * 256 + threadIdx.x;
     if (e >= E || !refine[e]) return;
     for (int f = 0; f < 2 * DIM; f++) {
         const uint32_t ent = face[(long long)f * E + e];
         if ((ent >> 30) == kCoarser) refine[ent & kIdMask30] = 1;
     }
 }
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_amr_close(int E, const uint32_t *face, uint8_t *refine)
+{
+    amr_close_body<DIM>(blockIdx.x, E, face, refine);
+}
+
+// its arguments, for a launch over many simulations (k_multi)
+template <int DIM>
+struct AmrCloseOp {
+    int E;
+    const uint32_t *face;
+    uint8_t *refine;
+    __device__ __forceinline__ void operator()(const int blk) const
+    {
+        amr_close_body<DIM>(blk, E, face, refine);
+    }
+};
 
 template <int DIM>
 __device__ __forceinline__ bool sibling_of(typename KeyOf<DIM>::type a, typename KeyOf<DIM>::type b)
@@ -211,12 +300,12 @@ __device__ __forceinline__ int child_index(typename KeyOf<DIM>::type a)
 
 // first child of a complete sibling group that may be coarsened
 template <int DIM>
-__global__ __launch_bounds__(256) void k_amr_coarsen(int E, const typename KeyOf<DIM>::type *key, const double *eta,
+__device__ __forceinline__ void amr_coarsen_body(const int blk, int E, const typename KeyOf<DIM>::type *key, const double *eta,
                                                      double tau_coarsen, const uint8_t *refine, const uint32_t *face,
                                                      uint8_t *cflag)
 {
     constexpr int NK = 1 << DIM;
-    const int e = blockIdx.x * 256 + threadIdx.x;
+    const int e = blk * 256 + threadIdx.x;
     if (e >= E) return;
     bool ok = (key[e] & 15) > 0 && child_index<DIM>(key[e]) == 0 && e + NK <= E;
     for (int j = 1; j < NK && ok; j++) ok = sibling_of<DIM>(key[e], key[e + j]) && child_index<DIM>(key[e + j]) == j;
@@ -237,16 +326,40 @@ __global__ __launch_bounds__(256) void k_amr_coarsen(int E, const typename KeyOf
     cflag[e] = ok ? 1 : 0;
 }
 
+template <int DIM>
+__global__ __launch_bounds__(256) void k_amr_coarsen(int E, const typename KeyOf<DIM>::type *key, const double *eta,
+                                                     double tau_coarsen, const uint8_t *refine, const uint32_t *face,
+                                                     uint8_t *cflag)
+{
+    amr_coarsen_body<DIM>(blockIdx.x, E, key, eta, tau_coarsen, refine, face, cflag);
+}
+
+// its arguments, for a launch over many simulations (k_multi)
+template <int DIM>
+struct AmrCoarsenOp {
+    int E;
+    const typename KeyOf<DIM>::type *key;
+    const double *eta;
+    double tau_coarsen;
+    const uint8_t *refine;
+    const uint32_t *face;
+    uint8_t *cflag;
+    __device__ __forceinline__ void operator()(const int blk) const
+    {
+        amr_coarsen_body<DIM>(blk, E, key, eta, tau_coarsen, refine, face, cflag);
+    }
+};
+
 
 template <int DIM>
-__global__ __launch_bounds__(256) void k_amr_emit(int E, const typename KeyOf<DIM>::type *key, const uint8_t *refine,
+__device__ __forceinline__ void amr_emit_body(const int blk, int E, const typename KeyOf<DIM>::type *key, const uint8_t *refine,
                                                   const uint8_t *cflag, const int *cnt, const int *off,
                                                   const int *block_off, typename KeyOf<DIM>::type *key_new,
                                                   uint8_t *xkind, int32_t *xsrc, uint8_t *xchild)
 {
     // off: exclusive scan of cnt within blocks of 1024 leaves; block_off:
     // exclusive scan of the blocks' totals
-    const int e = blockIdx.x * 256 + threadIdx.x;
+    const int e = blk * 256 + threadIdx.x;
     if (e >= E || cnt[e] == 0) return;
     int d;
     uint32_t c[3] = {0, 0, 0};
@@ -275,6 +388,35 @@ __global__ __launch_bounds__(256) void k_amr_emit(int E, const typename KeyOf<DI
         xchild[o] = 0;
     }
 }
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_amr_emit(int E, const typename KeyOf<DIM>::type *key, const uint8_t *refine,
+                                                  const uint8_t *cflag, const int *cnt, const int *off,
+                                                  const int *block_off, typename KeyOf<DIM>::type *key_new,
+                                                  uint8_t *xkind, int32_t *xsrc, uint8_t *xchild)
+{
+    amr_emit_body<DIM>(blockIdx.x, E, key, refine, cflag, cnt, off, block_off, key_new, xkind, xsrc, xchild);
+}
+
+// its arguments, for a launch over many simulations (k_multi)
+template <int DIM>
+struct AmrEmitOp {
+    int E;
+    const typename KeyOf<DIM>::type *key;
+    const uint8_t *refine;
+    const uint8_t *cflag;
+    const int *cnt;
+    const int *off;
+    const int *block_off;
+    typename KeyOf<DIM>::type *key_new;
+    uint8_t *xkind;
+    int32_t *xsrc;
+    uint8_t *xchild;
+    __device__ __forceinline__ void operator()(const int blk) const
+    {
+        amr_emit_body<DIM>(blk, E, key, refine, cflag, cnt, off, block_off, key_new, xkind, xsrc, xchild);
+    }
+};
 
 // ---- exclusive scan of int counts (1024 items per block) --------------------
 __device__ __forceinline__ int wave_incl_scan(int v)
@@ -315,12 +457,12 @@ __device__ __forceinline__ int block_excl_scan4(int *x4)
 // refine/coarsen tallies, and their block-local exclusive scan, in one
 // launch: each thread counts four consecutive leaves, then the block scans.
 template <int DIM>
-__global__ __launch_bounds__(256) void k_amr_count_scan(int E, const typename KeyOf<DIM>::type *key,
+__device__ __forceinline__ void amr_count_scan_body(const int blk, int E, const typename KeyOf<DIM>::type *key,
                                                         const uint8_t *refine, const uint8_t *cflag, int *cnt,
                                                         int *off, int *block_sums, unsigned long long *tallies)
 {
     int x[4];
-    const long long base = (long long)blockIdx.x * 1024 + threadIdx.x * 4;
+    const long long base = (long long)blk * 1024 + threadIdx.x * 4;
     for (int q = 0; q < 4; q++) {
         const long long el = base + q;
         int n = 0;
@@ -343,11 +485,36 @@ __global__ __launch_bounds__(256) void k_amr_count_scan(int E, const typename Ke
     const int tot = block_excl_scan4(x);
     for (int q = 0; q < 4; q++)
         if (base + q < E) off[base + q] = x[q];
-    if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+    if (threadIdx.x == 0) block_sums[blk] = tot;
 }
 
+template <int DIM>
+__global__ __launch_bounds__(256) void k_amr_count_scan(int E, const typename KeyOf<DIM>::type *key,
+                                                        const uint8_t *refine, const uint8_t *cflag, int *cnt,
+                                                        int *off, int *block_sums, unsigned long long *tallies)
+{
+    amr_count_scan_body<DIM>(blockIdx.x, E, key, refine, cflag, cnt, off, block_sums, tallies);
+}
+
+// its arguments, for a launch over many simulations (k_multi)
+template <int DIM>
+struct AmrCountScanOp {
+    int E;
+    const typename KeyOf<DIM>::type *key;
+    const uint8_t *refine;
+    const uint8_t *cflag;
+    int *cnt;
+    int *off;
+    int *block_sums;
+    unsigned long long *tallies;
+    __device__ __forceinline__ void operator()(const int blk) const
+    {
+        amr_count_scan_body<DIM>(blk, E, key, refine, cflag, cnt, off, block_sums, tallies);
+    }
+};
+
 // one block scans the block sums in chunks of 1024; total to *total
-__global__ __launch_bounds__(256) void k_scan_sums(int nb, int *sums, int *total)
+__device__ __forceinline__ void scan_sums_body(const int blk, int nb, int *sums, int *total)
 {
     __shared__ int carry;
     if (threadIdx.x == 0) carry = 0;
@@ -366,5 +533,21 @@ __global__ __launch_bounds__(256) void k_scan_sums(int nb, int *sums, int *total
     }
     if (threadIdx.x == 0) *total = carry;
 }
+
+__global__ __launch_bounds__(256) void k_scan_sums(int nb, int *sums, int *total)
+{
+    scan_sums_body(blockIdx.x, nb, sums, total);
+}
+
+// its arguments, for a launch over many simulations (k_multi)
+struct ScanSumsOp {
+    int nb;
+    int *sums;
+    int *total;
+    __device__ __forceinline__ void operator()(const int blk) const
+    {
+        scan_sums_body(blk, nb, sums, total);
+    }
+};
 
 }  // namespace mdlts

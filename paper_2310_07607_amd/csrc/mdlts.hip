@@ -7,7 +7,9 @@
 #include <cmath>
 #include <cstddef>
 #include <cstring>
+#include <functional>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -60,14 +62,15 @@ struct LevelArgs {
     int *bad;       // set if some leaf needs more levels than configured
 };
 
-template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_levels(const LevelArgs a)
+template <int DIM, typename A = LevelArgs>
+// (A: the arguments by value from a kernel parameter, by reference from an op table)
+__device__ __forceinline__ void levels_body(const int blk, A a)
 {
 #pragma clang fp contract(off)
     __shared__ int sh[kMaxLevels];
     if (threadIdx.x < kMaxLevels) sh[threadIdx.x] = 0;
     __syncthreads();
-    const int e = blockIdx.x * kBlock + threadIdx.x;
+    const int e = blk * kBlock + threadIdx.x;
     if (e < a.E) {
         int depth;
         uint32_t c[3];
@@ -103,8 +106,24 @@ __global__ __launch_bounds__(kBlock) void k_levels(const LevelArgs a)
         atomicAdd(&sh[b], 1);
     }
     __syncthreads();
-    if (threadIdx.x < kMaxLevels) a.hist[blockIdx.x * kMaxLevels + threadIdx.x] = sh[threadIdx.x];
+    if (threadIdx.x < kMaxLevels) a.hist[blk * kMaxLevels + threadIdx.x] = sh[threadIdx.x];
 }
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_levels(const LevelArgs a)
+{
+    levels_body<DIM>(blockIdx.x, a);
+}
+
+// its arguments, for a launch over many simulations (k_multi)
+template <int DIM>
+struct LevelsOp {
+    LevelArgs a;
+    __device__ __forceinline__ void operator()(const int blk) const
+    {
+        levels_body<DIM, const LevelArgs &>(blk, a);
+    }
+};
 
 // smallest of n positive doubles: wavefront minimum, one atomic per wave
 // (for positive doubles the bit patterns order like the values)
@@ -117,7 +136,7 @@ __global__ __launch_bounds__(kBlock) void k_min_positive(int n, const double *x,
 }
 
 // exclusive offsets of every (block, level) in the finest-first order
-__global__ __launch_bounds__(kBlock) void k_level_scan(int *hist, int nb, int n_levels, int *cnt_ge, int *cnt_ge2)
+__device__ __forceinline__ void level_scan_body(const int blk, int *hist, int nb, int n_levels, int *cnt_ge, int *cnt_ge2)
 {
     __shared__ int wtot[kBlock / 64][kMaxLevels];
     __shared__ int base[kMaxLevels];
@@ -168,13 +187,31 @@ __global__ __launch_bounds__(kBlock) void k_level_scan(int *hist, int nb, int n_
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_level_scan(int *hist, int nb, int n_levels, int *cnt_ge, int *cnt_ge2)
+{
+    level_scan_body(blockIdx.x, hist, nb, n_levels, cnt_ge, cnt_ge2);
+}
+
+// its arguments, for a launch over many simulations (k_multi)
+struct LevelScanOp {
+    int *hist;
+    int nb;
+    int n_levels;
+    int *cnt_ge;
+    int *cnt_ge2;
+    __device__ __forceinline__ void operator()(const int blk) const
+    {
+        level_scan_body(blk, hist, nb, n_levels, cnt_ge, cnt_ge2);
+    }
+};
+
 // position of every element: block offset + rank among equal levels inside
 // the block (wavefront ballots keep the canonical order: stable)
-__global__ __launch_bounds__(kBlock) void k_level_scatter(const uint8_t *level, int E, const int *off, int *perm,
+__device__ __forceinline__ void level_scatter_body(const int blk, const uint8_t *level, int E, const int *off, int *perm,
                                                           int *inv)
 {
     __shared__ int wcount[kBlock / 64][kMaxLevels];
-    const int e = blockIdx.x * kBlock + threadIdx.x;
+    const int e = blk * kBlock + threadIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int l = e < E ? level[e] : -1;
     int rank = 0;
@@ -185,20 +222,39 @@ __global__ __launch_bounds__(kBlock) void k_level_scatter(const uint8_t *level, 
     }
     __syncthreads();
     if (e < E) {
-        int pos = off[blockIdx.x * kMaxLevels + l] + rank;
+        int pos = off[blk * kMaxLevels + l] + rank;
         for (int w = 0; w < wave; w++) pos += wcount[w][l];
         perm[pos] = e;
         inv[e] = pos;
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_level_scatter(const uint8_t *level, int E, const int *off, int *perm,
+                                                          int *inv)
+{
+    level_scatter_body(blockIdx.x, level, E, off, perm, inv);
+}
+
+// its arguments, for a launch over many simulations (k_multi)
+struct LevelScatterOp {
+    const uint8_t *level;
+    int E;
+    const int *off;
+    int *perm;
+    int *inv;
+    __device__ __forceinline__ void operator()(const int blk) const
+    {
+        level_scatter_body(blk, level, E, off, perm, inv);
+    }
+};
+
 template <typename KT, int NS>
-__global__ __launch_bounds__(kBlock) void k_remap(int E, int nfaces, const int *perm, const int *inv,
+__device__ __forceinline__ void remap_body(const int blk, int E, int nfaces, const int *perm, const int *inv,
                                                   const uint8_t *level, const KT *key_c, const uint32_t *face_c,
                                                   const uint32_t *fine_c, KT *key_s, uint32_t *nbr_s,
                                                   uint32_t *fine_s, int cap)
 {
-    const int j = blockIdx.x * kBlock + threadIdx.x;
+    const int j = blk * kBlock + threadIdx.x;
     if (j >= E) return;
     const int e = perm[j];
     key_s[j] = key_c[e];
@@ -219,12 +275,42 @@ __global__ __launch_bounds__(kBlock) void k_remap(int E, int nfaces, const int *
     }
 }
 
+template <typename KT, int NS>
+__global__ __launch_bounds__(kBlock) void k_remap(int E, int nfaces, const int *perm, const int *inv,
+                                                  const uint8_t *level, const KT *key_c, const uint32_t *face_c,
+                                                  const uint32_t *fine_c, KT *key_s, uint32_t *nbr_s,
+                                                  uint32_t *fine_s, int cap)
+{
+    remap_body<KT, NS>(blockIdx.x, E, nfaces, perm, inv, level, key_c, face_c, fine_c, key_s, nbr_s, fine_s, cap);
+}
+
+// its arguments, for a launch over many simulations (k_multi)
+template <typename KT, int NS>
+struct RemapOp {
+    int E;
+    int nfaces;
+    const int *perm;
+    const int *inv;
+    const uint8_t *level;
+    const KT *key_c;
+    const uint32_t *face_c;
+    const uint32_t *fine_c;
+    KT *key_s;
+    uint32_t *nbr_s;
+    uint32_t *fine_s;
+    int cap;
+    __device__ __forceinline__ void operator()(const int blk) const
+    {
+        remap_body<KT, NS>(blk, E, nfaces, perm, inv, level, key_c, face_c, fine_c, key_s, nbr_s, fine_s, cap);
+    }
+};
+
 // canonical [np][E] -> grouped slot 0 [np][cap]
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_permute(int E, int np, int cap, const int *perm, const T *uc, const T *vc,
+__device__ __forceinline__ void permute_body(const int blk, int E, int np, int cap, const int *perm, const T *uc, const T *vc,
                                                     T *us, T *vs)
 {
-    const int j = blockIdx.x * kBlock + threadIdx.x;
+    const int j = blk * kBlock + threadIdx.x;
     if (j >= E) return;
     const int e = perm[j];
     for (int n = 0; n < np; n++) {
@@ -233,16 +319,40 @@ __global__ __launch_bounds__(kBlock) void k_permute(int E, int np, int cap, cons
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_permute(int E, int np, int cap, const int *perm, const T *uc, const T *vc,
+                                                    T *us, T *vs)
+{
+    permute_body<T>(blockIdx.x, E, np, cap, perm, uc, vc, us, vs);
+}
+
+// its arguments, for a launch over many simulations (k_multi)
+template <typename T>
+struct PermuteOp {
+    int E;
+    int np;
+    int cap;
+    const int *perm;
+    const T *uc;
+    const T *vc;
+    T *us;
+    T *vs;
+    __device__ __forceinline__ void operator()(const int blk) const
+    {
+        permute_body<T>(blk, E, np, cap, perm, uc, vc, us, vs);
+    }
+};
+
 // grouped current slot -> canonical [np][E] (at a barrier)
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_gather(int E, int np, int cap, long long slot_stride, const int *perm,
+__device__ __forceinline__ void gather_body(const int blk, int E, int np, int cap, long long slot_stride, const int *perm,
                                                    const int *cnt_ge, int parity, const T *us, const T *vs, T *uc,
                                                    T *vc, int *zero32)
 {
     // (zero32, if given: 32 ints cleared by the first block, for the
     // kernels that follow on the stream)
-    if (zero32 && blockIdx.x == 0 && threadIdx.x < 32) zero32[threadIdx.x] = 0;
-    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (zero32 && blk == 0 && threadIdx.x < 32) zero32[threadIdx.x] = 0;
+    const int j = blk * kBlock + threadIdx.x;
     if (j >= E) return;
     // level-0 elements sit at the end of the grouped order
     const bool lvl0 = j >= cnt_ge[1];
@@ -253,6 +363,35 @@ __global__ __launch_bounds__(kBlock) void k_gather(int E, int np, int cap, long 
         if (vc) vc[(long long)n * E + e] = vs[(long long)n * cap + j];
     }
 }
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gather(int E, int np, int cap, long long slot_stride, const int *perm,
+                                                   const int *cnt_ge, int parity, const T *us, const T *vs, T *uc,
+                                                   T *vc, int *zero32)
+{
+    gather_body<T>(blockIdx.x, E, np, cap, slot_stride, perm, cnt_ge, parity, us, vs, uc, vc, zero32);
+}
+
+// its arguments, for a launch over many simulations (k_multi)
+template <typename T>
+struct GatherOp {
+    int E;
+    int np;
+    int cap;
+    long long slot_stride;
+    const int *perm;
+    const int *cnt_ge;
+    int parity;
+    const T *us;
+    const T *vs;
+    T *uc;
+    T *vc;
+    int *zero32;
+    __device__ __forceinline__ void operator()(const int blk) const
+    {
+        gather_body<T>(blk, E, np, cap, slot_stride, perm, cnt_ge, parity, us, vs, uc, vc, zero32);
+    }
+};
 
 // clears n 32-bit words (a kernel rather than a memset, so that the
 // clearing is an ordinary kernel node if the caller captures the stream)
@@ -340,13 +479,14 @@ __device__ __forceinline__ void tangential_jump(const IndArgs &a, const RefConst
     }
 }
 
-template <int DIM, int P, typename T, bool FULL>
-__global__ __launch_bounds__(kBlock) void k_indicator(const IndArgs a)
+template <int DIM, int P, typename T, bool FULL, typename A = IndArgs>
+// (A: the arguments by value from a kernel parameter, by reference from an op table)
+__device__ __forceinline__ void indicator_body(const int blk, A a)
 {
     using S = Shape<DIM, P>;
     constexpr int M = S::M, NF = S::NF, NS = S::NS;
     constexpr RefConst R = ref_const(P);
-    const int e = blockIdx.x * kBlock + threadIdx.x;
+    const int e = blk * kBlock + threadIdx.x;
     double eta = 0.0;
     if (e < a.E) {
         int depth;
@@ -452,6 +592,22 @@ __global__ __launch_bounds__(kBlock) void k_indicator(const IndArgs a)
     if ((threadIdx.x & 63) == 0) atomicMax(a.eta_max_bits, (unsigned long long)__double_as_longlong(m));
 }
 
+template <int DIM, int P, typename T, bool FULL>
+__global__ __launch_bounds__(kBlock) void k_indicator(const IndArgs a)
+{
+    indicator_body<DIM, P, T, FULL>(blockIdx.x, a);
+}
+
+// its arguments, for a launch over many simulations (k_multi)
+template <int DIM, int P, typename T, bool FULL>
+struct IndicatorOp {
+    IndArgs a;
+    __device__ __forceinline__ void operator()(const int blk) const
+    {
+        indicator_body<DIM, P, T, FULL, const IndArgs &>(blk, a);
+    }
+};
+
 // ---------------------------------------------------------------------------
 // RV-T temporal indicator (Sec. 2.3): per element, over a barrier [t_a, t_b],
 // the L2 norms over [t_a, t_b] x e of the changes of the ionic current I and
@@ -556,12 +712,13 @@ struct XferArgs {
     DevRef<double> ref;
 };
 
-template <int DIM, int P, typename T>
-__global__ __launch_bounds__(kBlock) void k_transfer(const XferArgs a)
+template <int DIM, int P, typename T, typename A = XferArgs>
+// (A: the arguments by value from a kernel parameter, by reference from an op table)
+__device__ __forceinline__ void transfer_body(const int blk, A a)
 {
     using S = Shape<DIM, P>;
     constexpr int M = S::M, NP = S::NP;
-    const int e = blockIdx.x * kBlock + threadIdx.x;
+    const int e = blk * kBlock + threadIdx.x;
     if (e >= a.E_new) return;
     const int kind = a.kind[e], src = a.src[e], ci = a.child[e];
     for (int f = 0; f < 2; f++) {
@@ -591,6 +748,22 @@ __global__ __launch_bounds__(kBlock) void k_transfer(const XferArgs a)
         }
     }
 }
+
+template <int DIM, int P, typename T>
+__global__ __launch_bounds__(kBlock) void k_transfer(const XferArgs a)
+{
+    transfer_body<DIM, P, T>(blockIdx.x, a);
+}
+
+// its arguments, for a launch over many simulations (k_multi)
+template <int DIM, int P, typename T>
+struct TransferOp {
+    XferArgs a;
+    __device__ __forceinline__ void operator()(const int blk) const
+    {
+        transfer_body<DIM, P, T, const XferArgs &>(blk, a);
+    }
+};
 
 inline int nblocks(long long n) { return (int)((n + kBlock - 1) / kBlock); }
 
@@ -633,12 +806,12 @@ mdlts_status scratch_address(int device, void **out)
 // ---------------------------------------------------------------------------
 // context and simulation objects
 // ---------------------------------------------------------------------------
+struct BatchPlan;
+
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
 };
-
-struct BatchPlan;
 
 struct mdlts_ctx {
     int device = 0;
@@ -663,14 +836,18 @@ struct mdlts_ctx {
     void *stage = nullptr;
     size_t stage_bytes = 0;
     hipEvent_t stage_done = nullptr;
-    // auxiliary streams of the adaptation of several simulations, and the
-    // events that fork them from the context stream and join them back
-    std::vector<hipStream_t> aux;
-    hipEvent_t fork_ev = nullptr;
-    std::vector<hipEvent_t> join_ev;
     // completed synchronisations of the stream: work enqueued before the
     // last one has finished
     uint64_t sync_epoch = 0;
+    // launches over many simulations: their op tables (pinned staging and the
+    // device copy), and the flags blocks of every simulation collected for one
+    // readback
+    void *multi_host = nullptr;
+    size_t multi_host_bytes = 0;
+    DevBuf multi_dev;
+    void *flags_host = nullptr;
+    size_t flags_host_bytes = 0;
+    DevBuf flags_dev;
 };
 
 // Host-visible staging of a simulation's small readbacks (pinned memory, so
@@ -2052,59 +2229,522 @@ mdlts_status prepare_plan(mdlts_ctx *c, BatchPlan *&slot, mdlts_sim *const *sims
     return build_plan_data(c, *P);
 }
 
-// The adaptation work of several simulations side by side: simulation q's
-// work of a phase goes to auxiliary stream q mod kAuxStreams, which starts
-// after everything enqueued on the context stream before the phase (an
-// event) and which the context stream waits for at the phase's end.  Within
-// a phase the streams share no buffer: every buffer a phase frees (when it
-// grows) was last used before the phase began, and what it allocates
-// belongs to one simulation.
-constexpr int kAuxStreams = 3;  // with the context stream, one per hardware queue HIP gives a process by default (4)
+// ---------------------------------------------------------------------------
+// adaptation of many simulations with one launch per step and kernel variant
+// ---------------------------------------------------------------------------
+// a simulation's flags block: cleared, or copied to its row of the
+// collection buffer (one block each)
+struct ClearFlagsOp {
+    int *flags;
+    __device__ __forceinline__ void operator()(const int) const
+    {
+        if (threadIdx.x < kFlagBytes / sizeof(int)) flags[threadIdx.x] = 0;
+    }
+};
+struct CopyFlagsOp {
+    const int *flags;
+    int *row;
+    __device__ __forceinline__ void operator()(const int) const
+    {
+        if (threadIdx.x < kFlagBytes / sizeof(int)) row[threadIdx.x] = flags[threadIdx.x];
+    }
+};
 
-struct AuxStreams {
-    mdlts_ctx *c;
-    hipStream_t main;
-    int n = 0;            // streams in use (0: the phase runs on the context stream)
-    bool forked = false;  // an error return still joins the streams
-    AuxStreams(mdlts_ctx *c_, int n_sims)
-        : c(c_), main(c_->stream), n(n_sims > 1 ? std::min(n_sims, kAuxStreams) : 0)
+// The launches of one phase over many simulations.  Ops added between two
+// step() calls form one step: one k_multi launch per op type (kernel
+// variant), which the simulations' data keep independent; the steps run in
+// order on the context stream.  run() sends every op table of the phase to
+// the device in one copy before the first launch.
+class MultiPhase {
+    struct AnyBatch {
+        virtual ~AnyBatch() = default;
+        virtual void emit(MultiPhase &m) = 0;
+    };
+    template <typename Op>
+    struct TypedBatch : AnyBatch {
+        std::vector<Op> ops;
+        std::vector<int> block0;
+        long long total = 0;
+        void emit(MultiPhase &m) override { m.emit_launch(ops, block0, total); }
+    };
+    template <typename Op>
+    static const void *tag()
     {
+        static const char t = 0;
+        return &t;
     }
-    ~AuxStreams()
+    std::vector<std::pair<const void *, std::unique_ptr<AnyBatch>>> cur_;
+    std::vector<char> table_;
+    std::vector<std::function<void(hipStream_t, char *)>> steps_;
+
+    size_t put(const void *p, size_t bytes)
     {
-        if (forked) (void)join();
-        c->stream = main;
+        const size_t off = (table_.size() + 15) & ~(size_t)15;
+        table_.resize(off + bytes);
+        std::memcpy(table_.data() + off, p, bytes);
+        return off;
     }
-    mdlts_status fork()
+    template <typename Op>
+    void emit_launch(const std::vector<Op> &ops, const std::vector<int> &block0, long long total)
     {
-        if (n == 0) return MDLTS_OK;
-        while ((int)c->aux.size() < n) {
-            hipStream_t st;
-            HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-            c->aux.push_back(st);
-            hipEvent_t e;
-            HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-            c->join_ev.push_back(e);
+        const size_t o_ops = put(ops.data(), ops.size() * sizeof(Op));
+        const size_t o_b0 = put(block0.data(), block0.size() * sizeof(int));
+        const int n = (int)ops.size();
+        const unsigned grid = (unsigned)total;
+        steps_.push_back([=](hipStream_t st, char *dev) {
+            k_multi<Op><<<grid, kBlock, 0, st>>>(reinterpret_cast<const Op *>(dev + o_ops),
+                                                 reinterpret_cast<const int *>(dev + o_b0), n);
+        });
+    }
+
+public:
+    template <typename Op>
+    void add(const Op &op, long long n_blocks)
+    {
+        if (n_blocks <= 0) return;
+        TypedBatch<Op> *t = nullptr;
+        for (auto &e : cur_)
+            if (e.first == tag<Op>()) t = static_cast<TypedBatch<Op> *>(e.second.get());
+        if (!t) {
+            auto u = std::make_unique<TypedBatch<Op>>();
+            t = u.get();
+            cur_.emplace_back(tag<Op>(), std::move(u));
         }
-        if (!c->fork_ev) HIP_TRY(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
-        HIP_TRY(hipEventRecord(c->fork_ev, main));
-        for (int k = 0; k < n; k++) HIP_TRY(hipStreamWaitEvent(c->aux[k], c->fork_ev, 0));
-        forked = true;
-        return MDLTS_OK;
+        t->ops.push_back(op);
+        t->block0.push_back((int)t->total);
+        t->total += n_blocks;
     }
-    void use(int q) { c->stream = n ? c->aux[q % n] : main; }
-    mdlts_status join()
+    void step()
     {
-        c->stream = main;
-        if (!forked) return MDLTS_OK;
-        forked = false;
-        for (int k = 0; k < n; k++) {
-            HIP_TRY(hipEventRecord(c->join_ev[k], c->aux[k]));
-            HIP_TRY(hipStreamWaitEvent(main, c->join_ev[k], 0));
+        for (auto &e : cur_) e.second->emit(*this);
+        cur_.clear();
+    }
+    // work other than launches (copies), in order after the steps so far
+    void then(std::function<void(hipStream_t, char *)> f)
+    {
+        step();
+        steps_.push_back(std::move(f));
+    }
+    mdlts_status run(mdlts_ctx *c)
+    {
+        step();
+        if (steps_.empty()) return MDLTS_OK;
+        const size_t bytes = std::max(table_.size(), (size_t)16);
+        // the staging area is free: every copy out of it precedes the
+        // synchronisation that ended the previous phase
+        if (c->multi_host_bytes < bytes) {
+            if (c->multi_host) (void)hipHostFree(c->multi_host);
+            c->multi_host = nullptr;
+            c->multi_host_bytes = 0;
+            const size_t nb = std::max(bytes + bytes / 4, (size_t)64 << 10);
+            if (hipHostMalloc(&c->multi_host, nb, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                c->multi_host = nullptr;
+                return MDLTS_ENOMEM;
+            }
+            c->multi_host_bytes = nb;
         }
+        if (!table_.empty()) std::memcpy(c->multi_host, table_.data(), table_.size());
+        MD_TRY(dev_alloc(c, c->multi_dev, bytes));
+        HIP_TRY(hipMemcpyAsync(c->multi_dev.p, c->multi_host, bytes, hipMemcpyHostToDevice, c->stream));
+        for (auto &f : steps_) f(c->stream, static_cast<char *>(c->multi_dev.p));
+        HIP_TRY(hipGetLastError());
         return MDLTS_OK;
     }
 };
+
+// every simulation's flags block to its pinned readback (the first `bytes`
+// of it) after the next synchronisation: one collecting launch, one copy
+mdlts_status collect_flags(mdlts_ctx *c, MultiPhase &ph, mdlts_sim *const *sims, const std::vector<int> &which)
+{
+    const size_t row = kFlagBytes;
+    MD_TRY(dev_alloc(c, c->flags_dev, which.size() * row));
+    const size_t bytes = which.size() * row;
+    if (c->flags_host_bytes < bytes) {
+        if (c->flags_host) (void)hipHostFree(c->flags_host);
+        c->flags_host = nullptr;
+        c->flags_host_bytes = 0;
+        const size_t nb = std::max(bytes + bytes / 4, (size_t)16 << 10);
+        if (hipHostMalloc(&c->flags_host, nb, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            c->flags_host = nullptr;
+            return MDLTS_ENOMEM;
+        }
+        c->flags_host_bytes = nb;
+    }
+    for (size_t r = 0; r < which.size(); r++)
+        ph.add(CopyFlagsOp{P<int>(sims[which[r]]->flags), P<int>(c->flags_dev) + r * (row / sizeof(int))}, 1);
+    void *dst = c->flags_host, *src = c->flags_dev.p;
+    ph.then([=](hipStream_t st, char *) { (void)hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st); });
+    return MDLTS_OK;
+}
+
+void distribute_flags(mdlts_ctx *c, mdlts_sim *const *sims, const std::vector<int> &which, size_t bytes)
+{
+    for (size_t r = 0; r < which.size(); r++)
+        std::memcpy(sims[which[r]]->pin, static_cast<char *>(c->flags_host) + r * kFlagBytes, bytes);
+}
+
+// ops of the kernel variants chosen at run time
+template <typename T>
+void add_indicator(MultiPhase &ph, const mdlts_sim *s, const IndArgs &a)
+{
+    const long long nb = nblocks((long long)s->E);
+    const bool f = a.full != 0;
+    switch (s->desc.dim * 10 + s->desc.order) {
+    case 21: f ? ph.add(IndicatorOp<2, 1, T, true>{a}, nb) : ph.add(IndicatorOp<2, 1, T, false>{a}, nb); break;
+    case 22: f ? ph.add(IndicatorOp<2, 2, T, true>{a}, nb) : ph.add(IndicatorOp<2, 2, T, false>{a}, nb); break;
+    case 23: f ? ph.add(IndicatorOp<2, 3, T, true>{a}, nb) : ph.add(IndicatorOp<2, 3, T, false>{a}, nb); break;
+    case 31: f ? ph.add(IndicatorOp<3, 1, T, true>{a}, nb) : ph.add(IndicatorOp<3, 1, T, false>{a}, nb); break;
+    case 32: f ? ph.add(IndicatorOp<3, 2, T, true>{a}, nb) : ph.add(IndicatorOp<3, 2, T, false>{a}, nb); break;
+    case 33: f ? ph.add(IndicatorOp<3, 3, T, true>{a}, nb) : ph.add(IndicatorOp<3, 3, T, false>{a}, nb); break;
+    default: break;
+    }
+}
+
+template <typename T>
+void add_transfer(MultiPhase &ph, const mdlts_sim *s, const XferArgs &a)
+{
+    const long long nb = nblocks((long long)a.E_new);
+    switch (s->desc.dim * 10 + s->desc.order) {
+    case 21: ph.add(TransferOp<2, 1, T>{a}, nb); break;
+    case 22: ph.add(TransferOp<2, 2, T>{a}, nb); break;
+    case 23: ph.add(TransferOp<2, 3, T>{a}, nb); break;
+    case 31: ph.add(TransferOp<3, 1, T>{a}, nb); break;
+    case 32: ph.add(TransferOp<3, 2, T>{a}, nb); break;
+    case 33: ph.add(TransferOp<3, 3, T>{a}, nb); break;
+    default: break;
+    }
+}
+
+// The two halves of mdlts_batch_adapt for two or more simulations: the same
+// kernels with the same arguments as the per-simulation sequence, so the
+// results are bitwise the same; what changes is that each step of all
+// simulations is one launch per kernel variant (a few tens of launches per
+// call instead of a few tens per simulation).
+// First half: canonical state, indicator, marking, 2:1 closure, coarsening,
+// counts and their scan; the counts arrive in each pin after the caller's
+// synchronisation.
+mdlts_status multi_adapt_count(mdlts_ctx *c, mdlts_sim *const *sims, int n, double tau_refine, double tau_coarsen)
+{
+    MultiPhase ph;
+    // flags blocks cleared, grouped states gathered to canonical order
+    for (int q = 0; q < n; q++) {
+        mdlts_sim *s = sims[q];
+        MD_TRY(dev_alloc(c, s->flags, kFlagBytes));
+        ph.add(ClearFlagsOp{P<int>(s->flags)}, 1);
+        if (s->state_grouped) {
+            const int E = (int)s->E;
+            MD_TRY(alloc_canonical_state(s));
+            const long long stride = (long long)s->np * s->cap;
+            const int parity = (int)(s->n_since_assign & 1);
+            if (s->desc.precision == MDLTS_FP64)
+                ph.add(GatherOp<double>{E, s->np, s->cap, stride, P<int>(s->perm), P<int>(s->cnt_ge_d), parity,
+                                        P<double>(s->u_s), P<double>(s->v_s), P<double>(s->u_c), P<double>(s->v_c),
+                                        nullptr},
+                       nblocks(E));
+            else
+                ph.add(GatherOp<float>{E, s->np, s->cap, stride, P<int>(s->perm), P<int>(s->cnt_ge_d), parity,
+                                       P<float>(s->u_s), P<float>(s->v_s), P<float>(s->u_c), P<float>(s->v_c),
+                                       nullptr},
+                       nblocks(E));
+            s->state_grouped = false;
+        }
+    }
+    ph.step();
+    // indicator (as run_indicator)
+    for (int q = 0; q < n; q++) {
+        mdlts_sim *s = sims[q];
+        const int E = (int)s->E;
+        MD_TRY(dev_alloc(c, s->eta_c, (size_t)E * sizeof(double)));
+        IndArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.u = s->u_c.p;
+        a.key = s->key_c.p;
+        a.face = P<uint32_t>(s->face_c);
+        a.fine = P<uint32_t>(s->fine_c);
+        a.E = E;
+        a.p = s->desc.order;
+        for (int k = 0; k < 3; k++) { a.h0[k] = s->h0[k]; a.Dk[k] = s->Dk[k]; a.Dx[k] = s->Dx[k]; }
+        a.full = s->dfull ? 1 : 0;
+        fill_ref(s->ref, a.ref);
+        a.eta = P<double>(s->eta_c);
+        a.eta_max_bits = MD_FLAG(s, unsigned long long, eta_max_bits);
+        a.nonfinite = MD_FLAG(s, int, eta_nonfinite);
+        if (s->desc.precision == MDLTS_FP64) add_indicator<double>(ph, s, a);
+        else add_indicator<float>(ph, s, a);
+        s->eta_valid = true;
+    }
+    ph.step();
+    // marking (as adapt_count)
+    int passes = 0;
+    for (int q = 0; q < n; q++) {
+        mdlts_sim *s = sims[q];
+        const int E = (int)s->E;
+        const int nb4 = (E + 1023) / 1024;
+        MD_TRY(dev_alloc(c, s->refine, (size_t)E));
+        MD_TRY(dev_alloc(c, s->cflag, (size_t)E));
+        MD_TRY(dev_alloc(c, s->cnt, (size_t)E * sizeof(int)));
+        MD_TRY(dev_alloc(c, s->off, (size_t)E * sizeof(int)));
+        MD_TRY(dev_alloc(c, s->bsums, (size_t)(nb4 + 1) * sizeof(int)));
+        const MeshGeo g = geo_of(s);
+        if (s->desc.dim == 2)
+            ph.add(AmrMarkOp<2>{E, g, P<uint32_t>(s->key_c), P<double>(s->eta_c), tau_refine, P<uint8_t>(s->refine)},
+                   nblocks(E));
+        else
+            ph.add(AmrMarkOp<3>{E, g, P<uint64_t>(s->key_c), P<double>(s->eta_c), tau_refine, P<uint8_t>(s->refine)},
+                   nblocks(E));
+        passes = std::max(passes, s->desc.max_depth);
+    }
+    ph.step();
+    // 2:1 closure: max_depth passes per simulation
+    for (int pass = 0; pass < passes; pass++) {
+        for (int q = 0; q < n; q++) {
+            mdlts_sim *s = sims[q];
+            if (pass >= s->desc.max_depth) continue;
+            const int E = (int)s->E;
+            if (s->desc.dim == 2) ph.add(AmrCloseOp<2>{E, P<uint32_t>(s->face_c), P<uint8_t>(s->refine)}, nblocks(E));
+            else ph.add(AmrCloseOp<3>{E, P<uint32_t>(s->face_c), P<uint8_t>(s->refine)}, nblocks(E));
+        }
+        ph.step();
+    }
+    // coarsening flags, then counts with their block scan, then the scan of
+    // the block sums
+    for (int q = 0; q < n; q++) {
+        mdlts_sim *s = sims[q];
+        const int E = (int)s->E;
+        if (s->desc.dim == 2)
+            ph.add(AmrCoarsenOp<2>{E, P<uint32_t>(s->key_c), P<double>(s->eta_c), tau_coarsen, P<uint8_t>(s->refine),
+                                   P<uint32_t>(s->face_c), P<uint8_t>(s->cflag)},
+                   nblocks(E));
+        else
+            ph.add(AmrCoarsenOp<3>{E, P<uint64_t>(s->key_c), P<double>(s->eta_c), tau_coarsen, P<uint8_t>(s->refine),
+                                   P<uint32_t>(s->face_c), P<uint8_t>(s->cflag)},
+                   nblocks(E));
+    }
+    ph.step();
+    for (int q = 0; q < n; q++) {
+        mdlts_sim *s = sims[q];
+        const int E = (int)s->E;
+        const int nb4 = (E + 1023) / 1024;
+        unsigned long long *tallies = MD_FLAG(s, unsigned long long, tallies);
+        if (s->desc.dim == 2)
+            ph.add(AmrCountScanOp<2>{E, P<uint32_t>(s->key_c), P<uint8_t>(s->refine), P<uint8_t>(s->cflag),
+                                     P<int>(s->cnt), P<int>(s->off), P<int>(s->bsums), tallies},
+                   nb4);
+        else
+            ph.add(AmrCountScanOp<3>{E, P<uint64_t>(s->key_c), P<uint8_t>(s->refine), P<uint8_t>(s->cflag),
+                                     P<int>(s->cnt), P<int>(s->off), P<int>(s->bsums), tallies},
+                   nb4);
+    }
+    ph.step();
+    for (int q = 0; q < n; q++) {
+        mdlts_sim *s = sims[q];
+        const int nb4 = ((int)s->E + 1023) / 1024;
+        ph.add(ScanSumsOp{nb4, P<int>(s->bsums), MD_FLAG(s, int, total)}, 1);
+    }
+    ph.step();
+    std::vector<int> all(n);
+    for (int q = 0; q < n; q++) all[q] = q;
+    MD_TRY(collect_flags(c, ph, sims, all));
+    return ph.run(c);
+}
+
+// Second half, for the simulations in `which` (their counts are on the
+// host): new leaves, transfer, face tables, levels and grouping (as
+// adapt_emit, device_faces and levels_enqueue); the flags with the level
+// counts arrive in each pin after the caller's synchronisation.
+mdlts_status multi_adapt_emit(mdlts_ctx *c, mdlts_sim *const *sims, const std::vector<int> &which,
+                              const double *dt_barrier)
+{
+    MultiPhase ph;
+    // new leaf keys and the transfer map
+    for (int q : which) {
+        mdlts_sim *s = sims[q];
+        const int E = (int)s->E;
+        const int E_new = s->pin->total;
+        if (E_new <= 0 || E_new >= (1 << 27)) return MDLTS_EINVAL;
+        if (s->desc.dim == 2) {
+            MD_TRY(dev_alloc(c, s->key_n, (size_t)E_new * sizeof(uint32_t)));
+        } else {
+            MD_TRY(dev_alloc(c, s->key_n, (size_t)E_new * sizeof(uint64_t)));
+        }
+        MD_TRY(dev_alloc(c, s->xk, (size_t)E_new));
+        MD_TRY(dev_alloc(c, s->xs, (size_t)E_new * sizeof(int32_t)));
+        MD_TRY(dev_alloc(c, s->xc, (size_t)E_new));
+        if (s->desc.dim == 2)
+            ph.add(AmrEmitOp<2>{E, P<uint32_t>(s->key_c), P<uint8_t>(s->refine), P<uint8_t>(s->cflag), P<int>(s->cnt),
+                                P<int>(s->off), P<int>(s->bsums), P<uint32_t>(s->key_n), P<uint8_t>(s->xk),
+                                P<int32_t>(s->xs), P<uint8_t>(s->xc)},
+                   nblocks(E));
+        else
+            ph.add(AmrEmitOp<3>{E, P<uint64_t>(s->key_c), P<uint8_t>(s->refine), P<uint8_t>(s->cflag), P<int>(s->cnt),
+                                P<int>(s->off), P<int>(s->bsums), P<uint64_t>(s->key_n), P<uint8_t>(s->xk),
+                                P<int32_t>(s->xs), P<uint8_t>(s->xc)},
+                   nblocks(E));
+    }
+    ph.step();
+    // transfer of u and v to the new leaves (as run_transfer)
+    for (int q : which) {
+        mdlts_sim *s = sims[q];
+        const int E = (int)s->E;
+        const int E_new = s->pin->total;
+        const size_t bytes = (size_t)E_new * s->np * s->tsize;
+        MD_TRY(dev_alloc(c, s->tmp_u, bytes));
+        MD_TRY(dev_alloc(c, s->tmp_v, bytes));
+        XferArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.u_old = s->u_c.p;
+        a.v_old = s->v_c.p;
+        a.u_new = s->tmp_u.p;
+        a.v_new = s->tmp_v.p;
+        a.E_old = E;
+        a.E_new = E_new;
+        a.kind = P<uint8_t>(s->xk);
+        a.src = P<int32_t>(s->xs);
+        a.child = P<uint8_t>(s->xc);
+        fill_ref(s->ref, a.ref);
+        if (s->desc.precision == MDLTS_FP64) add_transfer<double>(ph, s, a);
+        else add_transfer<float>(ph, s, a);
+        std::swap(s->u_c, s->tmp_u);
+        std::swap(s->v_c, s->tmp_v);
+        std::swap(s->key_c, s->key_n);
+        s->E = (size_t)E_new;
+        s->tree_rev++;
+        s->host_forest_valid = false;
+        s->levels_valid = false;
+        s->eta_valid = false;
+    }
+    ph.step();
+    // face tables of the new leaves (as device_faces)
+    for (int q : which) {
+        mdlts_sim *s = sims[q];
+        const int E = (int)s->E;
+        const int dim = s->desc.dim;
+        const int n_roots = s->desc.n[0] * s->desc.n[1] * (dim == 3 ? s->desc.n[2] : 1);
+        MD_TRY(dev_alloc(c, s->root_start, (size_t)(n_roots + 1) * sizeof(int)));
+        MD_TRY(dev_alloc(c, s->mkey, (size_t)E * sizeof(uint32_t)));
+        MD_TRY(dev_alloc(c, s->face_c, (size_t)2 * dim * E * sizeof(uint32_t)));
+        MD_TRY(dev_alloc(c, s->fine_c, (size_t)2 * dim * E * n_sub(s) * sizeof(uint32_t)));
+        const MeshGeo g = geo_of(s);
+        if (dim == 2)
+            ph.add(MeshIndexOp<2>{E, n_roots, g, P<uint32_t>(s->key_c), P<int>(s->root_start), P<uint32_t>(s->mkey)},
+                   nblocks(E));
+        else
+            ph.add(MeshIndexOp<3>{E, n_roots, g, P<uint64_t>(s->key_c), P<int>(s->root_start), P<uint32_t>(s->mkey)},
+                   nblocks(E));
+    }
+    ph.step();
+    for (int q : which) {
+        mdlts_sim *s = sims[q];
+        const int E = (int)s->E;
+        const MeshGeo g = geo_of(s);
+        int *bad = MD_FLAG(s, int, face_bad);
+        if (s->desc.dim == 2)
+            ph.add(MeshFacesOp<2>{E, g, P<uint32_t>(s->key_c), P<int>(s->root_start), P<uint32_t>(s->mkey),
+                                  P<uint32_t>(s->face_c), P<uint32_t>(s->fine_c), bad},
+                   nblocks(2ll * 2 * E));
+        else
+            ph.add(MeshFacesOp<3>{E, g, P<uint64_t>(s->key_c), P<int>(s->root_start), P<uint32_t>(s->mkey),
+                                  P<uint32_t>(s->face_c), P<uint32_t>(s->fine_c), bad},
+                   nblocks(2ll * 3 * E));
+    }
+    ph.step();
+    // CFL levels (as levels_enqueue with the CFL criterion only)
+    for (size_t r = 0; r < which.size(); r++) {
+        mdlts_sim *s = sims[which[r]];
+        const double dt = dt_barrier[which[r]];
+        if ((uint64_t)2 * s->np * (uint64_t)s->E * s->tsize > 0xffffffffull) return MDLTS_ENOMEM;
+        s->version++;
+        s->levels_valid = false;
+        s->levels_plain_pending = true;
+        const int E = (int)s->E;
+        const int nb = nblocks(E);
+        MD_TRY(dev_alloc(c, s->level_c, (size_t)E));
+        MD_TRY(dev_alloc(c, s->cfl_c, (size_t)E * sizeof(double)));
+        MD_TRY(dev_alloc(c, s->hist, (size_t)nb * kMaxLevels * sizeof(int)));
+        MD_TRY(dev_alloc(c, s->cnt_ge_d, kMaxLevels * sizeof(int)));
+        MD_TRY(dev_alloc(c, s->perm, (size_t)E * sizeof(int)));
+        MD_TRY(dev_alloc(c, s->inv, (size_t)E * sizeof(int)));
+        LevelArgs la;
+        std::memset(&la, 0, sizeof(la));
+        la.key = s->key_c.p;
+        la.face = P<uint32_t>(s->face_c);
+        la.E = E;
+        la.dim = s->desc.dim;
+        la.n_levels = s->desc.n_levels;
+        la.force_level = -1;
+        la.dt_bar = dt;
+        for (int k = 0; k < 3; k++) { la.h0[k] = s->h0[k]; la.Dk[k] = s->Dk[k]; }
+        std::memcpy(la.G, s->G, sizeof(la.G));
+        if (s->dfull) {
+            if (s->otab_dirty || !s->otab_d.p) {
+                MD_TRY(dev_alloc(c, s->otab_d, s->otab.size() * sizeof(double)));
+                HIP_TRY(hipMemcpyAsync(s->otab_d.p, s->otab.data(), s->otab.size() * sizeof(double),
+                                       hipMemcpyHostToDevice, c->stream));
+                s->otab_dirty = false;
+            }
+            la.otab = P<double>(s->otab_d);
+        }
+        la.level = P<uint8_t>(s->level_c);
+        la.cfl = P<double>(s->cfl_c);
+        la.hist = P<int>(s->hist);
+        la.bad = MD_FLAG(s, int, level_bad);
+        if (s->desc.dim == 2) ph.add(LevelsOp<2>{la}, nb);
+        else ph.add(LevelsOp<3>{la}, nb);
+    }
+    ph.step();
+    for (int q : which) {
+        mdlts_sim *s = sims[q];
+        ph.add(LevelScanOp{P<int>(s->hist), nblocks((long long)s->E), s->desc.n_levels, P<int>(s->cnt_ge_d),
+                           MD_FLAG(s, int, cnt_ge)},
+               1);
+    }
+    ph.step();
+    for (int q : which) {
+        mdlts_sim *s = sims[q];
+        const int E = (int)s->E;
+        ph.add(LevelScatterOp{P<uint8_t>(s->level_c), E, P<int>(s->hist), P<int>(s->perm), P<int>(s->inv)},
+               nblocks(E));
+    }
+    ph.step();
+    // grouped tables and state (as the rest of levels_enqueue and to_grouped)
+    for (int q : which) {
+        mdlts_sim *s = sims[q];
+        const int E = (int)s->E;
+        s->cap = E;
+        const size_t ksz = s->desc.dim == 2 ? 4 : 8;
+        MD_TRY(dev_alloc(c, s->key_s, (size_t)s->cap * ksz));
+        MD_TRY(dev_alloc(c, s->nbr_s, (size_t)s->cap * 2 * s->desc.dim * sizeof(uint32_t)));
+        MD_TRY(dev_alloc(c, s->fine_s, (size_t)s->cap * 2 * s->desc.dim * n_sub(s) * sizeof(uint32_t)));
+        if (s->desc.dim == 2)
+            ph.add(RemapOp<uint32_t, 2>{E, 4, P<int>(s->perm), P<int>(s->inv), P<uint8_t>(s->level_c),
+                                        P<uint32_t>(s->key_c), P<uint32_t>(s->face_c), P<uint32_t>(s->fine_c),
+                                        P<uint32_t>(s->key_s), P<uint32_t>(s->nbr_s), P<uint32_t>(s->fine_s), s->cap},
+                   nblocks(E));
+        else
+            ph.add(RemapOp<uint64_t, 4>{E, 6, P<int>(s->perm), P<int>(s->inv), P<uint8_t>(s->level_c),
+                                        P<uint64_t>(s->key_c), P<uint32_t>(s->face_c), P<uint32_t>(s->fine_c),
+                                        P<uint64_t>(s->key_s), P<uint32_t>(s->nbr_s), P<uint32_t>(s->fine_s), s->cap},
+                   nblocks(E));
+        const size_t sbytes = (size_t)s->cap * s->np * s->tsize;
+        MD_TRY(dev_alloc(c, s->u_s, 2 * sbytes));
+        MD_TRY(dev_alloc(c, s->v_s, sbytes));
+        if (s->desc.precision == MDLTS_FP64)
+            ph.add(PermuteOp<double>{E, s->np, s->cap, P<int>(s->perm), P<double>(s->u_c), P<double>(s->v_c),
+                                     P<double>(s->u_s), P<double>(s->v_s)},
+                   nblocks(E));
+        else
+            ph.add(PermuteOp<float>{E, s->np, s->cap, P<int>(s->perm), P<float>(s->u_c), P<float>(s->v_c),
+                                    P<float>(s->u_s), P<float>(s->v_s)},
+                   nblocks(E));
+        s->state_grouped = true;
+        s->n_since_assign = 0;
+    }
+    ph.step();
+    MD_TRY(collect_flags(c, ph, sims, which));
+    return ph.run(c);
+}
 
 }  // namespace
 
@@ -2158,14 +2798,13 @@ mdlts_status mdlts_ctx_destroy(mdlts_ctx *ctx)
         if (!ctx) return MDLTS_EINVAL;
         if (ctx->n_sims > 0) return MDLTS_EBUSY;
         free_plan(ctx, ctx->batch);
-        for (hipStream_t st : ctx->aux) {
-            (void)hipStreamSynchronize(st);
-            (void)hipStreamDestroy(st);
-        }
-        for (hipEvent_t e : ctx->join_ev) (void)hipEventDestroy(e);
-        if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
         if (ctx->stage_done) (void)hipEventSynchronize(ctx->stage_done);
         if (ctx->stage) (void)hipHostFree(ctx->stage);
+        (void)hipStreamSynchronize(ctx->stream);
+        if (ctx->multi_host) (void)hipHostFree(ctx->multi_host);
+        if (ctx->flags_host) (void)hipHostFree(ctx->flags_host);
+        (void)dev_free(ctx, ctx->multi_dev);
+        (void)dev_free(ctx, ctx->flags_dev);
         if (ctx->stage_done) (void)hipEventDestroy(ctx->stage_done);
         delete ctx;
         return MDLTS_OK;
@@ -2928,17 +3567,31 @@ mdlts_status mdlts_batch_adapt(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sim
         for (int q = 0; q < n_sims; q++)
             keep[q] = sims[q]->levels_valid && sims[q]->state_grouped && sims[q]->levels_plain &&
                       dt_barrier[q] == sims[q]->dt_bar;
-        // indicator and the counting half of the adaptation, all simulations.
-        // Every phase writes its own fields of the flags block, cleared once
-        // here and read back in one copy per synchronisation.
-        AuxStreams aux(ctx, n_sims);
-        MD_TRY(aux.fork());
-        for (int q = 0; q < n_sims; q++) {
-            mdlts_sim *s = sims[q];
-            aux.use(q);
+        if (n_sims > 1) {
+            // every step of all simulations in one launch per kernel variant
+            MD_TRY(multi_adapt_count(ctx, sims, n_sims, tau_refine, tau_coarsen));
+            MD_TRY(sync(ctx));
+            std::vector<int> all(n_sims), change;
+            for (int q = 0; q < n_sims; q++) all[q] = q;
+            distribute_flags(ctx, sims, all, kFlagHead);
+            for (int q = 0; q < n_sims; q++) {
+                mdlts_sim *s = sims[q];
+                keep[q] = keep[q] && s->pin->tallies[0] == 0 && s->pin->tallies[1] == 0 && s->pin->total == (int)s->E;
+                if (keep[q]) s->state_grouped = true;
+                else change.push_back(q);
+            }
+            if (!change.empty()) {
+                for (int q : change) sims[q]->version++;
+                MD_TRY(multi_adapt_emit(ctx, sims, change, dt_barrier));
+                MD_TRY(sync(ctx));
+                distribute_flags(ctx, sims, change, sizeof(PinnedReadback));
+            }
+        } else {
+            // one simulation: its own launches (no tables to send)
+            mdlts_sim *s = sims[0];
             // the adaptation works on the canonical copy of the state; the
             // gather that makes it current also clears the flags block (the
-            // grouped copy stays valid for simulations that keep their leaves)
+            // grouped copy stays valid if the leaves do not change)
             if (s->state_grouped) {
                 MD_TRY(dev_alloc(ctx, s->flags, kFlagBytes));
                 MD_TRY(to_canonical(s, flag_at<int>(s, 0)));
@@ -2949,27 +3602,19 @@ mdlts_status mdlts_batch_adapt(mdlts_ctx *ctx, mdlts_sim *const *sims, int n_sim
             if (s->desc.dim == 2) MD_TRY(adapt_count<2>(s, tau_refine, tau_coarsen, false));
             else MD_TRY(adapt_count<3>(s, tau_refine, tau_coarsen, false));
             MD_TRY(flags_readback(s));
-        }
-        MD_TRY(aux.join());
-        MD_TRY(sync(ctx));
-        // new leaves, transfer, faces and levels, all simulations that change
-        MD_TRY(aux.fork());
-        for (int q = 0; q < n_sims; q++) {
-            mdlts_sim *s = sims[q];
-            aux.use(q);
-            keep[q] = keep[q] && s->pin->tallies[0] == 0 && s->pin->tallies[1] == 0 && s->pin->total == (int)s->E;
-            if (keep[q]) {
+            MD_TRY(sync(ctx));
+            keep[0] = keep[0] && s->pin->tallies[0] == 0 && s->pin->tallies[1] == 0 && s->pin->total == (int)s->E;
+            if (keep[0]) {
                 s->state_grouped = true;
-                continue;
+            } else {
+                s->version++;
+                if (s->desc.dim == 2) MD_TRY(adapt_emit<2>(s, false));
+                else MD_TRY(adapt_emit<3>(s, false));
+                MD_TRY(levels_enqueue(s, dt_barrier[0], -1, nullptr, 0.0, 0, false));
+                MD_TRY(flags_readback(s, true));
+                MD_TRY(sync(ctx));
             }
-            s->version++;
-            if (s->desc.dim == 2) MD_TRY(adapt_emit<2>(s, false));
-            else MD_TRY(adapt_emit<3>(s, false));
-            MD_TRY(levels_enqueue(s, dt_barrier[q], -1, nullptr, 0.0, 0, false));
-            MD_TRY(flags_readback(s, true));
         }
-        MD_TRY(aux.join());
-        MD_TRY(sync(ctx));
         mdlts_status first = MDLTS_OK;
         for (int q = 0; q < n_sims; q++) {
             mdlts_sim *s = sims[q];
