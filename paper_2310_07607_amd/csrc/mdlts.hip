@@ -1680,6 +1680,29 @@ void *batch_kernel(int dim, int order, int prec, bool full)
 }
 
 
+// tile k of a list of n_tiles from its runs (ascending k0), into the list of
+// this barrier's parity (t0) and of the next one's (t1)
+__global__ __launch_bounds__(256) void k_expand_tiles(const TileRun *__restrict__ runs, int n_runs,
+                                                      BatchTile *__restrict__ t0, BatchTile *__restrict__ t1,
+                                                      int n_tiles)
+{
+    const int k = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (k >= n_tiles) return;
+    int lo = 0, hi = n_runs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (runs[mid].k0 <= k) lo = mid;
+        else hi = mid - 1;
+    }
+    const TileRun &r = runs[lo];
+    BatchTile tt = r.t;
+    tt.start = r.lo + (k - r.k0) * r.per_tile;
+    tt.count = min(r.per_tile, r.hi - tt.start);
+    t0[k] = tt;
+    tt.packed ^= 1 << 4;
+    t1[k] = tt;
+}
+
 template <typename T>
 mdlts_status fill_group(mdlts_ctx *c, BatchPlan &P, BatchGroup &G)
 {
@@ -1736,18 +1759,31 @@ mdlts_status fill_group(mdlts_ctx *c, BatchPlan &P, BatchGroup &G)
         nt += n_i;
     }
     G.n_tiles = (int)nt;
-    // descriptors, clocks and both tile lists (this barrier's parity and the
-    // next one's) in one buffer, uploaded in one copy
+    // descriptors, clocks, the runs and both tile lists (this barrier's
+    // parity and the next one's) in one buffer; the host sends descriptors,
+    // clocks and runs in one copy and the device writes the tiles
+    size_t n_runs = 0;
+    for (const long long i : first)
+        for (int q = 0; q < nm; q++) {
+            const mdlts_sim *s = P.sims[G.members[q]];
+            if (i >= (1ll << s->lmax)) continue;
+            for (int l = s->lmax; l >= lmin_of(i, s->lmax); l--) {
+                int lo, hi;
+                level_range(s, l, lo, hi);
+                if (hi > lo) n_runs++;
+            }
+        }
     const size_t b_d = (size_t)nm * sizeof(BatchSim<T>), b_c = 2 * (size_t)nm * sizeof(BatchClock);
+    const size_t b_r = n_runs * sizeof(TileRun);
     const size_t b_t = 2 * nt * sizeof(BatchTile);
     G.off_clocks = (b_d + 255) / 256 * 256;
-    G.off_tiles = G.off_clocks + (b_c + 255) / 256 * 256;
+    const size_t off_runs = G.off_clocks + (b_c + 255) / 256 * 256;
+    G.off_tiles = off_runs + (b_r + 255) / 256 * 256;
     const size_t total = G.off_tiles + std::max<size_t>(b_t, sizeof(BatchTile));
     MD_TRY(dev_alloc(c, G.data, total));
     G.base = static_cast<char *>(G.data.p);
-    const long long base = (long long)(uintptr_t)G.base;
     char *st = nullptr;
-    MD_TRY(stage_acquire(c, total, &st));
+    MD_TRY(stage_acquire(c, G.off_tiles, &st));
     for (int q = 0; q < nm; q++) {
         mdlts_sim *s = P.sims[G.members[q]];
         BatchSim<T> d;
@@ -1760,19 +1796,21 @@ mdlts_status fill_group(mdlts_ctx *c, BatchPlan &P, BatchGroup &G)
     G.hclk.resize(2 * (size_t)nm);
     for (int q = 0; q < nm; q++) G.hclk[q] = G.hclk[nm + q] = BatchClock{P.sims[G.members[q]]->n_bar};
     std::memcpy(st + G.off_clocks, G.hclk.data(), b_c);
-    char *t0 = st + G.off_tiles;                      // this barrier's parity
-    char *t1 = t0 + nt * sizeof(BatchTile);           // the barrier after: the other parity
-    size_t k = 0;
+    TileRun *rr = reinterpret_cast<TileRun *>(st + off_runs);
+    size_t k = 0, r = 0;
+    const long long dbase = (long long)(uintptr_t)G.base;
     for (const long long i : first)
         for (int q = 0; q < nm; q++) {
             const mdlts_sim *s = P.sims[G.members[q]];
             if (i >= (1ll << s->lmax)) continue;
-            BatchTile tt{};  // array locations as offsets from the buffer's base
-            tt.off_u = (long long)(uintptr_t)s->u_s.p - base;
-            tt.off_v = (long long)(uintptr_t)s->v_s.p - base;
-            tt.off_key = (long long)(uintptr_t)s->key_s.p - base;
-            tt.off_nbr = (long long)(uintptr_t)s->nbr_s.p - base;
-            tt.off_fine = (long long)(uintptr_t)s->fine_s.p - base;
+            TileRun run;
+            std::memset(&run, 0, sizeof(run));
+            BatchTile &tt = run.t;  // array locations as offsets from the buffer's base
+            tt.off_u = (long long)(uintptr_t)s->u_s.p - dbase;
+            tt.off_v = (long long)(uintptr_t)s->v_s.p - dbase;
+            tt.off_key = (long long)(uintptr_t)s->key_s.p - dbase;
+            tt.off_nbr = (long long)(uintptr_t)s->nbr_s.p - dbase;
+            tt.off_fine = (long long)(uintptr_t)s->fine_s.p - dbase;
             tt.sim = q;
             tt.node_bytes = (uint32_t)((size_t)s->cap * sizeof(T));
             tt.slot_bytes = (uint32_t)((size_t)s->np * s->cap * sizeof(T));
@@ -1780,19 +1818,27 @@ mdlts_status fill_group(mdlts_ctx *c, BatchPlan &P, BatchGroup &G)
             for (int l = s->lmax; l >= lmin_of(i, s->lmax); l--) {
                 int lo, hi;
                 level_range(s, l, lo, hi);
-                for (int sa = lo; sa < hi; sa += per_tile) {
-                    tt.start = sa;
-                    tt.count = std::min(per_tile, hi - sa);
-                    tt.packed = l | parity << 4 | s->lmax << 8;
-                    std::memcpy(t0 + k * sizeof(BatchTile), &tt, sizeof(tt));
-                    tt.packed ^= 1 << 4;
-                    std::memcpy(t1 + k * sizeof(BatchTile), &tt, sizeof(tt));
-                    k++;
-                }
+                if (hi <= lo) continue;
+                tt.packed = l | parity << 4 | s->lmax << 8;
+                run.k0 = (int)k;
+                run.n = (hi - lo + per_tile - 1) / per_tile;
+                run.lo = lo;
+                run.hi = hi;
+                run.per_tile = per_tile;
+                if (r >= n_runs) return MDLTS_EINVAL;
+                std::memcpy(rr + r, &run, sizeof(run));
+                r++;
+                k += (size_t)run.n;
             }
         }
-    if (k != nt) return MDLTS_EINVAL;  // the two passes disagree (cannot happen)
-    HIP_TRY(hipMemcpyAsync(G.data.p, st, G.off_tiles + b_t, hipMemcpyHostToDevice, c->stream));
+    if (k != nt || r != n_runs) return MDLTS_EINVAL;  // the passes disagree (cannot happen)
+    HIP_TRY(hipMemcpyAsync(G.data.p, st, G.off_tiles, hipMemcpyHostToDevice, c->stream));
+    if (nt > 0) {
+        BatchTile *dt0 = G.tiles();
+        k_expand_tiles<<<(unsigned)((nt + 255) / 256), 256, 0, c->stream>>>(
+            reinterpret_cast<const TileRun *>(G.base + off_runs), (int)n_runs, dt0, dt0 + nt, (int)nt);
+        HIP_TRY(hipGetLastError());
+    }
     return stage_release(c);
 }
 
