@@ -1314,17 +1314,6 @@ struct BatchTile {
 };
 static_assert(sizeof(BatchTile) == 64, "one scalar load per tile");
 
-// A run of tiles of one simulation and level in a tile list: tiles k0 ..
-// k0 + n - 1 cover elements [lo, hi) in pieces of per_tile; t holds the
-// fields they share (the parity of the list's barrier in t.packed).  The
-// host sends the runs; k_expand_tiles writes the tiles on the device.
-struct TileRun {
-    BatchTile t;
-    int k0, n, lo, hi, per_tile;
-    int pad[3];
-};
-static_assert(sizeof(TileRun) == 96, "tile runs pack without holes");
-
 // Everything a batched launch needs about one simulation.  Data locations
 // are byte offsets from the kernel's base pointer so that the kernel derives
 // them from a global-memory kernel argument.

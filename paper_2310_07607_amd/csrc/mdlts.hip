@@ -1680,6 +1680,17 @@ void *batch_kernel(int dim, int order, int prec, bool full)
 }
 
 
+// A run of tiles of one simulation and level in a tile list: tiles k0 ..
+// k0 + n - 1 cover elements [lo, hi) in pieces of per_tile; t holds the
+// fields they share (the parity of the list's barrier in t.packed).  The
+// host sends the runs; k_expand_tiles writes the tiles on the device.
+struct TileRun {
+    BatchTile t;
+    int k0, n, lo, hi, per_tile;
+    int pad[3];
+};
+static_assert(sizeof(TileRun) == 96, "tile runs pack without holes");
+
 // tile k of a list of n_tiles from its runs (ascending k0), into the list of
 // this barrier's parity (t0) and of the next one's (t1)
 __global__ __launch_bounds__(256) void k_expand_tiles(const TileRun *__restrict__ runs, int n_runs,
