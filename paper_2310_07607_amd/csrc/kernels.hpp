@@ -176,8 +176,8 @@ struct StepLaunch {
     const void *key;
     const uint32_t *nbr;
     const uint32_t *fine;
-    uint32_t node_bytes;  // cap * sizeof(T): stride between nodes of u and v
-    uint32_t slot_bytes;  // np * node_bytes: stride between the two u slots
+    uint32_t node_bytes;  // cap * sizeof(T) (u and v are in the grouped layout, grp_elem)
+    uint32_t slot_bytes;  // np * cap * sizeof(T): stride between the two u slots
     int cap;              // elements per table column
     int lmax;             // finest level present
     int i;                // substep index in the barrier interval
@@ -274,6 +274,26 @@ __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t voff, 
     else
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(HIP_vector_base<uint32_t, 2>::Native_vec_, x), r,
                                               (int)voff, (int)soff, 0);
+}
+
+// Grouped state layout (u in two slots, v) of elements of np nodes: blocks
+// of 64 elements, [node][element] inside a block, so that a wave's loads of
+// its elements' nodes fall in one block of np * 64 values (the memory system
+// streams them faster than np arrays of cap values: measured 5.6 against
+// 5.1 TB/s for np = 27).  Q1 quadrilaterals (np = 4), whose launches are
+// cache-resident and latency-bound, keep [node][cap] (the block arithmetic
+// cost them 1 % per launch).  Byte offset of element j inside a slot:
+template <typename T, int NP>
+__host__ __device__ constexpr uint32_t grp_elem(uint32_t j)
+{
+    if (NP == 4) return j * (uint32_t)sizeof(T);
+    return (j >> 6) * (uint32_t)(NP * 64 * sizeof(T)) + (j & 63u) * (uint32_t)sizeof(T);
+}
+// and the byte stride between an element's nodes (node_bytes = cap * sizeof(T))
+template <typename T, int NP>
+__host__ __device__ constexpr uint32_t grp_node(uint32_t node_bytes)
+{
+    return NP == 4 ? node_bytes : 64u * (uint32_t)sizeof(T);
 }
 
 // out = (I[pos0] (x) I[pos1]) in over the tangential points of a face
@@ -391,7 +411,7 @@ __device__ __forceinline__ void neighbour_trace(const StepArgs<T> &a, const Step
     const int base = ln == 0 ? parity : 0;
     const int cur = base ^ ((si >> sh) & 1);
     const int rem = si & ((1 << sh) - 1);
-    const uint32_t o0 = (uint32_t)cur * L.slot_bytes + id * (uint32_t)sizeof(T);
+    const uint32_t o0 = (uint32_t)cur * L.slot_bytes + grp_elem<T, S::NP>(id);
 #pragma unroll
     for (int g = 0; g < S::NF; g++) { tu[g] = 0; tq[g] = 0; }
     if (rem == 0) {
@@ -399,18 +419,18 @@ __device__ __forceinline__ void neighbour_trace(const StepArgs<T> &a, const Step
         for (int g = 0; g < S::NF; g++)
 #pragma unroll
             for (int b = 0; b < M; b++) {
-                const T val = buf_ld<T>(ru, o0, (uint32_t)fnode<DIM, M>(k, g, b) * L.node_bytes);
+                const T val = buf_ld<T>(ru, o0, (uint32_t)fnode<DIM, M>(k, g, b) * grp_node<T, S::NP>(L.node_bytes));
                 tu[g] += (T)R.B[side][b] * val;
                 tq[g] += (T)R.G[side][b] * val;
             }
     } else {
         const T th = ldexp((T)rem, -sh);
-        const uint32_t o1 = (uint32_t)(cur ^ 1) * L.slot_bytes + id * (uint32_t)sizeof(T);
+        const uint32_t o1 = (uint32_t)(cur ^ 1) * L.slot_bytes + grp_elem<T, S::NP>(id);
 #pragma unroll
         for (int g = 0; g < S::NF; g++)
 #pragma unroll
             for (int b = 0; b < M; b++) {
-                const uint32_t so = (uint32_t)fnode<DIM, M>(k, g, b) * L.node_bytes;
+                const uint32_t so = (uint32_t)fnode<DIM, M>(k, g, b) * grp_node<T, S::NP>(L.node_bytes);
                 const T val = ((T)1 - th) * buf_ld<T>(ru, o0, so) + th * buf_ld<T>(ru, o1, so);
                 tu[g] += (T)R.B[side][b] * val;
                 tq[g] += (T)R.G[side][b] * val;
@@ -434,12 +454,12 @@ __device__ __forceinline__ void neighbour_values(const StepLaunch<T> &L, __amdgp
     const int cur = (ln == 0 ? L.parity : 0) ^ ((L.i >> sh) & 1);
     const int rem = L.i & ((1 << sh) - 1);
     const T th = ldexp((T)rem, -sh);
-    const uint32_t o0 = (uint32_t)cur * L.slot_bytes + id * (uint32_t)sizeof(T);
-    const uint32_t o1 = rem ? (uint32_t)(cur ^ 1) * L.slot_bytes + id * (uint32_t)sizeof(T) : o0;
+    const uint32_t o0 = (uint32_t)cur * L.slot_bytes + grp_elem<T, NP>(id);
+    const uint32_t o1 = rem ? (uint32_t)(cur ^ 1) * L.slot_bytes + grp_elem<T, NP>(id) : o0;
 #pragma unroll
     for (int n = 0; n < NP; n++) {
-        const T x0 = buf_ld<T>(ru, o0, (uint32_t)n * L.node_bytes);
-        const T x1 = buf_ld<T>(ru, o1, (uint32_t)n * L.node_bytes);
+        const T x0 = buf_ld<T>(ru, o0, (uint32_t)n * grp_node<T, NP>(L.node_bytes));
+        const T x1 = buf_ld<T>(ru, o1, (uint32_t)n * grp_node<T, NP>(L.node_bytes));
         val[n] = x0 + th * (x1 - x0);
     }
 }
@@ -455,9 +475,9 @@ __device__ __forceinline__ void neighbour_slot0(const StepLaunch<T> &L, __amdgpu
     const int ln = (int)((ent >> 27) & 7);
     const int sh = L.lmax - ln;
     const int cur = (ln == 0 ? L.parity : 0) ^ ((L.i >> sh) & 1);
-    const uint32_t o0 = (uint32_t)cur * L.slot_bytes + id * (uint32_t)sizeof(T);
+    const uint32_t o0 = (uint32_t)cur * L.slot_bytes + grp_elem<T, NP>(id);
 #pragma unroll
-    for (int n = 0; n < NP; n++) val[n] = buf_ld<T>(ru, o0, (uint32_t)n * L.node_bytes);
+    for (int n = 0; n < NP; n++) val[n] = buf_ld<T>(ru, o0, (uint32_t)n * grp_node<T, NP>(L.node_bytes));
 }
 
 template <typename T, int NP>
@@ -471,10 +491,10 @@ __device__ __forceinline__ void neighbour_interp(const StepLaunch<T> &L, __amdgp
     const int rem = L.i & ((1 << sh) - 1);
     if (rem) {
         const T th = ldexp((T)rem, -sh);
-        const uint32_t o1 = (uint32_t)(cur ^ 1) * L.slot_bytes + id * (uint32_t)sizeof(T);
+        const uint32_t o1 = (uint32_t)(cur ^ 1) * L.slot_bytes + grp_elem<T, NP>(id);
 #pragma unroll
         for (int n = 0; n < NP; n++) {
-            const T x1 = buf_ld<T>(ru, o1, (uint32_t)n * L.node_bytes);
+            const T x1 = buf_ld<T>(ru, o1, (uint32_t)n * grp_node<T, NP>(L.node_bytes));
             val[n] = val[n] + th * (x1 - val[n]);
         }
     }
@@ -548,7 +568,7 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
     // ---- loads that depend on nothing but j
     using KT = typename KeyOf<DIM>::type;
     const uint32_t oj = (uint32_t)j * 4u;                   // 32-bit tables
-    const uint32_t ojt = (uint32_t)j * (uint32_t)sizeof(T);  // bulk arrays
+    const uint32_t ojt = grp_elem<T, NP>((uint32_t)j);      // bulk arrays (grouped layout)
     const __amdgpu_buffer_rsrc_t ru = buf_of(L.u, 2u * L.slot_bytes);
     const __amdgpu_buffer_rsrc_t rv = buf_of(L.v, L.slot_bytes);
     const __amdgpu_buffer_rsrc_t rn = buf_of(L.nbr, (uint32_t)NFACE * (uint32_t)L.cap * 4u);
@@ -566,10 +586,10 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
     T u[NP], vv[kEarlyV ? NP : 1];
 #pragma unroll
     for (int n = 0; n < NP; n++) {
-        u[n] = buf_ld<T>(ru, ou, (uint32_t)n * L.node_bytes);
-        if constexpr (kEarlyV) vv[n] = buf_ld<T>(rv, ojt, (uint32_t)n * L.node_bytes);
+        u[n] = buf_ld<T>(ru, ou, (uint32_t)n * grp_node<T, NP>(L.node_bytes));
+        if constexpr (kEarlyV) vv[n] = buf_ld<T>(rv, ojt, (uint32_t)n * grp_node<T, NP>(L.node_bytes));
         if constexpr (kLdsV)
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rv, gv + n * 64, 4, ojt, (uint32_t)n * L.node_bytes, 0, 0);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rv, gv + n * 64, 4, ojt, (uint32_t)n * grp_node<T, NP>(L.node_bytes), 0, 0);
     }
     // ---- one neighbour per face (same-size or coarser), at the substep time
     T nb[kPrefetch ? NFACE : 1][NP];
@@ -953,7 +973,7 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
             if (n == 0) __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0)
             vn = gv[n * 64 + (threadIdx.x & 63)];
         } else {
-            vn = buf_ld<T>(rv, ojt, (uint32_t)n * L.node_bytes);
+            vn = buf_ld<T>(rv, ojt, (uint32_t)n * grp_node<T, NP>(L.node_bytes));
         }
         T stim = 0;
         if (hit) {
@@ -986,8 +1006,8 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
             const T eps = eps0 + mu1 * vn / den;
             decay = exp(-eps * dt);
         }
-        buf_st<T>(ru, ouo, (uint32_t)n * L.node_bytes, un + dt * (r[n] + f + stim));
-        buf_st<T>(rv, ojt, (uint32_t)n * L.node_bytes, vinf + (vn - vinf) * decay);
+        buf_st<T>(ru, ouo, (uint32_t)n * grp_node<T, NP>(L.node_bytes), un + dt * (r[n] + f + stim));
+        buf_st<T>(rv, ojt, (uint32_t)n * grp_node<T, NP>(L.node_bytes), vinf + (vn - vinf) * decay);
     }
 }
 
@@ -1063,22 +1083,22 @@ __device__ __forceinline__ void quad_neighbour(const StepLaunch<T> &L, __amdgpu_
     const int cur = (ln == 0 ? L.parity : 0) ^ ((L.i >> sh) & 1);
     const int rem = L.i & ((1 << sh) - 1);
     const T th = ldexp((T)rem, -sh);
-    const uint32_t o0 = (uint32_t)cur * L.slot_bytes + id * (uint32_t)sizeof(T);
-    const uint32_t o1 = rem ? (uint32_t)(cur ^ 1) * L.slot_bytes + id * (uint32_t)sizeof(T) : o0;
+    const uint32_t o0 = (uint32_t)cur * L.slot_bytes + grp_elem<T, 4>(id);
+    const uint32_t o1 = rem ? (uint32_t)(cur ^ 1) * L.slot_bytes + grp_elem<T, 4>(id) : o0;
     // the second slot only where some lane of the wave interpolates (a
     // wave-uniform branch; x0 + 0 (x1 - x0) = x0 for the others)
     if (__builtin_amdgcn_ballot_w64(rem != 0) != 0) {
         T x0[4], x1[4];
 #pragma unroll
         for (int n = 0; n < 4; n++) {
-            x0[n] = buf_ld<T>(ru, o0 + (uint32_t)n * L.node_bytes, 0);
-            x1[n] = buf_ld<T>(ru, o1 + (uint32_t)n * L.node_bytes, 0);
+            x0[n] = buf_ld<T>(ru, o0 + (uint32_t)n * grp_node<T, 4>(L.node_bytes), 0);
+            x1[n] = buf_ld<T>(ru, o1 + (uint32_t)n * grp_node<T, 4>(L.node_bytes), 0);
         }
 #pragma unroll
         for (int n = 0; n < 4; n++) val[n] = x0[n] + th * (x1[n] - x0[n]);
     } else {
 #pragma unroll
-        for (int n = 0; n < 4; n++) val[n] = buf_ld<T>(ru, o0 + (uint32_t)n * L.node_bytes, 0);
+        for (int n = 0; n < 4; n++) val[n] = buf_ld<T>(ru, o0 + (uint32_t)n * grp_node<T, 4>(L.node_bytes), 0);
     }
 }
 
@@ -1100,15 +1120,15 @@ __device__ __forceinline__ void substep_quad(const StepArgs<T> &a, const StepLau
     const T dt = (T)ldexp(a.dt_bar, -lv);
 
     // ---- loads: own node q (u, v), face entry q, key; then face q's neighbour
-    const uint32_t ojt = (uint32_t)j * (uint32_t)sizeof(T);
+    const uint32_t ojt = grp_elem<T, 4>((uint32_t)j);
     const __amdgpu_buffer_rsrc_t ru = buf_of(L.u, 2u * L.slot_bytes);
     const __amdgpu_buffer_rsrc_t rv = buf_of(L.v, L.slot_bytes);
     const __amdgpu_buffer_rsrc_t rn = buf_of(L.nbr, 4u * (uint32_t)L.cap * 4u);
     const uint32_t ent = buf_ld<uint32_t>(rn, (uint32_t)j * 4u + (uint32_t)q * (uint32_t)L.cap * 4u, 0);
     const uint32_t kraw = buf_ld<uint32_t>(buf_of(L.key, (uint32_t)L.cap * 4u), (uint32_t)j * 4u, 0);
     const uint32_t ou = (uint32_t)cur * L.slot_bytes + ojt;
-    const T uq = buf_ld<T>(ru, ou + (uint32_t)q * L.node_bytes, 0);
-    const T vq = buf_ld<T>(rv, ojt + (uint32_t)q * L.node_bytes, 0);
+    const T uq = buf_ld<T>(ru, ou + (uint32_t)q * grp_node<T, 4>(L.node_bytes), 0);
+    const T vq = buf_ld<T>(rv, ojt + (uint32_t)q * grp_node<T, 4>(L.node_bytes), 0);
     const uint32_t kind = ent >> 30;
     const bool one = kind == kSame || kind == kCoarser;
     T nv[4];
@@ -1245,7 +1265,7 @@ __device__ __forceinline__ void substep_quad(const StepArgs<T> &a, const StepLau
     rq += quad_reduce_scatter<T>(cf, q);
 
     // ---- node q: reaction, stimulus, update
-    const uint32_t ouo = (uint32_t)(cur ^ 1) * L.slot_bytes + ojt + (uint32_t)q * L.node_bytes;
+    const uint32_t ouo = (uint32_t)(cur ^ 1) * L.slot_bytes + ojt + (uint32_t)q * grp_node<T, 4>(L.node_bytes);
     const T apk = a.apk, apa = a.apa, eps0 = a.eps0, mu1 = a.mu1, mu2 = a.mu2;
     T stim = 0;
     bool on = false;  // some stimulus box is on at t_i (the same for every lane)
@@ -1277,7 +1297,7 @@ __device__ __forceinline__ void substep_quad(const StepArgs<T> &a, const StepLau
         decay = exp(-eps * dt);
     }
     buf_st<T>(ru, ouo, 0, uq + dt * (rq + f + stim));
-    buf_st<T>(rv, ojt + (uint32_t)q * L.node_bytes, 0, vinf + (vq - vinf) * decay);
+    buf_st<T>(rv, ojt + (uint32_t)q * grp_node<T, 4>(L.node_bytes), 0, vinf + (vq - vinf) * decay);
 }
 
 // one simulation: element j of the active prefix [0, n_act)

@@ -313,9 +313,13 @@ __device__ __forceinline__ void permute_body(const int blk, int E, int np, int c
     const int j = blk * kBlock + threadIdx.x;
     if (j >= E) return;
     const int e = perm[j];
+    // grouped layout (grp_elem, grp_node): blocks of 64 elements with
+    // [node][element] inside a block, [node][cap] for Q1 quadrilaterals
+    const long long gj = np == 4 ? j : (long long)(j >> 6) * np * 64 + (j & 63);
+    const long long gn = np == 4 ? cap : 64;
     for (int n = 0; n < np; n++) {
-        us[(long long)n * cap + j] = uc[(long long)n * E + e];
-        vs[(long long)n * cap + j] = vc[(long long)n * E + e];
+        us[gj + (long long)n * gn] = uc[(long long)n * E + e];
+        vs[gj + (long long)n * gn] = vc[(long long)n * E + e];
     }
 }
 
@@ -358,9 +362,12 @@ __device__ __forceinline__ void gather_body(const int blk, int E, int np, int ca
     const bool lvl0 = j >= cnt_ge[1];
     const int cur = lvl0 ? parity : 0;
     const int e = perm[j];
+    // grouped layout (grp_elem, grp_node)
+    const long long gj = np == 4 ? j : (long long)(j >> 6) * np * 64 + (j & 63);
+    const long long gn = np == 4 ? cap : 64;
     for (int n = 0; n < np; n++) {
-        uc[(long long)n * E + e] = us[(long long)cur * slot_stride + (long long)n * cap + j];
-        if (vc) vc[(long long)n * E + e] = vs[(long long)n * cap + j];
+        uc[(long long)n * E + e] = us[(long long)cur * slot_stride + gj + (long long)n * gn];
+        if (vc) vc[(long long)n * E + e] = vs[gj + (long long)n * gn];
     }
 }
 
@@ -2711,7 +2718,7 @@ mdlts_status multi_adapt_emit(mdlts_ctx *c, mdlts_sim *const *sims, const std::v
     for (size_t r = 0; r < which.size(); r++) {
         mdlts_sim *s = sims[which[r]];
         const double dt = dt_barrier[which[r]];
-        if ((uint64_t)2 * s->np * (uint64_t)s->E * s->tsize > 0xffffffffull) return MDLTS_ENOMEM;
+        if ((uint64_t)2 * s->np * (((uint64_t)s->E + 63) / 64 * 64) * s->tsize > 0xffffffffull) return MDLTS_ENOMEM;
         s->version++;
         s->levels_valid = false;
         s->levels_plain_pending = true;
@@ -2769,7 +2776,7 @@ mdlts_status multi_adapt_emit(mdlts_ctx *c, mdlts_sim *const *sims, const std::v
     for (int q : which) {
         mdlts_sim *s = sims[q];
         const int E = (int)s->E;
-        s->cap = E;
+        s->cap = (E + 63) / 64 * 64;  // whole blocks of the grouped layout
         const size_t ksz = s->desc.dim == 2 ? 4 : 8;
         MD_TRY(dev_alloc(c, s->key_s, (size_t)s->cap * ksz));
         MD_TRY(dev_alloc(c, s->nbr_s, (size_t)s->cap * 2 * s->desc.dim * sizeof(uint32_t)));
@@ -3128,7 +3135,7 @@ static mdlts_status levels_enqueue(mdlts_sim *s, double dt_barrier, int force_le
 {
     if (!(dt_barrier > 0.0) || !std::isfinite(dt_barrier)) return MDLTS_EINVAL;
     // the substep kernels address both u slots with 32-bit byte offsets
-    if ((uint64_t)2 * s->np * (uint64_t)s->E * s->tsize > 0xffffffffull) return MDLTS_ENOMEM;
+    if ((uint64_t)2 * s->np * (((uint64_t)s->E + 63) / 64 * 64) * s->tsize > 0xffffffffull) return MDLTS_ENOMEM;
     s->version++;
     s->levels_valid = false;
     s->levels_plain_pending = force_level < 0 && !eta_t;
@@ -3183,7 +3190,7 @@ static mdlts_status levels_enqueue(mdlts_sim *s, double dt_barrier, int force_le
     k_level_scatter<<<nb, kBlock, 0, c->stream>>>(P<uint8_t>(s->level_c), E, P<int>(s->hist), P<int>(s->perm),
                                                    P<int>(s->inv));
     // grouped tables
-    s->cap = E;
+    s->cap = (E + 63) / 64 * 64;  // whole blocks of the grouped layout
     const size_t ksz = s->desc.dim == 2 ? 4 : 8;
     MD_TRY(dev_alloc(c, s->key_s, (size_t)s->cap * ksz));
     MD_TRY(dev_alloc(c, s->nbr_s, (size_t)s->cap * 2 * s->desc.dim * sizeof(uint32_t)));
@@ -3827,7 +3834,8 @@ mdlts_status mdlts_memory_bound(const mdlts_mesh_desc *desc, int64_t max_leaves,
             + 1 + 8 + 4 + 4 + 8 + 8 + 1 // level, CFL, permutation both ways, indicators, histogram share
             + lanes_per_element(desc->dim, desc->order, false) * ((nsub * 16 + 31) / 32);
                                     // batch tiles: per substep one per 64 threads (blocks of >= 64)
-        const uint64_t fixed = 64 * 512         // allocator rounding of every buffer
+        const uint64_t fixed = 64 * per_leaf    // grouped arrays padded to whole blocks of 64 elements
+                               + 64 * 512       // allocator rounding of every buffer
                                + 4 * 4096       // flags, step constants, batch descriptor, small scans
                                + 8 * 4096       // own-block bounds of a full diffusion tensor
                                + nsub * 16 * 2; // tile list heads

@@ -177,3 +177,44 @@ def test_graph_and_direct_barriers_mix_bitwise(ctx):
     for (sd, cd), (sm, cm) in zip(direct, mixed):
         assert np.array_equal(sd[0], sm[0]) and np.array_equal(sd[1], sm[1])
         assert cd == cm
+
+
+def test_batch_adapt_of_more_than_64_simulations(ctx):
+    """Seventy simulations in one mdlts_batch_adapt (the launches over all of
+    them find a block's simulation in chunks of 64 table entries): trees,
+    levels and states bitwise those of the per-simulation calls."""
+    from paper_2310_07607_amd import mdlts
+    tau_r, tau_c = 2e-9, 1e-10
+    n_sims = 70
+    cases = [CASES[k % 5] for k in range(n_sims)]
+
+    def build():
+        out = []
+        for k, case in enumerate(cases):
+            dim, p, n, length, depth, D, gamma, seeds, L, prec = case
+            _, g, _, _, _, _ = _make(ctx, case, 200 + k)
+            desc = mdlts.make_desc(dim, p, n, length, depth, L)
+            dt = 2 ** (L - 1) * mdlts.cfl_bound(desc, D, gamma, depth) * (1 - 2 ** -20)
+            g.assign_levels(dt)
+            g.step(2)
+            out.append((g, dt))
+        return out
+
+    a = build()
+    for g, dt in a:
+        g.indicator(download=False)
+        g.adapt(tau_r, tau_c)
+        g.assign_levels(dt)
+    b = build()
+    ctx.batch_adapt([g for g, _ in b], tau_r, tau_c, [dt for _, dt in b])
+    for (ga, _), (gb, _) in zip(a, b):
+        ta, tb = ga.get_tree(), gb.get_tree()
+        assert np.array_equal(ta, tb)
+        la, pa, ca = ga.get_levels()
+        lb, pb, cb = gb.get_levels()
+        assert np.array_equal(la, lb) and np.array_equal(pa, pb) and np.array_equal(ca, cb)
+        ua, va = ga.get_state()
+        ub, vb = gb.get_state()
+        assert np.array_equal(ua, ub) and np.array_equal(va, vb)
+        ga.close()
+        gb.close()
