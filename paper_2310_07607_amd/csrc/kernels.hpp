@@ -649,15 +649,21 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
 
     // interior faces.  Elements that do not prefetch every face keep NB
     // faces' neighbours in flight: face f+NB's loads are issued as soon as
-    // face f is done, so memory overlaps the arithmetic.  NB = 1: a second
-    // buffer costs NP registers, and waves per SIMD hide more latency than
-    // a deeper pipeline within one wave (measured on all larger elements).
-    constexpr int NB = 1;
+    // face f is done, so memory overlaps the arithmetic.  NB = 2 in FP32 up
+    // to degree 2 (Q2 hexahedra 250 VGPRs, still 2 waves per SIMD; alone,
+    // 3.5 % faster than NB = 1 for Q2 hexahedra and 2-4 % for Q1
+    // hexahedra); degree 3 and FP64 keep NB = 1 for their register budget.
+    constexpr int NB = (sizeof(T) == 4 && P <= 2) ? 2 : 1;
     T nbuf[NB][kPrefetch ? 1 : NP];
     auto issue = [&](int f, T *dst) {
         const uint32_t kind = ent[f] >> 30;
         const bool one = kind == kSame || kind == kCoarser;
         neighbour_slot0<T, NP>(L, ru, one ? ent[f] : self_ent, dst);
+        // The loads are used only inside the next faces' conditional blocks,
+        // and the compiler would otherwise sink them into those blocks,
+        // issuing them just before their use (no time in flight).  An empty
+        // asm with a memory clobber keeps them here.
+        asm volatile("" ::: "memory");
     };
     if constexpr (!kPrefetch) {
 #pragma unroll
