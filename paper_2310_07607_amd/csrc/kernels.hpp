@@ -613,18 +613,24 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
 #pragma unroll
     for (int n = 0; n < NP; n++) r[n] = 0;
 
-    // element volume: -(4 D_kk / h_k^2) A along each direction
+    // element volume: -(4 D_kk / h_k^2) A along each direction, with the
+    // scale folded into this element's copy of A (one fused multiply-add
+    // per term)
 #pragma unroll
     for (int k = 0; k < DIM; k++) {
         const T ck = (T)4 * a.Dk[k] * ih[k] * ih[k];
+        T cA[M][M];
+#pragma unroll
+        for (int aa = 0; aa < M; aa++)
+#pragma unroll
+            for (int b = 0; b < M; b++) cA[aa][b] = ck * (T)R.A[aa][b];
 #pragma unroll
         for (int g = 0; g < NF; g++)
 #pragma unroll
             for (int aa = 0; aa < M; aa++) {
-                T s = 0;
+                T &rn = r[fnode<DIM, M>(k, g, aa)];
 #pragma unroll
-                for (int b = 0; b < M; b++) s += (T)R.A[aa][b] * u[fnode<DIM, M>(k, g, b)];
-                r[fnode<DIM, M>(k, g, aa)] -= ck * s;
+                for (int b = 0; b < M; b++) rn -= cA[aa][b] * u[fnode<DIM, M>(k, g, b)];
             }
     }
 
@@ -916,11 +922,15 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
             }
             // lift to the own nodes, already multiplied by the inverse mass:
             // r += c2 winv (F B + qs H G), with c2 and c2 qs already in Fl, Hl
+            // (two fused multiply-adds into r per node)
 #pragma unroll
             for (int g = 0; g < NF; g++)
 #pragma unroll
-                for (int b = 0; b < M; b++)
-                    r[fnode<DIM, M>(k, g, b)] += Fl[g] * (T)(R.winv[b] * R.B[s][b]) + Hl[g] * (T)(R.winv[b] * R.G[s][b]);
+                for (int b = 0; b < M; b++) {
+                    T &rn = r[fnode<DIM, M>(k, g, b)];
+                    rn += Fl[g] * (T)(R.winv[b] * R.B[s][b]);
+                    rn += Hl[g] * (T)(R.winv[b] * R.G[s][b]);
+                }
             }
             if constexpr (!kPrefetch)
                 if (f + NB < NFACE) issue(f + NB, nbuf[f % NB]);
@@ -949,6 +959,8 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
     // before the first store (the stores could alias them for the compiler)
     const uint32_t ouo = (uint32_t)(cur ^ 1) * L.slot_bytes + ojt;
     const T apk = a.apk, apa = a.apa, eps0 = a.eps0, mu1 = a.mu1, mu2 = a.mu2;
+    const T apa1 = (T)1 + apa;
+    const T ndt_l2e = -dt * (T)1.4426950408889634;  // -dt log2(e) (FP32 gate step)
     bool any = false;  // some stimulus box is on at t_i
     for (int b = 0; b < a.n_stim; b++) any = any || (L.t_i >= a.stim[b][6] && L.t_i < a.stim[b][7]);
     // Nodes lie inside the element's box [lo, lo + h] (also after rounding:
@@ -981,8 +993,12 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
         } else {
             vn = buf_ld<T>(rv, ojt, (uint32_t)n * grp_node<T, NP>(L.node_bytes));
         }
-        T stim = 0;
+        const T au = apk * un;
+        const T f = -au * (un - apa) * (un - (T)1) - un * vn;
+        // (r + f) + stimulus; the stimulus sum only where a box is on
+        T rf = r[n] + f;
         if (hit) {
+            T stim = 0;
             double X[3];
             int nn = n;
 #pragma unroll
@@ -998,21 +1014,22 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
                 for (int k = 0; k < DIM; k++) in = in && X[k] >= a.stim[b][k] && X[k] <= a.stim[b][3 + k];
                 if (in) stim += (T)a.stim[b][8];
             }
+            rf += stim;
         }
-        const T f = -apk * un * (un - apa) * (un - (T)1) - un * vn;
         T den = un + mu2;
         den = den < (T)1e-6 ? (T)1e-6 : den;
-        const T vinf = apk * un * ((T)1 + apa - un);
+        const T vinf = au * (apa1 - un);
         T decay;
         if constexpr (sizeof(T) == 4) {
-            // FP32 bulk: hardware reciprocal (1 ulp) and exponential
+            // FP32 bulk: hardware reciprocal (1 ulp) and base-2 exponential
+            // of -eps dt log2(e), the scale taken once per element
             const T eps = eps0 + mu1 * (vn * __builtin_amdgcn_rcpf(den));
-            decay = __expf(-eps * dt);
+            decay = __builtin_amdgcn_exp2f(eps * ndt_l2e);
         } else {
             const T eps = eps0 + mu1 * vn / den;
             decay = exp(-eps * dt);
         }
-        buf_st<T>(ru, ouo, (uint32_t)n * grp_node<T, NP>(L.node_bytes), un + dt * (r[n] + f + stim));
+        buf_st<T>(ru, ouo, (uint32_t)n * grp_node<T, NP>(L.node_bytes), un + dt * rf);
         buf_st<T>(rv, ojt, (uint32_t)n * grp_node<T, NP>(L.node_bytes), vinf + (vn - vinf) * decay);
     }
 }
