@@ -218,3 +218,30 @@ def test_batch_adapt_of_more_than_64_simulations(ctx):
         assert np.array_equal(ua, ub) and np.array_equal(va, vb)
         ga.close()
         gb.close()
+
+
+def test_q2_hexahedra_over_several_tiles_per_level(ctx):
+    """FP32 Q2 hexahedra on a mesh with several blocks of elements on a level
+    (full and ragged tiles, every block size the tuner tries): the batched
+    launches equal the eager per-element launches bitwise and the oracle to
+    the FP32 bar."""
+    case = (3, 2, (9, 8, 7), (0.09, 0.08, 0.07), 1, (1e-3, 0.8e-3, 0.6e-3), 4.0, (16,), 3, "f32")
+    n_bar = 14  # the tuner tries block sizes over the first 12 barriers
+    ctx.set_graphs(False)
+    _, g, _, _, _, _ = _make(ctx, case, 300)
+    g.step(n_bar)
+    eager = g.get_state()
+    g.close()
+    ctx.set_graphs(True)
+    o, g, dt, L, _, _ = _make(ctx, case, 300)
+    lv, _ = o.levels(dt, L)
+    hist = np.bincount(lv, minlength=L)
+    assert hist.max() > 512 and np.any(hist % 512 != 0), hist
+    ctx.batch_step([g], n_bar)
+    batched = g.get_state()
+    assert np.array_equal(batched[0], eager[0]) and np.array_equal(batched[1], eager[1])
+    for n in range(n_bar):
+        o.lts_barrier(dt, 0.125 + n * dt, lv)
+    assert rel_l2(batched[0], o.get_state()[0]) <= 1e-4
+    assert rel_l2(batched[1], o.get_state()[1]) <= 1e-4
+    g.close()
