@@ -656,7 +656,7 @@ __device__ __forceinline__ void substep_element(const StepArgs<T> &a, const Step
     // interior faces.  Elements that do not prefetch every face keep NB
     // faces' neighbours in flight: face f+NB's loads are issued as soon as
     // face f is done, so memory overlaps the arithmetic.  NB = 2 in FP32 up
-    // to degree 2 (Q2 hexahedra 250 VGPRs, still 2 waves per SIMD; alone,
+    // to degree 2 (Q2 hexahedra 249 VGPRs, still 2 waves per SIMD; alone,
     // 3.5 % faster than NB = 1 for Q2 hexahedra and 2-4 % for Q1
     // hexahedra); degree 3 and FP64 keep NB = 1 for their register budget.
     constexpr int NB = (sizeof(T) == 4 && P <= 2) ? 2 : 1;
